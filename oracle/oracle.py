@@ -1,0 +1,167 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes binding of the FP64 CPU oracle (ora.c).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this module.  The product (the HIP library and its binding) never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libora.so")
+_lib = None
+
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile ora.c into oracle/libora.so (plain C, FP64, no FMA contraction)."""
+    src = os.path.join(_HERE, "ora.c")
+    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", _LIB_PATH + ".tmp", src, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Setup(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("dx", _D), ("dy", _D), ("periodic", C.c_int),
+        ("n_obst", C.c_int), ("oi0", _I), ("oj0", _I), ("oi1", _I), ("oj1", _I),
+        ("Ma", C.c_double), ("Re", C.c_double), ("Pr", C.c_double), ("gamma", C.c_double),
+        ("u_in", _D), ("T_in", _D), ("p_in", C.c_double),
+        ("wall_type", C.c_int * 2), ("wall_u", C.c_double * 2), ("wall_T", _D * 2),
+        ("obstacle_T", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        L.ora_create.restype = C.c_void_p
+        L.ora_create.argtypes = [C.POINTER(_Setup)]
+        L.ora_destroy.argtypes = [C.c_void_p]
+        L.ora_set_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
+        L.ora_get_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
+        L.ora_step.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int]
+        L.ora_residuals.argtypes = [C.c_void_p, _D]
+        L.ora_mass.argtypes = [C.c_void_p, _D]
+        L.ora_params.argtypes = [C.c_double] * 4 + [_D]
+        L.ora_vanleer.restype = C.c_double
+        L.ora_vanleer.argtypes = [C.c_double, C.c_double]
+        L.ora_psi_s.restype = C.c_double
+        L.ora_psi_s.argtypes = [C.c_double] * 9
+        L.ora_psi_c.restype = C.c_double
+        L.ora_psi_c.argtypes = [C.c_double] * 8
+        L.ora_eq_residuals.argtypes = [C.c_void_p, C.c_double, C.c_int, _D, _D, _D, _D]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def params(Ma, Re, Pr, gamma):
+    out = np.zeros(5)
+    lib().ora_params(Ma, Re, Pr, gamma, _ptr(out))
+    return out
+
+
+def vanleer(a, b):
+    return lib().ora_vanleer(a, b)
+
+
+def psi_s(*args):
+    return lib().ora_psi_s(*[float(x) for x in args])
+
+
+def psi_c(*args):
+    return lib().ora_psi_c(*[float(x) for x in args])
+
+
+class Oracle:
+    """FP64 CPU SIMPLE-TS on a Problem (see paper_1802_04243_amd.workloads)."""
+
+    def __init__(self, prob):
+        L = lib()
+        self.prob = prob
+        self.nx, self.ny = prob.nx, prob.ny
+        dx, dy = prob.widths()
+        u_in, T_in = prob.inlet()
+        wb, wt = prob.walls()
+        ob = np.array(prob.obstacles, dtype=np.int32).reshape(-1, 4)
+        self._keep = [dx, dy, u_in, T_in, wb, wt]
+        oi0, oj0, oi1, oj1 = [np.ascontiguousarray(ob[:, k]) for k in range(4)]
+        self._keep += [oi0, oj0, oi1, oj1]
+        s = _Setup()
+        s.nx, s.ny = prob.nx, prob.ny
+        s.dx, s.dy = _ptr(dx), _ptr(dy)
+        s.periodic = int(prob.periodic)
+        s.n_obst = len(ob)
+        ip = lambda a: a.ctypes.data_as(_I)
+        s.oi0, s.oj0, s.oi1, s.oj1 = ip(oi0), ip(oj0), ip(oi1), ip(oj1)
+        s.Ma, s.Re, s.Pr, s.gamma = prob.Ma, prob.Re, prob.Pr, prob.gamma
+        s.u_in, s.T_in, s.p_in = _ptr(u_in), _ptr(T_in), prob.p_in
+        s.wall_type[0], s.wall_type[1] = prob.wall_type
+        s.wall_u[0], s.wall_u[1] = prob.wall_u
+        s.wall_T[0], s.wall_T[1] = _ptr(wb), _ptr(wt)
+        s.obstacle_T, s.gx, s.gy = prob.obstacle_T, prob.gx, prob.gy
+        h = L.ora_create(C.byref(s))
+        if not h:
+            raise ValueError("ora_create rejected the problem")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().ora_destroy(self._h)
+            self._h = None
+
+    def shapes(self):
+        nx, ny = self.nx, self.ny
+        return (ny, nx + 1), (ny + 1, nx), (ny, nx), (ny, nx)
+
+    def set_fields(self, u=None, v=None, p=None, T=None):
+        arrs = []
+        for a, shp in zip((u, v, p, T), self.shapes()):
+            if a is None:
+                arrs.append(None)
+            else:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                assert a.shape == shp, (a.shape, shp)
+                arrs.append(a)
+        lib().ora_set_fields(self._h, *[(_ptr(a) if a is not None else None) for a in arrs])
+
+    def fields(self):
+        out = [np.zeros(s) for s in self.shapes()]
+        lib().ora_get_fields(self._h, *[_ptr(a) for a in out])
+        return tuple(out)
+
+    def step(self, dt, n_inner, scheme):
+        lib().ora_step(self._h, float(dt), int(n_inner), int(scheme))
+
+    def residuals(self):
+        out = np.zeros(6)
+        lib().ora_residuals(self._h, _ptr(out))
+        return out
+
+    def mass(self):
+        out = np.zeros(3)
+        lib().ora_mass(self._h, _ptr(out))
+        return out
+
+    def eq_residuals(self, dt, scheme):
+        out = [np.zeros(s) for s in ((self.ny, self.nx), (self.ny, self.nx + 1),
+                                      (self.ny + 1, self.nx), (self.ny, self.nx))]
+        lib().ora_eq_residuals(self._h, float(dt), int(scheme), *[_ptr(a) for a in out])
+        return tuple(out)  # rT, ru, rv, rp
