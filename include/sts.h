@@ -1,0 +1,165 @@
+/*
+ * sts.h -- C ABI of the MI355X SIMPLE-TS library (libsts.so).
+ *
+ * SIMPLE-TS (Shterev, arXiv 1802.04243) advances the unsteady, viscous,
+ * compressible, heat-conductive 2-D Navier-Stokes-Fourier system (Sec. 2,
+ * eqs pl4-pl7) on a staggered Cartesian finite-volume grid (Sec. 3.2, the
+ * cell-volume figure).  One time step (loop 1) is a step prologue followed by
+ * n_inner Jacobi passes of loop 2 (Sec. 3.1, figures of the explicit and
+ * implicit GPU algorithms; pass order of Appendix A).  Every computation runs
+ * in hand-written HIP kernels on the GPU the context was created on.
+ *
+ * Conventions
+ *   - Every function returns sts_status (0 = OK, < 0 = error) and never
+ *     aborts.  On error sts_last_error() returns a message (thread-local).
+ *   - All quantities are nondimensional FP64: lengths in channel heights,
+ *     velocities in inlet speeds, T, p, rho relative to the inlet state.
+ *   - Host field arrays are dense, x fastest:
+ *       u [ny][nx+1]  x-velocity at x-faces (x^f_i, y^v_j)
+ *       v [ny+1][nx]  y-velocity at y-faces (x^v_i, y^f_j)
+ *       p [ny][nx], T [ny][nx]  at cell centres.
+ *   - One context per host thread.  Calls on one context are ordered on its
+ *     HIP stream; sts_step is asynchronous, sts_residuals / sts_fields wait.
+ */
+#ifndef STS_H
+#define STS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STS_OK = 0,
+  STS_EINVAL = -1,     /* invalid argument; the context is unchanged        */
+  STS_ENOMEM = -2,     /* device or host allocation failed                  */
+  STS_EDEVICE = -3,    /* a HIP call failed                                  */
+  STS_ENONFINITE = -4, /* the last step produced a non-finite value; the
+                          state is left as computed, for inspection         */
+  STS_ESTATE = -5      /* call not valid in the current state               */
+} sts_status;
+
+typedef struct sts_ctx sts_ctx; /* opaque; owns all device state */
+
+/* Grid (cell-volume figure, Sec. 3.2).  nx, ny >= 4 cells.  If dx (dy) is
+   NULL the spacing is uniform lx/nx (ly/ny); otherwise dx[nx] (dy[ny]) are the
+   positive cell widths.  Arrays are copied. */
+typedef struct {
+  int nx, ny;
+  double lx, ly;
+  const double *dx, *dy;
+} sts_grid;
+
+/* Solid obstacles: n closed rectangles of cells [i0, i1] x [j0, j1] (cell
+   indices).  A cell is solid iff it lies in a rectangle.  With inlet/outlet
+   in x, every rectangle must keep i0 >= 2 and i1 <= nx - 3.  Arrays copied. */
+typedef struct {
+  int n;
+  const int *i0, *j0, *i1, *j1;
+} sts_obstacles;
+
+enum { STS_X_INLET_OUTLET = 0, STS_X_PERIODIC = 1 };
+enum { STS_WALL_NOSLIP_ISOTHERMAL = 0, STS_WALL_SLIP_ADIABATIC = 1 };
+
+/* Boundary conditions (test case of Sec. 4 in convective units; the walls
+   are eqs pl38/pl39 with zero slip and jump lengths, or slip and adiabatic).
+     x_mode      inlet at x = 0 and outlet at x = Lx, or periodic in x.
+     u_in, T_in  [ny] inlet-face u and T (NULL -> 1); inlet v = 0.
+     p_in        inlet pressure (sets the inflow density p_in/T_in).
+     wall_type   [0] bottom wall y = 0, [1] top wall y = Ly.
+     wall_u      tangential velocity of each no-slip wall.
+     wall_T      [nx] wall temperature per cell column (NULL -> 1).
+     obstacle_T  surface temperature of the obstacles (no-slip, isothermal).
+     gx, gy      body force per unit mass (rho g in eqs pl2, pl3).
+   Arrays are copied. */
+typedef struct {
+  int x_mode;
+  const double *u_in, *T_in;
+  double p_in;
+  int wall_type[2];
+  double wall_u[2];
+  const double *wall_T[2];
+  double obstacle_T;
+  double gx, gy;
+} sts_bc;
+
+/* scheme bits for sts_step: convective terms explicit (Forward Euler) or
+   implicit (Backward Euler) in time, upwind or TVD (van Leer) in space
+   (Sec. 3.1, the four variants). */
+enum {
+  STS_EXPLICIT = 0,
+  STS_IMPLICIT = 1,
+  STS_UPWIND = 0,
+  STS_TVD = 2,
+  STS_SCHEME_MASK = 3
+};
+
+/* Device bytes the library needs for a grid (state, per-step constants,
+   reduction buffers), for callers that bring their own workspace. */
+sts_status sts_workspace_bytes(const sts_grid *grid, size_t *bytes);
+
+/* Create a solver.  Ma, Re, Pr > 0, gamma > 1 give the coefficients of
+   eqs pl2-pl6 (A = 1/(gamma Ma^2), B = 1/Re, energy equation in internal
+   energy form).  hip_stream: a hipStream_t to order all work on, or NULL for
+   a stream owned by the context.  workspace: device memory of at least
+   sts_workspace_bytes(), owned by the caller and kept alive until
+   sts_destroy, or NULL to let the library allocate.  The initial state is
+   the inlet state of each row (u = u_in, v = 0, p = p_in, T = T_in) with
+   the boundary values imposed.  *out is set only on success. */
+sts_status sts_create(const sts_grid *grid, const sts_obstacles *obstacles,
+                      double Ma, double Re, double Pr, double gamma,
+                      const sts_bc *bc, void *hip_stream, void *workspace,
+                      size_t workspace_bytes, sts_ctx **out);
+
+/* Advance one time step of size dt > 0 with n_inner >= 1 Jacobi passes of
+   loop 2 (scheme: STS_* bits).  Enqueues on the context's stream and returns
+   without waiting.  The residuals of the last pass are reduced on the device
+   and copied to pinned host memory. */
+sts_status sts_step(sts_ctx *ctx, double dt, int n_inner, int scheme);
+
+/* Wait for the stream; out[6] = max|du|, max|dv|, max|dp|, max|dT| of the
+   last pass over the unknowns, max|R| and sum R of the discrete continuity
+   residual R = ((p/T)_new - (p/T)^{n-1}) dV/dt + net outflow of
+   rho^u u_new dy and rho^v v_new dx.  Returns STS_ENONFINITE if the last
+   step produced a non-finite value. */
+sts_status sts_residuals(sts_ctx *ctx, double out[6]);
+
+/* Wait for the stream and copy the current state to host arrays (layout
+   above; caller-owned; NULL skips a field). */
+sts_status sts_fields(sts_ctx *ctx, double *u, double *v, double *p,
+                      double *T);
+
+/* Replace the state by host arrays (NULL keeps a field), then impose the
+   boundary values: inlet faces u = u_in, wall and obstacle faces 0, outlet
+   face u = its upstream neighbour, solid cells T = obstacle_T, p = p_in.
+   Synchronous. */
+sts_status sts_set_fields(sts_ctx *ctx, const double *u, const double *v,
+                          const double *p, const double *T);
+
+/* Device pointers of the current state and the element index of (0,0) and
+   row pitch (in doubles) of each array: element (i,j) of field f is
+   f[origin + j*pitch + i].  Valid until the next sts_step. */
+sts_status sts_field_ptrs(sts_ctx *ctx, double **u, double **v, double **p,
+                          double **T, size_t *origin, size_t *pitch);
+
+/* Per-step kernel timing with HIP events recorded on the context's stream:
+   enable (1) or disable (0); enabling waits and clears the accumulation. */
+sts_status sts_timing(sts_ctx *ctx, int enable);
+
+/* Wait, then return the kernel time summed over the steps recorded since
+   timing was enabled or last read: out_ms[0] step prologues, [1] all Jacobi
+   passes, [2] residual reductions (with the residual copy), in milliseconds;
+   out_n[0] = steps, out_n[1] = passes.  Clears the accumulation. */
+sts_status sts_read_timing(sts_ctx *ctx, double out_ms[3], long long out_n[2]);
+
+/* Release everything the context owns.  NULL-safe. */
+void sts_destroy(sts_ctx *ctx);
+
+/* Message of the last error on this thread ("" if none). */
+const char *sts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STS_H */

@@ -1,0 +1,609 @@
+// Host runtime of libsts.so: the C ABI declared in include/sts.h.
+//
+// Owns the device state (two ping-pong state buffers, four per-step constant
+// arrays, boundary data, reduction buffers), validates every argument, and
+// drives one time step as: prologue kernel, n_inner pass kernels (buffer swap,
+// no copy), residual kernel + finalize, and one asynchronous copy of the
+// reduced residuals to pinned host memory -- the only device-to-host traffic
+// of a step (Sec. 5 of the paper: only the max residuals of loop 2 cross).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sts.h"
+#include "sts_internal.h"
+
+using namespace sts;
+
+namespace {
+thread_local std::string g_err;
+
+sts_status fail(sts_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+#define HIPCHK(call)                                                     \
+  do {                                                                   \
+    hipError_t e_ = (call);                                              \
+    if (e_ != hipSuccess)                                                \
+      return fail(STS_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  long pitch, rows, off;
+  size_t field_bytes;  // one FP64 field array
+  size_t mask_bytes;
+};
+Layout make_layout(int nx, int ny) {
+  Layout L;
+  L.pitch = (long)align_up((size_t)(XO + nx + 1 + XPAD), 32);
+  L.rows = ny + 1 + 2 * YO;
+  L.off = (long)YO * L.pitch + XO;
+  L.field_bytes = align_up((size_t)L.pitch * L.rows * sizeof(double), 256);
+  L.mask_bytes = align_up((size_t)L.pitch * L.rows, 256);
+  return L;
+}
+struct Sizes {
+  size_t state, consts, mask, small, partials, res, total;
+};
+Sizes make_sizes(int nx, int ny, const Layout &L) {
+  Sizes S;
+  S.state = 8 * L.field_bytes;   // two buffers of u, v, p, T
+  S.consts = 4 * L.field_bytes;  // C_u, C_v, C_T, C_p
+  S.mask = L.mask_bytes;
+  // 1-D boundary arrays (see ctx_build), tile flags
+  const size_t tiles = (size_t)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
+  S.small = align_up(sizeof(double) * ((size_t)2 * (nx + 2 * XPAD) + 2 * (ny + 2 * XPAD) +
+                                        4 * (size_t)ny + 4 * (size_t)nx + 2 * (size_t)(nx + 1)),
+                     256) +
+            align_up(tiles, 256);
+  S.partials = align_up(sizeof(double) * NRES * 2048, 256);
+  S.res = 256;
+  S.total = S.state + S.consts + S.mask + S.small + S.partials + S.res;
+  return S;
+}
+
+}  // namespace
+
+struct sts_ctx {
+  int nx, ny, per;
+  Layout L;
+  Sizes S;
+  Params P;
+  hipStream_t stream;
+  bool own_stream;
+  int device;
+  char *base;
+  bool own_mem;
+  State st[2];
+  int cur;
+  Consts C;
+  double *partials, *dres;
+  double *hres;  // pinned
+  int nres_blocks;
+  bool stepped;
+  int last_scheme;
+  // host copies of the boundary data
+  std::vector<double> dx, dy, u_in, T_in, Tw[2];
+  std::vector<unsigned char> solid;  // [ny][nx]
+  double p_in, obsT;
+  // timing
+  bool timing;
+  std::vector<hipEvent_t> ev;  // 4 per recorded step
+  int ev_used;
+  long long t_steps, t_passes;
+  double t_ms[3];
+};
+
+extern "C" const char *sts_last_error(void) { return g_err.c_str(); }
+
+extern "C" sts_status sts_workspace_bytes(const sts_grid *grid, size_t *bytes) {
+  if (!grid || !bytes) return fail(STS_EINVAL, "NULL argument");
+  if (grid->nx < 4 || grid->ny < 4) return fail(STS_EINVAL, "nx, ny must be >= 4");
+  Layout L = make_layout(grid->nx, grid->ny);
+  *bytes = make_sizes(grid->nx, grid->ny, L).total;
+  return STS_OK;
+}
+
+namespace {
+
+sts_status validate(const sts_grid *g, const sts_obstacles *ob, double Ma,
+                    double Re, double Pr, double gamma, const sts_bc *bc) {
+  if (!g || !bc) return fail(STS_EINVAL, "grid and bc are required");
+  if (g->nx < 4 || g->ny < 4) return fail(STS_EINVAL, "nx, ny must be >= 4");
+  if ((long)g->nx * g->ny > (1L << 31)) return fail(STS_EINVAL, "grid too large");
+  if (!g->dx && !(g->lx > 0 && isfinite(g->lx))) return fail(STS_EINVAL, "lx must be > 0");
+  if (!g->dy && !(g->ly > 0 && isfinite(g->ly))) return fail(STS_EINVAL, "ly must be > 0");
+  if (g->dx)
+    for (int i = 0; i < g->nx; i++)
+      if (!(g->dx[i] > 0 && isfinite(g->dx[i]))) return fail(STS_EINVAL, "dx[%d] must be > 0", i);
+  if (g->dy)
+    for (int j = 0; j < g->ny; j++)
+      if (!(g->dy[j] > 0 && isfinite(g->dy[j]))) return fail(STS_EINVAL, "dy[%d] must be > 0", j);
+  if (!(Ma > 0 && isfinite(Ma)) || !(Re > 0 && isfinite(Re)) ||
+      !(Pr > 0 && isfinite(Pr)) || !(gamma > 1 && isfinite(gamma)))
+    return fail(STS_EINVAL, "need Ma, Re, Pr > 0 and gamma > 1");
+  if (bc->x_mode != STS_X_INLET_OUTLET && bc->x_mode != STS_X_PERIODIC)
+    return fail(STS_EINVAL, "unknown x_mode %d", bc->x_mode);
+  for (int w = 0; w < 2; w++)
+    if (bc->wall_type[w] != STS_WALL_NOSLIP_ISOTHERMAL &&
+        bc->wall_type[w] != STS_WALL_SLIP_ADIABATIC)
+      return fail(STS_EINVAL, "unknown wall_type[%d] = %d", w, bc->wall_type[w]);
+  if (!(bc->p_in > 0 && isfinite(bc->p_in))) return fail(STS_EINVAL, "p_in must be > 0");
+  if (!(bc->obstacle_T > 0 && isfinite(bc->obstacle_T)))
+    return fail(STS_EINVAL, "obstacle_T must be > 0");
+  for (int j = 0; j < g->ny; j++) {
+    if (bc->T_in && !(bc->T_in[j] > 0 && isfinite(bc->T_in[j])))
+      return fail(STS_EINVAL, "T_in[%d] must be > 0", j);
+    if (bc->u_in && !isfinite(bc->u_in[j])) return fail(STS_EINVAL, "u_in[%d] not finite", j);
+  }
+  for (int w = 0; w < 2; w++)
+    if (bc->wall_T[w])
+      for (int i = 0; i < g->nx; i++)
+        if (!(bc->wall_T[w][i] > 0 && isfinite(bc->wall_T[w][i])))
+          return fail(STS_EINVAL, "wall_T[%d][%d] must be > 0", w, i);
+  if (!isfinite(bc->wall_u[0]) || !isfinite(bc->wall_u[1]) || !isfinite(bc->gx) ||
+      !isfinite(bc->gy))
+    return fail(STS_EINVAL, "wall_u, gx, gy must be finite");
+  if (ob && ob->n > 0) {
+    if (!ob->i0 || !ob->j0 || !ob->i1 || !ob->j1) return fail(STS_EINVAL, "obstacle arrays are NULL");
+    for (int k = 0; k < ob->n; k++) {
+      if (ob->i0[k] > ob->i1[k] || ob->j0[k] > ob->j1[k] || ob->i0[k] < 0 ||
+          ob->j0[k] < 0 || ob->i1[k] >= g->nx || ob->j1[k] >= g->ny)
+        return fail(STS_EINVAL, "obstacle %d outside the grid or empty", k);
+      if (bc->x_mode == STS_X_INLET_OUTLET && (ob->i0[k] < 2 || ob->i1[k] > g->nx - 3))
+        return fail(STS_EINVAL, "obstacle %d touches the inlet or outlet", k);
+    }
+  } else if (ob && ob->n < 0) {
+    return fail(STS_EINVAL, "negative obstacle count");
+  }
+  return STS_OK;
+}
+
+bool u_is_unknown(const sts_ctx *c, int i, int j) {
+  if (!c->per && (i <= 0 || i >= c->nx)) return false;
+  if (c->per && i >= c->nx) return false;
+  const int l = (i - 1 + c->nx) % c->nx;
+  return !c->solid[(size_t)j * c->nx + l] && !c->solid[(size_t)j * c->nx + i];
+}
+bool v_is_unknown(const sts_ctx *c, int i, int j) {
+  if (j <= 0 || j >= c->ny) return false;
+  return !c->solid[(size_t)(j - 1) * c->nx + i] && !c->solid[(size_t)j * c->nx + i];
+}
+
+// Impose the boundary values on host state arrays (dense layout).
+void project(const sts_ctx *c, double *u, double *v, double *p, double *T) {
+  const int nx = c->nx, ny = c->ny;
+  for (int j = 0; j < ny; j++) {
+    for (int i = 0; i < nx; i++)
+      if (c->solid[(size_t)j * nx + i]) {
+        T[(size_t)j * nx + i] = c->obsT;
+        p[(size_t)j * nx + i] = c->p_in;
+      }
+    double *ur = u + (size_t)j * (nx + 1);
+    for (int i = 0; i < nx; i++) {
+      if (!c->per && i == 0) ur[0] = c->u_in[j];
+      else if (!u_is_unknown(c, i, j)) ur[i] = 0.0;
+    }
+    ur[nx] = c->per ? ur[0] : ur[nx - 1];
+  }
+  for (int j = 0; j <= ny; j++)
+    for (int i = 0; i < nx; i++)
+      if (!v_is_unknown(c, i, j)) v[(size_t)j * nx + i] = 0.0;
+}
+
+// Upload dense host fields into device buffer b (frame values untouched).
+sts_status upload(sts_ctx *c, int b, const double *u, const double *v,
+                  const double *p, const double *T) {
+  const int nx = c->nx, ny = c->ny;
+  const long P = c->L.pitch;
+  HIPCHK(hipMemcpy2DAsync(c->st[b].u + c->L.off, P * 8, u, (nx + 1) * 8, (nx + 1) * 8, ny,
+                          hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpy2DAsync(c->st[b].v + c->L.off, P * 8, v, nx * 8, nx * 8, ny + 1,
+                          hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpy2DAsync(c->st[b].p + c->L.off, P * 8, p, nx * 8, nx * 8, ny,
+                          hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpy2DAsync(c->st[b].T + c->L.off, P * 8, T, nx * 8, nx * 8, ny,
+                          hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return STS_OK;
+}
+
+sts_status fill_frames(sts_ctx *c) {
+  // every field buffer: u, v = 0 and p, T = 1 outside the domain
+  const size_t n = (size_t)c->L.pitch * c->L.rows;
+  std::vector<double> one(n, 1.0);
+  for (int b = 0; b < 2; b++) {
+    HIPCHK(hipMemsetAsync(c->st[b].u, 0, n * 8, c->stream));
+    HIPCHK(hipMemsetAsync(c->st[b].v, 0, n * 8, c->stream));
+    HIPCHK(hipMemcpyAsync(c->st[b].p, one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->st[b].T, one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(hipMemsetAsync(c->C.Cu, 0, 4 * c->L.field_bytes, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return STS_OK;
+}
+
+sts_status build(sts_ctx *c, const sts_bc *bc) {
+  const int nx = c->nx, ny = c->ny;
+  Params &P = c->P;
+  char *q = c->base;
+  for (int b = 0; b < 2; b++) {
+    c->st[b].u = (double *)q; q += c->L.field_bytes;
+    c->st[b].v = (double *)q; q += c->L.field_bytes;
+    c->st[b].p = (double *)q; q += c->L.field_bytes;
+    c->st[b].T = (double *)q; q += c->L.field_bytes;
+  }
+  c->C.Cu = (double *)q; q += c->L.field_bytes;
+  c->C.Cv = (double *)q; q += c->L.field_bytes;
+  c->C.CT = (double *)q; q += c->L.field_bytes;
+  c->C.Cp = (double *)q; q += c->L.field_bytes;
+  unsigned char *fl = (unsigned char *)q; q += c->S.mask;
+  char *small = q; q += c->S.small;
+  c->partials = (double *)q; q += c->S.partials;
+  c->dres = (double *)q; q += c->S.res;
+
+  // host-side boundary data
+  std::vector<double> hs;
+  auto put = [&](const std::vector<double> &a) {
+    size_t at = hs.size();
+    hs.insert(hs.end(), a.begin(), a.end());
+    return at;
+  };
+  std::vector<double> dxp(nx + 2 * XPAD), dyp(ny + 2 * XPAD);
+  for (int i = -XPAD; i < nx + XPAD; i++) {
+    int k = c->per ? ((i % nx) + nx) % nx : (i < 0 ? 0 : (i >= nx ? nx - 1 : i));
+    dxp[i + XPAD] = c->dx[k];
+  }
+  for (int j = -XPAD; j < ny + XPAD; j++) {
+    int k = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+    dyp[j + XPAD] = c->dy[k];
+  }
+  std::vector<double> sqTin(ny), rhoin(ny), sqTw0(nx), sqTw1(nx), sqTwu0(nx + 1), sqTwu1(nx + 1);
+  for (int j = 0; j < ny; j++) {
+    sqTin[j] = sqrt(c->T_in[j]);
+    rhoin[j] = c->p_in / c->T_in[j];
+  }
+  for (int i = 0; i < nx; i++) {
+    sqTw0[i] = sqrt(c->Tw[0][i]);
+    sqTw1[i] = sqrt(c->Tw[1][i]);
+  }
+  // wall temperature at the x-position of u-face i: linear between the two
+  // neighbouring cell columns
+  for (int i = 0; i <= nx; i++) {
+    int l = i - 1, r = i;
+    if (c->per) { l = (l + nx) % nx; r = r % nx; }
+    else { if (l < 0) l = 0; if (r > nx - 1) r = nx - 1; }
+    const double dl = c->dx[l], dr = c->dx[r];
+    sqTwu0[i] = sqrt((dr * c->Tw[0][l] + dl * c->Tw[0][r]) / (dl + dr));
+    sqTwu1[i] = sqrt((dr * c->Tw[1][l] + dl * c->Tw[1][r]) / (dl + dr));
+  }
+  size_t o_dx = put(dxp), o_dy = put(dyp), o_uin = put(c->u_in), o_tin = put(c->T_in),
+         o_sqtin = put(sqTin), o_rhoin = put(rhoin), o_tw0 = put(c->Tw[0]), o_tw1 = put(c->Tw[1]),
+         o_sqtw0 = put(sqTw0), o_sqtw1 = put(sqTw1), o_sqtwu0 = put(sqTwu0), o_sqtwu1 = put(sqTwu1);
+  HIPCHK(hipMemcpyAsync(small, hs.data(), hs.size() * 8, hipMemcpyHostToDevice, c->stream));
+  const double *sd = (const double *)small;
+  P.dxp = sd + o_dx; P.dyp = sd + o_dy;
+  P.u_in = sd + o_uin; P.T_in = sd + o_tin; P.sq_T_in = sd + o_sqtin; P.rho_in = sd + o_rhoin;
+  P.Tw0 = sd + o_tw0; P.Tw1 = sd + o_tw1; P.sq_Tw0 = sd + o_sqtw0; P.sq_Tw1 = sd + o_sqtw1;
+  P.sq_Twu0 = sd + o_sqtwu0; P.sq_Twu1 = sd + o_sqtwu1;
+  unsigned char *clean_dev = (unsigned char *)(small + align_up(hs.size() * 8, 256));
+
+  // fluid mask with frame
+  std::vector<unsigned char> hfl((size_t)c->L.pitch * c->L.rows, 0);
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++)
+      hfl[(size_t)(j + YO) * c->L.pitch + XO + i] = c->solid[(size_t)j * nx + i] ? 0 : 1;
+  HIPCHK(hipMemcpyAsync(fl, hfl.data(), hfl.size(), hipMemcpyHostToDevice, c->stream));
+  P.fl = fl;
+
+  // clean tiles: the whole window lies inside the domain (away from the
+  // inlet, outlet and walls) and contains no solid cell
+  P.tiles_x = (nx + TX - 1) / TX;
+  P.tiles_y = (ny + TY - 1) / TY;
+  std::vector<unsigned char> cl((size_t)P.tiles_x * P.tiles_y, 0);
+  for (int ty = 0; ty < P.tiles_y; ty++)
+    for (int tx = 0; tx < P.tiles_x; tx++) {
+      const int x0 = tx * TX, y0 = ty * TY;
+      const int xa = x0 - HB, xb = x0 + TX + HB - 1, ya = y0 - HB, yb = y0 + TY + HB - 1;
+      bool ok = ya >= 0 && yb <= ny - 1 && (c->per ? (xb - xa + 1 <= nx) : (xa >= 0 && xb <= nx - 1));
+      if (c->per && (x0 + TX > nx)) ok = false;  // partial periodic tile: general path
+      for (int j = ya; ok && j <= yb; j++)
+        for (int i = xa; ok && i <= xb; i++) {
+          const int ii = c->per ? ((i % nx) + nx) % nx : i;
+          if (c->solid[(size_t)j * nx + ii]) ok = false;
+        }
+      cl[(size_t)ty * P.tiles_x + tx] = ok ? 1 : 0;
+    }
+  HIPCHK(hipMemcpyAsync(clean_dev, cl.data(), cl.size(), hipMemcpyHostToDevice, c->stream));
+  P.clean = clean_dev;
+  P.nx = nx;
+  P.ny = ny;
+  P.per = c->per;
+  P.pitch = c->L.pitch;
+  P.off = c->L.off;
+  P.wtype0 = bc->wall_type[0];
+  P.wtype1 = bc->wall_type[1];
+  P.wu0 = bc->wall_u[0];
+  P.wu1 = bc->wall_u[1];
+  P.gx = bc->gx;
+  P.gy = bc->gy;
+  P.obsT = c->obsT;
+  P.sq_obsT = sqrt(c->obsT);
+  c->nres_blocks = residual_blocks(P);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return fill_frames(c);
+}
+
+sts_status initial_state(sts_ctx *c) {
+  const int nx = c->nx, ny = c->ny;
+  std::vector<double> u((size_t)(nx + 1) * ny), v((size_t)nx * (ny + 1), 0.0),
+      p((size_t)nx * ny), T((size_t)nx * ny);
+  for (int j = 0; j < ny; j++) {
+    for (int i = 0; i <= nx; i++) u[(size_t)j * (nx + 1) + i] = c->u_in[j];
+    for (int i = 0; i < nx; i++) {
+      p[(size_t)j * nx + i] = c->p_in;
+      T[(size_t)j * nx + i] = c->T_in[j];
+    }
+  }
+  project(c, u.data(), v.data(), p.data(), T.data());
+  sts_status s = upload(c, 0, u.data(), v.data(), p.data(), T.data());
+  if (s != STS_OK) return s;
+  s = upload(c, 1, u.data(), v.data(), p.data(), T.data());
+  c->cur = 0;
+  return s;
+}
+
+void release(sts_ctx *c) {
+  if (!c) return;
+  if (c->base && c->own_mem) (void)hipFree(c->base);
+  if (c->hres) (void)hipHostFree(c->hres);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" sts_status sts_create(const sts_grid *grid, const sts_obstacles *obstacles,
+                                 double Ma, double Re, double Pr, double gamma,
+                                 const sts_bc *bc, void *hip_stream, void *workspace,
+                                 size_t workspace_bytes, sts_ctx **out) {
+  if (!out) return fail(STS_EINVAL, "out is NULL");
+  sts_status s = validate(grid, obstacles, Ma, Re, Pr, gamma, bc);
+  if (s != STS_OK) return s;
+  sts_ctx *c = new (std::nothrow) sts_ctx();
+  if (!c) return fail(STS_ENOMEM, "host allocation failed");
+  const int nx = grid->nx, ny = grid->ny;
+  c->nx = nx;
+  c->ny = ny;
+  c->per = bc->x_mode == STS_X_PERIODIC;
+  c->L = make_layout(nx, ny);
+  c->S = make_sizes(nx, ny, c->L);
+  c->dx.resize(nx);
+  c->dy.resize(ny);
+  for (int i = 0; i < nx; i++) c->dx[i] = grid->dx ? grid->dx[i] : grid->lx / nx;
+  for (int j = 0; j < ny; j++) c->dy[j] = grid->dy ? grid->dy[j] : grid->ly / ny;
+  c->u_in.resize(ny);
+  c->T_in.resize(ny);
+  for (int j = 0; j < ny; j++) {
+    c->u_in[j] = bc->u_in ? bc->u_in[j] : 1.0;
+    c->T_in[j] = bc->T_in ? bc->T_in[j] : 1.0;
+  }
+  for (int w = 0; w < 2; w++) {
+    c->Tw[w].resize(nx);
+    for (int i = 0; i < nx; i++) c->Tw[w][i] = bc->wall_T[w] ? bc->wall_T[w][i] : 1.0;
+  }
+  c->solid.assign((size_t)nx * ny, 0);
+  if (obstacles)
+    for (int k = 0; k < obstacles->n; k++)
+      for (int j = obstacles->j0[k]; j <= obstacles->j1[k]; j++)
+        for (int i = obstacles->i0[k]; i <= obstacles->i1[k]; i++)
+          c->solid[(size_t)j * nx + i] = 1;
+  c->p_in = bc->p_in;
+  c->obsT = bc->obstacle_T;
+  // coefficients of eqs pl2-pl6 in convective scaling: A = 1/(gamma Ma^2),
+  // B = 1/Re, energy equation in internal-energy form (the discrete source
+  // carries p div u): C1 = gamma/(Re Pr), C2 = gamma(gamma-1)Ma^2/Re,
+  // C3 = -(gamma-1)
+  c->P.A = 1.0 / (gamma * Ma * Ma);
+  c->P.B = 1.0 / Re;
+  c->P.C1 = gamma / (Re * Pr);
+  c->P.C2 = gamma * (gamma - 1.0) * Ma * Ma / Re;
+  c->P.C3 = -(gamma - 1.0);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(STS_EDEVICE, "no HIP device");
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+    c->own_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(STS_EDEVICE, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  if (workspace) {
+    if (workspace_bytes < c->S.total || ((uintptr_t)workspace % 256) != 0) {
+      release(c);
+      return fail(STS_EINVAL, "workspace needs %zu bytes, 256-byte aligned", c->S.total);
+    }
+    c->base = (char *)workspace;
+    c->own_mem = false;
+  } else {
+    if (hipMalloc((void **)&c->base, c->S.total) != hipSuccess) {
+      c->base = nullptr;
+      release(c);
+      return fail(STS_ENOMEM, "hipMalloc of %zu bytes failed", c->S.total);
+    }
+    c->own_mem = true;
+  }
+  if (hipHostMalloc((void **)&c->hres, 256, hipHostMallocDefault) != hipSuccess) {
+    c->hres = nullptr;
+    release(c);
+    return fail(STS_ENOMEM, "pinned host allocation failed");
+  }
+  memset(c->hres, 0, 256);
+  if ((s = build(c, bc)) != STS_OK || (s = initial_state(c)) != STS_OK) {
+    std::string msg = g_err;
+    release(c);
+    g_err = msg;
+    return s;
+  }
+  *out = c;
+  return STS_OK;
+}
+
+extern "C" void sts_destroy(sts_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  release(ctx);
+}
+
+namespace {
+sts_status record(sts_ctx *c, int k) {
+  if (!c->timing) return STS_OK;
+  const size_t need = (size_t)c->ev_used * 4 + k + 1;
+  while (c->ev.size() < need) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  HIPCHK(hipEventRecord(c->ev[(size_t)c->ev_used * 4 + k], c->stream));
+  return STS_OK;
+}
+}  // namespace
+
+extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (!(dt > 0) || !isfinite(dt)) return fail(STS_EINVAL, "dt must be > 0");
+  if (n_inner < 1) return fail(STS_EINVAL, "n_inner must be >= 1");
+  if (scheme & ~STS_SCHEME_MASK) return fail(STS_EINVAL, "unknown scheme bits 0x%x", scheme);
+  c->P.dt = dt;
+  sts_status s;
+  if ((s = record(c, 0)) != STS_OK) return s;
+  launch_prologue(c->P, c->st[c->cur], c->C, scheme, c->stream);
+  HIPCHK(hipGetLastError());
+  if ((s = record(c, 1)) != STS_OK) return s;
+  for (int k = 0; k < n_inner; k++) {
+    launch_pass(c->P, c->st[c->cur], c->st[c->cur ^ 1], c->C, scheme, c->stream);
+    c->cur ^= 1;
+  }
+  HIPCHK(hipGetLastError());
+  if ((s = record(c, 2)) != STS_OK) return s;
+  launch_residual(c->P, c->st[c->cur ^ 1], c->st[c->cur], c->C, scheme, c->partials,
+                  c->nres_blocks, c->dres, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->hres, c->dres, NRES * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  if ((s = record(c, 3)) != STS_OK) return s;
+  if (c->timing) {
+    c->ev_used++;
+    c->t_passes += n_inner;
+  }
+  c->stepped = true;
+  c->last_scheme = scheme;
+  return STS_OK;
+}
+
+extern "C" sts_status sts_residuals(sts_ctx *c, double out[6]) {
+  if (!c || !out) return fail(STS_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 6; k++) out[k] = c->stepped ? c->hres[k] : 0.0;
+  if (c->stepped && c->hres[6] != 0.0)
+    return fail(STS_ENONFINITE, "the last step produced %g non-finite values", c->hres[6]);
+  return STS_OK;
+}
+
+extern "C" sts_status sts_fields(sts_ctx *c, double *u, double *v, double *p, double *T) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  const int nx = c->nx, ny = c->ny;
+  const long P = c->L.pitch;
+  const State &s = c->st[c->cur];
+  if (u) HIPCHK(hipMemcpy2DAsync(u, (nx + 1) * 8, s.u + c->L.off, P * 8, (nx + 1) * 8, ny,
+                                 hipMemcpyDeviceToHost, c->stream));
+  if (v) HIPCHK(hipMemcpy2DAsync(v, nx * 8, s.v + c->L.off, P * 8, nx * 8, ny + 1,
+                                 hipMemcpyDeviceToHost, c->stream));
+  if (p) HIPCHK(hipMemcpy2DAsync(p, nx * 8, s.p + c->L.off, P * 8, nx * 8, ny,
+                                 hipMemcpyDeviceToHost, c->stream));
+  if (T) HIPCHK(hipMemcpy2DAsync(T, nx * 8, s.T + c->L.off, P * 8, nx * 8, ny,
+                                 hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return STS_OK;
+}
+
+extern "C" sts_status sts_set_fields(sts_ctx *c, const double *u, const double *v,
+                                     const double *p, const double *T) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  const int nx = c->nx, ny = c->ny;
+  std::vector<double> hu((size_t)(nx + 1) * ny), hv((size_t)nx * (ny + 1)), hp((size_t)nx * ny),
+      hT((size_t)nx * ny);
+  sts_status s = sts_fields(c, hu.data(), hv.data(), hp.data(), hT.data());
+  if (s != STS_OK) return s;
+  if (u) memcpy(hu.data(), u, hu.size() * 8);
+  if (v) memcpy(hv.data(), v, hv.size() * 8);
+  if (p) memcpy(hp.data(), p, hp.size() * 8);
+  if (T) memcpy(hT.data(), T, hT.size() * 8);
+  project(c, hu.data(), hv.data(), hp.data(), hT.data());
+  if ((s = upload(c, 0, hu.data(), hv.data(), hp.data(), hT.data())) != STS_OK) return s;
+  if ((s = upload(c, 1, hu.data(), hv.data(), hp.data(), hT.data())) != STS_OK) return s;
+  c->cur = 0;
+  c->stepped = false;
+  return STS_OK;
+}
+
+extern "C" sts_status sts_field_ptrs(sts_ctx *c, double **u, double **v, double **p,
+                                     double **T, size_t *origin, size_t *pitch) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  const State &s = c->st[c->cur];
+  if (u) *u = s.u;
+  if (v) *v = s.v;
+  if (p) *p = s.p;
+  if (T) *T = s.T;
+  if (origin) *origin = (size_t)c->L.off;
+  if (pitch) *pitch = (size_t)c->L.pitch;
+  return STS_OK;
+}
+
+extern "C" sts_status sts_timing(sts_ctx *c, int enable) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->timing = enable != 0;
+  c->ev_used = 0;
+  c->t_passes = 0;
+  return STS_OK;
+}
+
+extern "C" sts_status sts_read_timing(sts_ctx *c, double out_ms[3], long long out_n[2]) {
+  if (!c || !out_ms || !out_n) return fail(STS_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double t[3] = {0, 0, 0};
+  for (int k = 0; k < c->ev_used; k++) {
+    float a = 0, b = 0, d = 0;
+    HIPCHK(hipEventElapsedTime(&a, c->ev[(size_t)k * 4 + 0], c->ev[(size_t)k * 4 + 1]));
+    HIPCHK(hipEventElapsedTime(&b, c->ev[(size_t)k * 4 + 1], c->ev[(size_t)k * 4 + 2]));
+    HIPCHK(hipEventElapsedTime(&d, c->ev[(size_t)k * 4 + 2], c->ev[(size_t)k * 4 + 3]));
+    t[0] += a;
+    t[1] += b;
+    t[2] += d;
+  }
+  for (int k = 0; k < 3; k++) out_ms[k] = t[k];
+  out_n[0] = c->ev_used;
+  out_n[1] = c->t_passes;
+  c->ev_used = 0;
+  c->t_passes = 0;
+  return STS_OK;
+}

@@ -1,0 +1,61 @@
+// Internal declarations shared by the host runtime and the kernels of
+// libsts.so (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace sts {
+
+// Tiling of the Jacobi pass: a block of BX x BY threads computes T, p,
+// u-hat, v-hat on the owned TX x TY cells plus a one-cell halo, and writes
+// the owned cells / faces.  The LDS window of old fields has a halo of HB.
+constexpr int TX = 30, TY = 6;
+constexpr int BX = TX + 2, BY = TY + 2;
+constexpr int NT = BX * BY;  // 256 threads
+constexpr int HB = 3;
+constexpr int LW = TX + 2 * HB, LH = TY + 2 * HB;
+
+// Device layout of every field array: a frame of ghost columns/rows around
+// the domain so that any window load stays inside the allocation.
+constexpr int XO = 32;  // column of i = 0 (256-byte aligned rows)
+constexpr int YO = 4;   // row of j = 0
+constexpr int XPAD = 4; // ghost entries of the padded 1-D width arrays
+
+struct State {
+  double *u, *v, *p, *T;
+};
+struct Consts {
+  double *Cu, *Cv, *CT, *Cp;
+};
+
+struct Params {
+  int nx, ny, per;
+  int tiles_x, tiles_y;
+  long pitch;  // doubles per row
+  long off;    // element index of (0,0)
+  double dt, A, B, C1, C2, C3, gx, gy, obsT, sq_obsT;
+  int wtype0, wtype1;
+  double wu0, wu1;
+  const double *dxp, *dyp;                 // widths, index + XPAD
+  const double *u_in, *T_in, *sq_T_in, *rho_in;  // [ny]
+  const double *Tw0, *Tw1, *sq_Tw0, *sq_Tw1;     // [nx] per cell column
+  const double *sq_Twu0, *sq_Twu1;               // [nx+1] at u-face x
+  const unsigned char *fl;   // 1 = fluid cell, frame = 0; cell layout
+  const unsigned char *clean; // [tiles] 1 = no boundary rule in the window
+};
+
+// residual partial per block: max|du|, max|dv|, max|dp|, max|dT|, max|R|,
+// sum R, non-finite count
+constexpr int NRES = 8;
+
+void launch_prologue(const Params &P, State m, Consts C, int scheme,
+                     hipStream_t st);
+void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
+                 hipStream_t st);
+void launch_residual(const Params &P, State o, State n, Consts C, int scheme,
+                     double *partials, int nblocks, double *out,
+                     hipStream_t st);
+int residual_blocks(const Params &P);
+
+}  // namespace sts

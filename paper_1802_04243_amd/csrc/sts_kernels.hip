@@ -1,0 +1,978 @@
+// HIP kernels of the SIMPLE-TS time step for gfx950 (MI355X).
+//
+// Method: Shterev, arXiv 1802.04243.  One time step = a step prologue (the
+// per-step constants, including the explicit convective terms of eqs pl15_11
+// and pl31_1) followed by n_inner Jacobi passes of loop 2 (Sec. 3.1).  One
+// pass follows the dependency analysis of Sec. 3.2 (eqs pl29_1-pl29_8):
+// T, u-hat, d^u, v-hat, d^v depend only on old values; p needs u-hat/d at the
+// four faces and the new T of its cell; u and v need the new p on both sides.
+//
+// GPU design (not the paper's row-marching OpenCL kernel): every pass is one
+// kernel over 2-D tiles.  A block stages the old u, v, p, T of its tile plus a
+// 3-cell halo in LDS (rho = p/T and Gamma = sqrt(T) are recomputed there,
+// never stored in HBM), computes face densities, then T, u-hat, v-hat on the
+// owned cells plus a one-cell halo, then p, then u and v, and writes only the
+// owned values.  HBM traffic per pass is the old state, four per-step
+// constant arrays and the new state.  Tiles whose window touches no boundary
+// and no obstacle run a compile-time specialisation with every boundary test
+// removed.  The bodies below are FP64 throughout; there is no dense
+// contraction, so no MFMA.
+#include "sts_internal.h"
+
+namespace sts {
+namespace {
+
+// ---------------------------------------------------------------------------
+// elementary functions (Sec. 3.2)
+// ---------------------------------------------------------------------------
+// van Leer limiter psi(r) = (r+|r|)/(1+|r|) of r = a/b; 0 for r <= 0 and
+// when r is undefined (b == 0), 2 when a/b overflows.
+__device__ __forceinline__ double vanleer(double a, double b) {
+  if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return 0.0;
+  const double r = a / b;
+  if (isinf(r)) return 2.0;
+  return (r + fabs(r)) / (1.0 + fabs(r));
+}
+// max(a, b) as a > b ? a : b (the sign of a zero result is that of b)
+__device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
+// TVD correction at a surface between nodes (eq pl15_2)
+__device__ __forceinline__ double psi_s(double f1, double f2, double f3,
+                                        double f4, double d1, double d2,
+                                        double d3, double d4, double vel) {
+  if (vel > 0.0)
+    return d2 / (d2 + d3) * vanleer((d2 + d3) * (f2 - f1), (d1 + d2) * (f3 - f2));
+  return -d3 / (d2 + d3) * vanleer((d2 + d3) * (f4 - f3), (d3 + d4) * (f3 - f2));
+}
+// TVD correction at a control-volume centre (eq pl15_1)
+__device__ __forceinline__ double psi_c(double f1, double f2, double f3,
+                                        double f4, double d1, double d2,
+                                        double d3, double vel) {
+  if (vel > 0.0) return 0.5 * vanleer(d2 * (f2 - f1), d1 * (f3 - f2));
+  return -0.5 * vanleer(d2 * (f4 - f3), d3 * (f3 - f2));
+}
+__device__ __forceinline__ double upw(double f1, double f2, double vel) {
+  return vel > 0.0 ? f1 : f2;  // eq pl15_12
+}
+// harmonic mean of Gamma between two nodes (eq pl33)
+__device__ __forceinline__ double hmean(double dl, double gl, double dr,
+                                        double gr) {
+  return (dl + dr) * gl * gr / (dl * gr + dr * gl);
+}
+// harmonic mean of a node value and a boundary value over a half cell
+__device__ __forceinline__ double hmean2(double a, double b) {
+  return 2.0 * a * b / (a + b);
+}
+__device__ __forceinline__ int clampi(int v, int lo, int hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+__device__ __forceinline__ int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// ---------------------------------------------------------------------------
+// LDS tile
+// ---------------------------------------------------------------------------
+struct Lds {
+  double u[LH][LW], v[LH][LW], p[LH][LW], T[LH][LW], r[LH][LW], g[LH][LW];
+  double ru[LH][LW], rv[LH][LW];  // face densities rho^u, rho^v
+  double Tn[BY][BX], pn[BY][BX], uh[BY][BX], du[BY][BX], vh[BY][BX],
+      dv[BY][BX];
+  double dx[LW], dy[LH];
+  unsigned char fl[LH][LW];
+};
+
+// tile-relative accessors: (i, j) with the tile origin at (0, 0)
+#define U_(i, j) s.u[(j) + HB][(i) + HB]
+#define V_(i, j) s.v[(j) + HB][(i) + HB]
+#define P_(i, j) s.p[(j) + HB][(i) + HB]
+#define T_(i, j) s.T[(j) + HB][(i) + HB]
+#define R_(i, j) s.r[(j) + HB][(i) + HB]
+#define G_(i, j) s.g[(j) + HB][(i) + HB]
+#define RU_(i, j) s.ru[(j) + HB][(i) + HB]
+#define RV_(i, j) s.rv[(j) + HB][(i) + HB]
+#define FL_(i, j) s.fl[(j) + HB][(i) + HB]
+#define DX_(i) s.dx[(i) + HB]
+#define DY_(j) s.dy[(j) + HB]
+#define TN_(i, j) s.Tn[(j) + 1][(i) + 1]
+#define PN_(i, j) s.pn[(j) + 1][(i) + 1]
+#define UH_(i, j) s.uh[(j) + 1][(i) + 1]
+#define DU_(i, j) s.du[(j) + 1][(i) + 1]
+#define VH_(i, j) s.vh[(j) + 1][(i) + 1]
+#define DV_(i, j) s.dv[(j) + 1][(i) + 1]
+
+// Block index -> tile index.  Consecutive blocks are dealt round-robin to
+// the 8 XCDs; remap so that every XCD works on one contiguous band of tiles
+// (neighbour halos then hit the same L2).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int k = b & 7, m = b >> 3, q = n >> 3, r = n & 7;
+  return k * q + (k < r ? k : r) + m;
+}
+
+// Stage the old fields of the window [x0-3, x0+TX+2] x [y0-3, y0+TY+2].
+__device__ void load_window(Lds &s, const Params &P, const State o, int x0,
+                            int y0) {
+  for (int k = threadIdx.x; k < LH * LW; k += NT) {
+    const int a = k % LW, b = k / LW;
+    const int gi = x0 - HB + a, gj = y0 - HB + b;
+    const int ci = P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD - 1);
+    const int ui = P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD);
+    const int cj = clampi(gj, -XPAD, P.ny + XPAD - 1);
+    const int vj = clampi(gj, -XPAD, P.ny + XPAD);
+    const long kc = P.off + (long)cj * P.pitch + ci;
+    const double pp = o.p[kc], tt = o.T[kc];
+    s.p[b][a] = pp;
+    s.T[b][a] = tt;
+    s.r[b][a] = pp / tt;
+    s.g[b][a] = sqrt(tt);
+    s.fl[b][a] = P.fl[kc];
+    s.u[b][a] = o.u[P.off + (long)cj * P.pitch + ui];
+    s.v[b][a] = o.v[P.off + (long)vj * P.pitch + ci];
+  }
+  for (int k = threadIdx.x; k < LW + LH; k += NT) {
+    if (k < LW) {
+      const int gi = x0 - HB + k;
+      const int ci = P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD - 1);
+      s.dx[k] = P.dxp[ci + XPAD];
+    } else {
+      const int gj = y0 - HB + (k - LW);
+      s.dy[k - LW] = P.dyp[clampi(gj, -XPAD, P.ny + XPAD - 1) + XPAD];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// face densities (eqs pl10, pl11 read as upwind value + psi * jump)
+// ---------------------------------------------------------------------------
+template <bool CL, bool TV>
+__device__ double rho_xface(const Lds &s, const Params &P, int i, int j,
+                            int gi, int gj) {
+  const double uf = U_(i, j);
+  if (!CL && !P.per) {
+    if (gi == 0) return uf > 0.0 ? P.rho_in[clampi(gj, 0, P.ny - 1)] : R_(i, j);
+    if (gi == P.nx) return R_(i - 1, j);
+  }
+  const double rl = R_(i - 1, j), rr = R_(i, j);
+  double r = upw(rl, rr, uf);
+  if (TV && (CL || (FL_(i - 2, j) & FL_(i - 1, j) & FL_(i, j) & FL_(i + 1, j))))
+    r += psi_s(R_(i - 2, j), rl, rr, R_(i + 1, j), DX_(i - 2), DX_(i - 1),
+               DX_(i), DX_(i + 1), uf) *
+         (rr - rl);
+  return r;
+}
+template <bool CL, bool TV>
+__device__ double rho_yface(const Lds &s, const Params &P, int i, int j,
+                            int gj) {
+  if (!CL) {
+    if (gj == 0) return R_(i, j);
+    if (gj == P.ny) return R_(i, j - 1);
+  }
+  const double vf = V_(i, j);
+  const double rs = R_(i, j - 1), rn = R_(i, j);
+  double r = upw(rs, rn, vf);
+  if (TV && (CL || (FL_(i, j - 2) & FL_(i, j - 1) & FL_(i, j) & FL_(i, j + 1))))
+    r += psi_s(R_(i, j - 2), rs, rn, R_(i, j + 1), DY_(j - 2), DY_(j - 1),
+               DY_(j), DY_(j + 1), vf) *
+         (rn - rs);
+  return r;
+}
+
+// Gamma at the corner (x^f_gi, y^f_gj): bilinear in the four cells; inlet
+// corners interpolate sqrt(T_in) in y, outlet corners use the last column,
+// corners on the channel walls are never used with a non-zero factor (0).
+template <bool CL>
+__device__ double gam_c(const Lds &s, const Params &P, int i, int j, int gi,
+                        int gj) {
+  if (!CL && (gj <= 0 || gj >= P.ny)) return 0.0;
+  const double dys = DY_(j - 1), dyn = DY_(j);
+  const double ws = dyn / (dys + dyn), wn = dys / (dys + dyn);
+  if (!CL && !P.per) {
+    if (gi == 0) return ws * P.sq_T_in[gj - 1] + wn * P.sq_T_in[gj];
+    if (gi == P.nx) return ws * G_(i - 1, j - 1) + wn * G_(i - 1, j);
+  }
+  const double dl = DX_(i - 1), dr = DX_(i);
+  const double wl = dr / (dl + dr), wr = dl / (dl + dr);
+  return ws * (wl * G_(i - 1, j - 1) + wr * G_(i, j - 1)) +
+         wn * (wl * G_(i - 1, j) + wr * G_(i, j));
+}
+
+// ---------------------------------------------------------------------------
+// energy equation (eqs pl30-pl33, pl28, pl29) for a fluid cell
+// ---------------------------------------------------------------------------
+template <bool CL, bool IM, bool TV>
+__device__ double t_update(const Lds &s, const Params &P, int i, int j,
+                           int gi, int gj, double CT) {
+  const double dxi = DX_(i), dyj = DY_(j), dV = dxi * dyj;
+  const double gP = G_(i, j), TP = T_(i, j);
+  double nW, nE, nS, nN, DW, DE, DS, DN;
+  if (!CL && !P.per && gi == 0) {  // inlet: T_in on the face
+    nW = P.T_in[gj];
+    DW = P.C1 * hmean2(gP, P.sq_T_in[gj]) * dyj / (0.5 * dxi);
+  } else {
+    nW = T_(i - 1, j);
+    if (!CL && !FL_(i - 1, j))
+      DW = P.C1 * hmean2(gP, P.sq_obsT) * dyj / (0.5 * dxi);
+    else {
+      const double dl = DX_(i - 1);
+      DW = P.C1 * hmean(dl, G_(i - 1, j), dxi, gP) * dyj / (0.5 * (dxi + dl));
+    }
+  }
+  if (!CL && !P.per && gi == P.nx - 1) {  // outlet: zero gradient
+    nE = TP;
+    DE = 0.0;
+  } else {
+    nE = T_(i + 1, j);
+    if (!CL && !FL_(i + 1, j))
+      DE = P.C1 * hmean2(gP, P.sq_obsT) * dyj / (0.5 * dxi);
+    else {
+      const double dr = DX_(i + 1);
+      DE = P.C1 * hmean(dxi, gP, dr, G_(i + 1, j)) * dyj / (0.5 * (dxi + dr));
+    }
+  }
+  if (!CL && gj == 0) {
+    if (P.wtype0 == 0) {
+      nS = P.Tw0[gi];
+      DS = P.C1 * hmean2(gP, P.sq_Tw0[gi]) * dxi / (0.5 * dyj);
+    } else {
+      nS = TP;
+      DS = 0.0;
+    }
+  } else {
+    nS = T_(i, j - 1);
+    if (!CL && !FL_(i, j - 1))
+      DS = P.C1 * hmean2(gP, P.sq_obsT) * dxi / (0.5 * dyj);
+    else {
+      const double ds = DY_(j - 1);
+      DS = P.C1 * hmean(ds, G_(i, j - 1), dyj, gP) * dxi / (0.5 * (dyj + ds));
+    }
+  }
+  if (!CL && gj == P.ny - 1) {
+    if (P.wtype1 == 0) {
+      nN = P.Tw1[gi];
+      DN = P.C1 * hmean2(gP, P.sq_Tw1[gi]) * dxi / (0.5 * dyj);
+    } else {
+      nN = TP;
+      DN = 0.0;
+    }
+  } else {
+    nN = T_(i, j + 1);
+    if (!CL && !FL_(i, j + 1))
+      DN = P.C1 * hmean2(gP, P.sq_obsT) * dxi / (0.5 * dyj);
+    else {
+      const double dn = DY_(j + 1);
+      DN = P.C1 * hmean(dyj, gP, dn, G_(i, j + 1)) * dxi / (0.5 * (dyj + dn));
+    }
+  }
+  double aW, aE, aS, aN, a0;
+  if (IM) {
+    const double uW = U_(i, j), uE = U_(i + 1, j), vS = V_(i, j), vN = V_(i, j + 1);
+    const double FW = RU_(i, j) * uW * dyj, FE = RU_(i + 1, j) * uE * dyj;
+    const double FS = RV_(i, j) * vS * dxi, FN = RV_(i, j + 1) * vN * dxi;
+    double pW = 0.0, pE = 0.0, pS = 0.0, pN = 0.0;
+    if (TV) {
+      if (CL || (FL_(i - 2, j) & FL_(i - 1, j) & FL_(i + 1, j)))
+        pW = psi_s(T_(i - 2, j), T_(i - 1, j), TP, T_(i + 1, j), DX_(i - 2),
+                   DX_(i - 1), dxi, DX_(i + 1), uW);
+      if (CL || (FL_(i - 1, j) & FL_(i + 1, j) & FL_(i + 2, j)))
+        pE = psi_s(T_(i - 1, j), TP, T_(i + 1, j), T_(i + 2, j), DX_(i - 1),
+                   dxi, DX_(i + 1), DX_(i + 2), uE);
+      if (CL || (FL_(i, j - 2) & FL_(i, j - 1) & FL_(i, j + 1)))
+        pS = psi_s(T_(i, j - 2), T_(i, j - 1), TP, T_(i, j + 1), DY_(j - 2),
+                   DY_(j - 1), dyj, DY_(j + 1), vS);
+      if (CL || (FL_(i, j - 1) & FL_(i, j + 1) & FL_(i, j + 2)))
+        pN = psi_s(T_(i, j - 1), TP, T_(i, j + 1), T_(i, j + 2), DY_(j - 1),
+                   dyj, DY_(j + 1), DY_(j + 2), vN);
+    }
+    aW = dmax(0.0, FW) - FW * pW + DW;
+    aE = dmax(0.0, -FE) - FE * pE + DE;
+    aS = dmax(0.0, FS) - FS * pS + DS;
+    aN = dmax(0.0, -FN) - FN * pN + DN;
+    a0 = P.dt * ((aW + aE + aS + aN) + ((FE - FW) + (FN - FS))) + R_(i, j) * dV;
+  } else {
+    aW = DW;
+    aE = DE;
+    aS = DS;
+    aN = DN;
+    a0 = P.dt * (aW + aE + aS + aN) + R_(i, j) * dV;
+  }
+  // source: viscous dissipation and pressure work (eq pl29); face-centre
+  // velocities bilinear in the nearest nodes, wall / inlet / outlet values
+  const double vc = 0.5 * (V_(i, j) + V_(i, j + 1));
+  const double uc = 0.5 * (U_(i, j) + U_(i + 1, j));
+  double vE, vW, uN, uS;
+  if (!CL && !P.per && gi == P.nx - 1) vE = vc;
+  else if (!CL && !FL_(i + 1, j)) vE = 0.0;
+  else {
+    const double dr = DX_(i + 1);
+    vE = dr / (dxi + dr) * vc +
+         dxi / (dxi + dr) * (0.5 * (V_(i + 1, j) + V_(i + 1, j + 1)));
+  }
+  if (!CL && !P.per && gi == 0) vW = 0.0;
+  else if (!CL && !FL_(i - 1, j)) vW = 0.0;
+  else {
+    const double dl = DX_(i - 1);
+    vW = dxi / (dl + dxi) * (0.5 * (V_(i - 1, j) + V_(i - 1, j + 1))) +
+         dl / (dl + dxi) * vc;
+  }
+  if (!CL && gj == P.ny - 1) uN = (P.wtype1 == 0) ? P.wu1 : uc;
+  else if (!CL && !FL_(i, j + 1)) uN = 0.0;
+  else {
+    const double dn = DY_(j + 1);
+    uN = dn / (dyj + dn) * uc +
+         dyj / (dyj + dn) * (0.5 * (U_(i, j + 1) + U_(i + 1, j + 1)));
+  }
+  if (!CL && gj == 0) uS = (P.wtype0 == 0) ? P.wu0 : uc;
+  else if (!CL && !FL_(i, j - 1)) uS = 0.0;
+  else {
+    const double ds = DY_(j - 1);
+    uS = dyj / (ds + dyj) * (0.5 * (U_(i, j - 1) + U_(i + 1, j - 1))) +
+         ds / (ds + dyj) * uc;
+  }
+  const double ux = (U_(i + 1, j) - U_(i, j)) / dxi;
+  const double vy = (V_(i, j + 1) - V_(i, j)) / dyj;
+  const double vx = (vE - vW) / dxi, uy = (uN - uS) / dyj;
+  const double dv = ux + vy;
+  const double Sc =
+      P.C2 * gP * (2.0 * (ux * ux + vy * vy) + (vx + uy) * (vx + uy) -
+                   2.0 / 3.0 * dv * dv) *
+          dV +
+      P.C3 * P_(i, j) * dv * dV;
+  return (P.dt * (aW * nW + aE * nE + aS * nS + aN * nN + Sc) + CT) / a0;
+}
+
+// ---------------------------------------------------------------------------
+// u-momentum (x<->y mirror of the printed v-equation) for a solved u-face
+// ---------------------------------------------------------------------------
+template <bool CL, bool IM, bool TV>
+__device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
+                         int gj, double Cu, double &uh, double &du) {
+  const double dxl = DX_(i - 1), dxr = DX_(i), dyj = DY_(j);
+  const double rl = R_(i - 1, j), rr = R_(i, j), gl = G_(i - 1, j), gr = G_(i, j);
+  const double uP = U_(i, j), uW = U_(i - 1, j), uE = U_(i + 1, j);
+  const double M = (rr * dxr + rl * dxl) * dyj / 2.0;
+  const double len = 0.5 * (dxl + dxr);
+  const double gnode = (dxr * gl + dxl * gr) / (dxl + dxr);
+  double uS, uN, DS, DN;
+  if (!CL && gj == 0) {
+    if (P.wtype0 == 0) {
+      uS = P.wu0;
+      DS = P.B * 0.5 * (gnode + P.sq_Twu0[gi]) * len / (0.5 * dyj);
+    } else {
+      uS = uP;
+      DS = 0.0;
+    }
+  } else {
+    uS = U_(i, j - 1);
+    if (!CL && !FL_(i - 1, j - 1) && !FL_(i, j - 1))
+      DS = P.B * 0.5 * (gnode + P.sq_obsT) * len / (0.5 * dyj);
+    else
+      DS = P.B * gam_c<CL>(s, P, i, j, gi, gj) * (dxr + dxl) / (dyj + DY_(j - 1));
+  }
+  if (!CL && gj == P.ny - 1) {
+    if (P.wtype1 == 0) {
+      uN = P.wu1;
+      DN = P.B * 0.5 * (gnode + P.sq_Twu1[gi]) * len / (0.5 * dyj);
+    } else {
+      uN = uP;
+      DN = 0.0;
+    }
+  } else {
+    uN = U_(i, j + 1);
+    if (!CL && !FL_(i - 1, j + 1) && !FL_(i, j + 1))
+      DN = P.B * 0.5 * (gnode + P.sq_obsT) * len / (0.5 * dyj);
+    else
+      DN = P.B * gam_c<CL>(s, P, i, j + 1, gi, gj + 1) * (dxr + dxl) /
+           (dyj + DY_(j + 1));
+  }
+  const double DW = P.B * gl * dyj / dxl, DE = P.B * gr * dyj / dxr;
+  double aS, aN, aW, aE, conv;
+  if (IM) {
+    const double Fs0 = RV_(i, j) * V_(i, j) * dxr, Fs1 = RV_(i - 1, j) * V_(i - 1, j) * dxl;
+    const double Fn0 = RV_(i, j + 1) * V_(i, j + 1) * dxr,
+                 Fn1 = RV_(i - 1, j + 1) * V_(i - 1, j + 1) * dxl;
+    const double ubW = 0.5 * (uW + uP), ubE = 0.5 * (uP + uE);
+    const double FbW = rl * ubW * dyj, FbE = rr * ubE * dyj;
+    double ps0 = 0.0, ps1 = 0.0, pn0 = 0.0, pn1 = 0.0, pw = 0.0, pe = 0.0;
+    if (TV) {
+      if (CL || (gj - 2 >= 0 && gj + 1 <= P.ny - 1)) {
+        const double f1 = U_(i, j - 2), f2 = U_(i, j - 1), f4 = U_(i, j + 1);
+        ps0 = psi_s(f1, f2, uP, f4, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), V_(i, j));
+        ps1 = psi_s(f1, f2, uP, f4, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), V_(i - 1, j));
+      }
+      if (CL || (gj - 1 >= 0 && gj + 2 <= P.ny - 1)) {
+        const double f1 = U_(i, j - 1), f3 = U_(i, j + 1), f4 = U_(i, j + 2);
+        pn0 = psi_s(f1, uP, f3, f4, DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), V_(i, j + 1));
+        pn1 = psi_s(f1, uP, f3, f4, DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), V_(i - 1, j + 1));
+      }
+      if (CL || P.per || (gi - 2 >= 0 && gi + 1 <= P.nx))
+        pw = psi_c(U_(i - 2, j), uW, uP, uE, DX_(i - 2), dxl, dxr, ubW);
+      if (CL || P.per || (gi - 1 >= 0 && gi + 2 <= P.nx))
+        pe = psi_c(uW, uP, uE, U_(i + 2, j), dxl, dxr, DX_(i + 1), ubE);
+    }
+    aS = 0.5 * (dmax(0.0, Fs0) - Fs0 * ps0 + dmax(0.0, Fs1) - Fs1 * ps1) + DS;
+    aN = 0.5 * (dmax(0.0, -Fn0) - Fn0 * pn0 + dmax(0.0, -Fn1) - Fn1 * pn1) + DN;
+    aW = dmax(0.0, FbW) - FbW * pw + 4.0 / 3.0 * DW;
+    aE = dmax(0.0, -FbE) - FbE * pe + 4.0 / 3.0 * DE;
+    conv = 0.5 * (Fn0 - Fs0 + Fn1 - Fs1) + FbE - FbW;
+  } else {
+    aS = DS;
+    aN = DN;
+    aW = 4.0 / 3.0 * DW;
+    aE = 4.0 / 3.0 * DE;
+    conv = 0.0;
+  }
+  const double a0 = aS + aN + aW + aE + conv + M / P.dt;
+  const double X = gam_c<CL>(s, P, i, j + 1, gi, gj + 1) * (V_(i, j + 1) - V_(i - 1, j + 1)) -
+                   gam_c<CL>(s, P, i, j, gi, gj) * (V_(i, j) - V_(i - 1, j)) -
+                   2.0 / 3.0 * gr * (V_(i, j + 1) - V_(i, j)) +
+                   2.0 / 3.0 * gl * (V_(i - 1, j + 1) - V_(i - 1, j));
+  const double b = Cu + P.B * X;
+  uh = (aS * uS + aN * uN + aW * uW + aE * uE + b) / a0;
+  du = P.A * dyj / a0;
+}
+
+// ---------------------------------------------------------------------------
+// v-momentum (eqs pl14-pl16, pl15, pl21) for a solved v-face
+// ---------------------------------------------------------------------------
+template <bool CL, bool IM, bool TV>
+__device__ void v_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
+                         int gj, double Cv, double &vh, double &dv) {
+  const double dxi = DX_(i), dys = DY_(j - 1), dyn = DY_(j);
+  const double rs = R_(i, j - 1), rn = R_(i, j), gs = G_(i, j - 1), gn = G_(i, j);
+  const double vP = V_(i, j), vS = V_(i, j - 1), vN = V_(i, j + 1);
+  const double vW = (!CL && !P.per && gi == 0) ? 0.0 : V_(i - 1, j);
+  const double vE = (!CL && !P.per && gi == P.nx - 1) ? vP : V_(i + 1, j);
+  const double M = (rn * dyn + rs * dys) * dxi / 2.0;
+  const double len = 0.5 * (dys + dyn);
+  const double gnode = (dyn * gs + dys * gn) / (dys + dyn);
+  double DW, DE;
+  if (!CL && !P.per && gi == 0)
+    DW = P.B * 0.5 * (gnode + gam_c<CL>(s, P, i, j, gi, gj)) * len / (0.5 * dxi);
+  else if (!CL && !FL_(i - 1, j - 1) && !FL_(i - 1, j))
+    DW = P.B * 0.5 * (gnode + P.sq_obsT) * len / (0.5 * dxi);
+  else
+    DW = P.B * gam_c<CL>(s, P, i, j, gi, gj) * (dyn + dys) / (dxi + DX_(i - 1));
+  if (!CL && !P.per && gi == P.nx - 1)
+    DE = 0.0;
+  else if (!CL && !FL_(i + 1, j - 1) && !FL_(i + 1, j))
+    DE = P.B * 0.5 * (gnode + P.sq_obsT) * len / (0.5 * dxi);
+  else
+    DE = P.B * gam_c<CL>(s, P, i + 1, j, gi + 1, gj) * (dyn + dys) / (dxi + DX_(i + 1));
+  const double DS = P.B * gs * dxi / dys, DN = P.B * gn * dxi / dyn;
+  double aW, aE, aS, aN, conv;
+  if (IM) {
+    const double Fw0 = RU_(i, j) * U_(i, j) * dyn, Fw1 = RU_(i, j - 1) * U_(i, j - 1) * dys;
+    const double Fe0 = RU_(i + 1, j) * U_(i + 1, j) * dyn,
+                 Fe1 = RU_(i + 1, j - 1) * U_(i + 1, j - 1) * dys;
+    const double vbS = 0.5 * (vS + vP), vbN = 0.5 * (vP + vN);
+    const double FbS = rs * vbS * dxi, FbN = rn * vbN * dxi;
+    double pw0 = 0.0, pw1 = 0.0, pe0 = 0.0, pe1 = 0.0, ps = 0.0, pn = 0.0;
+    if (TV) {
+      if (CL || P.per || (gi - 2 >= 0 && gi + 1 <= P.nx - 1)) {
+        const double f1 = V_(i - 2, j), f4 = V_(i + 1, j);
+        pw0 = psi_s(f1, vW, vP, f4, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), U_(i, j));
+        pw1 = psi_s(f1, vW, vP, f4, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), U_(i, j - 1));
+      }
+      if (CL || P.per || (gi - 1 >= 0 && gi + 2 <= P.nx - 1)) {
+        const double f1 = V_(i - 1, j), f4 = V_(i + 2, j);
+        pe0 = psi_s(f1, vP, vE, f4, DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), U_(i + 1, j));
+        pe1 = psi_s(f1, vP, vE, f4, DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), U_(i + 1, j - 1));
+      }
+      if (CL || (gj - 2 >= 0 && gj + 1 <= P.ny))
+        ps = psi_c(V_(i, j - 2), vS, vP, vN, DY_(j - 2), dys, dyn, vbS);
+      if (CL || (gj - 1 >= 0 && gj + 2 <= P.ny))
+        pn = psi_c(vS, vP, vN, V_(i, j + 2), dys, dyn, DY_(j + 1), vbN);
+    }
+    aW = 0.5 * (dmax(0.0, Fw0) - Fw0 * pw0 + dmax(0.0, Fw1) - Fw1 * pw1) + DW;
+    aE = 0.5 * (dmax(0.0, -Fe0) - Fe0 * pe0 + dmax(0.0, -Fe1) - Fe1 * pe1) + DE;
+    aS = dmax(0.0, FbS) - FbS * ps + 4.0 / 3.0 * DS;
+    aN = dmax(0.0, -FbN) - FbN * pn + 4.0 / 3.0 * DN;
+    conv = 0.5 * (Fe0 - Fw0 + Fe1 - Fw1) + FbN - FbS;
+  } else {
+    aW = DW;
+    aE = DE;
+    aS = 4.0 / 3.0 * DS;
+    aN = 4.0 / 3.0 * DN;
+    conv = 0.0;
+  }
+  const double a0 = aW + aE + aS + aN + conv + M / P.dt;
+  const double X = gam_c<CL>(s, P, i + 1, j, gi + 1, gj) * (U_(i + 1, j) - U_(i + 1, j - 1)) -
+                   gam_c<CL>(s, P, i, j, gi, gj) * (U_(i, j) - U_(i, j - 1)) -
+                   2.0 / 3.0 * gn * (U_(i + 1, j) - U_(i, j)) +
+                   2.0 / 3.0 * gs * (U_(i + 1, j - 1) - U_(i, j - 1));
+  const double b = Cv + P.B * X;
+  vh = (aW * vW + aE * vE + aS * vS + aN * vN + b) / a0;
+  dv = P.A * dxi / a0;
+}
+
+// unknown tests (the same rules as the boundary-value projection)
+__device__ __forceinline__ bool u_solved(const Lds &s, const Params &P, int i,
+                                         int j, int gi) {
+  return (P.per || (gi >= 1 && gi <= P.nx - 1)) && FL_(i - 1, j) && FL_(i, j);
+}
+__device__ __forceinline__ bool v_solved(const Lds &s, const Params &P, int i,
+                                         int j, int gj) {
+  return gj >= 1 && gj <= P.ny - 1 && FL_(i, j - 1) && FL_(i, j);
+}
+
+// ---------------------------------------------------------------------------
+// one Jacobi pass of loop 2
+// ---------------------------------------------------------------------------
+template <bool CL, bool IM, bool TV>
+__device__ void pass_body(Lds &s, const Params &P, const State o,
+                          const State n, const Consts C, int x0, int y0) {
+  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  const int i = tx - 1, j = ty - 1;  // (i, j) in [-1, TX] x [-1, TY]
+  const int gi = x0 + i, gj = y0 + j;
+
+  // stage 1: face densities rho^u on [-1,TX] x [-2,TY], rho^v on
+  // [-2,TX] x [-1,TY]
+  for (int k = threadIdx.x; k < BX * (BY + 1); k += NT) {
+    const int fi = k % BX - 1, fj = k / BX - 2;
+    RU_(fi, fj) = rho_xface<CL, TV>(s, P, fi, fj, x0 + fi, y0 + fj);
+  }
+  for (int k = threadIdx.x; k < (BX + 1) * BY; k += NT) {
+    const int fi = k % (BX + 1) - 2, fj = k / (BX + 1) - 1;
+    RV_(fi, fj) = rho_yface<CL, TV>(s, P, fi, fj, y0 + fj);
+  }
+  __syncthreads();
+
+  // stage 2: T on [-1,TX-1] x [-1,TY-1]; u-hat, d^u on [-1,TX] x [-1,TY-1];
+  // v-hat, d^v on [-1,TX-1] x [-1,TY]
+  const long kc = P.off + (long)clampi(gj, -XPAD, P.ny + XPAD - 1) * P.pitch +
+                  (P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD));
+  if (i <= TX - 1 && j <= TY - 1) {
+    double t = T_(i, j);
+    if (FL_(i, j)) t = t_update<CL, IM, TV>(s, P, i, j, gi, gj, C.CT[kc]);
+    TN_(i, j) = t;
+  }
+  if (j <= TY - 1) {
+    double uh = U_(i, j), du = 0.0;
+    if (u_solved(s, P, i, j, gi))
+      u_pseudo<CL, IM, TV>(s, P, i, j, gi, gj, C.Cu[kc], uh, du);
+    UH_(i, j) = uh;
+    DU_(i, j) = du;
+  }
+  if (i <= TX - 1) {
+    double vh = V_(i, j), dv = 0.0;
+    if (v_solved(s, P, i, j, gj))
+      v_pseudo<CL, IM, TV>(s, P, i, j, gi, gj, C.Cv[kc], vh, dv);
+    VH_(i, j) = vh;
+    DV_(i, j) = dv;
+  }
+  __syncthreads();
+
+  // stage 3: pressure (eqs pl23, pl24) on [-1,TX-1] x [-1,TY-1]
+  if (i <= TX - 1 && j <= TY - 1) {
+    double pnew = P_(i, j);
+    if (FL_(i, j)) {
+      const double dxi = DX_(i), dyj = DY_(j), dV = dxi * dyj;
+      const double aW = RU_(i, j) * DU_(i, j) * dyj, aE = RU_(i + 1, j) * DU_(i + 1, j) * dyj;
+      const double aS = RV_(i, j) * DV_(i, j) * dxi, aN = RV_(i, j + 1) * DV_(i, j + 1) * dxi;
+      const double bW = RU_(i, j) * UH_(i, j) * dyj, bE = RU_(i + 1, j) * UH_(i + 1, j) * dyj;
+      const double bS = RV_(i, j) * VH_(i, j) * dxi, bN = RV_(i, j + 1) * VH_(i, j + 1) * dxi;
+      const double a0 = dV / TN_(i, j) + (aW + aE + aS + aN) * P.dt;
+      const double bp = C.Cp[kc] - (bE - bW + bN - bS) * P.dt;
+      pnew = ((aW * P_(i - 1, j) + aE * P_(i + 1, j) + aS * P_(i, j - 1) +
+               aN * P_(i, j + 1)) * P.dt + bp) / a0;
+    }
+    PN_(i, j) = pnew;
+  }
+  __syncthreads();
+
+  // stage 4: velocities (eqs pl18, pl19); write the owned values
+  if (i >= 0 && i < TX && j >= 0 && j < TY && gi < P.nx && gj < P.ny) {
+    const long k = P.off + (long)gj * P.pitch + gi;
+    n.T[k] = TN_(i, j);
+    n.p[k] = PN_(i, j);
+    const double un = u_solved(s, P, i, j, gi)
+                          ? UH_(i, j) - DU_(i, j) * (PN_(i, j) - PN_(i - 1, j))
+                          : U_(i, j);
+    n.u[k] = un;
+    if ((!P.per && gi == P.nx - 1) || (P.per && gi == 0))
+      n.u[P.off + (long)gj * P.pitch + P.nx] = un;  // outlet / periodic copy
+    const double vn = v_solved(s, P, i, j, gj)
+                          ? VH_(i, j) - DV_(i, j) * (PN_(i, j) - PN_(i, j - 1))
+                          : V_(i, j);
+    n.v[k] = vn;
+  }
+}
+
+template <bool IM, bool TV>
+__global__ __launch_bounds__(NT) void k_pass(const Params P, const State o,
+                                             const State n, const Consts C) {
+  __shared__ Lds s;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
+  load_window(s, P, o, x0, y0);
+  __syncthreads();
+  if (P.clean[tile])
+    pass_body<true, IM, TV>(s, P, o, n, C, x0, y0);
+  else
+    pass_body<false, IM, TV>(s, P, o, n, C, x0, y0);
+}
+
+// ---------------------------------------------------------------------------
+// step prologue: per-step constants from the previous time level
+//   C_u = M^{n-1}_u / dt * u^{n-1} + g_x M^{n-1}_u + u^explicit
+//   C_v = M^{n-1}_v / dt * v^{n-1} + g_y M^{n-1}_v + v^explicit
+//   C_T = rho^{n-1} T^{n-1} dV + dt T^explicit,   C_p = rho^{n-1} dV
+// (first lines of eqs pl14, pl30, pl24; explicit terms eqs pl15_11, pl31_1
+// with fluxes and face densities of the n-1 fields; zero if implicit)
+// ---------------------------------------------------------------------------
+template <bool CL, bool TV>
+__device__ double t_explicit(const Lds &s, const Params &P, int i, int j,
+                             int gi, int gj) {
+  const double TP = T_(i, j);
+  const double TW = (!CL && !P.per && gi == 0) ? P.T_in[gj] : T_(i - 1, j);
+  const double TE = (!CL && !P.per && gi == P.nx - 1) ? TP : T_(i + 1, j);
+  const double TS = (!CL && gj == 0) ? TP : T_(i, j - 1);
+  const double TN = (!CL && gj == P.ny - 1) ? TP : T_(i, j + 1);
+  const double dxi = DX_(i), dyj = DY_(j);
+  const double uW = U_(i, j), uE = U_(i + 1, j), vS = V_(i, j), vN = V_(i, j + 1);
+  const double FW = RU_(i, j) * uW * dyj, FE = RU_(i + 1, j) * uE * dyj;
+  const double FS = RV_(i, j) * vS * dxi, FN = RV_(i, j + 1) * vN * dxi;
+  double pW = 0.0, pE = 0.0, pS = 0.0, pN = 0.0;
+  if (TV) {
+    if (CL || (FL_(i - 1, j) & FL_(i + 1, j) & FL_(i + 2, j)))
+      pE = psi_s(T_(i - 1, j), TP, TE, T_(i + 2, j), DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), uE);
+    if (CL || (FL_(i - 2, j) & FL_(i - 1, j) & FL_(i + 1, j)))
+      pW = psi_s(T_(i - 2, j), TW, TP, TE, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), uW);
+    if (CL || (FL_(i, j - 1) & FL_(i, j + 1) & FL_(i, j + 2)))
+      pN = psi_s(T_(i, j - 1), TP, TN, T_(i, j + 2), DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), vN);
+    if (CL || (FL_(i, j - 2) & FL_(i, j - 1) & FL_(i, j + 1)))
+      pS = psi_s(T_(i, j - 2), TS, TP, TN, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), vS);
+  }
+  return -FE * (upw(TP, TE, uE) + (TE - TP) * pE) +
+         FW * (upw(TW, TP, uW) + (TP - TW) * pW) -
+         FN * (upw(TP, TN, vN) + (TN - TP) * pN) +
+         FS * (upw(TS, TP, vS) + (TP - TS) * pS);
+}
+
+template <bool CL, bool TV>
+__device__ double u_explicit(const Lds &s, const Params &P, int i, int j,
+                             int gi, int gj) {
+  const double uP = U_(i, j), uW = U_(i - 1, j), uE = U_(i + 1, j);
+  const double uS = (!CL && gj == 0) ? uP : U_(i, j - 1);
+  const double uN = (!CL && gj == P.ny - 1) ? uP : U_(i, j + 1);
+  const double dxl = DX_(i - 1), dxr = DX_(i), dyj = DY_(j);
+  const double Fn0 = RV_(i - 1, j + 1) * V_(i - 1, j + 1) * dxl, Fn1 = RV_(i, j + 1) * V_(i, j + 1) * dxr;
+  const double Fs0 = RV_(i - 1, j) * V_(i - 1, j) * dxl, Fs1 = RV_(i, j) * V_(i, j) * dxr;
+  const double vn0 = V_(i - 1, j + 1), vn1 = V_(i, j + 1), vs0 = V_(i - 1, j), vs1 = V_(i, j);
+  const double ubE = 0.5 * (uP + uE), ubW = 0.5 * (uW + uP);
+  double pn0 = 0.0, pn1 = 0.0, ps0 = 0.0, ps1 = 0.0, pe = 0.0, pw = 0.0;
+  if (TV) {
+    if (CL || (gj - 1 >= 0 && gj + 2 <= P.ny - 1)) {
+      const double f1 = U_(i, j - 1), f4 = U_(i, j + 2);
+      pn0 = psi_s(f1, uP, uN, f4, DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), vn0);
+      pn1 = psi_s(f1, uP, uN, f4, DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), vn1);
+    }
+    if (CL || (gj - 2 >= 0 && gj + 1 <= P.ny - 1)) {
+      const double f1 = U_(i, j - 2), f4 = U_(i, j + 1);
+      ps0 = psi_s(f1, uS, uP, f4, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), vs0);
+      ps1 = psi_s(f1, uS, uP, f4, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), vs1);
+    }
+    if (CL || P.per || (gi - 1 >= 0 && gi + 2 <= P.nx))
+      pe = psi_c(uW, uP, uE, U_(i + 2, j), dxl, dxr, DX_(i + 1), ubE);
+    if (CL || P.per || (gi - 2 >= 0 && gi + 1 <= P.nx))
+      pw = psi_c(U_(i - 2, j), uW, uP, uE, DX_(i - 2), dxl, dxr, ubW);
+  }
+  const double FbE = R_(i, j) * ubE * dyj, FbW = R_(i - 1, j) * ubW * dyj;
+  return -0.5 * (Fn0 * (upw(uP, uN, vn0) + (uN - uP) * pn0) +
+                 Fn1 * (upw(uP, uN, vn1) + (uN - uP) * pn1)) +
+         0.5 * (Fs0 * (upw(uS, uP, vs0) + (uP - uS) * ps0) +
+                Fs1 * (upw(uS, uP, vs1) + (uP - uS) * ps1)) -
+         FbE * (upw(uP, uE, ubE) + (uE - uP) * pe) +
+         FbW * (upw(uW, uP, ubW) + (uP - uW) * pw);
+}
+
+template <bool CL, bool TV>
+__device__ double v_explicit(const Lds &s, const Params &P, int i, int j,
+                             int gi, int gj) {
+  const double vP = V_(i, j);
+  const double vW = (!CL && !P.per && gi == 0) ? 0.0 : V_(i - 1, j);
+  const double vE = (!CL && !P.per && gi == P.nx - 1) ? vP : V_(i + 1, j);
+  const double vS = V_(i, j - 1), vN = V_(i, j + 1);
+  const double dxi = DX_(i), dys = DY_(j - 1), dyn = DY_(j);
+  const double Fe0 = RU_(i + 1, j - 1) * U_(i + 1, j - 1) * dys, Fe1 = RU_(i + 1, j) * U_(i + 1, j) * dyn;
+  const double Fw0 = RU_(i, j - 1) * U_(i, j - 1) * dys, Fw1 = RU_(i, j) * U_(i, j) * dyn;
+  const double ue0 = U_(i + 1, j - 1), ue1 = U_(i + 1, j), uw0 = U_(i, j - 1), uw1 = U_(i, j);
+  const double vbN = 0.5 * (vP + vN), vbS = 0.5 * (vS + vP);
+  double pe0 = 0.0, pe1 = 0.0, pw0 = 0.0, pw1 = 0.0, pn = 0.0, ps = 0.0;
+  if (TV) {
+    if (CL || P.per || (gi - 1 >= 0 && gi + 2 <= P.nx - 1)) {
+      const double f1 = V_(i - 1, j), f4 = V_(i + 2, j);
+      pe0 = psi_s(f1, vP, vE, f4, DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), ue0);
+      pe1 = psi_s(f1, vP, vE, f4, DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), ue1);
+    }
+    if (CL || P.per || (gi - 2 >= 0 && gi + 1 <= P.nx - 1)) {
+      const double f1 = V_(i - 2, j), f4 = V_(i + 1, j);
+      pw0 = psi_s(f1, vW, vP, f4, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), uw0);
+      pw1 = psi_s(f1, vW, vP, f4, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), uw1);
+    }
+    if (CL || (gj - 1 >= 0 && gj + 2 <= P.ny))
+      pn = psi_c(vS, vP, vN, V_(i, j + 2), dys, dyn, DY_(j + 1), vbN);
+    if (CL || (gj - 2 >= 0 && gj + 1 <= P.ny))
+      ps = psi_c(V_(i, j - 2), vS, vP, vN, DY_(j - 2), dys, dyn, vbS);
+  }
+  const double FbN = R_(i, j) * vbN * dxi, FbS = R_(i, j - 1) * vbS * dxi;
+  return -0.5 * (Fe0 * (upw(vP, vE, ue0) + (vE - vP) * pe0) +
+                 Fe1 * (upw(vP, vE, ue1) + (vE - vP) * pe1)) +
+         0.5 * (Fw0 * (upw(vW, vP, uw0) + (vP - vW) * pw0) +
+                Fw1 * (upw(vW, vP, uw1) + (vP - vW) * pw1)) -
+         FbN * (upw(vP, vN, vbN) + (vN - vP) * pn) +
+         FbS * (upw(vS, vP, vbS) + (vP - vS) * ps);
+}
+
+template <bool CL, bool EX, bool TV>
+__device__ void prologue_body(Lds &s, const Params &P, const Consts C, int x0,
+                              int y0) {
+  if (EX) {
+    for (int k = threadIdx.x; k < BX * (BY + 1); k += NT) {
+      const int fi = k % BX - 1, fj = k / BX - 2;
+      RU_(fi, fj) = rho_xface<CL, TV>(s, P, fi, fj, x0 + fi, y0 + fj);
+    }
+    for (int k = threadIdx.x; k < (BX + 1) * BY; k += NT) {
+      const int fi = k % (BX + 1) - 2, fj = k / (BX + 1) - 1;
+      RV_(fi, fj) = rho_yface<CL, TV>(s, P, fi, fj, y0 + fj);
+    }
+    __syncthreads();
+  }
+  const int i = threadIdx.x % BX - 1, j = threadIdx.x / BX - 1;
+  const int gi = x0 + i, gj = y0 + j;
+  if (i < 0 || i >= TX || j < 0 || j >= TY) return;
+  if (gi >= P.nx || gj >= P.ny) return;
+  const long k = P.off + (long)gj * P.pitch + gi;
+  const double dxi = DX_(i), dyj = DY_(j);
+  // cell constants
+  double CT = 0.0, Cp = 0.0;
+  if (FL_(i, j)) {
+    const double dV = dxi * dyj;
+    CT = R_(i, j) * T_(i, j) * dV;
+    if (EX) CT += P.dt * t_explicit<CL, TV>(s, P, i, j, gi, gj);
+    Cp = R_(i, j) * dV;
+  }
+  C.CT[k] = CT;
+  C.Cp[k] = Cp;
+  double Cu = 0.0, Cv = 0.0;
+  if (u_solved(s, P, i, j, gi)) {
+    const double M = (R_(i, j) * dxi + R_(i - 1, j) * DX_(i - 1)) * dyj / 2.0;
+    Cu = M / P.dt * U_(i, j) + P.gx * M;
+    if (EX) Cu += u_explicit<CL, TV>(s, P, i, j, gi, gj);
+  }
+  if (v_solved(s, P, i, j, gj)) {
+    const double M = (R_(i, j) * dyj + R_(i, j - 1) * DY_(j - 1)) * dxi / 2.0;
+    Cv = M / P.dt * V_(i, j) + P.gy * M;
+    if (EX) Cv += v_explicit<CL, TV>(s, P, i, j, gi, gj);
+  }
+  C.Cu[k] = Cu;
+  C.Cv[k] = Cv;
+}
+
+template <bool EX, bool TV>
+__global__ __launch_bounds__(NT) void k_prologue(const Params P, const State m,
+                                                 const Consts C) {
+  __shared__ Lds s;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
+  load_window(s, P, m, x0, y0);
+  __syncthreads();
+  if (P.clean[tile])
+    prologue_body<true, EX, TV>(s, P, C, x0, y0);
+  else
+    prologue_body<false, EX, TV>(s, P, C, x0, y0);
+}
+
+// ---------------------------------------------------------------------------
+// residuals of the last pass: increments of the unknowns and the discrete
+// continuity residual with the face densities of the pass (old iterate)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double gld(const double *a, const Params &P,
+                                      int i, int j) {
+  return a[P.off + (long)j * P.pitch + i];
+}
+__device__ __forceinline__ bool gfl(const Params &P, int i, int j) {
+  if (j < 0 || j >= P.ny) return false;
+  if (P.per) i = wrapi(i, P.nx);
+  else if (i < 0 || i >= P.nx) return false;
+  return P.fl[P.off + (long)j * P.pitch + i] != 0;
+}
+__device__ __forceinline__ double grho(const State &o, const Params &P, int i,
+                                       int j) {
+  if (P.per) i = wrapi(i, P.nx);
+  const long k = P.off + (long)j * P.pitch + i;
+  return o.p[k] / o.T[k];
+}
+__device__ __forceinline__ double gdx(const Params &P, int i) {
+  return P.dxp[(P.per ? wrapi(i, P.nx) : clampi(i, -XPAD, P.nx + XPAD - 1)) + XPAD];
+}
+__device__ __forceinline__ double gdy(const Params &P, int j) {
+  return P.dyp[clampi(j, -XPAD, P.ny + XPAD - 1) + XPAD];
+}
+// rho^u at u-face (i, j) of the old iterate (global memory)
+template <bool TV>
+__device__ double grho_x(const State &o, const Params &P, int i, int j) {
+  const double uf = gld(o.u, P, i, j);
+  if (!P.per) {
+    if (i == 0) return uf > 0.0 ? P.rho_in[j] : grho(o, P, 0, j);
+    if (i == P.nx) return grho(o, P, P.nx - 1, j);
+  }
+  const double rl = grho(o, P, i - 1, j), rr = grho(o, P, i, j);
+  double r = upw(rl, rr, uf);
+  if (TV && gfl(P, i - 2, j) && gfl(P, i - 1, j) && gfl(P, i, j) && gfl(P, i + 1, j))
+    r += psi_s(grho(o, P, i - 2, j), rl, rr, grho(o, P, i + 1, j), gdx(P, i - 2),
+               gdx(P, i - 1), gdx(P, i), gdx(P, i + 1), uf) *
+         (rr - rl);
+  return r;
+}
+template <bool TV>
+__device__ double grho_y(const State &o, const Params &P, int i, int j) {
+  if (j == 0) return grho(o, P, i, 0);
+  if (j == P.ny) return grho(o, P, i, P.ny - 1);
+  const double vf = gld(o.v, P, i, j);
+  const double rs = grho(o, P, i, j - 1), rn = grho(o, P, i, j);
+  double r = upw(rs, rn, vf);
+  if (TV && gfl(P, i, j - 2) && gfl(P, i, j - 1) && gfl(P, i, j) && gfl(P, i, j + 1))
+    r += psi_s(grho(o, P, i, j - 2), rs, rn, grho(o, P, i, j + 1), gdy(P, j - 2),
+               gdy(P, j - 1), gdy(P, j), gdy(P, j + 1), vf) *
+         (rn - rs);
+  return r;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+constexpr int RB = 256;  // threads per residual block
+
+template <bool TV>
+__global__ __launch_bounds__(RB) void k_residual(const Params P, const State o,
+                                                 const State n, const Consts C,
+                                                 double *partials) {
+  double ru = 0.0, rv = 0.0, rp = 0.0, rT = 0.0, rm = 0.0, sm = 0.0, bad = 0.0;
+  const long ncell = (long)P.nx * P.ny;
+  for (long c = (long)blockIdx.x * RB + threadIdx.x; c < ncell;
+       c += (long)gridDim.x * RB) {
+    const int i = (int)(c % P.nx), j = (int)(c / P.nx);
+    const long k = P.off + (long)j * P.pitch + i;
+    const bool fi = P.fl[k] != 0;
+    // u-face (i, j) and v-face (i, j)
+    const double un = n.u[k], vn = n.v[k];
+    if (!isfinite(un) || !isfinite(vn)) bad += 1.0;
+    const bool us = (P.per || i >= 1) && fi && gfl(P, i - 1, j);
+    if (us) ru = fmax(ru, fabs(un - o.u[k]));
+    const bool vs = j >= 1 && fi && gfl(P, i, j - 1);
+    if (vs) rv = fmax(rv, fabs(vn - o.v[k]));
+    if (fi) {
+      const double pn = n.p[k], Tn = n.T[k];
+      if (!isfinite(pn) || !isfinite(Tn)) bad += 1.0;
+      rp = fmax(rp, fabs(pn - o.p[k]));
+      rT = fmax(rT, fabs(Tn - o.T[k]));
+      const double dxi = gdx(P, i), dyj = gdy(P, j), dV = dxi * dyj;
+      const int ie = (P.per && i + 1 == P.nx) ? P.nx : i + 1;
+      const double GW = grho_x<TV>(o, P, i, j) * un * dyj;
+      const double GE = grho_x<TV>(o, P, ie, j) * gld(n.u, P, ie, j) * dyj;
+      const double GS = grho_y<TV>(o, P, i, j) * vn * dxi;
+      const double GN = grho_y<TV>(o, P, i, j + 1) * gld(n.v, P, i, j + 1) * dxi;
+      const double R = (pn / Tn * dV - C.Cp[k]) / P.dt + (GE - GW) + (GN - GS);
+      if (!isfinite(R)) bad += 1.0;
+      rm = fmax(rm, fabs(R));
+      sm += R;
+    }
+  }
+  __shared__ double red[RB / 64][NRES];
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  double v[NRES] = {wave_max(ru), wave_max(rv), wave_max(rp), wave_max(rT),
+                    wave_max(rm), wave_sum(sm), wave_sum(bad), 0.0};
+  if (l == 0)
+    for (int q = 0; q < NRES; q++) red[w][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double out[NRES];
+    for (int q = 0; q < NRES; q++) out[q] = red[0][q];
+    for (int ww = 1; ww < RB / 64; ww++) {
+      for (int q = 0; q < 5; q++) out[q] = fmax(out[q], red[ww][q]);
+      out[5] += red[ww][5];
+      out[6] += red[ww][6];
+    }
+    for (int q = 0; q < NRES; q++) partials[(long)blockIdx.x * NRES + q] = out[q];
+  }
+}
+
+__global__ __launch_bounds__(RB) void k_finalize(const double *partials,
+                                                 int nb, double *out) {
+  double m[5] = {0, 0, 0, 0, 0}, sm = 0.0, bad = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RB) {
+    const double *q = partials + (long)b * NRES;
+    for (int t = 0; t < 5; t++) m[t] = fmax(m[t], q[t]);
+    sm += q[5];
+    bad += q[6];
+  }
+  __shared__ double red[RB / 64][NRES];
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  double v[NRES] = {wave_max(m[0]), wave_max(m[1]), wave_max(m[2]),
+                    wave_max(m[3]), wave_max(m[4]), wave_sum(sm),
+                    wave_sum(bad), 0.0};
+  if (l == 0)
+    for (int q = 0; q < NRES; q++) red[w][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o[NRES];
+    for (int q = 0; q < NRES; q++) o[q] = red[0][q];
+    for (int ww = 1; ww < RB / 64; ww++) {
+      for (int q = 0; q < 5; q++) o[q] = fmax(o[q], red[ww][q]);
+      o[5] += red[ww][5];
+      o[6] += red[ww][6];
+    }
+    for (int q = 0; q < NRES; q++) out[q] = o[q];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int ntiles(const Params &P) { return P.tiles_x * P.tiles_y; }
+
+void launch_prologue(const Params &P, State m, Consts C, int scheme,
+                     hipStream_t st) {
+  const bool ex = !(scheme & 1), tv = (scheme & 2) != 0;
+  dim3 g(ntiles(P)), b(NT);
+  if (ex && tv) hipLaunchKernelGGL((k_prologue<true, true>), g, b, 0, st, P, m, C);
+  else if (ex) hipLaunchKernelGGL((k_prologue<true, false>), g, b, 0, st, P, m, C);
+  else hipLaunchKernelGGL((k_prologue<false, false>), g, b, 0, st, P, m, C);
+}
+
+void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
+                 hipStream_t st) {
+  const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0;
+  dim3 g(ntiles(P)), b(NT);
+  if (im && tv) hipLaunchKernelGGL((k_pass<true, true>), g, b, 0, st, P, o, n, C);
+  else if (im) hipLaunchKernelGGL((k_pass<true, false>), g, b, 0, st, P, o, n, C);
+  else if (tv) hipLaunchKernelGGL((k_pass<false, true>), g, b, 0, st, P, o, n, C);
+  else hipLaunchKernelGGL((k_pass<false, false>), g, b, 0, st, P, o, n, C);
+}
+
+int residual_blocks(const Params &P) {
+  const long n = (long)P.nx * P.ny;
+  long b = (n + RB - 1) / RB;
+  if (b > 2048) b = 2048;
+  return (int)b;
+}
+
+void launch_residual(const Params &P, State o, State n, Consts C, int scheme,
+                     double *partials, int nblocks, double *out,
+                     hipStream_t st) {
+  const bool tv = (scheme & 2) != 0;
+  if (tv) hipLaunchKernelGGL((k_residual<true>), dim3(nblocks), dim3(RB), 0, st, P, o, n, C, partials);
+  else hipLaunchKernelGGL((k_residual<false>), dim3(nblocks), dim3(RB), 0, st, P, o, n, C, partials);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RB), 0, st, partials, nblocks, out);
+}
+
+}  // namespace sts
