@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Throughput of the SIMPLE-TS time step on one MI355X.
+
+A step is one full time step of the method on the 5120x1152 channel
+(5.9M finite volumes, two squares, Ma 2.43, Re 20): the step prologue, 10
+Jacobi passes of loop 2 and the residual reduction.  Inputs are synthetic
+(seeded noise on the inlet state) and resident in HBM before timing starts.
+
+Prints one JSON line: MFV-iterations/s (finite volumes x inner passes per
+second), the pass kernel's achieved bandwidth against the HBM roofline, and
+the FP64 CPU oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1802_04243_amd import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+BYTES_PER_FV_PASS = 96.0       # read u,v,p,T (32) + 4 step constants (32) + write u,v,p,T (32)
+HEADLINE = "explicit_tvd"
+KERNEL_SOURCES = ["paper_1802_04243_amd/csrc/sts_kernels.hip",
+                  "paper_1802_04243_amd/csrc/sts_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_kernel_hbm_traffic_5120x1152.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(scheme_name: str):
+    """HBM bytes per pass launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on a different kernel source."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch", {}).get(scheme_name)
+
+
+def run_gpu(name: str, steps: int, warmup: int, scheme: int):
+    import torch
+    from paper_1802_04243_amd import sts
+
+    p, run = W.workload(name)
+    g = sts.Solver(p)
+    g.set_fields(*W.initial_fields(p, run["seed"]))
+    dt, inner = run["dt"], run["inner"]
+    for _ in range(warmup):
+        g.step(dt, inner, scheme)
+    g.residuals()
+    torch.cuda.synchronize()
+    g.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.step(dt, inner, scheme)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = g.residuals()
+    ms, n = g.read_timing()
+    g.timing(False)
+    g.close()
+    wall = t1 - t0
+    fv_iters = p.n_fv * inner * steps
+    pass_ms = ms[1] / max(n[1], 1)
+    return dict(wall_s=wall, mfv_iters_s=fv_iters / wall / 1e6, ms_per_step=wall / steps * 1e3,
+                pass_ms=pass_ms, prologue_ms=ms[0] / max(n[0], 1), residual_ms=ms[2] / max(n[0], 1),
+                pass_gbs=BYTES_PER_FV_PASS * p.n_fv / (pass_ms * 1e-3) / 1e9,
+                residuals=[float(x) for x in res], nx=p.nx, ny=p.ny, dt=dt, inner=inner)
+
+
+def run_cpu_baseline(name: str, scheme: int, steps: int):
+    """The FP64 oracle as it stands, on the host cores, on a bounded sample."""
+    from oracle import oracle as O
+    p, run = W.workload(name)
+    o = O.Oracle(p)
+    o.set_fields(*W.initial_fields(p, run["seed"]))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.step(run["dt"], run["inner"], scheme)
+    t = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=p.n_fv * run["inner"] * steps / t / 1e6, unit="MFV-iters/s", cores=cores,
+                kind="oracle",
+                sample=f"{steps} step(s) x {run['inner']} passes of {name} ({p.n_fv} FV), "
+                       f"{[k for k, v in W.SCHEMES.items() if v == scheme][0]}, {t:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="channel_5120x1152")
+    ap.add_argument("--schemes", default="all", help="'all' or a comma list of scheme names")
+    ap.add_argument("--cpu-baseline-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
+              f"multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    names = list(W.SCHEMES) if a.schemes == "all" else a.schemes.split(",")
+    if HEADLINE in names:
+        names.remove(HEADLINE)
+    names = [HEADLINE] + names
+    per = {}
+    for nm in names:
+        per[nm] = run_gpu(a.workload, a.steps, a.warmup, W.SCHEMES[nm])
+        print(f"# {nm}: {per[nm]['mfv_iters_s']:.1f} MFV-iters/s, pass {per[nm]['pass_ms']:.3f} ms "
+              f"({per[nm]['pass_gbs']:.0f} GB/s algorithmic), step {per[nm]['ms_per_step']:.2f} ms",
+              file=sys.stderr, flush=True)
+    h = per[HEADLINE]
+    traffic = measured_traffic(HEADLINE)
+    roof = dict(bound="hbm", achieved=round(h["pass_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(h["pass_gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel="k_pass (one Jacobi pass)",
+                bytes_per_launch=BYTES_PER_FV_PASS * h["nx"] * h["ny"],
+                avg_launch_ms=round(h["pass_ms"], 5))
+    cpu = None
+    if rank == 0 and not a.no_cpu_baseline:
+        cpu = run_cpu_baseline(a.workload, W.SCHEMES[HEADLINE], a.cpu_baseline_steps)
+        cpu["value"] = round(cpu["value"], 3)
+    out = {
+        "metric": "MFV-iters/s (FP64 SIMPLE-TS step)",
+        "value": round(h["mfv_iters_s"], 2),
+        "unit": "MFV-iters/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(h["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "grid": f"{h['nx']}x{h['ny']}", "scheme": HEADLINE,
+                   "n_inner": h["inner"], "dt": h["dt"], "parallelism": "single-gpu"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "schemes": {nm: {"mfv_iters_s": round(r["mfv_iters_s"], 2), "pass_ms": round(r["pass_ms"], 5),
+                         "pass_gbs_algorithmic": round(r["pass_gbs"], 1),
+                         "hbm_frac": round(r["pass_gbs"] / HBM_PEAK_GBS, 4),
+                         "prologue_ms": round(r["prologue_ms"], 4),
+                         "residual_ms": round(r["residual_ms"], 4),
+                         "max_residuals": r["residuals"][:5]}
+                    for nm, r in per.items()},
+    }
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -255,3 +255,130 @@ def test_u_equation_is_mirror_of_printed_v_equation(oracle_lib, scheme):
             assert rva[j, i] == pytest.approx(rub[i, j], rel=1e-12, abs=1e-14)
             assert rTa[j, i] == pytest.approx(rTb[i, j], rel=1e-12, abs=1e-14)
     assert np.abs(rua[lo:hi, lo:hi]).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# P2: compressible Couette flow with heat conduction (closed form)
+# ---------------------------------------------------------------------------
+def _couette_exact(y, Uw, Tb, Tt, K):
+    """Steady Couette with mu, lambda ~ sqrt(T): T(u) = Tb + (Tt-Tb) u/Uw + K/2 u (Uw-u)
+    (Crocco relation, K = C2/C1 = (gamma-1) Ma^2 Pr) and y(u) = int_0^u sqrt(T) / int_0^Uw sqrt(T)."""
+    from scipy.integrate import quad
+    from scipy.optimize import brentq
+    Tu = lambda u: Tb + (Tt - Tb) * u / Uw + 0.5 * K * u * (Uw - u)
+    I = lambda u: quad(lambda s: math.sqrt(Tu(s)), 0.0, u, epsabs=1e-15, epsrel=1e-14, limit=200)[0]
+    IW = I(Uw)
+    out = []
+    for yy in y:
+        uu = brentq(lambda u: I(u) / IW - yy, 0.0, Uw, xtol=1e-15, rtol=1e-15)
+        out.append((uu, Tu(uu)))
+    return np.array(out)
+
+
+def _steady(oracle_lib, p, u0, T0, dt, inner=20, max_steps=3000):
+    o = oracle_lib.Oracle(p)
+    o.set_fields(u0, np.zeros((p.ny + 1, p.nx)), np.ones((p.ny, p.nx)), T0)
+    for s in range(max_steps):
+        o.step(dt, inner, W.IMPLICIT | W.UPWIND)
+        if s > 5 and o.residuals()[:4].max() < 1e-13:
+            return o
+    raise AssertionError("no steady state")
+
+
+def test_couette_with_heat_conduction_converges_at_second_order(oracle_lib):
+    Ma, Re, Pr, g, Uw, Tb, Tt = 1.0, 5.0, 0.7, 1.4, 1.0, 1.0, 1.2
+    K = (g - 1) * Ma ** 2 * Pr
+    errs = []
+    for N in (8, 16, 32):
+        nx = 4
+        p = W.Problem(nx=nx, ny=N, lx=0.5, ly=1.0, periodic=True, Ma=Ma, Re=Re, Pr=Pr, gamma=g,
+                      wall_u=(0.0, Uw), wall_T=(np.full(nx, Tb), np.full(nx, Tt)))
+        y = (np.arange(N) + 0.5) / N
+        o = _steady(oracle_lib, p, np.repeat((Uw * y)[:, None], nx + 1, 1),
+                    np.repeat((Tb + (Tt - Tb) * y)[:, None], nx, 1), dt=0.02)
+        u, v, pr, T = o.fields()
+        ex = _couette_exact(y, Uw, Tb, Tt, K)
+        errs.append((np.abs(u[:, 0] - ex[:, 0]).max(), np.abs(T[:, 0] - ex[:, 1]).max()))
+        assert np.abs(v).max() < 1e-6
+    e = np.array(errs)
+    order_u, order_T = np.log2(e[:-1, 0] / e[1:, 0]), np.log2(e[:-1, 1] / e[1:, 1])
+    assert np.all((order_T > 1.9) & (order_T < 2.1)), order_T
+    assert order_u[-1] > 1.7, order_u
+    assert e[-1, 0] < 2e-7 and e[-1, 1] < 5e-5, e[-1]
+
+
+# ---------------------------------------------------------------------------
+# P3: Poiseuille flow driven by a body force, with viscous heating
+# ---------------------------------------------------------------------------
+def test_poiseuille_with_heating_converges_at_second_order(oracle_lib):
+    from scipy.integrate import solve_bvp
+    Ma, Re, Pr, g, gx = 0.5, 2.0, 0.7, 1.4, 1.0
+    B, C1, C2 = 1 / Re, g / (Re * Pr), g * (g - 1) * Ma ** 2 / Re
+
+    def reference(M):
+        # u' = tau/Gamma, tau' = -rho gx/B, T' = q/Gamma, q' = -(C2/C1) tau^2/Gamma,
+        # m' = rho (mass below y), rho = p/T with p uniform and fixed by m(1) = M
+        def f(y, s, par):
+            u, tau, T, q, m = s
+            G = np.sqrt(T)
+            return np.vstack([tau / G, -(par[0] / T) * gx / B, q / G, -(C2 / C1) * tau ** 2 / G,
+                              par[0] / T])
+
+        def bc(a, b, par):
+            return np.array([a[0], b[0], a[2] - 1, b[2] - 1, a[4], b[4] - M])
+        y = np.linspace(0, 1, 2001)
+        s0 = np.vstack([gx / (2 * B) * y * (1 - y), gx / (2 * B) * (1 - 2 * y), np.ones_like(y),
+                        np.zeros_like(y), y])
+        sol = solve_bvp(f, bc, y, s0, p=[1.0], tol=1e-9, bc_tol=1e-12, max_nodes=1000000)
+        assert sol.success, sol.message
+        return sol
+
+    errs = []
+    for N in (8, 16, 32):
+        nx = 4
+        p = W.Problem(nx=nx, ny=N, lx=0.5, ly=1.0, periodic=True, Ma=Ma, Re=Re, Pr=Pr, gamma=g, gx=gx)
+        y = (np.arange(N) + 0.5) / N
+        o = _steady(oracle_lib, p, np.repeat((gx / (2 * B) * y * (1 - y))[:, None], nx + 1, 1),
+                    np.ones((N, nx)), dt=0.02)
+        u, v, pr, T = o.fields()
+        sol = reference(o.mass()[0] / 0.5)
+        errs.append((np.abs(u[:, 0] - sol.sol(y)[0]).max(), np.abs(T[:, 0] - sol.sol(y)[2]).max()))
+        assert abs(pr.mean() / sol.p[0] - 1) < 1e-4
+    e = np.array(errs)
+    order_u, order_T = np.log2(e[:-1, 0] / e[1:, 0]), np.log2(e[:-1, 1] / e[1:, 1])
+    assert np.all((order_u > 1.9) & (order_u < 2.1)), order_u
+    assert np.all((order_T > 1.8) & (order_T < 2.2)), order_T
+
+
+# ---------------------------------------------------------------------------
+# P10: speed of sound c = sqrt(gamma A T) = sqrt(T)/Ma.  Pins A and the sign and
+# scale of the pressure-work coefficient C3: +(gamma-1) would give
+# c^2 = (2-gamma) T/(gamma Ma^2), the c_p-form value -(gamma-1)/gamma would give
+# c^2 = (2 gamma - 1) T/(gamma^2 Ma^2) -- both about 20 % off.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("Ma,T0,scheme", [(1.0, 1.0, W.IMPLICIT | W.UPWIND),
+                                          (0.5, 1.0, W.IMPLICIT | W.UPWIND),
+                                          (1.0, 1.5, W.IMPLICIT | W.UPWIND),
+                                          (1.0, 1.0, W.EXPLICIT | W.UPWIND)])
+def test_acoustic_pulse_travels_at_the_speed_of_sound(oracle_lib, Ma, T0, scheme):
+    g, nx, ny, lx = 1.4, 200, 4, 1.0
+    p = W.Problem(nx=nx, ny=ny, lx=lx, ly=0.02, periodic=True, Ma=Ma, Re=1e8, Pr=0.7, gamma=g,
+                  wall_type=(W.WALL_SLIP_ADIABATIC, W.WALL_SLIP_ADIABATIC),
+                  u_in=np.zeros(ny), T_in=np.full(ny, T0))
+    o = oracle_lib.Oracle(p)
+    dx = lx / nx
+    x = (np.arange(nx) + 0.5) * dx
+    pr = 1 + 1e-4 * np.exp(-((x - 0.5) / 0.05) ** 2)
+    T = T0 * pr ** ((g - 1) / g)   # isentropic pulse
+    o.set_fields(np.zeros((ny, nx + 1)), np.zeros((ny + 1, nx)), np.repeat(pr[None], ny, 0),
+                 np.repeat(T[None], ny, 0))
+    c = math.sqrt(T0) / Ma
+    t_end = 0.25 / c
+    n = int(round(t_end / (0.2 * dx / c)))
+    for _ in range(n):
+        o.step(t_end / n, 20, scheme)
+    q = o.fields()[2][0]
+    k = int(np.argmax(q[nx // 2:])) + nx // 2
+    off = 0.5 * (q[k - 1] - q[k + 1]) / (q[k - 1] - 2 * q[k] + q[k + 1])
+    speed = (x[k] + off * dx - 0.5) / t_end
+    assert abs(speed / c - 1) < 5e-3, speed / c
