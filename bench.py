@@ -101,6 +101,18 @@ def run_cpu_baseline(name: str, scheme: int, steps: int):
                        f"{[k for k, v in W.SCHEMES.items() if v == scheme][0]}, {t:.1f} s")
 
 
+def copy_probe(nbytes: int = 1 << 30, reps: int = 3):
+    """A plain copy kernel of known size: reads and writes nbytes per launch."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,7 +122,12 @@ def main():
     ap.add_argument("--schemes", default="all", help="'all' or a comma list of scheme names")
     ap.add_argument("--cpu-baseline-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (counter calibration)")
     a = ap.parse_args()
+    if a.copy_probe:
+        copy_probe()
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
               f"multi-GPU path", file=sys.stderr)

@@ -29,6 +29,15 @@
 struct ora_ctx {
   int nx, ny, per;
   double *dx, *dy;
+  /* geometric factors (computed once from the widths):
+     per cell column i: idx = 1/dx, ihx = 1/(dx/2);
+     per x-face k (between cells k-1 and k): sx = dx_{k-1} + dx_k,
+     wlx = dx_k/sx (weight of cell k-1 at the face), wrx = dx_{k-1}/sx
+     (weight of cell k), icx = 1/(sx/2) (inverse centre distance),
+     isx = 1/sx; the same in y */
+  double *idx, *ihx, *sx, *wlx, *wrx, *icx, *isx;
+  double *idy, *ihy, *sy, *wly, *wry, *icy, *isy;
+  double idt;
   unsigned char *solid; /* [ny][nx] */
   double A, B, C1, C2, C3, gx, gy;
   double *u_in, *T_in, p_in;
@@ -64,6 +73,8 @@ static int cw(const ora_ctx *c, int i) {
   return i;
 }
 static double DX(const ora_ctx *c, int i) { return c->dx[cw(c, i)]; }
+/* x-face factor arrays are stored for faces 0..nx; wrap when periodic */
+static int fwx(const ora_ctx *c, int k) { return c->per ? cw(c, k) : k; }
 static int solid(const ora_ctx *c, int i, int j) {
   return c->solid[IC(c, cw(c, i), j)];
 }
@@ -134,22 +145,37 @@ static double upwind(double f1, double f2, double vel) {
 /* van Leer limiter psi(r) (Sec. 3.2 after pl15_2) of r = a/b.  The printed
    denominator (1+r) is read as (1+|r|), the standard van Leer form the paper
    cites: both agree wherever the printed form is defined.  r <= 0 gives 0;
-   r undefined (b == 0) is taken as 0. */
+   r undefined (b == 0) is taken as 0; for r > 0 it is 2a/(a+b). */
 double ora_vanleer(double a, double b) {
   if (!((a > 0 && b > 0) || (a < 0 && b < 0))) return 0.0;
-  double r = a / b;
-  if (isinf(r)) return 2.0;
-  return (r + fabs(r)) / (1.0 + fabs(r));
+  /* r > 0: (r+|r|)/(1+|r|) = 2r/(1+r) = 2a/(a+b) */
+  return 2.0 * a / (a + b);
 }
 
-/* TVD correction at a surface between two nodes, non-uniform grid (pl15_2) */
+/* TVD correction at a surface between two nodes, non-uniform grid (pl15_2).
+   In terms of the face factors of the face between nodes 2 and 3:
+   s12 = d1+d2, s23 = d2+d3, s34 = d3+d4, w2 = d2/s23, w3 = d3/s23. */
+static double psi_sf(double f1, double f2, double f3, double f4, double s12,
+                     double s23, double s34, double w2, double w3,
+                     double vel) {
+  if (vel > 0) return w2 * ora_vanleer(s23 * (f2 - f1), s12 * (f3 - f2));
+  return -w3 * ora_vanleer(s23 * (f4 - f3), s34 * (f3 - f2));
+}
 double ora_psi_s(double f1, double f2, double f3, double f4, double d1,
                  double d2, double d3, double d4, double vel) {
-  if (vel > 0)
-    return d2 / (d2 + d3) *
-           ora_vanleer((d2 + d3) * (f2 - f1), (d1 + d2) * (f3 - f2));
-  return -d3 / (d2 + d3) *
-         ora_vanleer((d2 + d3) * (f4 - f3), (d3 + d4) * (f3 - f2));
+  return psi_sf(f1, f2, f3, f4, d1 + d2, d2 + d3, d3 + d4, d2 / (d2 + d3),
+                d3 / (d2 + d3), vel);
+}
+/* psi_s at x-face k of a cell-row stencil k-2 .. k+1, and at y-face k */
+static double psi_x(const ora_ctx *c, double f1, double f2, double f3,
+                    double f4, int k, double vel) {
+  return psi_sf(f1, f2, f3, f4, c->sx[fwx(c, k - 1)], c->sx[fwx(c, k)],
+                c->sx[fwx(c, k + 1)], c->wrx[fwx(c, k)], c->wlx[fwx(c, k)], vel);
+}
+static double psi_y(const ora_ctx *c, double f1, double f2, double f3,
+                    double f4, int k, double vel) {
+  return psi_sf(f1, f2, f3, f4, c->sy[k - 1], c->sy[k], c->sy[k + 1],
+                c->wry[k], c->wly[k], vel);
 }
 
 /* TVD correction at a control-volume centre (pl15_1) */
@@ -183,9 +209,8 @@ static double gam_harm2(double a, double b) { return 2.0 * a * b / (a + b); }
 
 /* wall temperature of wall w at the x-position of u-face i */
 static double wallT_uface(const ora_ctx *c, int w, int i) {
-  int l = cw(c, i - 1), r = cw(c, i);
-  double dl = c->dx[l], dr = c->dx[r];
-  return (dr * c->wT[w][l] + dl * c->wT[w][r]) / (dl + dr);
+  int l = cw(c, i - 1), r = cw(c, i), k = fwx(c, i);
+  return c->wlx[k] * c->wT[w][l] + c->wrx[k] * c->wT[w][r];
 }
 
 /* Gamma at the corner (x^f_i, y^f_j), bilinear in the four surrounding
@@ -194,15 +219,13 @@ static double wallT_uface(const ora_ctx *c, int w, int i) {
    channel walls only ever multiply wall velocities, which are zero: 0. */
 static double gam_corner(const ora_ctx *c, const double *gam, int i, int j) {
   if (j <= 0 || j >= c->ny) return 0.0;
-  double dys = c->dy[j - 1], dyn = c->dy[j];
-  double ws = dyn / (dys + dyn), wn = dys / (dys + dyn);
+  double ws = c->wly[j], wn = c->wry[j];
   if (!c->per && i == 0)
     return ws * sqrt(c->T_in[j - 1]) + wn * sqrt(c->T_in[j]);
   if (!c->per && i == c->nx)
     return ws * gam[IC(c, c->nx - 1, j - 1)] + wn * gam[IC(c, c->nx - 1, j)];
-  int l = cw(c, i - 1), r = cw(c, i);
-  double dl = c->dx[l], dr = c->dx[r];
-  double wl = dr / (dl + dr), wr = dl / (dl + dr);
+  int l = cw(c, i - 1), r = cw(c, i), k = fwx(c, i);
+  double wl = c->wlx[k], wr = c->wrx[k];
   return ws * (wl * gam[IC(c, l, j - 1)] + wr * gam[IC(c, r, j - 1)]) +
          wn * (wl * gam[IC(c, l, j)] + wr * gam[IC(c, r, j)]);
 }
@@ -238,9 +261,7 @@ static void face_fluxes(ora_ctx *c, const double *u, const double *v,
         double rl = Cat(c, rho, i - 1, j), rr = Cat(c, rho, i, j);
         r = upwind(rl, rr, uf);
         if (tvd && cells_ok_x(c, i - 2, j))
-          r += ora_psi_s(Cat(c, rho, i - 2, j), rl, rr, Cat(c, rho, i + 1, j),
-                         DX(c, i - 2), DX(c, i - 1), DX(c, i), DX(c, i + 1),
-                         uf) *
+          r += psi_x(c, Cat(c, rho, i - 2, j), rl, rr, Cat(c, rho, i + 1, j), i, uf) *
                (rr - rl);
       }
       c->rhou[IU(c, i, j)] = r;
@@ -259,9 +280,7 @@ static void face_fluxes(ora_ctx *c, const double *u, const double *v,
         double rs = rho[IC(c, i, j - 1)], rn = rho[IC(c, i, j)];
         r = upwind(rs, rn, vf);
         if (tvd && cells_ok_y(c, i, j - 2))
-          r += ora_psi_s(rho[IC(c, i, j - 2)], rs, rn, rho[IC(c, i, j + 1)],
-                         c->dy[j - 2], c->dy[j - 1], c->dy[j], c->dy[j + 1],
-                         vf) *
+          r += psi_y(c, rho[IC(c, i, j - 2)], rs, rn, rho[IC(c, i, j + 1)], j, vf) *
                (rn - rs);
       }
       c->rhov[IV(c, i, j)] = r;
@@ -288,17 +307,13 @@ static double T_explicit(const ora_ctx *c, int i, int j, int tvd) {
   double pW = 0, pE = 0, pS = 0, pN = 0;
   if (tvd) {
     if (cells_ok_x(c, i - 1, j))
-      pE = ora_psi_s(Cat(c, T, i - 1, j), TP, TE, Cat(c, T, i + 2, j),
-                     DX(c, i - 1), DX(c, i), DX(c, i + 1), DX(c, i + 2), uE);
+      pE = psi_x(c, Cat(c, T, i - 1, j), TP, TE, Cat(c, T, i + 2, j), i + 1, uE);
     if (cells_ok_x(c, i - 2, j))
-      pW = ora_psi_s(Cat(c, T, i - 2, j), TW, TP, TE, DX(c, i - 2),
-                     DX(c, i - 1), DX(c, i), DX(c, i + 1), uW);
+      pW = psi_x(c, Cat(c, T, i - 2, j), TW, TP, TE, i, uW);
     if (cells_ok_y(c, i, j - 1))
-      pN = ora_psi_s(T[IC(c, i, j - 1)], TP, TN, T[IC(c, i, j + 2)],
-                     c->dy[j - 1], c->dy[j], c->dy[j + 1], c->dy[j + 2], vN);
+      pN = psi_y(c, T[IC(c, i, j - 1)], TP, TN, T[IC(c, i, j + 2)], j + 1, vN);
     if (cells_ok_y(c, i, j - 2))
-      pS = ora_psi_s(T[IC(c, i, j - 2)], TS, TP, TN, c->dy[j - 2],
-                     c->dy[j - 1], c->dy[j], c->dy[j + 1], vS);
+      pS = psi_y(c, T[IC(c, i, j - 2)], TS, TP, TN, j, vS);
   }
   return -FE * (upwind(TP, TE, uE) + (TE - TP) * pE) +
          FW * (upwind(TW, TP, uW) + (TP - TW) * pW) -
@@ -324,17 +339,13 @@ static double v_explicit(const ora_ctx *c, int i, int j, int tvd) {
   if (tvd) {
     if (vcols_ok(c, i - 1)) {
       double f1 = Vat(c, v, i - 1, j), f4 = Vat(c, v, i + 2, j);
-      pe0 = ora_psi_s(f1, vP, vE, f4, DX(c, i - 1), DX(c, i), DX(c, i + 1),
-                      DX(c, i + 2), ue0);
-      pe1 = ora_psi_s(f1, vP, vE, f4, DX(c, i - 1), DX(c, i), DX(c, i + 1),
-                      DX(c, i + 2), ue1);
+      pe0 = psi_x(c, f1, vP, vE, f4, i + 1, ue0);
+      pe1 = psi_x(c, f1, vP, vE, f4, i + 1, ue1);
     }
     if (vcols_ok(c, i - 2)) {
       double f1 = Vat(c, v, i - 2, j), f4 = Vat(c, v, i + 1, j);
-      pw0 = ora_psi_s(f1, vW, vP, f4, DX(c, i - 2), DX(c, i - 1), DX(c, i),
-                      DX(c, i + 1), uw0);
-      pw1 = ora_psi_s(f1, vW, vP, f4, DX(c, i - 2), DX(c, i - 1), DX(c, i),
-                      DX(c, i + 1), uw1);
+      pw0 = psi_x(c, f1, vW, vP, f4, i, uw0);
+      pw1 = psi_x(c, f1, vW, vP, f4, i, uw1);
     }
     if (vrows_ok(c, j - 1))
       pn = ora_psi_c(vS, vP, vN, v[IV(c, i, j + 2)], c->dy[j - 1], c->dy[j],
@@ -371,17 +382,13 @@ static double u_explicit(const ora_ctx *c, int i, int j, int tvd) {
   if (tvd) {
     if (urows_ok(c, j - 1)) {
       double f1 = u[IU(c, r, j - 1)], f4 = u[IU(c, r, j + 2)];
-      pn0 = ora_psi_s(f1, uP, uN, f4, c->dy[j - 1], c->dy[j], c->dy[j + 1],
-                      c->dy[j + 2], vn0);
-      pn1 = ora_psi_s(f1, uP, uN, f4, c->dy[j - 1], c->dy[j], c->dy[j + 1],
-                      c->dy[j + 2], vn1);
+      pn0 = psi_y(c, f1, uP, uN, f4, j + 1, vn0);
+      pn1 = psi_y(c, f1, uP, uN, f4, j + 1, vn1);
     }
     if (urows_ok(c, j - 2)) {
       double f1 = u[IU(c, r, j - 2)], f4 = u[IU(c, r, j + 1)];
-      ps0 = ora_psi_s(f1, uS, uP, f4, c->dy[j - 2], c->dy[j - 1], c->dy[j],
-                      c->dy[j + 1], vs0);
-      ps1 = ora_psi_s(f1, uS, uP, f4, c->dy[j - 2], c->dy[j - 1], c->dy[j],
-                      c->dy[j + 1], vs1);
+      ps0 = psi_y(c, f1, uS, uP, f4, j, vs0);
+      ps1 = psi_y(c, f1, uS, uP, f4, j, vs1);
     }
     if (ufaces_ok_x(c, i - 1))
       pe = ora_psi_c(uW, uP, uE, Uat(c, u, i + 2, j), DX(c, i - 1), DX(c, i),
@@ -417,48 +424,38 @@ static void face_centre_vel(const ora_ctx *c, int i, int j, double *vE,
                             double *vW, double *uN, double *uS) {
   const double *u = c->u, *v = c->v;
   double vc = 0.5 * (v[IV(c, i, j)] + v[IV(c, i, j + 1)]);
-  double dxi = c->dx[i];
   if (!c->per && i == c->nx - 1) {
     *vE = vc;
   } else if (solid(c, i + 1, j)) {
     *vE = 0.0;
   } else {
-    int r = cw(c, i + 1);
-    double dr = c->dx[r];
-    *vE = dr / (dxi + dr) * vc +
-          dxi / (dxi + dr) * (0.5 * (v[IV(c, r, j)] + v[IV(c, r, j + 1)]));
+    int r = cw(c, i + 1), k = fwx(c, i + 1);
+    *vE = c->wlx[k] * vc + c->wrx[k] * (0.5 * (v[IV(c, r, j)] + v[IV(c, r, j + 1)]));
   }
   if (!c->per && i == 0) {
     *vW = 0.0;
   } else if (solid(c, i - 1, j)) {
     *vW = 0.0;
   } else {
-    int l = cw(c, i - 1);
-    double dl = c->dx[l];
-    *vW = dxi / (dl + dxi) * (0.5 * (v[IV(c, l, j)] + v[IV(c, l, j + 1)])) +
-          dl / (dl + dxi) * vc;
+    int l = cw(c, i - 1), k = fwx(c, i);
+    *vW = c->wlx[k] * (0.5 * (v[IV(c, l, j)] + v[IV(c, l, j + 1)])) + c->wrx[k] * vc;
   }
   double uc = 0.5 * (Uat(c, u, i, j) + Uat(c, u, i + 1, j));
-  double dyj = c->dy[j];
   if (j == c->ny - 1) {
     *uN = (c->wtype[1] == 0) ? c->wu[1] : uc;
   } else if (solid(c, i, j + 1)) {
     *uN = 0.0;
   } else {
-    double dn = c->dy[j + 1];
-    *uN = dn / (dyj + dn) * uc +
-          dyj / (dyj + dn) *
-              (0.5 * (Uat(c, u, i, j + 1) + Uat(c, u, i + 1, j + 1)));
+    *uN = c->wly[j + 1] * uc +
+          c->wry[j + 1] * (0.5 * (Uat(c, u, i, j + 1) + Uat(c, u, i + 1, j + 1)));
   }
   if (j == 0) {
     *uS = (c->wtype[0] == 0) ? c->wu[0] : uc;
   } else if (solid(c, i, j - 1)) {
     *uS = 0.0;
   } else {
-    double ds = c->dy[j - 1];
-    *uS = dyj / (ds + dyj) *
-              (0.5 * (Uat(c, u, i, j - 1) + Uat(c, u, i + 1, j - 1))) +
-          ds / (ds + dyj) * uc;
+    *uS = c->wly[j] * (0.5 * (Uat(c, u, i, j - 1) + Uat(c, u, i + 1, j - 1))) +
+          c->wry[j] * uc;
   }
 }
 
@@ -472,15 +469,15 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   /* west face x^f_i */
   if (!c->per && i == 0) { /* inlet: T_in on the face, half cell away */
     q.nb[0] = c->T_in[j];
-    D[0] = c->C1 * gam_harm2(gP, sqrt(c->T_in[j])) * dyj / (0.5 * dxi);
+    D[0] = c->C1 * gam_harm2(gP, sqrt(c->T_in[j])) * dyj * c->ihx[i];
   } else {
     int l = cw(c, i - 1);
     q.nb[0] = T[IC(c, l, j)];
     if (c->solid[IC(c, l, j)])
-      D[0] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj / (0.5 * dxi);
+      D[0] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj * c->ihx[i];
     else
-      D[0] = c->C1 * gam_harm(c->dx[l], gam[IC(c, l, j)], dxi, gP) * dyj /
-             (0.5 * (dxi + c->dx[l]));
+      D[0] = c->C1 * gam_harm(c->dx[l], gam[IC(c, l, j)], dxi, gP) * dyj *
+             c->icx[fwx(c, i)];
   }
   /* east face x^f_{i+1} */
   if (!c->per && i == c->nx - 1) { /* outlet: zero gradient */
@@ -490,16 +487,16 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     int r = cw(c, i + 1);
     q.nb[1] = T[IC(c, r, j)];
     if (c->solid[IC(c, r, j)])
-      D[1] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj / (0.5 * dxi);
+      D[1] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj * c->ihx[i];
     else
-      D[1] = c->C1 * gam_harm(dxi, gP, c->dx[r], gam[IC(c, r, j)]) * dyj /
-             (0.5 * (dxi + c->dx[r]));
+      D[1] = c->C1 * gam_harm(dxi, gP, c->dx[r], gam[IC(c, r, j)]) * dyj *
+             c->icx[fwx(c, i + 1)];
   }
   /* south face y^f_j */
   if (j == 0) {
     if (c->wtype[0] == 0) {
       q.nb[2] = c->wT[0][i];
-      D[2] = c->C1 * gam_harm2(gP, sqrt(c->wT[0][i])) * dxi / (0.5 * dyj);
+      D[2] = c->C1 * gam_harm2(gP, sqrt(c->wT[0][i])) * dxi * c->ihy[j];
     } else {
       q.nb[2] = TP;
       D[2] = 0.0;
@@ -507,16 +504,16 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   } else {
     q.nb[2] = T[IC(c, i, j - 1)];
     if (c->solid[IC(c, i, j - 1)])
-      D[2] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi / (0.5 * dyj);
+      D[2] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi * c->ihy[j];
     else
       D[2] = c->C1 * gam_harm(c->dy[j - 1], gam[IC(c, i, j - 1)], dyj, gP) *
-             dxi / (0.5 * (dyj + c->dy[j - 1]));
+             dxi * c->icy[j];
   }
   /* north face y^f_{j+1} */
   if (j == c->ny - 1) {
     if (c->wtype[1] == 0) {
       q.nb[3] = c->wT[1][i];
-      D[3] = c->C1 * gam_harm2(gP, sqrt(c->wT[1][i])) * dxi / (0.5 * dyj);
+      D[3] = c->C1 * gam_harm2(gP, sqrt(c->wT[1][i])) * dxi * c->ihy[j];
     } else {
       q.nb[3] = TP;
       D[3] = 0.0;
@@ -524,10 +521,10 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   } else {
     q.nb[3] = T[IC(c, i, j + 1)];
     if (c->solid[IC(c, i, j + 1)])
-      D[3] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi / (0.5 * dyj);
+      D[3] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi * c->ihy[j];
     else
       D[3] = c->C1 * gam_harm(dyj, gP, c->dy[j + 1], gam[IC(c, i, j + 1)]) *
-             dxi / (0.5 * (dyj + c->dy[j + 1]));
+             dxi * c->icy[j + 1];
   }
   F[0] = c->Fx[IU(c, i, j)];
   F[1] = c->Fx[IU(c, i + 1, j)];
@@ -539,21 +536,13 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
       double uW = c->u[IU(c, i, j)], uE = c->u[IU(c, i + 1, j)];
       double vS = c->v[IV(c, i, j)], vN = c->v[IV(c, i, j + 1)];
       if (cells_ok_x(c, i - 2, j))
-        psi[0] = ora_psi_s(Cat(c, T, i - 2, j), Cat(c, T, i - 1, j), TP,
-                           Cat(c, T, i + 1, j), DX(c, i - 2), DX(c, i - 1),
-                           DX(c, i), DX(c, i + 1), uW);
+        psi[0] = psi_x(c, Cat(c, T, i - 2, j), Cat(c, T, i - 1, j), TP, Cat(c, T, i + 1, j), i, uW);
       if (cells_ok_x(c, i - 1, j))
-        psi[1] = ora_psi_s(Cat(c, T, i - 1, j), TP, Cat(c, T, i + 1, j),
-                           Cat(c, T, i + 2, j), DX(c, i - 1), DX(c, i),
-                           DX(c, i + 1), DX(c, i + 2), uE);
+        psi[1] = psi_x(c, Cat(c, T, i - 1, j), TP, Cat(c, T, i + 1, j), Cat(c, T, i + 2, j), i + 1, uE);
       if (cells_ok_y(c, i, j - 2))
-        psi[2] = ora_psi_s(T[IC(c, i, j - 2)], T[IC(c, i, j - 1)], TP,
-                           T[IC(c, i, j + 1)], c->dy[j - 2], c->dy[j - 1],
-                           c->dy[j], c->dy[j + 1], vS);
+        psi[2] = psi_y(c, T[IC(c, i, j - 2)], T[IC(c, i, j - 1)], TP, T[IC(c, i, j + 1)], j, vS);
       if (cells_ok_y(c, i, j - 1))
-        psi[3] = ora_psi_s(T[IC(c, i, j - 1)], TP, T[IC(c, i, j + 1)],
-                           T[IC(c, i, j + 2)], c->dy[j - 1], c->dy[j],
-                           c->dy[j + 1], c->dy[j + 2], vN);
+        psi[3] = psi_y(c, T[IC(c, i, j - 1)], TP, T[IC(c, i, j + 1)], T[IC(c, i, j + 2)], j + 1, vN);
     }
     q.a[0] = dmax(0.0, F[0]) - F[0] * psi[0] + D[0];
     q.a[1] = dmax(0.0, -F[1]) - F[1] * psi[1] + D[1];
@@ -570,9 +559,9 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   /* source S^T_c (pl29), S^T_p = 0 (pl28) */
   double vE, vW, uN, uS;
   face_centre_vel(c, i, j, &vE, &vW, &uN, &uS);
-  double ux = (Uat(c, c->u, i + 1, j) - Uat(c, c->u, i, j)) / dxi;
-  double vy = (c->v[IV(c, i, j + 1)] - c->v[IV(c, i, j)]) / dyj;
-  double vx = (vE - vW) / dxi, uy = (uN - uS) / dyj;
+  double ux = (Uat(c, c->u, i + 1, j) - Uat(c, c->u, i, j)) * c->idx[i];
+  double vy = (c->v[IV(c, i, j + 1)] - c->v[IV(c, i, j)]) * c->idy[j];
+  double vx = (vE - vW) * c->idx[i], uy = (uN - uS) * c->idy[j];
   double div = ux + vy;
   q.src = c->C2 * gP *
               (2.0 * (ux * ux + vy * vy) + (vx + uy) * (vx + uy) -
@@ -604,28 +593,27 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   double vE = (!c->per && i == c->nx - 1) ? vP : Vat(c, v, i + 1, j);
   double M = (rn * dyn + rs * dys) * dxi / 2.0;
   double len = 0.5 * (dys + dyn);
-  double gnode = (dyn * gs + dys * gn) / (dys + dyn);
+  double gnode = c->wly[j] * gs + c->wry[j] * gn;
   double DW, DE;
   if (!c->per && i == 0) {
-    DW = c->B * 0.5 * (gnode + gam_corner(c, gam, 0, j)) * len / (0.5 * dxi);
+    DW = c->B * 0.5 * (gnode + gam_corner(c, gam, 0, j)) * len * c->ihx[i];
   } else {
     int l = cw(c, i - 1);
     if (solid(c, l, j - 1) && solid(c, l, j))
-      DW = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len / (0.5 * dxi);
+      DW = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihx[i];
     else
-      DW = c->B * gam_corner(c, gam, i, j) * (dyn + dys) / (dxi + c->dx[l]);
+      DW = c->B * gam_corner(c, gam, i, j) * c->sy[j] * c->isx[fwx(c, i)];
   }
   if (!c->per && i == c->nx - 1) {
     DE = 0.0;
   } else {
     int r = cw(c, i + 1);
     if (solid(c, r, j - 1) && solid(c, r, j))
-      DE = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len / (0.5 * dxi);
+      DE = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihx[i];
     else
-      DE = c->B * gam_corner(c, gam, i + 1, j) * (dyn + dys) /
-           (dxi + c->dx[r]);
+      DE = c->B * gam_corner(c, gam, i + 1, j) * c->sy[j] * c->isx[fwx(c, i + 1)];
   }
-  double DS = c->B * gs * dxi / dys, DN = c->B * gn * dxi / dyn;
+  double DS = c->B * gs * dxi * c->idy[j - 1], DN = c->B * gn * dxi * c->idy[j];
   double conv = 0.0;
   if (implicit) {
     double Fw0 = c->Fx[IU(c, i, j)], Fw1 = c->Fx[IU(c, i, j - 1)];
@@ -636,17 +624,13 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     if (tvd) {
       if (vcols_ok(c, i - 2)) {
         double f1 = Vat(c, v, i - 2, j), f4 = Vat(c, v, i + 1, j);
-        pw0 = ora_psi_s(f1, vW, vP, f4, DX(c, i - 2), DX(c, i - 1), DX(c, i),
-                        DX(c, i + 1), Uat(c, u, i, j));
-        pw1 = ora_psi_s(f1, vW, vP, f4, DX(c, i - 2), DX(c, i - 1), DX(c, i),
-                        DX(c, i + 1), Uat(c, u, i, j - 1));
+        pw0 = psi_x(c, f1, vW, vP, f4, i, Uat(c, u, i, j));
+        pw1 = psi_x(c, f1, vW, vP, f4, i, Uat(c, u, i, j - 1));
       }
       if (vcols_ok(c, i - 1)) {
         double f1 = Vat(c, v, i - 1, j), f4 = Vat(c, v, i + 2, j);
-        pe0 = ora_psi_s(f1, vP, vE, f4, DX(c, i - 1), DX(c, i), DX(c, i + 1),
-                        DX(c, i + 2), Uat(c, u, i + 1, j));
-        pe1 = ora_psi_s(f1, vP, vE, f4, DX(c, i - 1), DX(c, i), DX(c, i + 1),
-                        DX(c, i + 2), Uat(c, u, i + 1, j - 1));
+        pe0 = psi_x(c, f1, vP, vE, f4, i + 1, Uat(c, u, i + 1, j));
+        pe1 = psi_x(c, f1, vP, vE, f4, i + 1, Uat(c, u, i + 1, j - 1));
       }
       if (vrows_ok(c, j - 2))
         ps = ora_psi_c(v[IV(c, i, j - 2)], vS, vP, vN, c->dy[j - 2], dys, dyn,
@@ -668,7 +652,7 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     q.a[2] = 4.0 / 3.0 * DS;
     q.a[3] = 4.0 / 3.0 * DN;
   }
-  q.a0 = q.a[0] + q.a[1] + q.a[2] + q.a[3] + conv + M / dt;
+  q.a0 = q.a[0] + q.a[1] + q.a[2] + q.a[3] + conv + M * c->idt;
   double Mm = (c->pm[IC(c, i, j)] / c->Tm[IC(c, i, j)] * dyn +
                c->pm[IC(c, i, j - 1)] / c->Tm[IC(c, i, j - 1)] * dys) *
               dxi / 2.0;
@@ -679,7 +663,7 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
              2.0 / 3.0 * gs * (Uat(c, u, i + 1, j - 1) - Uat(c, u, i, j - 1));
   /* b^v (pl14) + v^explicit (pl21): the part fixed for the whole step
      first, then the cross-diffusion of the current iterate */
-  q.b = (Mm / dt * c->vm[IV(c, i, j)] + c->gy * Mm +
+  q.b = (Mm * c->idt * c->vm[IV(c, i, j)] + c->gy * Mm +
          ((scheme & ORA_IMPLICIT) ? 0.0 : c->vexp[IV(c, i, j)])) +
         c->B * X;
   q.nb[0] = vW;
@@ -703,12 +687,11 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   double uS, uN, DS, DN;
   double M = (rr * dxr + rl * dxl) * dyj / 2.0;
   double len = 0.5 * (dxl + dxr);
-  double gnode = (dxr * gl + dxl * gr) / (dxl + dxr);
+  double gnode = c->wlx[fwx(c, i)] * gl + c->wrx[fwx(c, i)] * gr;
   if (j == 0) {
     if (c->wtype[0] == 0) {
       uS = c->wu[0];
-      DS = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 0, i))) * len /
-           (0.5 * dyj);
+      DS = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 0, i))) * len * c->ihy[j];
     } else {
       uS = uP;
       DS = 0.0;
@@ -716,15 +699,14 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   } else {
     uS = u[IU(c, r, j - 1)];
     if (solid(c, l, j - 1) && solid(c, r, j - 1))
-      DS = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len / (0.5 * dyj);
+      DS = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihy[j];
     else
-      DS = c->B * gam_corner(c, gam, i, j) * (dxr + dxl) / (dyj + c->dy[j - 1]);
+      DS = c->B * gam_corner(c, gam, i, j) * c->sx[fwx(c, i)] * c->isy[j];
   }
   if (j == c->ny - 1) {
     if (c->wtype[1] == 0) {
       uN = c->wu[1];
-      DN = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 1, i))) * len /
-           (0.5 * dyj);
+      DN = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 1, i))) * len * c->ihy[j];
     } else {
       uN = uP;
       DN = 0.0;
@@ -732,12 +714,11 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   } else {
     uN = u[IU(c, r, j + 1)];
     if (solid(c, l, j + 1) && solid(c, r, j + 1))
-      DN = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len / (0.5 * dyj);
+      DN = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihy[j];
     else
-      DN = c->B * gam_corner(c, gam, i, j + 1) * (dxr + dxl) /
-           (dyj + c->dy[j + 1]);
+      DN = c->B * gam_corner(c, gam, i, j + 1) * c->sx[fwx(c, i)] * c->isy[j + 1];
   }
-  double DW = c->B * gl * dyj / dxl, DE = c->B * gr * dyj / dxr;
+  double DW = c->B * gl * dyj * c->idx[l], DE = c->B * gr * dyj * c->idx[r];
   double conv = 0.0;
   if (implicit) {
     double Fs0 = c->Fy[IV(c, r, j)], Fs1 = c->Fy[IV(c, l, j)];
@@ -748,17 +729,13 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     if (tvd) {
       if (urows_ok(c, j - 2)) {
         double f1 = u[IU(c, r, j - 2)], f4 = u[IU(c, r, j + 1)];
-        ps0 = ora_psi_s(f1, uS, uP, f4, c->dy[j - 2], c->dy[j - 1], dyj,
-                        c->dy[j + 1], v[IV(c, r, j)]);
-        ps1 = ora_psi_s(f1, uS, uP, f4, c->dy[j - 2], c->dy[j - 1], dyj,
-                        c->dy[j + 1], v[IV(c, l, j)]);
+        ps0 = psi_y(c, f1, uS, uP, f4, j, v[IV(c, r, j)]);
+        ps1 = psi_y(c, f1, uS, uP, f4, j, v[IV(c, l, j)]);
       }
       if (urows_ok(c, j - 1)) {
         double f1 = u[IU(c, r, j - 1)], f4 = u[IU(c, r, j + 2)];
-        pn0 = ora_psi_s(f1, uP, uN, f4, c->dy[j - 1], dyj, c->dy[j + 1],
-                        c->dy[j + 2], v[IV(c, r, j + 1)]);
-        pn1 = ora_psi_s(f1, uP, uN, f4, c->dy[j - 1], dyj, c->dy[j + 1],
-                        c->dy[j + 2], v[IV(c, l, j + 1)]);
+        pn0 = psi_y(c, f1, uP, uN, f4, j + 1, v[IV(c, r, j + 1)]);
+        pn1 = psi_y(c, f1, uP, uN, f4, j + 1, v[IV(c, l, j + 1)]);
       }
       if (ufaces_ok_x(c, i - 2))
         pw = ora_psi_c(Uat(c, u, i - 2, j), uW, uP, uE, DX(c, i - 2), dxl, dxr,
@@ -782,7 +759,7 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     q.a[0] = 4.0 / 3.0 * DW;
     q.a[1] = 4.0 / 3.0 * DE;
   }
-  q.a0 = q.a[2] + q.a[3] + q.a[0] + q.a[1] + conv + M / dt;
+  q.a0 = q.a[2] + q.a[3] + q.a[0] + q.a[1] + conv + M * c->idt;
   double Mm = (c->pm[IC(c, r, j)] / c->Tm[IC(c, r, j)] * dxr +
                c->pm[IC(c, l, j)] / c->Tm[IC(c, l, j)] * dxl) *
               dyj / 2.0;
@@ -791,7 +768,7 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
              gam_corner(c, gam, i, j) * (v[IV(c, r, j)] - v[IV(c, l, j)]) -
              2.0 / 3.0 * gr * (v[IV(c, r, j + 1)] - v[IV(c, r, j)]) +
              2.0 / 3.0 * gl * (v[IV(c, l, j + 1)] - v[IV(c, l, j)]);
-  q.b = (Mm / dt * Uat(c, c->um, i, j) + c->gx * Mm +
+  q.b = (Mm * c->idt * Uat(c, c->um, i, j) + c->gx * Mm +
          ((scheme & ORA_IMPLICIT) ? 0.0 : c->uexp[IU(c, r, j)])) +
         c->B * X;
   q.nb[0] = uW;
@@ -859,6 +836,53 @@ ora_ctx *ora_create(const ora_setup *s) {
   c->dy = dalloc(ny);
   memcpy(c->dx, s->dx, sizeof(double) * nx);
   memcpy(c->dy, s->dy, sizeof(double) * ny);
+  /* geometric factors; the faces on a non-periodic edge take the edge
+     width twice (they are never used by an interior formula) */
+  c->idx = dalloc(nx);
+  c->ihx = dalloc(nx);
+  c->idy = dalloc(ny);
+  c->ihy = dalloc(ny);
+  c->sx = dalloc(nx + 1);
+  c->wlx = dalloc(nx + 1);
+  c->wrx = dalloc(nx + 1);
+  c->icx = dalloc(nx + 1);
+  c->isx = dalloc(nx + 1);
+  c->sy = dalloc(ny + 1);
+  c->wly = dalloc(ny + 1);
+  c->wry = dalloc(ny + 1);
+  c->icy = dalloc(ny + 1);
+  c->isy = dalloc(ny + 1);
+  for (int i = 0; i < nx; i++) {
+    c->idx[i] = 1.0 / c->dx[i];
+    c->ihx[i] = 1.0 / (0.5 * c->dx[i]);
+  }
+  for (int j = 0; j < ny; j++) {
+    c->idy[j] = 1.0 / c->dy[j];
+    c->ihy[j] = 1.0 / (0.5 * c->dy[j]);
+  }
+  for (int k = 0; k <= nx; k++) {
+    int l = k - 1, r = k;
+    if (c->per) {
+      l = cw(c, l);
+      r = cw(c, r);
+    } else {
+      if (l < 0) l = 0;
+      if (r > nx - 1) r = nx - 1;
+    }
+    c->sx[k] = c->dx[l] + c->dx[r];
+    c->wlx[k] = c->dx[r] / c->sx[k];
+    c->wrx[k] = c->dx[l] / c->sx[k];
+    c->icx[k] = 1.0 / (0.5 * c->sx[k]);
+    c->isx[k] = 1.0 / c->sx[k];
+  }
+  for (int k = 0; k <= ny; k++) {
+    int l = k - 1 < 0 ? 0 : k - 1, r = k > ny - 1 ? ny - 1 : k;
+    c->sy[k] = c->dy[l] + c->dy[r];
+    c->wly[k] = c->dy[r] / c->sy[k];
+    c->wry[k] = c->dy[l] / c->sy[k];
+    c->icy[k] = 1.0 / (0.5 * c->sy[k]);
+    c->isy[k] = 1.0 / c->sy[k];
+  }
   c->solid = (unsigned char *)calloc((size_t)nx * ny, 1);
   for (int k = 0; k < s->n_obst; k++)
     for (int j = s->oj0[k]; j <= s->oj1[k]; j++)
@@ -929,6 +953,9 @@ ora_ctx *ora_create(const ora_setup *s) {
 
 void ora_destroy(ora_ctx *c) {
   if (!c) return;
+  double *geo[] = {c->idx, c->ihx, c->idy, c->ihy, c->sx, c->wlx, c->wrx,
+                   c->icx, c->isx, c->sy, c->wly, c->wry, c->icy, c->isy};
+  for (size_t k = 0; k < sizeof(geo) / sizeof(geo[0]); k++) free(geo[k]);
   double *bufs[] = {c->dx,  c->dy,   c->u_in, c->T_in, c->wT[0], c->wT[1],
                     c->u,   c->un,   c->um,   c->v,    c->vn,    c->vm,
                     c->p,   c->pn,   c->pm,   c->T,    c->Tn,    c->Tm,
@@ -1144,7 +1171,7 @@ static void pass(ora_ctx *c, double dt, int scheme) {
       double GE = c->rhou[ke] * c->un[ke] * dyj;
       double GS = c->rhov[ks] * c->vn[ks] * dxi;
       double GN = c->rhov[kn] * c->vn[kn] * dxi;
-      double R = (c->pn[k] / c->Tn[k] * dV - c->pm[k] / c->Tm[k] * dV) / dt +
+      double R = (c->pn[k] / c->Tn[k] * dV - c->pm[k] / c->Tm[k] * dV) * c->idt +
                  (GE - GW) + (GN - GS);
       rm = dmax(rm, fabs(R));
       sm += R;
@@ -1176,6 +1203,7 @@ static void pass(ora_ctx *c, double dt, int scheme) {
 }
 
 void ora_step(ora_ctx *c, double dt, int n_inner, int scheme) {
+  c->idt = 1.0 / dt;
   prologue(c, scheme);
   for (int k = 0; k < n_inner; k++) pass(c, dt, scheme);
 }
@@ -1183,6 +1211,7 @@ void ora_step(ora_ctx *c, double dt, int n_inner, int scheme) {
 void ora_eq_residuals(ora_ctx *c, double dt, int scheme, double *rT,
                       double *ru, double *rv, double *rp) {
   const int nx = c->nx, ny = c->ny;
+  c->idt = 1.0 / dt;
   prologue(c, scheme);
   cell_props(c, c->p, c->T);
   face_fluxes(c, c->u, c->v, scheme & ORA_TVD);

@@ -64,7 +64,7 @@ Sizes make_sizes(int nx, int ny, const Layout &L) {
   S.mask = L.mask_bytes;
   // 1-D boundary arrays (see ctx_build), tile flags
   const size_t tiles = (size_t)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
-  S.small = align_up(sizeof(double) * ((size_t)2 * (nx + 2 * XPAD) + 2 * (ny + 2 * XPAD) +
+  S.small = align_up(sizeof(double) * ((size_t)6 * (nx + 2 * XPAD) + 6 * (ny + 2 * XPAD) +
                                         4 * (size_t)ny + 4 * (size_t)nx + 2 * (size_t)(nx + 1)),
                      256) +
             align_up(tiles, 256);
@@ -261,15 +261,27 @@ sts_status build(sts_ctx *c, const sts_bc *bc) {
     hs.insert(hs.end(), a.begin(), a.end());
     return at;
   };
-  std::vector<double> dxp(nx + 2 * XPAD), dyp(ny + 2 * XPAD);
-  for (int i = -XPAD; i < nx + XPAD; i++) {
-    int k = c->per ? ((i % nx) + nx) % nx : (i < 0 ? 0 : (i >= nx ? nx - 1 : i));
-    dxp[i + XPAD] = c->dx[k];
-  }
-  for (int j = -XPAD; j < ny + XPAD; j++) {
-    int k = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
-    dyp[j + XPAD] = c->dy[k];
-  }
+  // geometry factors (see Params): widths and inverse widths per column,
+  // width sums, their inverses and interpolation weights per face
+  auto geometry = [](const std::vector<double> &d, int n, bool per,
+                     std::vector<double> out[6]) {
+    auto idx = [&](int i) {
+      return per ? ((i % n) + n) % n : (i < 0 ? 0 : (i >= n ? n - 1 : i));
+    };
+    for (int q = 0; q < 6; q++) out[q].resize(n + 2 * XPAD);
+    for (int i = -XPAD; i < n + XPAD; i++) {
+      const double w = d[idx(i)], wl = d[idx(i - 1)], sum = wl + w;
+      out[0][i + XPAD] = w;
+      out[1][i + XPAD] = 1.0 / w;
+      out[2][i + XPAD] = sum;
+      out[3][i + XPAD] = 1.0 / sum;
+      out[4][i + XPAD] = w / sum;
+      out[5][i + XPAD] = wl / sum;
+    }
+  };
+  std::vector<double> gxv[6], gyv[6];
+  geometry(c->dx, nx, c->per != 0, gxv);
+  geometry(c->dy, ny, false, gyv);
   std::vector<double> sqTin(ny), rhoin(ny), sqTw0(nx), sqTw1(nx), sqTwu0(nx + 1), sqTwu1(nx + 1);
   for (int j = 0; j < ny; j++) {
     sqTin[j] = sqrt(c->T_in[j]);
@@ -285,16 +297,22 @@ sts_status build(sts_ctx *c, const sts_bc *bc) {
     int l = i - 1, r = i;
     if (c->per) { l = (l + nx) % nx; r = r % nx; }
     else { if (l < 0) l = 0; if (r > nx - 1) r = nx - 1; }
-    const double dl = c->dx[l], dr = c->dx[r];
-    sqTwu0[i] = sqrt((dr * c->Tw[0][l] + dl * c->Tw[0][r]) / (dl + dr));
-    sqTwu1[i] = sqrt((dr * c->Tw[1][l] + dl * c->Tw[1][r]) / (dl + dr));
+    const double wl = gxv[4][i + XPAD], wr = gxv[5][i + XPAD];
+    sqTwu0[i] = sqrt(wl * c->Tw[0][l] + wr * c->Tw[0][r]);
+    sqTwu1[i] = sqrt(wl * c->Tw[1][l] + wr * c->Tw[1][r]);
   }
-  size_t o_dx = put(dxp), o_dy = put(dyp), o_uin = put(c->u_in), o_tin = put(c->T_in),
+  size_t o_gx[6], o_gy[6];
+  for (int q = 0; q < 6; q++) o_gx[q] = put(gxv[q]);
+  for (int q = 0; q < 6; q++) o_gy[q] = put(gyv[q]);
+  size_t o_uin = put(c->u_in), o_tin = put(c->T_in),
          o_sqtin = put(sqTin), o_rhoin = put(rhoin), o_tw0 = put(c->Tw[0]), o_tw1 = put(c->Tw[1]),
          o_sqtw0 = put(sqTw0), o_sqtw1 = put(sqTw1), o_sqtwu0 = put(sqTwu0), o_sqtwu1 = put(sqTwu1);
   HIPCHK(hipMemcpyAsync(small, hs.data(), hs.size() * 8, hipMemcpyHostToDevice, c->stream));
   const double *sd = (const double *)small;
-  P.dxp = sd + o_dx; P.dyp = sd + o_dy;
+  for (int q = 0; q < 6; q++) {
+    P.gx_[q] = sd + o_gx[q];
+    P.gy_[q] = sd + o_gy[q];
+  }
   P.u_in = sd + o_uin; P.T_in = sd + o_tin; P.sq_T_in = sd + o_sqtin; P.rho_in = sd + o_rhoin;
   P.Tw0 = sd + o_tw0; P.Tw1 = sd + o_tw1; P.sq_Tw0 = sd + o_sqtw0; P.sq_Tw1 = sd + o_sqtw1;
   P.sq_Twu0 = sd + o_sqtwu0; P.sq_Twu1 = sd + o_sqtwu1;
@@ -493,6 +511,7 @@ extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
   if (n_inner < 1) return fail(STS_EINVAL, "n_inner must be >= 1");
   if (scheme & ~STS_SCHEME_MASK) return fail(STS_EINVAL, "unknown scheme bits 0x%x", scheme);
   c->P.dt = dt;
+  c->P.idt = 1.0 / dt;
   sts_status s;
   if ((s = record(c, 0)) != STS_OK) return s;
   launch_prologue(c->P, c->st[c->cur], c->C, scheme, c->stream);

@@ -34,10 +34,14 @@ struct Params {
   int tiles_x, tiles_y;
   long pitch;  // doubles per row
   long off;    // element index of (0,0)
-  double dt, A, B, C1, C2, C3, gx, gy, obsT, sq_obsT;
+  double dt, idt, A, B, C1, C2, C3, gx, gy, obsT, sq_obsT;
   int wtype0, wtype1;
   double wu0, wu1;
-  const double *dxp, *dyp;                 // widths, index + XPAD
+  // geometry per column i (index i + XPAD, wrapped or clamped outside the
+  // domain): [0] dx_i, [1] 1/dx_i; per x-face i (between cells i-1 and i):
+  // [2] s = dx_{i-1} + dx_i, [3] 1/s, [4] dx_i/s (weight of cell i-1),
+  // [5] dx_{i-1}/s (weight of cell i).  The same in y.
+  const double *gx_[6], *gy_[6];
   const double *u_in, *T_in, *sq_T_in, *rho_in;  // [ny]
   const double *Tw0, *Tw1, *sq_Tw0, *sq_Tw1;     // [nx] per cell column
   const double *sq_Twu0, *sq_Twu1;               // [nx+1] at u-face x

@@ -26,22 +26,22 @@ namespace {
 // elementary functions (Sec. 3.2)
 // ---------------------------------------------------------------------------
 // van Leer limiter psi(r) = (r+|r|)/(1+|r|) of r = a/b; 0 for r <= 0 and
-// when r is undefined (b == 0), 2 when a/b overflows.
+// when r is undefined (b == 0).
 __device__ __forceinline__ double vanleer(double a, double b) {
   if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return 0.0;
-  const double r = a / b;
-  if (isinf(r)) return 2.0;
-  return (r + fabs(r)) / (1.0 + fabs(r));
+  return 2.0 * a / (a + b);  // 2r/(1+r) for r = a/b > 0
 }
 // max(a, b) as a > b ? a : b (the sign of a zero result is that of b)
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
-// TVD correction at a surface between nodes (eq pl15_2)
-__device__ __forceinline__ double psi_s(double f1, double f2, double f3,
-                                        double f4, double d1, double d2,
-                                        double d3, double d4, double vel) {
-  if (vel > 0.0)
-    return d2 / (d2 + d3) * vanleer((d2 + d3) * (f2 - f1), (d1 + d2) * (f3 - f2));
-  return -d3 / (d2 + d3) * vanleer((d2 + d3) * (f4 - f3), (d3 + d4) * (f3 - f2));
+// TVD correction at a surface between nodes (eq pl15_2), written with the
+// factors of the face between nodes 2 and 3: s12 = d1+d2, s23 = d2+d3,
+// s34 = d3+d4, w2 = d2/s23, w3 = d3/s23
+__device__ __forceinline__ double psi_sf(double f1, double f2, double f3,
+                                         double f4, double s12, double s23,
+                                         double s34, double w2, double w3,
+                                         double vel) {
+  if (vel > 0.0) return w2 * vanleer(s23 * (f2 - f1), s12 * (f3 - f2));
+  return -w3 * vanleer(s23 * (f4 - f3), s34 * (f3 - f2));
 }
 // TVD correction at a control-volume centre (eq pl15_1)
 __device__ __forceinline__ double psi_c(double f1, double f2, double f3,
@@ -76,9 +76,12 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 struct Lds {
   double u[LH][LW], v[LH][LW], p[LH][LW], T[LH][LW], r[LH][LW], g[LH][LW];
   double ru[LH][LW], rv[LH][LW];  // face densities rho^u, rho^v
-  double Tn[BY][BX], pn[BY][BX], uh[BY][BX], du[BY][BX], vh[BY][BX],
-      dv[BY][BX];
-  double dx[LW], dy[LH];
+  double pn[BY][BX], uh[BY][BX], du[BY][BX], vh[BY][BX], dv[BY][BX];
+  // geometry of the window: cell widths and their inverses; for the face
+  // on the low side of each column/row: sum of the two adjacent widths,
+  // its inverse, and the interpolation weights of the low and high cell
+  double dx[LW], idx[LW], sx[LW], isx[LW], wlx[LW], wrx[LW];
+  double dy[LH], idy[LH], sy[LH], isy[LH], wly[LH], wry[LH];
   unsigned char fl[LH][LW];
 };
 
@@ -94,7 +97,21 @@ struct Lds {
 #define FL_(i, j) s.fl[(j) + HB][(i) + HB]
 #define DX_(i) s.dx[(i) + HB]
 #define DY_(j) s.dy[(j) + HB]
-#define TN_(i, j) s.Tn[(j) + 1][(i) + 1]
+#define IDX_(i) s.idx[(i) + HB]
+#define IDY_(j) s.idy[(j) + HB]
+#define SX_(k) s.sx[(k) + HB]
+#define SY_(k) s.sy[(k) + HB]
+#define ISX_(k) s.isx[(k) + HB]
+#define ISY_(k) s.isy[(k) + HB]
+#define WLX_(k) s.wlx[(k) + HB]
+#define WRX_(k) s.wrx[(k) + HB]
+#define WLY_(k) s.wly[(k) + HB]
+#define WRY_(k) s.wry[(k) + HB]
+// psi_s at the x-face k (stencil cells k-2..k+1) and at the y-face k
+#define PSIX(f1, f2, f3, f4, k, vel) \
+  psi_sf(f1, f2, f3, f4, SX_((k)-1), SX_(k), SX_((k) + 1), WRX_(k), WLX_(k), vel)
+#define PSIY(f1, f2, f3, f4, k, vel) \
+  psi_sf(f1, f2, f3, f4, SY_((k)-1), SY_(k), SY_((k) + 1), WRY_(k), WLY_(k), vel)
 #define PN_(i, j) s.pn[(j) + 1][(i) + 1]
 #define UH_(i, j) s.uh[(j) + 1][(i) + 1]
 #define DU_(i, j) s.du[(j) + 1][(i) + 1]
@@ -132,11 +149,22 @@ __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
   for (int k = threadIdx.x; k < LW + LH; k += NT) {
     if (k < LW) {
       const int gi = x0 - HB + k;
-      const int ci = P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD - 1);
-      s.dx[k] = P.dxp[ci + XPAD];
+      const int ci = (P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD - 1)) + XPAD;
+      s.dx[k] = P.gx_[0][ci];
+      s.idx[k] = P.gx_[1][ci];
+      s.sx[k] = P.gx_[2][ci];
+      s.isx[k] = P.gx_[3][ci];
+      s.wlx[k] = P.gx_[4][ci];
+      s.wrx[k] = P.gx_[5][ci];
     } else {
-      const int gj = y0 - HB + (k - LW);
-      s.dy[k - LW] = P.dyp[clampi(gj, -XPAD, P.ny + XPAD - 1) + XPAD];
+      const int b = k - LW;
+      const int cj = clampi(y0 - HB + b, -XPAD, P.ny + XPAD - 1) + XPAD;
+      s.dy[b] = P.gy_[0][cj];
+      s.idy[b] = P.gy_[1][cj];
+      s.sy[b] = P.gy_[2][cj];
+      s.isy[b] = P.gy_[3][cj];
+      s.wly[b] = P.gy_[4][cj];
+      s.wry[b] = P.gy_[5][cj];
     }
   }
 }
@@ -155,9 +183,7 @@ __device__ double rho_xface(const Lds &s, const Params &P, int i, int j,
   const double rl = R_(i - 1, j), rr = R_(i, j);
   double r = upw(rl, rr, uf);
   if (TV && (CL || (FL_(i - 2, j) & FL_(i - 1, j) & FL_(i, j) & FL_(i + 1, j))))
-    r += psi_s(R_(i - 2, j), rl, rr, R_(i + 1, j), DX_(i - 2), DX_(i - 1),
-               DX_(i), DX_(i + 1), uf) *
-         (rr - rl);
+    r += PSIX(R_(i - 2, j), rl, rr, R_(i + 1, j), i, uf) * (rr - rl);
   return r;
 }
 template <bool CL, bool TV>
@@ -171,9 +197,7 @@ __device__ double rho_yface(const Lds &s, const Params &P, int i, int j,
   const double rs = R_(i, j - 1), rn = R_(i, j);
   double r = upw(rs, rn, vf);
   if (TV && (CL || (FL_(i, j - 2) & FL_(i, j - 1) & FL_(i, j) & FL_(i, j + 1))))
-    r += psi_s(R_(i, j - 2), rs, rn, R_(i, j + 1), DY_(j - 2), DY_(j - 1),
-               DY_(j), DY_(j + 1), vf) *
-         (rn - rs);
+    r += PSIY(R_(i, j - 2), rs, rn, R_(i, j + 1), j, vf) * (rn - rs);
   return r;
 }
 
@@ -184,14 +208,12 @@ template <bool CL>
 __device__ double gam_c(const Lds &s, const Params &P, int i, int j, int gi,
                         int gj) {
   if (!CL && (gj <= 0 || gj >= P.ny)) return 0.0;
-  const double dys = DY_(j - 1), dyn = DY_(j);
-  const double ws = dyn / (dys + dyn), wn = dys / (dys + dyn);
+  const double ws = WLY_(j), wn = WRY_(j);
   if (!CL && !P.per) {
     if (gi == 0) return ws * P.sq_T_in[gj - 1] + wn * P.sq_T_in[gj];
     if (gi == P.nx) return ws * G_(i - 1, j - 1) + wn * G_(i - 1, j);
   }
-  const double dl = DX_(i - 1), dr = DX_(i);
-  const double wl = dr / (dl + dr), wr = dl / (dl + dr);
+  const double wl = WLX_(i), wr = WRX_(i);
   return ws * (wl * G_(i - 1, j - 1) + wr * G_(i, j - 1)) +
          wn * (wl * G_(i - 1, j) + wr * G_(i, j));
 }
@@ -207,15 +229,13 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   double nW, nE, nS, nN, DW, DE, DS, DN;
   if (!CL && !P.per && gi == 0) {  // inlet: T_in on the face
     nW = P.T_in[gj];
-    DW = P.C1 * hmean2(gP, P.sq_T_in[gj]) * dyj / (0.5 * dxi);
+    DW = P.C1 * hmean2(gP, P.sq_T_in[gj]) * dyj * (2.0 * IDX_(i));
   } else {
     nW = T_(i - 1, j);
     if (!CL && !FL_(i - 1, j))
-      DW = P.C1 * hmean2(gP, P.sq_obsT) * dyj / (0.5 * dxi);
-    else {
-      const double dl = DX_(i - 1);
-      DW = P.C1 * hmean(dl, G_(i - 1, j), dxi, gP) * dyj / (0.5 * (dxi + dl));
-    }
+      DW = P.C1 * hmean2(gP, P.sq_obsT) * dyj * (2.0 * IDX_(i));
+    else
+      DW = P.C1 * hmean(DX_(i - 1), G_(i - 1, j), dxi, gP) * dyj * (2.0 * ISX_(i));
   }
   if (!CL && !P.per && gi == P.nx - 1) {  // outlet: zero gradient
     nE = TP;
@@ -223,16 +243,14 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   } else {
     nE = T_(i + 1, j);
     if (!CL && !FL_(i + 1, j))
-      DE = P.C1 * hmean2(gP, P.sq_obsT) * dyj / (0.5 * dxi);
-    else {
-      const double dr = DX_(i + 1);
-      DE = P.C1 * hmean(dxi, gP, dr, G_(i + 1, j)) * dyj / (0.5 * (dxi + dr));
-    }
+      DE = P.C1 * hmean2(gP, P.sq_obsT) * dyj * (2.0 * IDX_(i));
+    else
+      DE = P.C1 * hmean(dxi, gP, DX_(i + 1), G_(i + 1, j)) * dyj * (2.0 * ISX_(i + 1));
   }
   if (!CL && gj == 0) {
     if (P.wtype0 == 0) {
       nS = P.Tw0[gi];
-      DS = P.C1 * hmean2(gP, P.sq_Tw0[gi]) * dxi / (0.5 * dyj);
+      DS = P.C1 * hmean2(gP, P.sq_Tw0[gi]) * dxi * (2.0 * IDY_(j));
     } else {
       nS = TP;
       DS = 0.0;
@@ -240,16 +258,14 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   } else {
     nS = T_(i, j - 1);
     if (!CL && !FL_(i, j - 1))
-      DS = P.C1 * hmean2(gP, P.sq_obsT) * dxi / (0.5 * dyj);
-    else {
-      const double ds = DY_(j - 1);
-      DS = P.C1 * hmean(ds, G_(i, j - 1), dyj, gP) * dxi / (0.5 * (dyj + ds));
-    }
+      DS = P.C1 * hmean2(gP, P.sq_obsT) * dxi * (2.0 * IDY_(j));
+    else
+      DS = P.C1 * hmean(DY_(j - 1), G_(i, j - 1), dyj, gP) * dxi * (2.0 * ISY_(j));
   }
   if (!CL && gj == P.ny - 1) {
     if (P.wtype1 == 0) {
       nN = P.Tw1[gi];
-      DN = P.C1 * hmean2(gP, P.sq_Tw1[gi]) * dxi / (0.5 * dyj);
+      DN = P.C1 * hmean2(gP, P.sq_Tw1[gi]) * dxi * (2.0 * IDY_(j));
     } else {
       nN = TP;
       DN = 0.0;
@@ -257,11 +273,9 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   } else {
     nN = T_(i, j + 1);
     if (!CL && !FL_(i, j + 1))
-      DN = P.C1 * hmean2(gP, P.sq_obsT) * dxi / (0.5 * dyj);
-    else {
-      const double dn = DY_(j + 1);
-      DN = P.C1 * hmean(dyj, gP, dn, G_(i, j + 1)) * dxi / (0.5 * (dyj + dn));
-    }
+      DN = P.C1 * hmean2(gP, P.sq_obsT) * dxi * (2.0 * IDY_(j));
+    else
+      DN = P.C1 * hmean(dyj, gP, DY_(j + 1), G_(i, j + 1)) * dxi * (2.0 * ISY_(j + 1));
   }
   double aW, aE, aS, aN, a0;
   if (IM) {
@@ -271,17 +285,13 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
     double pW = 0.0, pE = 0.0, pS = 0.0, pN = 0.0;
     if (TV) {
       if (CL || (FL_(i - 2, j) & FL_(i - 1, j) & FL_(i + 1, j)))
-        pW = psi_s(T_(i - 2, j), T_(i - 1, j), TP, T_(i + 1, j), DX_(i - 2),
-                   DX_(i - 1), dxi, DX_(i + 1), uW);
+        pW = PSIX(T_(i - 2, j), T_(i - 1, j), TP, T_(i + 1, j), i, uW);
       if (CL || (FL_(i - 1, j) & FL_(i + 1, j) & FL_(i + 2, j)))
-        pE = psi_s(T_(i - 1, j), TP, T_(i + 1, j), T_(i + 2, j), DX_(i - 1),
-                   dxi, DX_(i + 1), DX_(i + 2), uE);
+        pE = PSIX(T_(i - 1, j), TP, T_(i + 1, j), T_(i + 2, j), i + 1, uE);
       if (CL || (FL_(i, j - 2) & FL_(i, j - 1) & FL_(i, j + 1)))
-        pS = psi_s(T_(i, j - 2), T_(i, j - 1), TP, T_(i, j + 1), DY_(j - 2),
-                   DY_(j - 1), dyj, DY_(j + 1), vS);
+        pS = PSIY(T_(i, j - 2), T_(i, j - 1), TP, T_(i, j + 1), j, vS);
       if (CL || (FL_(i, j - 1) & FL_(i, j + 1) & FL_(i, j + 2)))
-        pN = psi_s(T_(i, j - 1), TP, T_(i, j + 1), T_(i, j + 2), DY_(j - 1),
-                   dyj, DY_(j + 1), DY_(j + 2), vN);
+        pN = PSIY(T_(i, j - 1), TP, T_(i, j + 1), T_(i, j + 2), j + 1, vN);
     }
     aW = dmax(0.0, FW) - FW * pW + DW;
     aE = dmax(0.0, -FE) - FE * pE + DE;
@@ -302,35 +312,23 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   double vE, vW, uN, uS;
   if (!CL && !P.per && gi == P.nx - 1) vE = vc;
   else if (!CL && !FL_(i + 1, j)) vE = 0.0;
-  else {
-    const double dr = DX_(i + 1);
-    vE = dr / (dxi + dr) * vc +
-         dxi / (dxi + dr) * (0.5 * (V_(i + 1, j) + V_(i + 1, j + 1)));
-  }
+  else
+    vE = WLX_(i + 1) * vc + WRX_(i + 1) * (0.5 * (V_(i + 1, j) + V_(i + 1, j + 1)));
   if (!CL && !P.per && gi == 0) vW = 0.0;
   else if (!CL && !FL_(i - 1, j)) vW = 0.0;
-  else {
-    const double dl = DX_(i - 1);
-    vW = dxi / (dl + dxi) * (0.5 * (V_(i - 1, j) + V_(i - 1, j + 1))) +
-         dl / (dl + dxi) * vc;
-  }
+  else
+    vW = WLX_(i) * (0.5 * (V_(i - 1, j) + V_(i - 1, j + 1))) + WRX_(i) * vc;
   if (!CL && gj == P.ny - 1) uN = (P.wtype1 == 0) ? P.wu1 : uc;
   else if (!CL && !FL_(i, j + 1)) uN = 0.0;
-  else {
-    const double dn = DY_(j + 1);
-    uN = dn / (dyj + dn) * uc +
-         dyj / (dyj + dn) * (0.5 * (U_(i, j + 1) + U_(i + 1, j + 1)));
-  }
+  else
+    uN = WLY_(j + 1) * uc + WRY_(j + 1) * (0.5 * (U_(i, j + 1) + U_(i + 1, j + 1)));
   if (!CL && gj == 0) uS = (P.wtype0 == 0) ? P.wu0 : uc;
   else if (!CL && !FL_(i, j - 1)) uS = 0.0;
-  else {
-    const double ds = DY_(j - 1);
-    uS = dyj / (ds + dyj) * (0.5 * (U_(i, j - 1) + U_(i + 1, j - 1))) +
-         ds / (ds + dyj) * uc;
-  }
-  const double ux = (U_(i + 1, j) - U_(i, j)) / dxi;
-  const double vy = (V_(i, j + 1) - V_(i, j)) / dyj;
-  const double vx = (vE - vW) / dxi, uy = (uN - uS) / dyj;
+  else
+    uS = WLY_(j) * (0.5 * (U_(i, j - 1) + U_(i + 1, j - 1))) + WRY_(j) * uc;
+  const double ux = (U_(i + 1, j) - U_(i, j)) * IDX_(i);
+  const double vy = (V_(i, j + 1) - V_(i, j)) * IDY_(j);
+  const double vx = (vE - vW) * IDX_(i), uy = (uN - uS) * IDY_(j);
   const double dv = ux + vy;
   const double Sc =
       P.C2 * gP * (2.0 * (ux * ux + vy * vy) + (vx + uy) * (vx + uy) -
@@ -351,12 +349,12 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   const double uP = U_(i, j), uW = U_(i - 1, j), uE = U_(i + 1, j);
   const double M = (rr * dxr + rl * dxl) * dyj / 2.0;
   const double len = 0.5 * (dxl + dxr);
-  const double gnode = (dxr * gl + dxl * gr) / (dxl + dxr);
+  const double gnode = WLX_(i) * gl + WRX_(i) * gr;
   double uS, uN, DS, DN;
   if (!CL && gj == 0) {
     if (P.wtype0 == 0) {
       uS = P.wu0;
-      DS = P.B * 0.5 * (gnode + P.sq_Twu0[gi]) * len / (0.5 * dyj);
+      DS = P.B * 0.5 * (gnode + P.sq_Twu0[gi]) * len * (2.0 * IDY_(j));
     } else {
       uS = uP;
       DS = 0.0;
@@ -364,14 +362,14 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   } else {
     uS = U_(i, j - 1);
     if (!CL && !FL_(i - 1, j - 1) && !FL_(i, j - 1))
-      DS = P.B * 0.5 * (gnode + P.sq_obsT) * len / (0.5 * dyj);
+      DS = P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDY_(j));
     else
-      DS = P.B * gam_c<CL>(s, P, i, j, gi, gj) * (dxr + dxl) / (dyj + DY_(j - 1));
+      DS = P.B * gam_c<CL>(s, P, i, j, gi, gj) * SX_(i) * ISY_(j);
   }
   if (!CL && gj == P.ny - 1) {
     if (P.wtype1 == 0) {
       uN = P.wu1;
-      DN = P.B * 0.5 * (gnode + P.sq_Twu1[gi]) * len / (0.5 * dyj);
+      DN = P.B * 0.5 * (gnode + P.sq_Twu1[gi]) * len * (2.0 * IDY_(j));
     } else {
       uN = uP;
       DN = 0.0;
@@ -379,12 +377,11 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   } else {
     uN = U_(i, j + 1);
     if (!CL && !FL_(i - 1, j + 1) && !FL_(i, j + 1))
-      DN = P.B * 0.5 * (gnode + P.sq_obsT) * len / (0.5 * dyj);
+      DN = P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDY_(j));
     else
-      DN = P.B * gam_c<CL>(s, P, i, j + 1, gi, gj + 1) * (dxr + dxl) /
-           (dyj + DY_(j + 1));
+      DN = P.B * gam_c<CL>(s, P, i, j + 1, gi, gj + 1) * SX_(i) * ISY_(j + 1);
   }
-  const double DW = P.B * gl * dyj / dxl, DE = P.B * gr * dyj / dxr;
+  const double DW = P.B * gl * dyj * IDX_(i - 1), DE = P.B * gr * dyj * IDX_(i);
   double aS, aN, aW, aE, conv;
   if (IM) {
     const double Fs0 = RV_(i, j) * V_(i, j) * dxr, Fs1 = RV_(i - 1, j) * V_(i - 1, j) * dxl;
@@ -396,13 +393,13 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
     if (TV) {
       if (CL || (gj - 2 >= 0 && gj + 1 <= P.ny - 1)) {
         const double f1 = U_(i, j - 2), f2 = U_(i, j - 1), f4 = U_(i, j + 1);
-        ps0 = psi_s(f1, f2, uP, f4, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), V_(i, j));
-        ps1 = psi_s(f1, f2, uP, f4, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), V_(i - 1, j));
+        ps0 = PSIY(f1, f2, uP, f4, j, V_(i, j));
+        ps1 = PSIY(f1, f2, uP, f4, j, V_(i - 1, j));
       }
       if (CL || (gj - 1 >= 0 && gj + 2 <= P.ny - 1)) {
         const double f1 = U_(i, j - 1), f3 = U_(i, j + 1), f4 = U_(i, j + 2);
-        pn0 = psi_s(f1, uP, f3, f4, DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), V_(i, j + 1));
-        pn1 = psi_s(f1, uP, f3, f4, DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), V_(i - 1, j + 1));
+        pn0 = PSIY(f1, uP, f3, f4, j + 1, V_(i, j + 1));
+        pn1 = PSIY(f1, uP, f3, f4, j + 1, V_(i - 1, j + 1));
       }
       if (CL || P.per || (gi - 2 >= 0 && gi + 1 <= P.nx))
         pw = psi_c(U_(i - 2, j), uW, uP, uE, DX_(i - 2), dxl, dxr, ubW);
@@ -421,7 +418,7 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
     aE = 4.0 / 3.0 * DE;
     conv = 0.0;
   }
-  const double a0 = aS + aN + aW + aE + conv + M / P.dt;
+  const double a0 = aS + aN + aW + aE + conv + M * P.idt;
   const double X = gam_c<CL>(s, P, i, j + 1, gi, gj + 1) * (V_(i, j + 1) - V_(i - 1, j + 1)) -
                    gam_c<CL>(s, P, i, j, gi, gj) * (V_(i, j) - V_(i - 1, j)) -
                    2.0 / 3.0 * gr * (V_(i, j + 1) - V_(i, j)) +
@@ -444,21 +441,21 @@ __device__ void v_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   const double vE = (!CL && !P.per && gi == P.nx - 1) ? vP : V_(i + 1, j);
   const double M = (rn * dyn + rs * dys) * dxi / 2.0;
   const double len = 0.5 * (dys + dyn);
-  const double gnode = (dyn * gs + dys * gn) / (dys + dyn);
+  const double gnode = WLY_(j) * gs + WRY_(j) * gn;
   double DW, DE;
   if (!CL && !P.per && gi == 0)
-    DW = P.B * 0.5 * (gnode + gam_c<CL>(s, P, i, j, gi, gj)) * len / (0.5 * dxi);
+    DW = P.B * 0.5 * (gnode + gam_c<CL>(s, P, i, j, gi, gj)) * len * (2.0 * IDX_(i));
   else if (!CL && !FL_(i - 1, j - 1) && !FL_(i - 1, j))
-    DW = P.B * 0.5 * (gnode + P.sq_obsT) * len / (0.5 * dxi);
+    DW = P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDX_(i));
   else
-    DW = P.B * gam_c<CL>(s, P, i, j, gi, gj) * (dyn + dys) / (dxi + DX_(i - 1));
+    DW = P.B * gam_c<CL>(s, P, i, j, gi, gj) * SY_(j) * ISX_(i);
   if (!CL && !P.per && gi == P.nx - 1)
     DE = 0.0;
   else if (!CL && !FL_(i + 1, j - 1) && !FL_(i + 1, j))
-    DE = P.B * 0.5 * (gnode + P.sq_obsT) * len / (0.5 * dxi);
+    DE = P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDX_(i));
   else
-    DE = P.B * gam_c<CL>(s, P, i + 1, j, gi + 1, gj) * (dyn + dys) / (dxi + DX_(i + 1));
-  const double DS = P.B * gs * dxi / dys, DN = P.B * gn * dxi / dyn;
+    DE = P.B * gam_c<CL>(s, P, i + 1, j, gi + 1, gj) * SY_(j) * ISX_(i + 1);
+  const double DS = P.B * gs * dxi * IDY_(j - 1), DN = P.B * gn * dxi * IDY_(j);
   double aW, aE, aS, aN, conv;
   if (IM) {
     const double Fw0 = RU_(i, j) * U_(i, j) * dyn, Fw1 = RU_(i, j - 1) * U_(i, j - 1) * dys;
@@ -470,13 +467,13 @@ __device__ void v_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
     if (TV) {
       if (CL || P.per || (gi - 2 >= 0 && gi + 1 <= P.nx - 1)) {
         const double f1 = V_(i - 2, j), f4 = V_(i + 1, j);
-        pw0 = psi_s(f1, vW, vP, f4, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), U_(i, j));
-        pw1 = psi_s(f1, vW, vP, f4, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), U_(i, j - 1));
+        pw0 = PSIX(f1, vW, vP, f4, i, U_(i, j));
+        pw1 = PSIX(f1, vW, vP, f4, i, U_(i, j - 1));
       }
       if (CL || P.per || (gi - 1 >= 0 && gi + 2 <= P.nx - 1)) {
         const double f1 = V_(i - 1, j), f4 = V_(i + 2, j);
-        pe0 = psi_s(f1, vP, vE, f4, DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), U_(i + 1, j));
-        pe1 = psi_s(f1, vP, vE, f4, DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), U_(i + 1, j - 1));
+        pe0 = PSIX(f1, vP, vE, f4, i + 1, U_(i + 1, j));
+        pe1 = PSIX(f1, vP, vE, f4, i + 1, U_(i + 1, j - 1));
       }
       if (CL || (gj - 2 >= 0 && gj + 1 <= P.ny))
         ps = psi_c(V_(i, j - 2), vS, vP, vN, DY_(j - 2), dys, dyn, vbS);
@@ -495,7 +492,7 @@ __device__ void v_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
     aN = 4.0 / 3.0 * DN;
     conv = 0.0;
   }
-  const double a0 = aW + aE + aS + aN + conv + M / P.dt;
+  const double a0 = aW + aE + aS + aN + conv + M * P.idt;
   const double X = gam_c<CL>(s, P, i + 1, j, gi + 1, gj) * (U_(i + 1, j) - U_(i + 1, j - 1)) -
                    gam_c<CL>(s, P, i, j, gi, gj) * (U_(i, j) - U_(i, j - 1)) -
                    2.0 / 3.0 * gn * (U_(i + 1, j) - U_(i, j)) +
@@ -541,11 +538,10 @@ __device__ void pass_body(Lds &s, const Params &P, const State o,
   // v-hat, d^v on [-1,TX-1] x [-1,TY]
   const long kc = P.off + (long)clampi(gj, -XPAD, P.ny + XPAD - 1) * P.pitch +
                   (P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD));
-  if (i <= TX - 1 && j <= TY - 1) {
-    double t = T_(i, j);
-    if (FL_(i, j)) t = t_update<CL, IM, TV>(s, P, i, j, gi, gj, C.CT[kc]);
-    TN_(i, j) = t;
-  }
+  // the new T of a cell is read only by the thread that owns the cell
+  double tnew = T_(i, j);
+  if (i <= TX - 1 && j <= TY - 1 && FL_(i, j))
+    tnew = t_update<CL, IM, TV>(s, P, i, j, gi, gj, C.CT[kc]);
   if (j <= TY - 1) {
     double uh = U_(i, j), du = 0.0;
     if (u_solved(s, P, i, j, gi))
@@ -571,7 +567,7 @@ __device__ void pass_body(Lds &s, const Params &P, const State o,
       const double aS = RV_(i, j) * DV_(i, j) * dxi, aN = RV_(i, j + 1) * DV_(i, j + 1) * dxi;
       const double bW = RU_(i, j) * UH_(i, j) * dyj, bE = RU_(i + 1, j) * UH_(i + 1, j) * dyj;
       const double bS = RV_(i, j) * VH_(i, j) * dxi, bN = RV_(i, j + 1) * VH_(i, j + 1) * dxi;
-      const double a0 = dV / TN_(i, j) + (aW + aE + aS + aN) * P.dt;
+      const double a0 = dV / tnew + (aW + aE + aS + aN) * P.dt;
       const double bp = C.Cp[kc] - (bE - bW + bN - bS) * P.dt;
       pnew = ((aW * P_(i - 1, j) + aE * P_(i + 1, j) + aS * P_(i, j - 1) +
                aN * P_(i, j + 1)) * P.dt + bp) / a0;
@@ -583,7 +579,7 @@ __device__ void pass_body(Lds &s, const Params &P, const State o,
   // stage 4: velocities (eqs pl18, pl19); write the owned values
   if (i >= 0 && i < TX && j >= 0 && j < TY && gi < P.nx && gj < P.ny) {
     const long k = P.off + (long)gj * P.pitch + gi;
-    n.T[k] = TN_(i, j);
+    n.T[k] = tnew;
     n.p[k] = PN_(i, j);
     const double un = u_solved(s, P, i, j, gi)
                           ? UH_(i, j) - DU_(i, j) * (PN_(i, j) - PN_(i - 1, j))
@@ -635,13 +631,13 @@ __device__ double t_explicit(const Lds &s, const Params &P, int i, int j,
   double pW = 0.0, pE = 0.0, pS = 0.0, pN = 0.0;
   if (TV) {
     if (CL || (FL_(i - 1, j) & FL_(i + 1, j) & FL_(i + 2, j)))
-      pE = psi_s(T_(i - 1, j), TP, TE, T_(i + 2, j), DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), uE);
+      pE = PSIX(T_(i - 1, j), TP, TE, T_(i + 2, j), i + 1, uE);
     if (CL || (FL_(i - 2, j) & FL_(i - 1, j) & FL_(i + 1, j)))
-      pW = psi_s(T_(i - 2, j), TW, TP, TE, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), uW);
+      pW = PSIX(T_(i - 2, j), TW, TP, TE, i, uW);
     if (CL || (FL_(i, j - 1) & FL_(i, j + 1) & FL_(i, j + 2)))
-      pN = psi_s(T_(i, j - 1), TP, TN, T_(i, j + 2), DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), vN);
+      pN = PSIY(T_(i, j - 1), TP, TN, T_(i, j + 2), j + 1, vN);
     if (CL || (FL_(i, j - 2) & FL_(i, j - 1) & FL_(i, j + 1)))
-      pS = psi_s(T_(i, j - 2), TS, TP, TN, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), vS);
+      pS = PSIY(T_(i, j - 2), TS, TP, TN, j, vS);
   }
   return -FE * (upw(TP, TE, uE) + (TE - TP) * pE) +
          FW * (upw(TW, TP, uW) + (TP - TW) * pW) -
@@ -664,13 +660,13 @@ __device__ double u_explicit(const Lds &s, const Params &P, int i, int j,
   if (TV) {
     if (CL || (gj - 1 >= 0 && gj + 2 <= P.ny - 1)) {
       const double f1 = U_(i, j - 1), f4 = U_(i, j + 2);
-      pn0 = psi_s(f1, uP, uN, f4, DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), vn0);
-      pn1 = psi_s(f1, uP, uN, f4, DY_(j - 1), dyj, DY_(j + 1), DY_(j + 2), vn1);
+      pn0 = PSIY(f1, uP, uN, f4, j + 1, vn0);
+      pn1 = PSIY(f1, uP, uN, f4, j + 1, vn1);
     }
     if (CL || (gj - 2 >= 0 && gj + 1 <= P.ny - 1)) {
       const double f1 = U_(i, j - 2), f4 = U_(i, j + 1);
-      ps0 = psi_s(f1, uS, uP, f4, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), vs0);
-      ps1 = psi_s(f1, uS, uP, f4, DY_(j - 2), DY_(j - 1), dyj, DY_(j + 1), vs1);
+      ps0 = PSIY(f1, uS, uP, f4, j, vs0);
+      ps1 = PSIY(f1, uS, uP, f4, j, vs1);
     }
     if (CL || P.per || (gi - 1 >= 0 && gi + 2 <= P.nx))
       pe = psi_c(uW, uP, uE, U_(i + 2, j), dxl, dxr, DX_(i + 1), ubE);
@@ -702,13 +698,13 @@ __device__ double v_explicit(const Lds &s, const Params &P, int i, int j,
   if (TV) {
     if (CL || P.per || (gi - 1 >= 0 && gi + 2 <= P.nx - 1)) {
       const double f1 = V_(i - 1, j), f4 = V_(i + 2, j);
-      pe0 = psi_s(f1, vP, vE, f4, DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), ue0);
-      pe1 = psi_s(f1, vP, vE, f4, DX_(i - 1), dxi, DX_(i + 1), DX_(i + 2), ue1);
+      pe0 = PSIX(f1, vP, vE, f4, i + 1, ue0);
+      pe1 = PSIX(f1, vP, vE, f4, i + 1, ue1);
     }
     if (CL || P.per || (gi - 2 >= 0 && gi + 1 <= P.nx - 1)) {
       const double f1 = V_(i - 2, j), f4 = V_(i + 1, j);
-      pw0 = psi_s(f1, vW, vP, f4, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), uw0);
-      pw1 = psi_s(f1, vW, vP, f4, DX_(i - 2), DX_(i - 1), dxi, DX_(i + 1), uw1);
+      pw0 = PSIX(f1, vW, vP, f4, i, uw0);
+      pw1 = PSIX(f1, vW, vP, f4, i, uw1);
     }
     if (CL || (gj - 1 >= 0 && gj + 2 <= P.ny))
       pn = psi_c(vS, vP, vN, V_(i, j + 2), dys, dyn, DY_(j + 1), vbN);
@@ -757,12 +753,12 @@ __device__ void prologue_body(Lds &s, const Params &P, const Consts C, int x0,
   double Cu = 0.0, Cv = 0.0;
   if (u_solved(s, P, i, j, gi)) {
     const double M = (R_(i, j) * dxi + R_(i - 1, j) * DX_(i - 1)) * dyj / 2.0;
-    Cu = M / P.dt * U_(i, j) + P.gx * M;
+    Cu = M * P.idt * U_(i, j) + P.gx * M;
     if (EX) Cu += u_explicit<CL, TV>(s, P, i, j, gi, gj);
   }
   if (v_solved(s, P, i, j, gj)) {
     const double M = (R_(i, j) * dyj + R_(i, j - 1) * DY_(j - 1)) * dxi / 2.0;
-    Cv = M / P.dt * V_(i, j) + P.gy * M;
+    Cv = M * P.idt * V_(i, j) + P.gy * M;
     if (EX) Cv += v_explicit<CL, TV>(s, P, i, j, gi, gj);
   }
   C.Cu[k] = Cu;
@@ -803,11 +799,13 @@ __device__ __forceinline__ double grho(const State &o, const Params &P, int i,
   const long k = P.off + (long)j * P.pitch + i;
   return o.p[k] / o.T[k];
 }
-__device__ __forceinline__ double gdx(const Params &P, int i) {
-  return P.dxp[(P.per ? wrapi(i, P.nx) : clampi(i, -XPAD, P.nx + XPAD - 1)) + XPAD];
+// geometry factor q (0 width, 1 inverse width, 2 face sum, 3 its inverse,
+// 4/5 low/high interpolation weight) of column i / row j
+__device__ __forceinline__ double ggx(const Params &P, int q, int i) {
+  return P.gx_[q][(P.per ? wrapi(i, P.nx) : clampi(i, -XPAD, P.nx + XPAD - 1)) + XPAD];
 }
-__device__ __forceinline__ double gdy(const Params &P, int j) {
-  return P.dyp[clampi(j, -XPAD, P.ny + XPAD - 1) + XPAD];
+__device__ __forceinline__ double ggy(const Params &P, int q, int j) {
+  return P.gy_[q][clampi(j, -XPAD, P.ny + XPAD - 1) + XPAD];
 }
 // rho^u at u-face (i, j) of the old iterate (global memory)
 template <bool TV>
@@ -820,8 +818,8 @@ __device__ double grho_x(const State &o, const Params &P, int i, int j) {
   const double rl = grho(o, P, i - 1, j), rr = grho(o, P, i, j);
   double r = upw(rl, rr, uf);
   if (TV && gfl(P, i - 2, j) && gfl(P, i - 1, j) && gfl(P, i, j) && gfl(P, i + 1, j))
-    r += psi_s(grho(o, P, i - 2, j), rl, rr, grho(o, P, i + 1, j), gdx(P, i - 2),
-               gdx(P, i - 1), gdx(P, i), gdx(P, i + 1), uf) *
+    r += psi_sf(grho(o, P, i - 2, j), rl, rr, grho(o, P, i + 1, j), ggx(P, 2, i - 1),
+                ggx(P, 2, i), ggx(P, 2, i + 1), ggx(P, 5, i), ggx(P, 4, i), uf) *
          (rr - rl);
   return r;
 }
@@ -833,8 +831,8 @@ __device__ double grho_y(const State &o, const Params &P, int i, int j) {
   const double rs = grho(o, P, i, j - 1), rn = grho(o, P, i, j);
   double r = upw(rs, rn, vf);
   if (TV && gfl(P, i, j - 2) && gfl(P, i, j - 1) && gfl(P, i, j) && gfl(P, i, j + 1))
-    r += psi_s(grho(o, P, i, j - 2), rs, rn, grho(o, P, i, j + 1), gdy(P, j - 2),
-               gdy(P, j - 1), gdy(P, j), gdy(P, j + 1), vf) *
+    r += psi_sf(grho(o, P, i, j - 2), rs, rn, grho(o, P, i, j + 1), ggy(P, 2, j - 1),
+                ggy(P, 2, j), ggy(P, 2, j + 1), ggy(P, 5, j), ggy(P, 4, j), vf) *
          (rn - rs);
   return r;
 }
@@ -873,13 +871,13 @@ __global__ __launch_bounds__(RB) void k_residual(const Params P, const State o,
       if (!isfinite(pn) || !isfinite(Tn)) bad += 1.0;
       rp = fmax(rp, fabs(pn - o.p[k]));
       rT = fmax(rT, fabs(Tn - o.T[k]));
-      const double dxi = gdx(P, i), dyj = gdy(P, j), dV = dxi * dyj;
+      const double dxi = ggx(P, 0, i), dyj = ggy(P, 0, j), dV = dxi * dyj;
       const int ie = (P.per && i + 1 == P.nx) ? P.nx : i + 1;
       const double GW = grho_x<TV>(o, P, i, j) * un * dyj;
       const double GE = grho_x<TV>(o, P, ie, j) * gld(n.u, P, ie, j) * dyj;
       const double GS = grho_y<TV>(o, P, i, j) * vn * dxi;
       const double GN = grho_y<TV>(o, P, i, j + 1) * gld(n.v, P, i, j + 1) * dxi;
-      const double R = (pn / Tn * dV - C.Cp[k]) / P.dt + (GE - GW) + (GN - GS);
+      const double R = (pn / Tn * dV - C.Cp[k]) * P.idt + (GE - GW) + (GN - GS);
       if (!isfinite(R)) bad += 1.0;
       rm = fmax(rm, fabs(R));
       sm += R;
