@@ -10,9 +10,9 @@ namespace sts {
 // Tiling of the Jacobi pass: a block of BX x BY threads computes T, p,
 // u-hat, v-hat on the owned TX x TY cells plus a one-cell halo, and writes
 // the owned cells / faces.  The LDS window of old fields has a halo of HB.
-constexpr int TX = 30, TY = 6;
+constexpr int TX = 30, TY = 14;
 constexpr int BX = TX + 2, BY = TY + 2;
-constexpr int NT = BX * BY;  // 256 threads
+constexpr int NT = BX * BY;  // 512 threads
 constexpr int HB = 3;
 constexpr int LW = TX + 2 * HB, LH = TY + 2 * HB;
 

@@ -28,8 +28,11 @@ namespace {
 // van Leer limiter psi(r) = (r+|r|)/(1+|r|) of r = a/b; 0 for r <= 0 and
 // when r is undefined (b == 0).
 __device__ __forceinline__ double vanleer(double a, double b) {
-  if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return 0.0;
-  return 2.0 * a / (a + b);  // 2r/(1+r) for r = a/b > 0
+  // branch-free: the quotient is formed in every lane and discarded where
+  // r <= 0 (2r/(1+r) = 2a/(a+b) for r = a/b > 0)
+  const bool pos = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);
+  const double q = 2.0 * a / (a + b);
+  return pos ? q : 0.0;
 }
 // max(a, b) as a > b ? a : b (the sign of a zero result is that of b)
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
@@ -40,15 +43,22 @@ __device__ __forceinline__ double psi_sf(double f1, double f2, double f3,
                                          double f4, double s12, double s23,
                                          double s34, double w2, double w3,
                                          double vel) {
-  if (vel > 0.0) return w2 * vanleer(s23 * (f2 - f1), s12 * (f3 - f2));
-  return -w3 * vanleer(s23 * (f4 - f3), s34 * (f3 - f2));
+  // the two flow directions differ only in their operands: select them,
+  // then evaluate the limiter once (no divergent branch)
+  const bool up = vel > 0.0;
+  const double a = s23 * (up ? f2 - f1 : f4 - f3);
+  const double b = (up ? s12 : s34) * (f3 - f2);
+  const double w = up ? w2 : -w3;
+  return w * vanleer(a, b);
 }
 // TVD correction at a control-volume centre (eq pl15_1)
 __device__ __forceinline__ double psi_c(double f1, double f2, double f3,
                                         double f4, double d1, double d2,
                                         double d3, double vel) {
-  if (vel > 0.0) return 0.5 * vanleer(d2 * (f2 - f1), d1 * (f3 - f2));
-  return -0.5 * vanleer(d2 * (f4 - f3), d3 * (f3 - f2));
+  const bool up = vel > 0.0;
+  const double a = d2 * (up ? f2 - f1 : f4 - f3);
+  const double b = (up ? d1 : d3) * (f3 - f2);
+  return (up ? 0.5 : -0.5) * vanleer(a, b);
 }
 __device__ __forceinline__ double upw(double f1, double f2, double vel) {
   return vel > 0.0 ? f1 : f2;  // eq pl15_12
@@ -83,6 +93,9 @@ struct Lds {
   double dx[LW], idx[LW], sx[LW], isx[LW], wlx[LW], wrx[LW];
   double dy[LH], idy[LH], sy[LH], isy[LH], wly[LH], wry[LH];
   unsigned char fl[LH][LW];
+  // global column of every window column (cells, u-faces: wrapped when
+  // periodic, clamped into the frame otherwise) and row (cells, v-faces)
+  int ci[LW], ui[LW], cj[LH], vj[LH];
 };
 
 // tile-relative accessors: (i, j) with the tile origin at (0, 0)
@@ -129,27 +142,39 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 // Stage the old fields of the window [x0-3, x0+TX+2] x [y0-3, y0+TY+2].
 __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
                             int y0) {
+  const int t = threadIdx.x;
+  if (t < LW) {
+    const int gi = x0 - HB + t;
+    if (P.per) {
+      const int w = wrapi(gi, P.nx);
+      s.ci[t] = w;
+      s.ui[t] = w;
+    } else {
+      s.ci[t] = clampi(gi, -XPAD, P.nx + XPAD - 1);
+      s.ui[t] = clampi(gi, -XPAD, P.nx + XPAD);
+    }
+  } else if (t < LW + LH) {
+    const int gj = y0 - HB + (t - LW);
+    s.cj[t - LW] = clampi(gj, -XPAD, P.ny + XPAD - 1);
+    s.vj[t - LW] = clampi(gj, -XPAD, P.ny + XPAD);
+  }
+  __syncthreads();
   for (int k = threadIdx.x; k < LH * LW; k += NT) {
     const int a = k % LW, b = k / LW;
-    const int gi = x0 - HB + a, gj = y0 - HB + b;
-    const int ci = P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD - 1);
-    const int ui = P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD);
-    const int cj = clampi(gj, -XPAD, P.ny + XPAD - 1);
-    const int vj = clampi(gj, -XPAD, P.ny + XPAD);
-    const long kc = P.off + (long)cj * P.pitch + ci;
+    const long rc = P.off + (long)s.cj[b] * P.pitch;
+    const long kc = rc + s.ci[a];
     const double pp = o.p[kc], tt = o.T[kc];
     s.p[b][a] = pp;
     s.T[b][a] = tt;
     s.r[b][a] = pp / tt;
     s.g[b][a] = sqrt(tt);
     s.fl[b][a] = P.fl[kc];
-    s.u[b][a] = o.u[P.off + (long)cj * P.pitch + ui];
-    s.v[b][a] = o.v[P.off + (long)vj * P.pitch + ci];
+    s.u[b][a] = o.u[rc + s.ui[a]];
+    s.v[b][a] = o.v[P.off + (long)s.vj[b] * P.pitch + s.ci[a]];
   }
   for (int k = threadIdx.x; k < LW + LH; k += NT) {
     if (k < LW) {
-      const int gi = x0 - HB + k;
-      const int ci = (P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD - 1)) + XPAD;
+      const int ci = s.ci[k] + XPAD;
       s.dx[k] = P.gx_[0][ci];
       s.idx[k] = P.gx_[1][ci];
       s.sx[k] = P.gx_[2][ci];
@@ -158,7 +183,7 @@ __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
       s.wrx[k] = P.gx_[5][ci];
     } else {
       const int b = k - LW;
-      const int cj = clampi(y0 - HB + b, -XPAD, P.ny + XPAD - 1) + XPAD;
+      const int cj = s.cj[b] + XPAD;
       s.dy[b] = P.gy_[0][cj];
       s.idy[b] = P.gy_[1][cj];
       s.sy[b] = P.gy_[2][cj];
@@ -523,21 +548,22 @@ __device__ void pass_body(Lds &s, const Params &P, const State o,
   const int gi = x0 + i, gj = y0 + j;
 
   // stage 1: face densities rho^u on [-1,TX] x [-2,TY], rho^v on
-  // [-2,TX] x [-1,TY]
-  for (int k = threadIdx.x; k < BX * (BY + 1); k += NT) {
-    const int fi = k % BX - 1, fj = k / BX - 2;
-    RU_(fi, fj) = rho_xface<CL, TV>(s, P, fi, fj, x0 + fi, y0 + fj);
-  }
-  for (int k = threadIdx.x; k < (BX + 1) * BY; k += NT) {
-    const int fi = k % (BX + 1) - 2, fj = k / (BX + 1) - 1;
-    RV_(fi, fj) = rho_yface<CL, TV>(s, P, fi, fj, y0 + fj);
+  // [-2,TX] x [-1,TY] (one combined loop)
+  for (int k = threadIdx.x; k < BX * (BY + 1) + (BX + 1) * BY; k += NT) {
+    if (k < BX * (BY + 1)) {
+      const int fi = k % BX - 1, fj = k / BX - 2;
+      RU_(fi, fj) = rho_xface<CL, TV>(s, P, fi, fj, x0 + fi, y0 + fj);
+    } else {
+      const int q = k - BX * (BY + 1);
+      const int fi = q % (BX + 1) - 2, fj = q / (BX + 1) - 1;
+      RV_(fi, fj) = rho_yface<CL, TV>(s, P, fi, fj, y0 + fj);
+    }
   }
   __syncthreads();
 
   // stage 2: T on [-1,TX-1] x [-1,TY-1]; u-hat, d^u on [-1,TX] x [-1,TY-1];
   // v-hat, d^v on [-1,TX-1] x [-1,TY]
-  const long kc = P.off + (long)clampi(gj, -XPAD, P.ny + XPAD - 1) * P.pitch +
-                  (P.per ? wrapi(gi, P.nx) : clampi(gi, -XPAD, P.nx + XPAD));
+  const long kc = P.off + (long)s.cj[j + HB] * P.pitch + s.ui[i + HB];
   // the new T of a cell is read only by the thread that owns the cell
   double tnew = T_(i, j);
   if (i <= TX - 1 && j <= TY - 1 && FL_(i, j))

@@ -1,0 +1,83 @@
+"""Turn rocprofv3 CSV output of bench.py into the committed profile summaries.
+
+Usage (after the rocprofv3 runs listed in the summary files):
+  python -m paper_1802_04243_amd.prof_summary <kt_dir> <fetch_dir> <write_dir> \
+      <copy_fetch_dir> <copy_write_dir> <out_dir>
+
+FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch; each is scaled by
+what the same counter reads for a plain 1 GiB device copy (bench.py
+--copy-probe), so that the bytes are HBM bytes.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_1802_04243_amd/csrc/sts_kernels.hip", "paper_1802_04243_amd/csrc/sts_internal.h"]
+SCHEME_OF = {"k_pass<false, false>": "explicit_upwind", "k_pass<false, true>": "explicit_tvd",
+             "k_pass<true, false>": "implicit_upwind", "k_pass<true, true>": "implicit_tvd"}
+NFV = 5120 * 1152
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def short(name: str) -> str:
+    return name.replace("sts::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
+
+def counters(d: str):
+    out = defaultdict(list)
+    for f in glob.glob(os.path.join(d, "*counter_collection.csv")):
+        for r in csv.DictReader(open(f)):
+            out[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return out
+
+
+def main(kt, fetch, write, cfetch, cwrite, outdir):
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(kt, "*kernel_stats.csv"))[0])))
+    f, w = counters(fetch), counters(write)
+    cf, cw = counters(cfetch), counters(cwrite)
+    copy = "__amd_rocclr_copyBuffer"
+    fscale = (1 << 30) / (sum(cf[copy]) / len(cf[copy]) * 1024)
+    wscale = (1 << 30) / (sum(cw[copy]) / len(cw[copy]) * 1024)
+    per = {}
+    for k in sorted(f):
+        if k not in w or not k.startswith("k_"):
+            continue
+        rd = sum(f[k]) / len(f[k]) * 1024 * fscale
+        wr = sum(w[k]) / len(w[k]) * 1024 * wscale
+        per[k] = dict(read_bytes=rd, write_bytes=wr, bytes=rd + wr, bytes_per_fv=(rd + wr) / NFV,
+                      dispatches=len(f[k]))
+    traffic = {"kernel_hash": kernel_hash(), "workload": "channel_5120x1152",
+               "fetch_scale": fscale, "write_scale": wscale,
+               "bytes_per_launch": {SCHEME_OF[k]: v["bytes"] for k, v in per.items() if k in SCHEME_OF},
+               "per_kernel": per}
+    os.makedirs(outdir, exist_ok=True)
+    json.dump(traffic, open(os.path.join(outdir, "pass_kernel_hbm_traffic_5120x1152.json"), "w"), indent=1)
+    lines = ["| kernel | calls | avg us | min us | max us | HBM read MB | HBM write MB | HBM B/FV |",
+             "|---|---|---|---|---|---|---|---|"]
+    for r in stats:
+        k = short(r["Name"])
+        t = per.get(k)
+        extra = (f"{t['read_bytes'] / 1e6:.1f} | {t['write_bytes'] / 1e6:.1f} | {t['bytes_per_fv']:.1f}"
+                 if t else " | | ")
+        lines.append(f"| {k} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {extra} |")
+    print("\n".join(lines))
+    print(f"\nFETCH_SIZE scale {fscale:.4f}, WRITE_SIZE scale {wscale:.4f} (1 GiB copy probe)")
+    return lines, fscale, wscale
+
+
+if __name__ == "__main__":
+    main(*sys.argv[1:7])
