@@ -60,7 +60,7 @@ struct Sizes {
 Sizes make_sizes(int nx, int ny, const Layout &L) {
   Sizes S;
   S.state = 8 * L.field_bytes;   // two buffers of u, v, p, T
-  S.consts = 4 * L.field_bytes;  // C_u, C_v, C_T, C_p
+  S.consts = 6 * L.field_bytes;  // C_u, C_v, C_T, C_p, face mass fluxes
   S.mask = L.mask_bytes;
   // 1-D boundary arrays (see ctx_build), tile flags
   const size_t tiles = (size_t)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
@@ -68,7 +68,7 @@ Sizes make_sizes(int nx, int ny, const Layout &L) {
                                         4 * (size_t)ny + 4 * (size_t)nx + 2 * (size_t)(nx + 1)),
                      256) +
             align_up(tiles, 256);
-  S.partials = align_up(sizeof(double) * NRES * 2048, 256);
+  S.partials = align_up(sizeof(double) * NRES * (tiles + RES_BLOCKS), 256);
   S.res = 256;
   S.total = S.state + S.consts + S.mask + S.small + S.partials + S.res;
   return S;
@@ -89,9 +89,9 @@ struct sts_ctx {
   State st[2];
   int cur;
   Consts C;
-  double *partials, *dres;
+  Resid X;
+  double *dres;
   double *hres;  // pinned
-  int nres_blocks;
   bool stepped;
   int last_scheme;
   // host copies of the boundary data
@@ -230,7 +230,7 @@ sts_status fill_frames(sts_ctx *c) {
     HIPCHK(hipMemcpyAsync(c->st[b].p, one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->st[b].T, one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
   }
-  HIPCHK(hipMemsetAsync(c->C.Cu, 0, 4 * c->L.field_bytes, c->stream));
+  HIPCHK(hipMemsetAsync(c->C.Cu, 0, 6 * c->L.field_bytes, c->stream));  // C_*, fluxes
   HIPCHK(hipStreamSynchronize(c->stream));
   return STS_OK;
 }
@@ -249,9 +249,11 @@ sts_status build(sts_ctx *c, const sts_bc *bc) {
   c->C.Cv = (double *)q; q += c->L.field_bytes;
   c->C.CT = (double *)q; q += c->L.field_bytes;
   c->C.Cp = (double *)q; q += c->L.field_bytes;
+  c->X.gu = (double *)q; q += c->L.field_bytes;
+  c->X.gv = (double *)q; q += c->L.field_bytes;
   unsigned char *fl = (unsigned char *)q; q += c->S.mask;
   char *small = q; q += c->S.small;
-  c->partials = (double *)q; q += c->S.partials;
+  c->X.partials = (double *)q; q += c->S.partials;
   c->dres = (double *)q; q += c->S.res;
 
   // host-side boundary data
@@ -359,7 +361,6 @@ sts_status build(sts_ctx *c, const sts_bc *bc) {
   P.gy = bc->gy;
   P.obsT = c->obsT;
   P.sq_obsT = sqrt(c->obsT);
-  c->nres_blocks = residual_blocks(P);
   HIPCHK(hipStreamSynchronize(c->stream));
   return fill_frames(c);
 }
@@ -518,13 +519,13 @@ extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
   HIPCHK(hipGetLastError());
   if ((s = record(c, 1)) != STS_OK) return s;
   for (int k = 0; k < n_inner; k++) {
-    launch_pass(c->P, c->st[c->cur], c->st[c->cur ^ 1], c->C, scheme, c->stream);
+    launch_pass(c->P, c->st[c->cur], c->st[c->cur ^ 1], c->C, scheme,
+                k == n_inner - 1 ? &c->X : nullptr, c->stream);
     c->cur ^= 1;
   }
   HIPCHK(hipGetLastError());
   if ((s = record(c, 2)) != STS_OK) return s;
-  launch_residual(c->P, c->st[c->cur ^ 1], c->st[c->cur], c->C, scheme, c->partials,
-                  c->nres_blocks, c->dres, c->stream);
+  launch_residual(c->P, c->st[c->cur], c->C, c->X, c->dres, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(c->hres, c->dres, NRES * sizeof(double), hipMemcpyDeviceToHost,
                         c->stream));

@@ -52,14 +52,21 @@ struct Params {
 // residual partial per block: max|du|, max|dv|, max|dp|, max|dT|, max|R|,
 // sum R, non-finite count
 constexpr int NRES = 8;
+constexpr int RES_BLOCKS = 2048;  // blocks of the continuity-residual kernel
+
+// Outputs of the last pass of a step used by the residual reduction: the
+// face mass fluxes rho^u u dy (u-face layout) and rho^v v dx (v-face layout)
+// of the new velocities, and one row of NRES partials per tile.
+struct Resid {
+  double *gu, *gv;
+  double *partials;  // [tiles + RES_BLOCKS][NRES]
+};
 
 void launch_prologue(const Params &P, State m, Consts C, int scheme,
                      hipStream_t st);
 void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
-                 hipStream_t st);
-void launch_residual(const Params &P, State o, State n, Consts C, int scheme,
-                     double *partials, int nblocks, double *out,
+                 const Resid *last, hipStream_t st);
+void launch_residual(const Params &P, State n, Consts C, Resid R, double *out,
                      hipStream_t st);
-int residual_blocks(const Params &P);
 
 }  // namespace sts

@@ -96,6 +96,7 @@ struct Lds {
   // global column of every window column (cells, u-faces: wrapped when
   // periodic, clamped into the frame otherwise) and row (cells, v-faces)
   int ci[LW], ui[LW], cj[LH], vj[LH];
+  double red[NT / 64][NRES];  // per-wave residual partials (last pass)
 };
 
 // tile-relative accessors: (i, j) with the tile origin at (0, 0)
@@ -537,12 +538,47 @@ __device__ __forceinline__ bool v_solved(const Lds &s, const Params &P, int i,
   return gj >= 1 && gj <= P.ny - 1 && FL_(i, j - 1) && FL_(i, j);
 }
 
+__device__ __forceinline__ double wave_max(double x) {
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Block-wide reduction of the residual partials v[0..NRES): maxima in 0..4,
+// sums in 5..6; thread 0 writes the block's row.  Needs s.red; ends with
+// the row written by thread 0 only.
+template <int NTH>
+__device__ void block_partials(double (*red)[NRES], double v[NRES],
+                               double *row) {
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  for (int q = 0; q < 5; q++) v[q] = wave_max(v[q]);
+  v[5] = wave_sum(v[5]);
+  v[6] = wave_sum(v[6]);
+  if (l == 0)
+    for (int q = 0; q < NRES; q++) red[w][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double out[NRES];
+    for (int q = 0; q < NRES; q++) out[q] = red[0][q];
+    for (int ww = 1; ww < NTH / 64; ww++) {
+      for (int q = 0; q < 5; q++) out[q] = fmax(out[q], red[ww][q]);
+      out[5] += red[ww][5];
+      out[6] += red[ww][6];
+    }
+    for (int q = 0; q < NRES; q++) row[q] = out[q];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // one Jacobi pass of loop 2
 // ---------------------------------------------------------------------------
-template <bool CL, bool IM, bool TV>
+template <bool CL, bool IM, bool TV, bool RS>
 __device__ void pass_body(Lds &s, const Params &P, const State o,
-                          const State n, const Consts C, int x0, int y0) {
+                          const State n, const Consts C, const Resid X,
+                          int tile, int x0, int y0) {
   const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
   const int i = tx - 1, j = ty - 1;  // (i, j) in [-1, TX] x [-1, TY]
   const int gi = x0 + i, gj = y0 + j;
@@ -603,35 +639,61 @@ __device__ void pass_body(Lds &s, const Params &P, const State o,
   __syncthreads();
 
   // stage 4: velocities (eqs pl18, pl19); write the owned values
+  double rv[NRES] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (i >= 0 && i < TX && j >= 0 && j < TY && gi < P.nx && gj < P.ny) {
     const long k = P.off + (long)gj * P.pitch + gi;
+    const double pn = PN_(i, j);
     n.T[k] = tnew;
-    n.p[k] = PN_(i, j);
+    n.p[k] = pn;
     const double un = u_solved(s, P, i, j, gi)
-                          ? UH_(i, j) - DU_(i, j) * (PN_(i, j) - PN_(i - 1, j))
+                          ? UH_(i, j) - DU_(i, j) * (pn - PN_(i - 1, j))
                           : U_(i, j);
     n.u[k] = un;
-    if ((!P.per && gi == P.nx - 1) || (P.per && gi == 0))
-      n.u[P.off + (long)gj * P.pitch + P.nx] = un;  // outlet / periodic copy
+    const bool ucopy = (!P.per && gi == P.nx - 1) || (P.per && gi == 0);
+    const long kcopy = P.off + (long)gj * P.pitch + P.nx;
+    if (ucopy) n.u[kcopy] = un;  // outlet / periodic copy
     const double vn = v_solved(s, P, i, j, gj)
-                          ? VH_(i, j) - DV_(i, j) * (PN_(i, j) - PN_(i, j - 1))
+                          ? VH_(i, j) - DV_(i, j) * (pn - PN_(i, j - 1))
                           : V_(i, j);
     n.v[k] = vn;
+    if (RS) {
+      // increments of the unknowns (zero on the faces and cells that are not
+      // solved) and the mass fluxes of the new velocities through the owned
+      // faces with the face densities of this pass; the outlet / periodic
+      // face nx and the top face ny are written by the cells below them
+      const double dxi = DX_(i), dyj = DY_(j);
+      const double gw = RU_(i, j) * un * dyj;
+      X.gu[k] = gw;
+      X.gv[k] = RV_(i, j) * vn * dxi;
+      if (ucopy) X.gu[kcopy] = P.per ? gw : RU_(i + 1, j) * un * dyj;
+      if (gj == P.ny - 1) X.gv[k + P.pitch] = RV_(i, j + 1) * V_(i, j + 1) * dxi;
+      rv[0] = fabs(un - U_(i, j));
+      rv[1] = fabs(vn - V_(i, j));
+      rv[6] = (double)(!isfinite(un)) + (double)(!isfinite(vn));
+      if (FL_(i, j)) {
+        rv[2] = fabs(pn - P_(i, j));
+        rv[3] = fabs(tnew - T_(i, j));
+        rv[6] += (double)(!isfinite(pn)) + (double)(!isfinite(tnew));
+      }
+    }
   }
+  if (RS) block_partials<NT>(s.red, rv, X.partials + (long)tile * NRES);
 }
 
-template <bool IM, bool TV>
+// RS: last pass of a step, which also produces the residual inputs
+template <bool IM, bool TV, bool RS>
 __global__ __launch_bounds__(NT) void k_pass(const Params P, const State o,
-                                             const State n, const Consts C) {
+                                             const State n, const Consts C,
+                                             const Resid X) {
   __shared__ Lds s;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
   load_window(s, P, o, x0, y0);
   __syncthreads();
   if (P.clean[tile])
-    pass_body<true, IM, TV>(s, P, o, n, C, x0, y0);
+    pass_body<true, IM, TV, RS>(s, P, o, n, C, X, tile, x0, y0);
   else
-    pass_body<false, IM, TV>(s, P, o, n, C, x0, y0);
+    pass_body<false, IM, TV, RS>(s, P, o, n, C, X, tile, x0, y0);
 }
 
 // ---------------------------------------------------------------------------
@@ -806,155 +868,50 @@ __global__ __launch_bounds__(NT) void k_prologue(const Params P, const State m,
 }
 
 // ---------------------------------------------------------------------------
-// residuals of the last pass: increments of the unknowns and the discrete
-// continuity residual with the face densities of the pass (old iterate)
+// continuity residual of the last pass (eq pl24 written as a residual):
+//   R = (rho_new - rho^{n-1}) dV / dt + net outflow of the face mass fluxes,
+// with rho^{n-1} dV = C_p and the fluxes written by the last pass
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double gld(const double *a, const Params &P,
-                                      int i, int j) {
-  return a[P.off + (long)j * P.pitch + i];
-}
-__device__ __forceinline__ bool gfl(const Params &P, int i, int j) {
-  if (j < 0 || j >= P.ny) return false;
-  if (P.per) i = wrapi(i, P.nx);
-  else if (i < 0 || i >= P.nx) return false;
-  return P.fl[P.off + (long)j * P.pitch + i] != 0;
-}
-__device__ __forceinline__ double grho(const State &o, const Params &P, int i,
-                                       int j) {
-  if (P.per) i = wrapi(i, P.nx);
-  const long k = P.off + (long)j * P.pitch + i;
-  return o.p[k] / o.T[k];
-}
-// geometry factor q (0 width, 1 inverse width, 2 face sum, 3 its inverse,
-// 4/5 low/high interpolation weight) of column i / row j
-__device__ __forceinline__ double ggx(const Params &P, int q, int i) {
-  return P.gx_[q][(P.per ? wrapi(i, P.nx) : clampi(i, -XPAD, P.nx + XPAD - 1)) + XPAD];
-}
-__device__ __forceinline__ double ggy(const Params &P, int q, int j) {
-  return P.gy_[q][clampi(j, -XPAD, P.ny + XPAD - 1) + XPAD];
-}
-// rho^u at u-face (i, j) of the old iterate (global memory)
-template <bool TV>
-__device__ double grho_x(const State &o, const Params &P, int i, int j) {
-  const double uf = gld(o.u, P, i, j);
-  if (!P.per) {
-    if (i == 0) return uf > 0.0 ? P.rho_in[j] : grho(o, P, 0, j);
-    if (i == P.nx) return grho(o, P, P.nx - 1, j);
-  }
-  const double rl = grho(o, P, i - 1, j), rr = grho(o, P, i, j);
-  double r = upw(rl, rr, uf);
-  if (TV && gfl(P, i - 2, j) && gfl(P, i - 1, j) && gfl(P, i, j) && gfl(P, i + 1, j))
-    r += psi_sf(grho(o, P, i - 2, j), rl, rr, grho(o, P, i + 1, j), ggx(P, 2, i - 1),
-                ggx(P, 2, i), ggx(P, 2, i + 1), ggx(P, 5, i), ggx(P, 4, i), uf) *
-         (rr - rl);
-  return r;
-}
-template <bool TV>
-__device__ double grho_y(const State &o, const Params &P, int i, int j) {
-  if (j == 0) return grho(o, P, i, 0);
-  if (j == P.ny) return grho(o, P, i, P.ny - 1);
-  const double vf = gld(o.v, P, i, j);
-  const double rs = grho(o, P, i, j - 1), rn = grho(o, P, i, j);
-  double r = upw(rs, rn, vf);
-  if (TV && gfl(P, i, j - 2) && gfl(P, i, j - 1) && gfl(P, i, j) && gfl(P, i, j + 1))
-    r += psi_sf(grho(o, P, i, j - 2), rs, rn, grho(o, P, i, j + 1), ggy(P, 2, j - 1),
-                ggy(P, 2, j), ggy(P, 2, j + 1), ggy(P, 5, j), ggy(P, 4, j), vf) *
-         (rn - rs);
-  return r;
-}
-
-__device__ __forceinline__ double wave_max(double x) {
-  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
-  return x;
-}
-__device__ __forceinline__ double wave_sum(double x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
 constexpr int RB = 256;  // threads per residual block
 
-template <bool TV>
-__global__ __launch_bounds__(RB) void k_residual(const Params P, const State o,
-                                                 const State n, const Consts C,
-                                                 double *partials) {
-  double ru = 0.0, rv = 0.0, rp = 0.0, rT = 0.0, rm = 0.0, sm = 0.0, bad = 0.0;
+__global__ __launch_bounds__(RB) void k_continuity(const Params P,
+                                                   const State n,
+                                                   const Consts C,
+                                                   const Resid X,
+                                                   double *rows) {
+  __shared__ double red[RB / 64][NRES];
+  double rm = 0.0, sm = 0.0, bad = 0.0;
   const long ncell = (long)P.nx * P.ny;
   for (long c = (long)blockIdx.x * RB + threadIdx.x; c < ncell;
        c += (long)gridDim.x * RB) {
     const int i = (int)(c % P.nx), j = (int)(c / P.nx);
     const long k = P.off + (long)j * P.pitch + i;
-    const bool fi = P.fl[k] != 0;
-    // u-face (i, j) and v-face (i, j)
-    const double un = n.u[k], vn = n.v[k];
-    if (!isfinite(un) || !isfinite(vn)) bad += 1.0;
-    const bool us = (P.per || i >= 1) && fi && gfl(P, i - 1, j);
-    if (us) ru = fmax(ru, fabs(un - o.u[k]));
-    const bool vs = j >= 1 && fi && gfl(P, i, j - 1);
-    if (vs) rv = fmax(rv, fabs(vn - o.v[k]));
-    if (fi) {
-      const double pn = n.p[k], Tn = n.T[k];
-      if (!isfinite(pn) || !isfinite(Tn)) bad += 1.0;
-      rp = fmax(rp, fabs(pn - o.p[k]));
-      rT = fmax(rT, fabs(Tn - o.T[k]));
-      const double dxi = ggx(P, 0, i), dyj = ggy(P, 0, j), dV = dxi * dyj;
-      const int ie = (P.per && i + 1 == P.nx) ? P.nx : i + 1;
-      const double GW = grho_x<TV>(o, P, i, j) * un * dyj;
-      const double GE = grho_x<TV>(o, P, ie, j) * gld(n.u, P, ie, j) * dyj;
-      const double GS = grho_y<TV>(o, P, i, j) * vn * dxi;
-      const double GN = grho_y<TV>(o, P, i, j + 1) * gld(n.v, P, i, j + 1) * dxi;
-      const double R = (pn / Tn * dV - C.Cp[k]) * P.idt + (GE - GW) + (GN - GS);
-      if (!isfinite(R)) bad += 1.0;
-      rm = fmax(rm, fabs(R));
-      sm += R;
-    }
+    if (!P.fl[k]) continue;
+    const double dV = P.gx_[0][i + XPAD] * P.gy_[0][j + XPAD];
+    const double GW = X.gu[k], GE = X.gu[k + 1];
+    const double GS = X.gv[k], GN = X.gv[k + P.pitch];
+    const double R = (n.p[k] / n.T[k] * dV - C.Cp[k]) * P.idt + (GE - GW) + (GN - GS);
+    bad += (double)(!isfinite(R));
+    rm = fmax(rm, fabs(R));
+    sm += R;
   }
-  __shared__ double red[RB / 64][NRES];
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  double v[NRES] = {wave_max(ru), wave_max(rv), wave_max(rp), wave_max(rT),
-                    wave_max(rm), wave_sum(sm), wave_sum(bad), 0.0};
-  if (l == 0)
-    for (int q = 0; q < NRES; q++) red[w][q] = v[q];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double out[NRES];
-    for (int q = 0; q < NRES; q++) out[q] = red[0][q];
-    for (int ww = 1; ww < RB / 64; ww++) {
-      for (int q = 0; q < 5; q++) out[q] = fmax(out[q], red[ww][q]);
-      out[5] += red[ww][5];
-      out[6] += red[ww][6];
-    }
-    for (int q = 0; q < NRES; q++) partials[(long)blockIdx.x * NRES + q] = out[q];
-  }
+  double v[NRES] = {0.0, 0.0, 0.0, 0.0, rm, sm, bad, 0.0};
+  block_partials<RB>(red, v, rows + (long)blockIdx.x * NRES);
 }
 
-__global__ __launch_bounds__(RB) void k_finalize(const double *partials,
-                                                 int nb, double *out) {
-  double m[5] = {0, 0, 0, 0, 0}, sm = 0.0, bad = 0.0;
-  for (int b = threadIdx.x; b < nb; b += RB) {
-    const double *q = partials + (long)b * NRES;
-    for (int t = 0; t < 5; t++) m[t] = fmax(m[t], q[t]);
-    sm += q[5];
-    bad += q[6];
+// merge the rows of the last pass (one per tile) and of k_continuity
+constexpr int FB = 1024;
+__global__ __launch_bounds__(FB) void k_finalize(const double *rows, int nrows,
+                                                 double *out) {
+  __shared__ double red[FB / 64][NRES];
+  double v[NRES] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nrows; b += FB) {
+    const double *q = rows + (long)b * NRES;
+    for (int t = 0; t < 5; t++) v[t] = fmax(v[t], q[t]);
+    v[5] += q[5];
+    v[6] += q[6];
   }
-  __shared__ double red[RB / 64][NRES];
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  double v[NRES] = {wave_max(m[0]), wave_max(m[1]), wave_max(m[2]),
-                    wave_max(m[3]), wave_max(m[4]), wave_sum(sm),
-                    wave_sum(bad), 0.0};
-  if (l == 0)
-    for (int q = 0; q < NRES; q++) red[w][q] = v[q];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double o[NRES];
-    for (int q = 0; q < NRES; q++) o[q] = red[0][q];
-    for (int ww = 1; ww < RB / 64; ww++) {
-      for (int q = 0; q < 5; q++) o[q] = fmax(o[q], red[ww][q]);
-      o[5] += red[ww][5];
-      o[6] += red[ww][6];
-    }
-    for (int q = 0; q < NRES; q++) out[q] = o[q];
-  }
+  block_partials<FB>(red, v, out);
 }
 
 }  // namespace
@@ -974,29 +931,28 @@ void launch_prologue(const Params &P, State m, Consts C, int scheme,
 }
 
 void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
-                 hipStream_t st) {
+                 const Resid *last, hipStream_t st) {
   const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0;
   dim3 g(ntiles(P)), b(NT);
-  if (im && tv) hipLaunchKernelGGL((k_pass<true, true>), g, b, 0, st, P, o, n, C);
-  else if (im) hipLaunchKernelGGL((k_pass<true, false>), g, b, 0, st, P, o, n, C);
-  else if (tv) hipLaunchKernelGGL((k_pass<false, true>), g, b, 0, st, P, o, n, C);
-  else hipLaunchKernelGGL((k_pass<false, false>), g, b, 0, st, P, o, n, C);
+  const Resid X = last ? *last : Resid{nullptr, nullptr, nullptr};
+#define STS_PASS(IM_, TV_)                                                          \
+  do {                                                                              \
+    if (last) hipLaunchKernelGGL((k_pass<IM_, TV_, true>), g, b, 0, st, P, o, n, C, X); \
+    else hipLaunchKernelGGL((k_pass<IM_, TV_, false>), g, b, 0, st, P, o, n, C, X);     \
+  } while (0)
+  if (im && tv) STS_PASS(true, true);
+  else if (im) STS_PASS(true, false);
+  else if (tv) STS_PASS(false, true);
+  else STS_PASS(false, false);
+#undef STS_PASS
 }
 
-int residual_blocks(const Params &P) {
-  const long n = (long)P.nx * P.ny;
-  long b = (n + RB - 1) / RB;
-  if (b > 2048) b = 2048;
-  return (int)b;
-}
-
-void launch_residual(const Params &P, State o, State n, Consts C, int scheme,
-                     double *partials, int nblocks, double *out,
+void launch_residual(const Params &P, State n, Consts C, Resid X, double *out,
                      hipStream_t st) {
-  const bool tv = (scheme & 2) != 0;
-  if (tv) hipLaunchKernelGGL((k_residual<true>), dim3(nblocks), dim3(RB), 0, st, P, o, n, C, partials);
-  else hipLaunchKernelGGL((k_residual<false>), dim3(nblocks), dim3(RB), 0, st, P, o, n, C, partials);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RB), 0, st, partials, nblocks, out);
+  double *rows = X.partials + (long)ntiles(P) * NRES;
+  hipLaunchKernelGGL(k_continuity, dim3(RES_BLOCKS), dim3(RB), 0, st, P, n, C, X, rows);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, X.partials,
+                     ntiles(P) + RES_BLOCKS, out);
 }
 
 }  // namespace sts

@@ -78,5 +78,6 @@ def test_workspace_bytes_scale_with_the_grid():
         assert L.sts_workspace_bytes(C.byref(g), C.byref(b)) == sts.STS_OK
         sizes.append(b.value)
     assert sizes[0] < sizes[1] < sizes[2]
-    # 12 FP64 arrays per cell plus framing: about 96 B per finite volume
-    assert 96 * 256 * 256 < sizes[2] < 1.3 * 96 * 256 * 256 + 4e5
+    # 14 FP64 arrays per cell (two states, four step constants, two face
+    # mass fluxes) plus framing: about 112 B per finite volume
+    assert 112 * 256 * 256 < sizes[2] < 1.3 * 112 * 256 * 256 + 4e5
