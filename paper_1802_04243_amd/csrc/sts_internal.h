@@ -12,7 +12,10 @@ namespace sts {
 // the owned cells / faces.  The LDS window of old fields has a halo of HB.
 constexpr int TX = 30, TY = 14;
 constexpr int BX = TX + 2, BY = TY + 2;
-constexpr int NT = BX * BY;  // 512 threads
+constexpr int NT = BX * BY;  // 512 cell positions (threads of the prologue)
+// Threads of a pass block: the NT cell threads plus NT/2 more, so that the
+// cell, u-face and v-face items of a pass (3 NT) take two rounds.
+constexpr int NTP = 3 * NT / 2;
 constexpr int HB = 3;
 constexpr int LW = TX + 2 * HB, LH = TY + 2 * HB;
 

@@ -96,7 +96,7 @@ struct Lds {
   // global column of every window column (cells, u-faces: wrapped when
   // periodic, clamped into the frame otherwise) and row (cells, v-faces)
   int ci[LW], ui[LW], cj[LH], vj[LH];
-  double red[NT / 64][NRES];  // per-wave residual partials (last pass)
+  double red[NTP / 64][NRES];  // per-wave residual partials (last pass)
 };
 
 // tile-relative accessors: (i, j) with the tile origin at (0, 0)
@@ -132,6 +132,18 @@ struct Lds {
 #define VH_(i, j) s.vh[(j) + 1][(i) + 1]
 #define DV_(i, j) s.dv[(j) + 1][(i) + 1]
 
+// Column of the per-column wall arrays for window cell column i and for the
+// u-face i: wrapped when periodic; clamped into the domain otherwise, where
+// only cells and faces inside the domain use the value.
+__device__ __forceinline__ int wall_c(const Lds &s, const Params &P, int i) {
+  const int c = s.ci[i + HB];
+  return P.per ? c : clampi(c, 0, P.nx - 1);
+}
+__device__ __forceinline__ int wall_u(const Lds &s, const Params &P, int i) {
+  const int c = s.ui[i + HB];
+  return P.per ? c : clampi(c, 0, P.nx);
+}
+
 // Block index -> tile index.  Consecutive blocks are dealt round-robin to
 // the 8 XCDs; remap so that every XCD works on one contiguous band of tiles
 // (neighbour halos then hit the same L2).
@@ -140,58 +152,96 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return k * q + (k < r ? k : r) + m;
 }
 
-// Stage the old fields of the window [x0-3, x0+TX+2] x [y0-3, y0+TY+2].
+// Global column of window column a (cells; u-faces) and row of window row b
+// (cells; v-faces): wrapped when periodic, clamped into the ghost frame
+// otherwise.
+__device__ __forceinline__ int win_ci(const Params &P, int x0, int a) {
+  const int g = x0 - HB + a;
+  return P.per ? wrapi(g, P.nx) : clampi(g, -XPAD, P.nx + XPAD - 1);
+}
+__device__ __forceinline__ int win_ui(const Params &P, int x0, int a) {
+  const int g = x0 - HB + a;
+  return P.per ? wrapi(g, P.nx) : clampi(g, -XPAD, P.nx + XPAD);
+}
+__device__ __forceinline__ int win_cj(const Params &P, int y0, int b) {
+  return clampi(y0 - HB + b, -XPAD, P.ny + XPAD - 1);
+}
+__device__ __forceinline__ int win_vj(const Params &P, int y0, int b) {
+  return clampi(y0 - HB + b, -XPAD, P.ny + XPAD);
+}
+
+constexpr int NW = LH * LW;  // cells of the window
+
+// Stage the old fields of the window [x0-3, x0+TX+2] x [y0-3, y0+TY+2] with
+// NTH threads: every global load of the thread is issued before the first
+// LDS store, so that their latencies overlap; the caller synchronises.
+template <int NTH>
 __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
                             int y0) {
+  constexpr int WPT = (NW + NTH - 1) / NTH;  // window cells per thread
   const int t = threadIdx.x;
-  if (t < LW) {
-    const int gi = x0 - HB + t;
-    if (P.per) {
-      const int w = wrapi(gi, P.nx);
-      s.ci[t] = w;
-      s.ui[t] = w;
-    } else {
-      s.ci[t] = clampi(gi, -XPAD, P.nx + XPAD - 1);
-      s.ui[t] = clampi(gi, -XPAD, P.nx + XPAD);
+  double pp[WPT], tt[WPT], uu[WPT], vv[WPT];
+  unsigned char ff[WPT];
+#pragma unroll
+  for (int m = 0; m < WPT; m++) {
+    const int k = t + m * NTH;
+    if (k < NW) {
+      const int a = k % LW, b = k / LW;
+      const int ci = win_ci(P, x0, a);
+      const long rc = P.off + (long)win_cj(P, y0, b) * P.pitch;
+      pp[m] = o.p[rc + ci];
+      tt[m] = o.T[rc + ci];
+      ff[m] = P.fl[rc + ci];
+      uu[m] = o.u[rc + win_ui(P, x0, a)];
+      vv[m] = o.v[P.off + (long)win_vj(P, y0, b) * P.pitch + ci];
     }
-  } else if (t < LW + LH) {
-    const int gj = y0 - HB + (t - LW);
-    s.cj[t - LW] = clampi(gj, -XPAD, P.ny + XPAD - 1);
-    s.vj[t - LW] = clampi(gj, -XPAD, P.ny + XPAD);
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < LH * LW; k += NT) {
-    const int a = k % LW, b = k / LW;
-    const long rc = P.off + (long)s.cj[b] * P.pitch;
-    const long kc = rc + s.ci[a];
-    const double pp = o.p[kc], tt = o.T[kc];
-    s.p[b][a] = pp;
-    s.T[b][a] = tt;
-    s.r[b][a] = pp / tt;
-    s.g[b][a] = sqrt(tt);
-    s.fl[b][a] = P.fl[kc];
-    s.u[b][a] = o.u[rc + s.ui[a]];
-    s.v[b][a] = o.v[P.off + (long)s.vj[b] * P.pitch + s.ci[a]];
+  // geometry: threads [0, LW) load the columns, [LW, LW + LH) the rows
+  double gq[6];
+  const bool gcol = t < LW, grow = !gcol && t < LW + LH;
+  int c0 = 0, c1 = 0;
+  if (gcol) {
+    c0 = win_ci(P, x0, t);
+    c1 = win_ui(P, x0, t);
+    for (int q = 0; q < 6; q++) gq[q] = P.gx_[q][c0 + XPAD];
+  } else if (grow) {
+    c0 = win_cj(P, y0, t - LW);
+    c1 = win_vj(P, y0, t - LW);
+    for (int q = 0; q < 6; q++) gq[q] = P.gy_[q][c0 + XPAD];
   }
-  for (int k = threadIdx.x; k < LW + LH; k += NT) {
-    if (k < LW) {
-      const int ci = s.ci[k] + XPAD;
-      s.dx[k] = P.gx_[0][ci];
-      s.idx[k] = P.gx_[1][ci];
-      s.sx[k] = P.gx_[2][ci];
-      s.isx[k] = P.gx_[3][ci];
-      s.wlx[k] = P.gx_[4][ci];
-      s.wrx[k] = P.gx_[5][ci];
-    } else {
-      const int b = k - LW;
-      const int cj = s.cj[b] + XPAD;
-      s.dy[b] = P.gy_[0][cj];
-      s.idy[b] = P.gy_[1][cj];
-      s.sy[b] = P.gy_[2][cj];
-      s.isy[b] = P.gy_[3][cj];
-      s.wly[b] = P.gy_[4][cj];
-      s.wry[b] = P.gy_[5][cj];
+#pragma unroll
+  for (int m = 0; m < WPT; m++) {
+    const int k = t + m * NTH;
+    if (k < NW) {
+      const int a = k % LW, b = k / LW;
+      s.p[b][a] = pp[m];
+      s.T[b][a] = tt[m];
+      s.r[b][a] = pp[m] / tt[m];
+      s.g[b][a] = sqrt(tt[m]);
+      s.fl[b][a] = ff[m];
+      s.u[b][a] = uu[m];
+      s.v[b][a] = vv[m];
     }
+  }
+  if (gcol) {
+    s.ci[t] = c0;
+    s.ui[t] = c1;
+    s.dx[t] = gq[0];
+    s.idx[t] = gq[1];
+    s.sx[t] = gq[2];
+    s.isx[t] = gq[3];
+    s.wlx[t] = gq[4];
+    s.wrx[t] = gq[5];
+  } else if (grow) {
+    const int b = t - LW;
+    s.cj[b] = c0;
+    s.vj[b] = c1;
+    s.dy[b] = gq[0];
+    s.idy[b] = gq[1];
+    s.sy[b] = gq[2];
+    s.isy[b] = gq[3];
+    s.wly[b] = gq[4];
+    s.wry[b] = gq[5];
   }
 }
 
@@ -275,8 +325,8 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   }
   if (!CL && gj == 0) {
     if (P.wtype0 == 0) {
-      nS = P.Tw0[gi];
-      DS = P.C1 * hmean2(gP, P.sq_Tw0[gi]) * dxi * (2.0 * IDY_(j));
+      nS = P.Tw0[wall_c(s, P, i)];
+      DS = P.C1 * hmean2(gP, P.sq_Tw0[wall_c(s, P, i)]) * dxi * (2.0 * IDY_(j));
     } else {
       nS = TP;
       DS = 0.0;
@@ -290,8 +340,8 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   }
   if (!CL && gj == P.ny - 1) {
     if (P.wtype1 == 0) {
-      nN = P.Tw1[gi];
-      DN = P.C1 * hmean2(gP, P.sq_Tw1[gi]) * dxi * (2.0 * IDY_(j));
+      nN = P.Tw1[wall_c(s, P, i)];
+      DN = P.C1 * hmean2(gP, P.sq_Tw1[wall_c(s, P, i)]) * dxi * (2.0 * IDY_(j));
     } else {
       nN = TP;
       DN = 0.0;
@@ -380,7 +430,7 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   if (!CL && gj == 0) {
     if (P.wtype0 == 0) {
       uS = P.wu0;
-      DS = P.B * 0.5 * (gnode + P.sq_Twu0[gi]) * len * (2.0 * IDY_(j));
+      DS = P.B * 0.5 * (gnode + P.sq_Twu0[wall_u(s, P, i)]) * len * (2.0 * IDY_(j));
     } else {
       uS = uP;
       DS = 0.0;
@@ -395,7 +445,7 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   if (!CL && gj == P.ny - 1) {
     if (P.wtype1 == 0) {
       uN = P.wu1;
-      DN = P.B * 0.5 * (gnode + P.sq_Twu1[gi]) * len * (2.0 * IDY_(j));
+      DN = P.B * 0.5 * (gnode + P.sq_Twu1[wall_u(s, P, i)]) * len * (2.0 * IDY_(j));
     } else {
       uN = uP;
       DN = 0.0;
@@ -575,17 +625,87 @@ __device__ void block_partials(double (*red)[NRES], double v[NRES],
 // ---------------------------------------------------------------------------
 // one Jacobi pass of loop 2
 // ---------------------------------------------------------------------------
-template <bool CL, bool IM, bool TV, bool RS>
-__device__ void pass_body(Lds &s, const Params &P, const State o,
-                          const State n, const Consts C, const Resid X,
-                          int tile, int x0, int y0) {
-  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
-  const int i = tx - 1, j = ty - 1;  // (i, j) in [-1, TX] x [-1, TY]
+// Work items of stage 2, numbered v in [0, 3 NT): cells (T) for v < NT,
+// u-faces (u-hat, d^u) for v < 2 NT, v-faces (v-hat, d^v) otherwise; item q
+// of a kind sits at (i, j) = (q % BX - 1, q / BX - 1).  With NTH threads,
+// thread t takes the items t, t + NTH, ...: NTH = NT gives every thread its
+// cell and the two faces on its low side (three rounds); NTH = NTP = 3/2 NT
+// gives two rounds.  Wave boundaries are multiples of 64 in both, so every
+// wave runs one kind per round, and the cell threads (t < NT) keep their
+// new T in a register.
+__device__ __forceinline__ long item_index(const Params &P, int q, int x0,
+                                           int y0) {
+  const int i = q % BX - 1, j = q / BX - 1;
+  return P.off + (long)win_cj(P, y0, j + HB) * P.pitch + win_ui(P, x0, i + HB);
+}
+
+template <bool CL, bool IM, bool TV>
+__device__ __forceinline__ void u_item(Lds &s, const Params &P, int q, int x0,
+                                       int y0, double cu) {
+  const int i = q % BX - 1, j = q / BX - 1;
+  if (j <= TY - 1) {
+    double uh = U_(i, j), du = 0.0;
+    if (u_solved(s, P, i, j, x0 + i))
+      u_pseudo<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cu, uh, du);
+    UH_(i, j) = uh;
+    DU_(i, j) = du;
+  }
+}
+template <bool CL, bool IM, bool TV>
+__device__ __forceinline__ void v_item(Lds &s, const Params &P, int q, int x0,
+                                       int y0, double cv) {
+  const int i = q % BX - 1, j = q / BX - 1;
+  if (i <= TX - 1) {
+    double vh = V_(i, j), dv = 0.0;
+    if (v_solved(s, P, i, j, y0 + j))
+      v_pseudo<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cv, vh, dv);
+    VH_(i, j) = vh;
+    DV_(i, j) = dv;
+  }
+}
+
+template <int NTH>
+struct Items {
+  static constexpr int rounds = (3 * NT + NTH - 1) / NTH;
+  // item of thread t in round r, and its kind (0 cell, 1 u-face, 2 v-face)
+  static __device__ __forceinline__ int item(int t, int r) { return t + r * NTH; }
+};
+
+// Step constant (C_T, C_u or C_v) of the thread's item in every round, and
+// C_p of a cell thread's cell
+template <int NTH>
+__device__ __forceinline__ void item_consts(const Params &P, const Consts &C,
+                                            int x0, int y0, double c[],
+                                            double &cp) {
+  const int t = threadIdx.x;
+  cp = 0.0;
+#pragma unroll
+  for (int r = 0; r < Items<NTH>::rounds; r++) {
+    const int v = Items<NTH>::item(t, r), kind = v / NT, q = v - kind * NT;
+    c[r] = 0.0;
+    if (v < 3 * NT) {
+      const long k = item_index(P, q, x0, y0);
+      c[r] = kind == 0 ? C.CT[k] : (kind == 1 ? C.Cu[k] : C.Cv[k]);
+      if (kind == 0) cp = C.Cp[k];
+    }
+  }
+}
+
+// c: the step constants of the thread's items (item_consts); cp: C_p of a
+// cell thread's cell
+template <int NTH, bool CL, bool IM, bool TV, bool RS>
+__device__ void pass_body(Lds &s, const Params &P, const State n,
+                          const Resid X, int tile, int x0, int y0,
+                          const double c[], double cp) {
+  const int t = threadIdx.x;
+  const bool cellt = t < NT;
+  const int tx = t % BX, ty = t / BX;
+  const int i = tx - 1, j = ty - 1;  // cell threads: (i, j) in [-1, TX] x [-1, TY]
   const int gi = x0 + i, gj = y0 + j;
 
   // stage 1: face densities rho^u on [-1,TX] x [-2,TY], rho^v on
   // [-2,TX] x [-1,TY] (one combined loop)
-  for (int k = threadIdx.x; k < BX * (BY + 1) + (BX + 1) * BY; k += NT) {
+  for (int k = t; k < BX * (BY + 1) + (BX + 1) * BY; k += NTH) {
     if (k < BX * (BY + 1)) {
       const int fi = k % BX - 1, fj = k / BX - 2;
       RU_(fi, fj) = rho_xface<CL, TV>(s, P, fi, fj, x0 + fi, y0 + fj);
@@ -599,29 +719,27 @@ __device__ void pass_body(Lds &s, const Params &P, const State o,
 
   // stage 2: T on [-1,TX-1] x [-1,TY-1]; u-hat, d^u on [-1,TX] x [-1,TY-1];
   // v-hat, d^v on [-1,TX-1] x [-1,TY]
-  const long kc = P.off + (long)s.cj[j + HB] * P.pitch + s.ui[i + HB];
-  // the new T of a cell is read only by the thread that owns the cell
-  double tnew = T_(i, j);
-  if (i <= TX - 1 && j <= TY - 1 && FL_(i, j))
-    tnew = t_update<CL, IM, TV>(s, P, i, j, gi, gj, C.CT[kc]);
-  if (j <= TY - 1) {
-    double uh = U_(i, j), du = 0.0;
-    if (u_solved(s, P, i, j, gi))
-      u_pseudo<CL, IM, TV>(s, P, i, j, gi, gj, C.Cu[kc], uh, du);
-    UH_(i, j) = uh;
-    DU_(i, j) = du;
+  double tnew = 0.0;  // the new T of a cell thread's cell
+  if (cellt) {
+    tnew = T_(i, j);
+    if (i <= TX - 1 && j <= TY - 1 && FL_(i, j))
+      tnew = t_update<CL, IM, TV>(s, P, i, j, gi, gj, c[0]);
   }
-  if (i <= TX - 1) {
-    double vh = V_(i, j), dv = 0.0;
-    if (v_solved(s, P, i, j, gj))
-      v_pseudo<CL, IM, TV>(s, P, i, j, gi, gj, C.Cv[kc], vh, dv);
-    VH_(i, j) = vh;
-    DV_(i, j) = dv;
+  if constexpr (NTH == NT) {
+    u_item<CL, IM, TV>(s, P, t, x0, y0, c[1]);
+    v_item<CL, IM, TV>(s, P, t, x0, y0, c[2]);
+  } else {
+    static_assert(NTH == NTP, "two rounds");
+    if (!cellt) u_item<CL, IM, TV>(s, P, t - NT, x0, y0, c[0]);
+    if (t < NTP - NT)
+      u_item<CL, IM, TV>(s, P, t + NTP - NT, x0, y0, c[1]);
+    else
+      v_item<CL, IM, TV>(s, P, t + NTP - 2 * NT, x0, y0, c[1]);
   }
   __syncthreads();
 
   // stage 3: pressure (eqs pl23, pl24) on [-1,TX-1] x [-1,TY-1]
-  if (i <= TX - 1 && j <= TY - 1) {
+  if (cellt && i <= TX - 1 && j <= TY - 1) {
     double pnew = P_(i, j);
     if (FL_(i, j)) {
       const double dxi = DX_(i), dyj = DY_(j), dV = dxi * dyj;
@@ -630,7 +748,7 @@ __device__ void pass_body(Lds &s, const Params &P, const State o,
       const double bW = RU_(i, j) * UH_(i, j) * dyj, bE = RU_(i + 1, j) * UH_(i + 1, j) * dyj;
       const double bS = RV_(i, j) * VH_(i, j) * dxi, bN = RV_(i, j + 1) * VH_(i, j + 1) * dxi;
       const double a0 = dV / tnew + (aW + aE + aS + aN) * P.dt;
-      const double bp = C.Cp[kc] - (bE - bW + bN - bS) * P.dt;
+      const double bp = cp - (bE - bW + bN - bS) * P.dt;
       pnew = ((aW * P_(i - 1, j) + aE * P_(i + 1, j) + aS * P_(i, j - 1) +
                aN * P_(i, j + 1)) * P.dt + bp) / a0;
     }
@@ -640,7 +758,7 @@ __device__ void pass_body(Lds &s, const Params &P, const State o,
 
   // stage 4: velocities (eqs pl18, pl19); write the owned values
   double rv[NRES] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (i >= 0 && i < TX && j >= 0 && j < TY && gi < P.nx && gj < P.ny) {
+  if (cellt && i >= 0 && i < TX && j >= 0 && j < TY && gi < P.nx && gj < P.ny) {
     const long k = P.off + (long)gj * P.pitch + gi;
     const double pn = PN_(i, j);
     n.T[k] = tnew;
@@ -677,23 +795,28 @@ __device__ void pass_body(Lds &s, const Params &P, const State o,
       }
     }
   }
-  if (RS) block_partials<NT>(s.red, rv, X.partials + (long)tile * NRES);
+  if (RS) block_partials<NTH>(s.red, rv, X.partials + (long)tile * NRES);
 }
 
-// RS: last pass of a step, which also produces the residual inputs
-template <bool IM, bool TV, bool RS>
-__global__ __launch_bounds__(NT) void k_pass(const Params P, const State o,
-                                             const State n, const Consts C,
-                                             const Resid X) {
+// One pass over the tiles; RS: the last pass of a step, which also produces
+// the residual inputs.  Two blocks share a CU (LDS bound).  The explicit
+// schemes use NTP threads (6 waves per SIMD, at most 80 VGPRs); the
+// implicit ones need more registers and use NT threads (4 waves per SIMD,
+// at most 128 VGPRs).
+template <int NTH, bool IM, bool TV, bool RS>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_pass(
+    const Params P, const State o, const State n, const Consts C, const Resid X) {
   __shared__ Lds s;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
-  load_window(s, P, o, x0, y0);
+  double c[Items<NTH>::rounds], cp;
+  item_consts<NTH>(P, C, x0, y0, c, cp);
+  load_window<NTH>(s, P, o, x0, y0);
   __syncthreads();
   if (P.clean[tile])
-    pass_body<true, IM, TV, RS>(s, P, o, n, C, X, tile, x0, y0);
+    pass_body<NTH, true, IM, TV, RS>(s, P, n, X, tile, x0, y0, c, cp);
   else
-    pass_body<false, IM, TV, RS>(s, P, o, n, C, X, tile, x0, y0);
+    pass_body<NTH, false, IM, TV, RS>(s, P, n, X, tile, x0, y0, c, cp);
 }
 
 // ---------------------------------------------------------------------------
@@ -808,63 +931,83 @@ __device__ double v_explicit(const Lds &s, const Params &P, int i, int j,
          FbS * (upw(vS, vP, vbS) + (vP - vS) * ps);
 }
 
+// One prologue item (numbering as in the pass: cell, u-face, v-face) at an
+// owned position
 template <bool CL, bool EX, bool TV>
+__device__ __forceinline__ void prologue_item(const Lds &s, const Params &P,
+                                              const Consts &C, int v, int x0,
+                                              int y0) {
+  const int kind = v / NT, q = v - kind * NT;
+  const int i = q % BX - 1, j = q / BX - 1;
+  const int gi = x0 + i, gj = y0 + j;
+  if (i < 0 || i >= TX || j < 0 || j >= TY || gi >= P.nx || gj >= P.ny) return;
+  const long k = P.off + (long)gj * P.pitch + gi;
+  const double dxi = DX_(i), dyj = DY_(j);
+  if (kind == 0) {  // cell constants
+    double CT = 0.0, Cp = 0.0;
+    if (FL_(i, j)) {
+      const double dV = dxi * dyj;
+      CT = R_(i, j) * T_(i, j) * dV;
+      if (EX) CT += P.dt * t_explicit<CL, TV>(s, P, i, j, gi, gj);
+      Cp = R_(i, j) * dV;
+    }
+    C.CT[k] = CT;
+    C.Cp[k] = Cp;
+  } else if (kind == 1) {
+    double Cu = 0.0;
+    if (u_solved(s, P, i, j, gi)) {
+      const double M = (R_(i, j) * dxi + R_(i - 1, j) * DX_(i - 1)) * dyj / 2.0;
+      Cu = M * P.idt * U_(i, j) + P.gx * M;
+      if (EX) Cu += u_explicit<CL, TV>(s, P, i, j, gi, gj);
+    }
+    C.Cu[k] = Cu;
+  } else {
+    double Cv = 0.0;
+    if (v_solved(s, P, i, j, gj)) {
+      const double M = (R_(i, j) * dyj + R_(i, j - 1) * DY_(j - 1)) * dxi / 2.0;
+      Cv = M * P.idt * V_(i, j) + P.gy * M;
+      if (EX) Cv += v_explicit<CL, TV>(s, P, i, j, gi, gj);
+    }
+    C.Cv[k] = Cv;
+  }
+}
+
+template <int NTH, bool CL, bool EX, bool TV>
 __device__ void prologue_body(Lds &s, const Params &P, const Consts C, int x0,
                               int y0) {
   if (EX) {
-    for (int k = threadIdx.x; k < BX * (BY + 1); k += NT) {
-      const int fi = k % BX - 1, fj = k / BX - 2;
-      RU_(fi, fj) = rho_xface<CL, TV>(s, P, fi, fj, x0 + fi, y0 + fj);
-    }
-    for (int k = threadIdx.x; k < (BX + 1) * BY; k += NT) {
-      const int fi = k % (BX + 1) - 2, fj = k / (BX + 1) - 1;
-      RV_(fi, fj) = rho_yface<CL, TV>(s, P, fi, fj, y0 + fj);
+    for (int k = threadIdx.x; k < BX * (BY + 1) + (BX + 1) * BY; k += NTH) {
+      if (k < BX * (BY + 1)) {
+        const int fi = k % BX - 1, fj = k / BX - 2;
+        RU_(fi, fj) = rho_xface<CL, TV>(s, P, fi, fj, x0 + fi, y0 + fj);
+      } else {
+        const int q = k - BX * (BY + 1);
+        const int fi = q % (BX + 1) - 2, fj = q / (BX + 1) - 1;
+        RV_(fi, fj) = rho_yface<CL, TV>(s, P, fi, fj, y0 + fj);
+      }
     }
     __syncthreads();
   }
-  const int i = threadIdx.x % BX - 1, j = threadIdx.x / BX - 1;
-  const int gi = x0 + i, gj = y0 + j;
-  if (i < 0 || i >= TX || j < 0 || j >= TY) return;
-  if (gi >= P.nx || gj >= P.ny) return;
-  const long k = P.off + (long)gj * P.pitch + gi;
-  const double dxi = DX_(i), dyj = DY_(j);
-  // cell constants
-  double CT = 0.0, Cp = 0.0;
-  if (FL_(i, j)) {
-    const double dV = dxi * dyj;
-    CT = R_(i, j) * T_(i, j) * dV;
-    if (EX) CT += P.dt * t_explicit<CL, TV>(s, P, i, j, gi, gj);
-    Cp = R_(i, j) * dV;
-  }
-  C.CT[k] = CT;
-  C.Cp[k] = Cp;
-  double Cu = 0.0, Cv = 0.0;
-  if (u_solved(s, P, i, j, gi)) {
-    const double M = (R_(i, j) * dxi + R_(i - 1, j) * DX_(i - 1)) * dyj / 2.0;
-    Cu = M * P.idt * U_(i, j) + P.gx * M;
-    if (EX) Cu += u_explicit<CL, TV>(s, P, i, j, gi, gj);
-  }
-  if (v_solved(s, P, i, j, gj)) {
-    const double M = (R_(i, j) * dyj + R_(i, j - 1) * DY_(j - 1)) * dxi / 2.0;
-    Cv = M * P.idt * V_(i, j) + P.gy * M;
-    if (EX) Cv += v_explicit<CL, TV>(s, P, i, j, gi, gj);
-  }
-  C.Cu[k] = Cu;
-  C.Cv[k] = Cv;
+  // the items in rounds, one kind per wave and round
+#pragma unroll
+  for (int r = 0; r < Items<NTH>::rounds; r++)
+    prologue_item<CL, EX, TV>(s, P, C, Items<NTH>::item(threadIdx.x, r), x0, y0);
 }
 
-template <bool EX, bool TV>
-__global__ __launch_bounds__(NT) void k_prologue(const Params P, const State m,
-                                                 const Consts C) {
+// Two blocks share a CU (LDS bound); the explicit TVD terms need more
+// registers than 6 waves per SIMD allow, so that variant runs NT threads.
+template <int NTH, bool EX, bool TV>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_prologue(
+    const Params P, const State m, const Consts C) {
   __shared__ Lds s;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
-  load_window(s, P, m, x0, y0);
+  load_window<NTH>(s, P, m, x0, y0);
   __syncthreads();
   if (P.clean[tile])
-    prologue_body<true, EX, TV>(s, P, C, x0, y0);
+    prologue_body<NTH, true, EX, TV>(s, P, C, x0, y0);
   else
-    prologue_body<false, EX, TV>(s, P, C, x0, y0);
+    prologue_body<NTH, false, EX, TV>(s, P, C, x0, y0);
 }
 
 // ---------------------------------------------------------------------------
@@ -924,21 +1067,22 @@ static int ntiles(const Params &P) { return P.tiles_x * P.tiles_y; }
 void launch_prologue(const Params &P, State m, Consts C, int scheme,
                      hipStream_t st) {
   const bool ex = !(scheme & 1), tv = (scheme & 2) != 0;
-  dim3 g(ntiles(P)), b(NT);
-  if (ex && tv) hipLaunchKernelGGL((k_prologue<true, true>), g, b, 0, st, P, m, C);
-  else if (ex) hipLaunchKernelGGL((k_prologue<true, false>), g, b, 0, st, P, m, C);
-  else hipLaunchKernelGGL((k_prologue<false, false>), g, b, 0, st, P, m, C);
+  dim3 g(ntiles(P));
+  if (ex && tv) hipLaunchKernelGGL((k_prologue<NT, true, true>), g, dim3(NT), 0, st, P, m, C);
+  else if (ex) hipLaunchKernelGGL((k_prologue<NTP, true, false>), g, dim3(NTP), 0, st, P, m, C);
+  else hipLaunchKernelGGL((k_prologue<NTP, false, false>), g, dim3(NTP), 0, st, P, m, C);
 }
 
 void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
                  const Resid *last, hipStream_t st) {
   const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0;
-  dim3 g(ntiles(P)), b(NT);
+  dim3 g(ntiles(P));
   const Resid X = last ? *last : Resid{nullptr, nullptr, nullptr};
-#define STS_PASS(IM_, TV_)                                                          \
-  do {                                                                              \
-    if (last) hipLaunchKernelGGL((k_pass<IM_, TV_, true>), g, b, 0, st, P, o, n, C, X); \
-    else hipLaunchKernelGGL((k_pass<IM_, TV_, false>), g, b, 0, st, P, o, n, C, X);     \
+#define STS_PASS(IM_, TV_)                                                              \
+  do {                                                                                  \
+    constexpr int nth = IM_ ? NT : NTP;                                                 \
+    if (last) hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true>), g, dim3(nth), 0, st, P, o, n, C, X); \
+    else hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false>), g, dim3(nth), 0, st, P, o, n, C, X);     \
   } while (0)
   if (im && tv) STS_PASS(true, true);
   else if (im) STS_PASS(true, false);

@@ -96,6 +96,24 @@ def test_periodic_and_slip(sts_mod, oracle_lib, scheme):
              label="periodic")
 
 
+@pytest.mark.parametrize("scheme", list(W.SCHEMES.values()))
+def test_periodic_nonuniform_walls(sts_mod, oracle_lib, scheme):
+    # isothermal no-slip walls whose temperature varies along x: the cells and
+    # faces on both sides of the periodic seam read the wall data of their
+    # wrapped column; a ragged tile count (67 = 2 x 30 + 7) puts the seam
+    # inside the halo of a partial tile
+    nx = 67
+    x = (np.arange(nx) + 0.5) / nx
+    p = W.Problem(nx=nx, ny=12, lx=2.0, periodic=True, obstacles=[(20, 4, 24, 7)],
+                  wall_type=(W.WALL_NOSLIP_ISOTHERMAL, W.WALL_NOSLIP_ISOTHERMAL),
+                  wall_u=(0.2, -0.1),
+                  wall_T=(1.0 + 0.2 * np.sin(2 * np.pi * x) + 0.05 * x,
+                          1.1 - 0.15 * np.cos(4 * np.pi * x) - 0.03 * x),
+                  gx=0.1, Re=30.0)
+    run_pair(sts_mod, oracle_lib, p, 0.2 * 2.0 / nx, 8, 8, scheme, 23, amp=1e-2,
+             label="periodic-walls")
+
+
 @pytest.mark.parametrize("scheme", [W.EXPLICIT | W.TVD, W.IMPLICIT | W.UPWIND])
 def test_tiny_grid(sts_mod, oracle_lib, scheme):
     p = W.Problem(nx=4, ny=4, lx=1.0, ly=1.0)
