@@ -7,8 +7,12 @@ Jacobi passes of loop 2 and the residual reduction.  Inputs are synthetic
 (seeded noise on the inlet state) and resident in HBM before timing starts.
 
 Prints one JSON line: MFV-iterations/s (finite volumes x inner passes per
-second), the pass kernel's achieved bandwidth against the HBM roofline, and
-the FP64 CPU oracle timed on a bounded sample on the host cores.
+second), the pass kernel's achieved bandwidth against the HBM roofline, the
+FP64 CPU oracle timed on a bounded sample on the host cores, and the
+mixed-precision form of every scheme (FP32 coefficient assembly and Jacobi
+corrections through an FP64 defect): its rate, its speedup over the FP64 form
+and its max / L2 relative difference from the FP64 fields after the same
+steps.
 """
 from __future__ import annotations
 
@@ -53,7 +57,7 @@ def measured_traffic(scheme_name: str):
     return d.get("bytes_per_launch", {}).get(scheme_name)
 
 
-def run_gpu(name: str, steps: int, warmup: int, scheme: int):
+def run_gpu(name: str, steps: int, warmup: int, scheme: int, want_fields: bool = False):
     import torch
     from paper_1802_04243_amd import sts
 
@@ -74,6 +78,7 @@ def run_gpu(name: str, steps: int, warmup: int, scheme: int):
     res = g.residuals()
     ms, n = g.read_timing()
     g.timing(False)
+    fields = g.fields() if want_fields else None
     g.close()
     wall = t1 - t0
     fv_iters = p.n_fv * inner * steps
@@ -81,7 +86,17 @@ def run_gpu(name: str, steps: int, warmup: int, scheme: int):
     return dict(wall_s=wall, mfv_iters_s=fv_iters / wall / 1e6, ms_per_step=wall / steps * 1e3,
                 pass_ms=pass_ms, prologue_ms=ms[0] / max(n[0], 1), residual_ms=ms[2] / max(n[0], 1),
                 pass_gbs=BYTES_PER_FV_PASS * p.n_fv / (pass_ms * 1e-3) / 1e9,
-                residuals=[float(x) for x in res], nx=p.nx, ny=p.ny, dt=dt, inner=inner)
+                residuals=[float(x) for x in res], nx=p.nx, ny=p.ny, dt=dt, inner=inner,
+                fields=fields)
+
+
+def field_errors(fm, fd):
+    """max |a - b| / max |b| and rms(a - b) / rms(b) per field (u, v, p, T)."""
+    mx, l2 = {}, {}
+    for nm, a, b in zip("uvpT", fm, fd):
+        mx[nm] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+        l2[nm] = float(np.sqrt(np.mean((a - b) ** 2)) / max(np.sqrt(np.mean(b * b)), 1e-300))
+    return mx, l2
 
 
 def run_cpu_baseline(name: str, scheme: int, steps: int):
@@ -122,6 +137,7 @@ def main():
     ap.add_argument("--schemes", default="all", help="'all' or a comma list of scheme names")
     ap.add_argument("--cpu-baseline-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration)")
     a = ap.parse_args()
@@ -138,12 +154,25 @@ def main():
     if HEADLINE in names:
         names.remove(HEADLINE)
     names = [HEADLINE] + names
-    per = {}
+    per, mixed = {}, {}
     for nm in names:
-        per[nm] = run_gpu(a.workload, a.steps, a.warmup, W.SCHEMES[nm])
+        per[nm] = run_gpu(a.workload, a.steps, a.warmup, W.SCHEMES[nm], want_fields=not a.no_mixed)
         print(f"# {nm}: {per[nm]['mfv_iters_s']:.1f} MFV-iters/s, pass {per[nm]['pass_ms']:.3f} ms "
               f"({per[nm]['pass_gbs']:.0f} GB/s algorithmic), step {per[nm]['ms_per_step']:.2f} ms",
               file=sys.stderr, flush=True)
+        if a.no_mixed:
+            continue
+        m = run_gpu(a.workload, a.steps, a.warmup, W.SCHEMES[nm] | W.MIXED, want_fields=True)
+        mx, l2 = field_errors(m["fields"], per[nm]["fields"])
+        mixed[nm] = {"mfv_iters_s": round(m["mfv_iters_s"], 2),
+                     "speedup": round(m["mfv_iters_s"] / per[nm]["mfv_iters_s"], 4),
+                     "pass_ms": round(m["pass_ms"], 5),
+                     "max_rel_err_vs_fp64": {k: float(f"{v:.3e}") for k, v in mx.items()},
+                     "l2_rel_err_vs_fp64": {k: float(f"{v:.3e}") for k, v in l2.items()},
+                     "after_steps": a.warmup + a.steps}
+        per[nm]["fields"] = m["fields"] = None
+        print(f"# {nm}+mixed: {m['mfv_iters_s']:.1f} MFV-iters/s (x{mixed[nm]['speedup']:.3f}), "
+              f"max rel err {max(mx.values()):.2e}", file=sys.stderr, flush=True)
     h = per[HEADLINE]
     traffic = measured_traffic(HEADLINE)
     roof = dict(bound="hbm", achieved=round(h["pass_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -179,6 +208,7 @@ def main():
                          "residual_ms": round(r["residual_ms"], 4),
                          "max_residuals": r["residuals"][:5]}
                     for nm, r in per.items()},
+        "mixed": mixed or None,
     }
     if rank == 0:
         print(json.dumps(out), flush=True)

@@ -86,13 +86,20 @@ typedef struct {
 
 /* scheme bits for sts_step: convective terms explicit (Forward Euler) or
    implicit (Backward Euler) in time, upwind or TVD (van Leer) in space
-   (Sec. 3.1, the four variants). */
+   (Sec. 3.1, the four variants).  STS_MIXED selects the mixed-precision
+   form of any variant: the T, u and v coefficients are assembled and the
+   Jacobi corrections formed in FP32, applied to the FP64 state through an
+   FP64 defect of each equation; face densities, the pressure equation, the
+   velocity update, the per-step constants and the residuals stay FP64.  Its
+   results differ from the FP64 form at the level of FP32 rounding of the
+   coefficients (not bitwise). */
 enum {
   STS_EXPLICIT = 0,
   STS_IMPLICIT = 1,
   STS_UPWIND = 0,
   STS_TVD = 2,
-  STS_SCHEME_MASK = 3
+  STS_MIXED = 4,
+  STS_SCHEME_MASK = 7
 };
 
 /* Device bytes the library needs for a grid (state, per-step constants,

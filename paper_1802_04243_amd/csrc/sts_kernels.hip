@@ -175,7 +175,8 @@ constexpr int NW = LH * LW;  // cells of the window
 // Stage the old fields of the window [x0-3, x0+TX+2] x [y0-3, y0+TY+2] with
 // NTH threads: every global load of the thread is issued before the first
 // LDS store, so that their latencies overlap; the caller synchronises.
-template <int NTH>
+// MX: Gamma is only read by FP32 code (mixed form): FP32 square root.
+template <int NTH, bool MX = false>
 __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
                             int y0) {
   constexpr int WPT = (NW + NTH - 1) / NTH;  // window cells per thread
@@ -217,7 +218,7 @@ __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
       s.p[b][a] = pp[m];
       s.T[b][a] = tt[m];
       s.r[b][a] = pp[m] / tt[m];
-      s.g[b][a] = sqrt(tt[m]);
+      s.g[b][a] = MX ? (double)__builtin_amdgcn_sqrtf((float)tt[m]) : sqrt(tt[m]);
       s.fl[b][a] = ff[m];
       s.u[b][a] = uu[m];
       s.v[b][a] = vv[m];
@@ -245,10 +246,57 @@ __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
   }
 }
 
+// FP32 helpers of the mixed-precision form (see the mixed T, u, v updates)
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fdmax(float a, float b) { return a > b ? a : b; }
+__device__ __forceinline__ float vanleer_f(float a, float b) {
+  const bool pos = (a > 0.0f && b > 0.0f) || (a < 0.0f && b < 0.0f);
+  const float q = 2.0f * a * frcp(a + b);
+  return pos ? q : 0.0f;
+}
+// psi_s / psi_c with the node differences taken in FP64 (no cancellation)
+__device__ __forceinline__ float psi_sf_f(double f1, double f2, double f3,
+                                          double f4, float s12, float s23,
+                                          float s34, float w2, float w3,
+                                          float vel) {
+#pragma clang fp contract(fast)
+  const bool up = vel > 0.0f;
+  const float a = s23 * (float)(up ? f2 - f1 : f4 - f3);
+  const float b = (up ? s12 : s34) * (float)(f3 - f2);
+  const float w = up ? w2 : -w3;
+  return w * vanleer_f(a, b);
+}
+__device__ __forceinline__ float psi_c_f(double f1, double f2, double f3,
+                                         double f4, float d1, float d2,
+                                         float d3, float vel) {
+#pragma clang fp contract(fast)
+  const bool up = vel > 0.0f;
+  const float a = d2 * (float)(up ? f2 - f1 : f4 - f3);
+  const float b = (up ? d1 : d3) * (float)(f3 - f2);
+  return (up ? 0.5f : -0.5f) * vanleer_f(a, b);
+}
+__device__ __forceinline__ float hmean_f(float dl, float gl, float dr, float gr) {
+#pragma clang fp contract(fast)
+  return (dl + dr) * gl * gr * frcp(dl * gr + dr * gl);
+}
+__device__ __forceinline__ float hmean2_f(float a, float b) {
+#pragma clang fp contract(fast)
+  return 2.0f * a * b * frcp(a + b);
+}
+#define F_(x) ((float)(x))
+#define PSIXF(f1, f2, f3, f4, k, vel)                                               \
+  psi_sf_f(f1, f2, f3, f4, F_(SX_((k)-1)), F_(SX_(k)), F_(SX_((k) + 1)), F_(WRX_(k)), \
+           F_(WLX_(k)), vel)
+#define PSIYF(f1, f2, f3, f4, k, vel)                                               \
+  psi_sf_f(f1, f2, f3, f4, F_(SY_((k)-1)), F_(SY_(k)), F_(SY_((k) + 1)), F_(WRY_(k)), \
+           F_(WLY_(k)), vel)
+
 // ---------------------------------------------------------------------------
 // face densities (eqs pl10, pl11 read as upwind value + psi * jump)
 // ---------------------------------------------------------------------------
-template <bool CL, bool TV>
+// MX: the limiter in FP32 (mixed form); the density stays FP64
+template <bool CL, bool TV, bool MX = false>
 __device__ double rho_xface(const Lds &s, const Params &P, int i, int j,
                             int gi, int gj) {
   const double uf = U_(i, j);
@@ -258,11 +306,13 @@ __device__ double rho_xface(const Lds &s, const Params &P, int i, int j,
   }
   const double rl = R_(i - 1, j), rr = R_(i, j);
   double r = upw(rl, rr, uf);
-  if (TV && (CL || (FL_(i - 2, j) & FL_(i - 1, j) & FL_(i, j) & FL_(i + 1, j))))
-    r += PSIX(R_(i - 2, j), rl, rr, R_(i + 1, j), i, uf) * (rr - rl);
+  if (TV && (CL || (FL_(i - 2, j) & FL_(i - 1, j) & FL_(i, j) & FL_(i + 1, j)))) {
+    if (MX) r += (double)PSIXF(R_(i - 2, j), rl, rr, R_(i + 1, j), i, F_(uf)) * (rr - rl);
+    else r += PSIX(R_(i - 2, j), rl, rr, R_(i + 1, j), i, uf) * (rr - rl);
+  }
   return r;
 }
-template <bool CL, bool TV>
+template <bool CL, bool TV, bool MX = false>
 __device__ double rho_yface(const Lds &s, const Params &P, int i, int j,
                             int gj) {
   if (!CL) {
@@ -272,8 +322,10 @@ __device__ double rho_yface(const Lds &s, const Params &P, int i, int j,
   const double vf = V_(i, j);
   const double rs = R_(i, j - 1), rn = R_(i, j);
   double r = upw(rs, rn, vf);
-  if (TV && (CL || (FL_(i, j - 2) & FL_(i, j - 1) & FL_(i, j) & FL_(i, j + 1))))
-    r += PSIY(R_(i, j - 2), rs, rn, R_(i, j + 1), j, vf) * (rn - rs);
+  if (TV && (CL || (FL_(i, j - 2) & FL_(i, j - 1) & FL_(i, j) & FL_(i, j + 1)))) {
+    if (MX) r += (double)PSIYF(R_(i, j - 2), rs, rn, R_(i, j + 1), j, F_(vf)) * (rn - rs);
+    else r += PSIY(R_(i, j - 2), rs, rn, R_(i, j + 1), j, vf) * (rn - rs);
+  }
   return r;
 }
 
@@ -578,6 +630,313 @@ __device__ void v_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   dv = P.A * dxi / a0;
 }
 
+// ---------------------------------------------------------------------------
+// mixed-precision form of the T, u and v updates
+// ---------------------------------------------------------------------------
+// The coefficients (conductances, Gamma at corners, convective coefficients
+// and limiters, the energy source, the cross-diffusion) are assembled in
+// FP32 from FP64 state differences; each equation's defect
+//   r = sum_nb a_nb (phi_nb - phi_P) - (net outflow) phi_P
+//       + (C - a_unsteady phi_P) + (source)
+// is accumulated in FP64 with the FP64 unsteady part (C_T, C_u, C_v and
+// rho dV, M/dt of the iterate), and the Jacobi correction r / a0 is formed in
+// FP32 and added to the FP64 value.  Algebraically this is the FP64 update
+// (a0 phi_P + r = sum a_nb phi_nb + b); the fixed point of a pass is that of
+// the FP32-assembled operator.  FP32 divisions and square roots use the
+// hardware reciprocal / square root (about 1 ulp), and FP32 products may be
+// fused.
+template <bool CL>
+__device__ float gam_c_f(const Lds &s, const Params &P, int i, int j, int gi,
+                         int gj) {
+#pragma clang fp contract(fast)
+  if (!CL && (gj <= 0 || gj >= P.ny)) return 0.0f;
+  const float ws = F_(WLY_(j)), wn = F_(WRY_(j));
+  if (!CL && !P.per) {
+    if (gi == 0) return ws * F_(P.sq_T_in[gj - 1]) + wn * F_(P.sq_T_in[gj]);
+    if (gi == P.nx) return ws * F_(G_(i - 1, j - 1)) + wn * F_(G_(i - 1, j));
+  }
+  const float wl = F_(WLX_(i)), wr = F_(WRX_(i));
+  return ws * (wl * F_(G_(i - 1, j - 1)) + wr * F_(G_(i, j - 1))) +
+         wn * (wl * F_(G_(i - 1, j)) + wr * F_(G_(i, j)));
+}
+
+template <bool CL, bool IM, bool TV>
+__device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
+                              int gi, int gj, double CT) {
+#pragma clang fp contract(fast)
+  const float dxi = F_(DX_(i)), dyj = F_(DY_(j));
+  const float gP = F_(G_(i, j)), C1 = F_(P.C1), obs = F_(P.sq_obsT);
+  const double TP = T_(i, j);
+  double nW, nE, nS, nN;
+  float DW, DE, DS, DN;
+  if (!CL && !P.per && gi == 0) {
+    nW = P.T_in[gj];
+    DW = C1 * hmean2_f(gP, F_(P.sq_T_in[gj])) * dyj * (2.0f * F_(IDX_(i)));
+  } else {
+    nW = T_(i - 1, j);
+    if (!CL && !FL_(i - 1, j))
+      DW = C1 * hmean2_f(gP, obs) * dyj * (2.0f * F_(IDX_(i)));
+    else
+      DW = C1 * hmean_f(F_(DX_(i - 1)), F_(G_(i - 1, j)), dxi, gP) * dyj * (2.0f * F_(ISX_(i)));
+  }
+  if (!CL && !P.per && gi == P.nx - 1) {
+    nE = TP;
+    DE = 0.0f;
+  } else {
+    nE = T_(i + 1, j);
+    if (!CL && !FL_(i + 1, j))
+      DE = C1 * hmean2_f(gP, obs) * dyj * (2.0f * F_(IDX_(i)));
+    else
+      DE = C1 * hmean_f(dxi, gP, F_(DX_(i + 1)), F_(G_(i + 1, j))) * dyj * (2.0f * F_(ISX_(i + 1)));
+  }
+  if (!CL && gj == 0) {
+    if (P.wtype0 == 0) {
+      nS = P.Tw0[wall_c(s, P, i)];
+      DS = C1 * hmean2_f(gP, F_(P.sq_Tw0[wall_c(s, P, i)])) * dxi * (2.0f * F_(IDY_(j)));
+    } else {
+      nS = TP;
+      DS = 0.0f;
+    }
+  } else {
+    nS = T_(i, j - 1);
+    if (!CL && !FL_(i, j - 1))
+      DS = C1 * hmean2_f(gP, obs) * dxi * (2.0f * F_(IDY_(j)));
+    else
+      DS = C1 * hmean_f(F_(DY_(j - 1)), F_(G_(i, j - 1)), dyj, gP) * dxi * (2.0f * F_(ISY_(j)));
+  }
+  if (!CL && gj == P.ny - 1) {
+    if (P.wtype1 == 0) {
+      nN = P.Tw1[wall_c(s, P, i)];
+      DN = C1 * hmean2_f(gP, F_(P.sq_Tw1[wall_c(s, P, i)])) * dxi * (2.0f * F_(IDY_(j)));
+    } else {
+      nN = TP;
+      DN = 0.0f;
+    }
+  } else {
+    nN = T_(i, j + 1);
+    if (!CL && !FL_(i, j + 1))
+      DN = C1 * hmean2_f(gP, obs) * dxi * (2.0f * F_(IDY_(j)));
+    else
+      DN = C1 * hmean_f(dyj, gP, F_(DY_(j + 1)), F_(G_(i, j + 1))) * dxi * (2.0f * F_(ISY_(j + 1)));
+  }
+  float aW = DW, aE = DE, aS = DS, aN = DN, netF = 0.0f;
+  if (IM) {
+    const double uW = U_(i, j), uE = U_(i + 1, j), vS = V_(i, j), vN = V_(i, j + 1);
+    const float FW = F_(RU_(i, j)) * F_(uW) * dyj, FE = F_(RU_(i + 1, j)) * F_(uE) * dyj;
+    const float FS = F_(RV_(i, j)) * F_(vS) * dxi, FN = F_(RV_(i, j + 1)) * F_(vN) * dxi;
+    float pW = 0.0f, pE = 0.0f, pS = 0.0f, pN = 0.0f;
+    if (TV) {
+      if (CL || (FL_(i - 2, j) & FL_(i - 1, j) & FL_(i + 1, j)))
+        pW = PSIXF(T_(i - 2, j), T_(i - 1, j), TP, T_(i + 1, j), i, F_(uW));
+      if (CL || (FL_(i - 1, j) & FL_(i + 1, j) & FL_(i + 2, j)))
+        pE = PSIXF(T_(i - 1, j), TP, T_(i + 1, j), T_(i + 2, j), i + 1, F_(uE));
+      if (CL || (FL_(i, j - 2) & FL_(i, j - 1) & FL_(i, j + 1)))
+        pS = PSIYF(T_(i, j - 2), T_(i, j - 1), TP, T_(i, j + 1), j, F_(vS));
+      if (CL || (FL_(i, j - 1) & FL_(i, j + 1) & FL_(i, j + 2)))
+        pN = PSIYF(T_(i, j - 1), TP, T_(i, j + 1), T_(i, j + 2), j + 1, F_(vN));
+    }
+    aW = fdmax(0.0f, FW) - FW * pW + DW;
+    aE = fdmax(0.0f, -FE) - FE * pE + DE;
+    aS = fdmax(0.0f, FS) - FS * pS + DS;
+    aN = fdmax(0.0f, -FN) - FN * pN + DN;
+    netF = (FE - FW) + (FN - FS);
+  }
+  // source: viscous dissipation and pressure work, velocity differences in
+  // FP64 rounded once
+  const double vc = 0.5 * (V_(i, j) + V_(i, j + 1));
+  const double uc = 0.5 * (U_(i, j) + U_(i + 1, j));
+  double vE, vW, uN, uS;
+  if (!CL && !P.per && gi == P.nx - 1) vE = vc;
+  else if (!CL && !FL_(i + 1, j)) vE = 0.0;
+  else
+    vE = WLX_(i + 1) * vc + WRX_(i + 1) * (0.5 * (V_(i + 1, j) + V_(i + 1, j + 1)));
+  if (!CL && !P.per && gi == 0) vW = 0.0;
+  else if (!CL && !FL_(i - 1, j)) vW = 0.0;
+  else
+    vW = WLX_(i) * (0.5 * (V_(i - 1, j) + V_(i - 1, j + 1))) + WRX_(i) * vc;
+  if (!CL && gj == P.ny - 1) uN = (P.wtype1 == 0) ? P.wu1 : uc;
+  else if (!CL && !FL_(i, j + 1)) uN = 0.0;
+  else
+    uN = WLY_(j + 1) * uc + WRY_(j + 1) * (0.5 * (U_(i, j + 1) + U_(i + 1, j + 1)));
+  if (!CL && gj == 0) uS = (P.wtype0 == 0) ? P.wu0 : uc;
+  else if (!CL && !FL_(i, j - 1)) uS = 0.0;
+  else
+    uS = WLY_(j) * (0.5 * (U_(i, j - 1) + U_(i + 1, j - 1))) + WRY_(j) * uc;
+  const float idx = F_(IDX_(i)), idy = F_(IDY_(j)), dVf = dxi * dyj;
+  const float ux = F_(U_(i + 1, j) - U_(i, j)) * idx;
+  const float vy = F_(V_(i, j + 1) - V_(i, j)) * idy;
+  const float vx = F_(vE - vW) * idx, uy = F_(uN - uS) * idy;
+  const float dv = ux + vy;
+  const float Sc = F_(P.C2) * gP * (2.0f * (ux * ux + vy * vy) + (vx + uy) * (vx + uy) -
+                                    (2.0f / 3.0f) * dv * dv) * dVf +
+                   F_(P.C3) * F_(P_(i, j)) * dv * dVf;
+  // FP64 defect and FP32 correction
+  const double dV = DX_(i) * DY_(j), ru = R_(i, j) * dV;
+  const double r = P.dt * ((double)aW * (nW - TP) + (double)aE * (nE - TP) +
+                           (double)aS * (nS - TP) + (double)aN * (nN - TP) -
+                           (double)netF * TP + (double)Sc) +
+                   (CT - ru * TP);
+  const double a0 = P.dt * (double)(aW + aE + aS + aN + netF) + ru;
+  return TP + (double)(F_(r) * frcp(F_(a0)));
+}
+
+template <bool CL, bool IM, bool TV>
+__device__ void u_pseudo_mx(const Lds &s, const Params &P, int i, int j,
+                            int gi, int gj, double Cu, double &uh, double &du) {
+#pragma clang fp contract(fast)
+  const float dxl = F_(DX_(i - 1)), dxr = F_(DX_(i)), dyj = F_(DY_(j));
+  const float gl = F_(G_(i - 1, j)), gr = F_(G_(i, j)), B = F_(P.B);
+  const double uP = U_(i, j), uW = U_(i - 1, j), uE = U_(i + 1, j);
+  const double M = (R_(i, j) * DX_(i) + R_(i - 1, j) * DX_(i - 1)) * DY_(j) / 2.0;
+  const float len = 0.5f * (dxl + dxr);
+  const float gnode = F_(WLX_(i)) * gl + F_(WRX_(i)) * gr;
+  const float gcS = gam_c_f<CL>(s, P, i, j, gi, gj), gcN = gam_c_f<CL>(s, P, i, j + 1, gi, gj + 1);
+  double uS, uN;
+  float DS, DN;
+  if (!CL && gj == 0) {
+    if (P.wtype0 == 0) {
+      uS = P.wu0;
+      DS = B * 0.5f * (gnode + F_(P.sq_Twu0[wall_u(s, P, i)])) * len * (2.0f * F_(IDY_(j)));
+    } else {
+      uS = uP;
+      DS = 0.0f;
+    }
+  } else {
+    uS = U_(i, j - 1);
+    if (!CL && !FL_(i - 1, j - 1) && !FL_(i, j - 1))
+      DS = B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDY_(j)));
+    else
+      DS = B * gcS * F_(SX_(i)) * F_(ISY_(j));
+  }
+  if (!CL && gj == P.ny - 1) {
+    if (P.wtype1 == 0) {
+      uN = P.wu1;
+      DN = B * 0.5f * (gnode + F_(P.sq_Twu1[wall_u(s, P, i)])) * len * (2.0f * F_(IDY_(j)));
+    } else {
+      uN = uP;
+      DN = 0.0f;
+    }
+  } else {
+    uN = U_(i, j + 1);
+    if (!CL && !FL_(i - 1, j + 1) && !FL_(i, j + 1))
+      DN = B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDY_(j)));
+    else
+      DN = B * gcN * F_(SX_(i)) * F_(ISY_(j + 1));
+  }
+  const float DW = B * gl * dyj * F_(IDX_(i - 1)), DE = B * gr * dyj * F_(IDX_(i));
+  float aS = DS, aN = DN, aW = (4.0f / 3.0f) * DW, aE = (4.0f / 3.0f) * DE, conv = 0.0f;
+  if (IM) {
+    const float rl = F_(R_(i - 1, j)), rr = F_(R_(i, j));
+    const float Fs0 = F_(RV_(i, j)) * F_(V_(i, j)) * dxr, Fs1 = F_(RV_(i - 1, j)) * F_(V_(i - 1, j)) * dxl;
+    const float Fn0 = F_(RV_(i, j + 1)) * F_(V_(i, j + 1)) * dxr,
+                Fn1 = F_(RV_(i - 1, j + 1)) * F_(V_(i - 1, j + 1)) * dxl;
+    const float ubW = F_(0.5 * (uW + uP)), ubE = F_(0.5 * (uP + uE));
+    const float FbW = rl * ubW * dyj, FbE = rr * ubE * dyj;
+    float ps0 = 0.0f, ps1 = 0.0f, pn0 = 0.0f, pn1 = 0.0f, pw = 0.0f, pe = 0.0f;
+    if (TV) {
+      if (CL || (gj - 2 >= 0 && gj + 1 <= P.ny - 1)) {
+        const double f1 = U_(i, j - 2), f2 = U_(i, j - 1), f4 = U_(i, j + 1);
+        ps0 = PSIYF(f1, f2, uP, f4, j, F_(V_(i, j)));
+        ps1 = PSIYF(f1, f2, uP, f4, j, F_(V_(i - 1, j)));
+      }
+      if (CL || (gj - 1 >= 0 && gj + 2 <= P.ny - 1)) {
+        const double f1 = U_(i, j - 1), f3 = U_(i, j + 1), f4 = U_(i, j + 2);
+        pn0 = PSIYF(f1, uP, f3, f4, j + 1, F_(V_(i, j + 1)));
+        pn1 = PSIYF(f1, uP, f3, f4, j + 1, F_(V_(i - 1, j + 1)));
+      }
+      if (CL || P.per || (gi - 2 >= 0 && gi + 1 <= P.nx))
+        pw = psi_c_f(U_(i - 2, j), uW, uP, uE, F_(DX_(i - 2)), dxl, dxr, ubW);
+      if (CL || P.per || (gi - 1 >= 0 && gi + 2 <= P.nx))
+        pe = psi_c_f(uW, uP, uE, U_(i + 2, j), dxl, dxr, F_(DX_(i + 1)), ubE);
+    }
+    aS = 0.5f * (fdmax(0.0f, Fs0) - Fs0 * ps0 + fdmax(0.0f, Fs1) - Fs1 * ps1) + DS;
+    aN = 0.5f * (fdmax(0.0f, -Fn0) - Fn0 * pn0 + fdmax(0.0f, -Fn1) - Fn1 * pn1) + DN;
+    aW = fdmax(0.0f, FbW) - FbW * pw + (4.0f / 3.0f) * DW;
+    aE = fdmax(0.0f, -FbE) - FbE * pe + (4.0f / 3.0f) * DE;
+    conv = 0.5f * (Fn0 - Fs0 + Fn1 - Fs1) + FbE - FbW;
+  }
+  const float X = gcN * F_(V_(i, j + 1) - V_(i - 1, j + 1)) - gcS * F_(V_(i, j) - V_(i - 1, j)) -
+                  (2.0f / 3.0f) * gr * F_(V_(i, j + 1) - V_(i, j)) +
+                  (2.0f / 3.0f) * gl * F_(V_(i - 1, j + 1) - V_(i - 1, j));
+  const double mdt = M * P.idt;
+  const double r = (double)aS * (uS - uP) + (double)aN * (uN - uP) + (double)aW * (uW - uP) +
+                   (double)aE * (uE - uP) - (double)conv * uP + (Cu - mdt * uP) +
+                   (double)(B * X);
+  const float ia0 = frcp(F_((double)(aS + aN + aW + aE + conv) + mdt));
+  uh = uP + (double)(F_(r) * ia0);
+  du = (double)(F_(P.A) * dyj * ia0);
+}
+
+template <bool CL, bool IM, bool TV>
+__device__ void v_pseudo_mx(const Lds &s, const Params &P, int i, int j,
+                            int gi, int gj, double Cv, double &vh, double &dv) {
+#pragma clang fp contract(fast)
+  const float dxi = F_(DX_(i)), dys = F_(DY_(j - 1)), dyn = F_(DY_(j));
+  const float gs = F_(G_(i, j - 1)), gn = F_(G_(i, j)), B = F_(P.B);
+  const double vP = V_(i, j), vS = V_(i, j - 1), vN = V_(i, j + 1);
+  const double vW = (!CL && !P.per && gi == 0) ? 0.0 : V_(i - 1, j);
+  const double vE = (!CL && !P.per && gi == P.nx - 1) ? vP : V_(i + 1, j);
+  const double M = (R_(i, j) * DY_(j) + R_(i, j - 1) * DY_(j - 1)) * DX_(i) / 2.0;
+  const float len = 0.5f * (dys + dyn);
+  const float gnode = F_(WLY_(j)) * gs + F_(WRY_(j)) * gn;
+  const float gcW = gam_c_f<CL>(s, P, i, j, gi, gj), gcE = gam_c_f<CL>(s, P, i + 1, j, gi + 1, gj);
+  float DW, DE;
+  if (!CL && !P.per && gi == 0)
+    DW = B * 0.5f * (gnode + gcW) * len * (2.0f * F_(IDX_(i)));
+  else if (!CL && !FL_(i - 1, j - 1) && !FL_(i - 1, j))
+    DW = B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDX_(i)));
+  else
+    DW = B * gcW * F_(SY_(j)) * F_(ISX_(i));
+  if (!CL && !P.per && gi == P.nx - 1)
+    DE = 0.0f;
+  else if (!CL && !FL_(i + 1, j - 1) && !FL_(i + 1, j))
+    DE = B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDX_(i)));
+  else
+    DE = B * gcE * F_(SY_(j)) * F_(ISX_(i + 1));
+  const float DS = B * gs * dxi * F_(IDY_(j - 1)), DN = B * gn * dxi * F_(IDY_(j));
+  float aW = DW, aE = DE, aS = (4.0f / 3.0f) * DS, aN = (4.0f / 3.0f) * DN, conv = 0.0f;
+  if (IM) {
+    const float rs = F_(R_(i, j - 1)), rn = F_(R_(i, j));
+    const float Fw0 = F_(RU_(i, j)) * F_(U_(i, j)) * dyn, Fw1 = F_(RU_(i, j - 1)) * F_(U_(i, j - 1)) * dys;
+    const float Fe0 = F_(RU_(i + 1, j)) * F_(U_(i + 1, j)) * dyn,
+                Fe1 = F_(RU_(i + 1, j - 1)) * F_(U_(i + 1, j - 1)) * dys;
+    const float vbS = F_(0.5 * (vS + vP)), vbN = F_(0.5 * (vP + vN));
+    const float FbS = rs * vbS * dxi, FbN = rn * vbN * dxi;
+    float pw0 = 0.0f, pw1 = 0.0f, pe0 = 0.0f, pe1 = 0.0f, ps = 0.0f, pn = 0.0f;
+    if (TV) {
+      if (CL || P.per || (gi - 2 >= 0 && gi + 1 <= P.nx - 1)) {
+        const double f1 = V_(i - 2, j), f4 = V_(i + 1, j);
+        pw0 = PSIXF(f1, vW, vP, f4, i, F_(U_(i, j)));
+        pw1 = PSIXF(f1, vW, vP, f4, i, F_(U_(i, j - 1)));
+      }
+      if (CL || P.per || (gi - 1 >= 0 && gi + 2 <= P.nx - 1)) {
+        const double f1 = V_(i - 1, j), f4 = V_(i + 2, j);
+        pe0 = PSIXF(f1, vP, vE, f4, i + 1, F_(U_(i + 1, j)));
+        pe1 = PSIXF(f1, vP, vE, f4, i + 1, F_(U_(i + 1, j - 1)));
+      }
+      if (CL || (gj - 2 >= 0 && gj + 1 <= P.ny))
+        ps = psi_c_f(V_(i, j - 2), vS, vP, vN, F_(DY_(j - 2)), dys, dyn, vbS);
+      if (CL || (gj - 1 >= 0 && gj + 2 <= P.ny))
+        pn = psi_c_f(vS, vP, vN, V_(i, j + 2), dys, dyn, F_(DY_(j + 1)), vbN);
+    }
+    aW = 0.5f * (fdmax(0.0f, Fw0) - Fw0 * pw0 + fdmax(0.0f, Fw1) - Fw1 * pw1) + DW;
+    aE = 0.5f * (fdmax(0.0f, -Fe0) - Fe0 * pe0 + fdmax(0.0f, -Fe1) - Fe1 * pe1) + DE;
+    aS = fdmax(0.0f, FbS) - FbS * ps + (4.0f / 3.0f) * DS;
+    aN = fdmax(0.0f, -FbN) - FbN * pn + (4.0f / 3.0f) * DN;
+    conv = 0.5f * (Fe0 - Fw0 + Fe1 - Fw1) + FbN - FbS;
+  }
+  const float X = gcE * F_(U_(i + 1, j) - U_(i + 1, j - 1)) - gcW * F_(U_(i, j) - U_(i, j - 1)) -
+                  (2.0f / 3.0f) * gn * F_(U_(i + 1, j) - U_(i, j)) +
+                  (2.0f / 3.0f) * gs * F_(U_(i + 1, j - 1) - U_(i, j - 1));
+  const double mdt = M * P.idt;
+  const double r = (double)aW * (vW - vP) + (double)aE * (vE - vP) + (double)aS * (vS - vP) +
+                   (double)aN * (vN - vP) - (double)conv * vP + (Cv - mdt * vP) +
+                   (double)(B * X);
+  const float ia0 = frcp(F_((double)(aW + aE + aS + aN + conv) + mdt));
+  vh = vP + (double)(F_(r) * ia0);
+  dv = (double)(F_(P.A) * dxi * ia0);
+}
+
 // unknown tests (the same rules as the boundary-value projection)
 __device__ __forceinline__ bool u_solved(const Lds &s, const Params &P, int i,
                                          int j, int gi) {
@@ -639,26 +998,30 @@ __device__ __forceinline__ long item_index(const Params &P, int q, int x0,
   return P.off + (long)win_cj(P, y0, j + HB) * P.pitch + win_ui(P, x0, i + HB);
 }
 
-template <bool CL, bool IM, bool TV>
+template <bool CL, bool IM, bool TV, bool MX>
 __device__ __forceinline__ void u_item(Lds &s, const Params &P, int q, int x0,
                                        int y0, double cu) {
   const int i = q % BX - 1, j = q / BX - 1;
   if (j <= TY - 1) {
     double uh = U_(i, j), du = 0.0;
-    if (u_solved(s, P, i, j, x0 + i))
-      u_pseudo<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cu, uh, du);
+    if (u_solved(s, P, i, j, x0 + i)) {
+      if (MX) u_pseudo_mx<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cu, uh, du);
+      else u_pseudo<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cu, uh, du);
+    }
     UH_(i, j) = uh;
     DU_(i, j) = du;
   }
 }
-template <bool CL, bool IM, bool TV>
+template <bool CL, bool IM, bool TV, bool MX>
 __device__ __forceinline__ void v_item(Lds &s, const Params &P, int q, int x0,
                                        int y0, double cv) {
   const int i = q % BX - 1, j = q / BX - 1;
   if (i <= TX - 1) {
     double vh = V_(i, j), dv = 0.0;
-    if (v_solved(s, P, i, j, y0 + j))
-      v_pseudo<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cv, vh, dv);
+    if (v_solved(s, P, i, j, y0 + j)) {
+      if (MX) v_pseudo_mx<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cv, vh, dv);
+      else v_pseudo<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cv, vh, dv);
+    }
     VH_(i, j) = vh;
     DV_(i, j) = dv;
   }
@@ -678,6 +1041,14 @@ __device__ __forceinline__ void item_consts(const Params &P, const Consts &C,
                                             int x0, int y0, double c[],
                                             double &cp) {
   const int t = threadIdx.x;
+  if constexpr (NTH == NT) {  // the three items share the thread's (i, j)
+    const long k = item_index(P, t, x0, y0);
+    c[0] = C.CT[k];
+    c[1] = C.Cu[k];
+    c[2] = C.Cv[k];
+    cp = C.Cp[k];
+    return;
+  }
   cp = 0.0;
 #pragma unroll
   for (int r = 0; r < Items<NTH>::rounds; r++) {
@@ -693,7 +1064,7 @@ __device__ __forceinline__ void item_consts(const Params &P, const Consts &C,
 
 // c: the step constants of the thread's items (item_consts); cp: C_p of a
 // cell thread's cell
-template <int NTH, bool CL, bool IM, bool TV, bool RS>
+template <int NTH, bool CL, bool IM, bool TV, bool RS, bool MX>
 __device__ void pass_body(Lds &s, const Params &P, const State n,
                           const Resid X, int tile, int x0, int y0,
                           const double c[], double cp) {
@@ -708,11 +1079,11 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
   for (int k = t; k < BX * (BY + 1) + (BX + 1) * BY; k += NTH) {
     if (k < BX * (BY + 1)) {
       const int fi = k % BX - 1, fj = k / BX - 2;
-      RU_(fi, fj) = rho_xface<CL, TV>(s, P, fi, fj, x0 + fi, y0 + fj);
+      RU_(fi, fj) = rho_xface<CL, TV, MX>(s, P, fi, fj, x0 + fi, y0 + fj);
     } else {
       const int q = k - BX * (BY + 1);
       const int fi = q % (BX + 1) - 2, fj = q / (BX + 1) - 1;
-      RV_(fi, fj) = rho_yface<CL, TV>(s, P, fi, fj, y0 + fj);
+      RV_(fi, fj) = rho_yface<CL, TV, MX>(s, P, fi, fj, y0 + fj);
     }
   }
   __syncthreads();
@@ -723,18 +1094,19 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
   if (cellt) {
     tnew = T_(i, j);
     if (i <= TX - 1 && j <= TY - 1 && FL_(i, j))
-      tnew = t_update<CL, IM, TV>(s, P, i, j, gi, gj, c[0]);
+      tnew = MX ? t_update_mx<CL, IM, TV>(s, P, i, j, gi, gj, c[0])
+                : t_update<CL, IM, TV>(s, P, i, j, gi, gj, c[0]);
   }
   if constexpr (NTH == NT) {
-    u_item<CL, IM, TV>(s, P, t, x0, y0, c[1]);
-    v_item<CL, IM, TV>(s, P, t, x0, y0, c[2]);
+    u_item<CL, IM, TV, MX>(s, P, t, x0, y0, c[1]);
+    v_item<CL, IM, TV, MX>(s, P, t, x0, y0, c[2]);
   } else {
     static_assert(NTH == NTP, "two rounds");
-    if (!cellt) u_item<CL, IM, TV>(s, P, t - NT, x0, y0, c[0]);
+    if (!cellt) u_item<CL, IM, TV, MX>(s, P, t - NT, x0, y0, c[0]);
     if (t < NTP - NT)
-      u_item<CL, IM, TV>(s, P, t + NTP - NT, x0, y0, c[1]);
+      u_item<CL, IM, TV, MX>(s, P, t + NTP - NT, x0, y0, c[1]);
     else
-      v_item<CL, IM, TV>(s, P, t + NTP - 2 * NT, x0, y0, c[1]);
+      v_item<CL, IM, TV, MX>(s, P, t + NTP - 2 * NT, x0, y0, c[1]);
   }
   __syncthreads();
 
@@ -799,11 +1171,12 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
 }
 
 // One pass over the tiles; RS: the last pass of a step, which also produces
-// the residual inputs.  Two blocks share a CU (LDS bound).  The explicit
-// schemes use NTP threads (6 waves per SIMD, at most 80 VGPRs); the
-// implicit ones need more registers and use NT threads (4 waves per SIMD,
-// at most 128 VGPRs).
-template <int NTH, bool IM, bool TV, bool RS>
+// the residual inputs; MX: the mixed-precision form of the T, u, v updates.
+// Two blocks share a CU (LDS bound).  The explicit schemes use NTP threads
+// (6 waves per SIMD, at most 80 VGPRs); the implicit ones and the mixed
+// explicit TVD pass need more registers and use NT threads (4 waves per
+// SIMD, at most 128 VGPRs).
+template <int NTH, bool IM, bool TV, bool RS, bool MX>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_pass(
     const Params P, const State o, const State n, const Consts C, const Resid X) {
   __shared__ Lds s;
@@ -811,12 +1184,12 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
   double c[Items<NTH>::rounds], cp;
   item_consts<NTH>(P, C, x0, y0, c, cp);
-  load_window<NTH>(s, P, o, x0, y0);
+  load_window<NTH, MX>(s, P, o, x0, y0);
   __syncthreads();
   if (P.clean[tile])
-    pass_body<NTH, true, IM, TV, RS>(s, P, n, X, tile, x0, y0, c, cp);
+    pass_body<NTH, true, IM, TV, RS, MX>(s, P, n, X, tile, x0, y0, c, cp);
   else
-    pass_body<NTH, false, IM, TV, RS>(s, P, n, X, tile, x0, y0, c, cp);
+    pass_body<NTH, false, IM, TV, RS, MX>(s, P, n, X, tile, x0, y0, c, cp);
 }
 
 // ---------------------------------------------------------------------------
@@ -931,13 +1304,13 @@ __device__ double v_explicit(const Lds &s, const Params &P, int i, int j,
          FbS * (upw(vS, vP, vbS) + (vP - vS) * ps);
 }
 
-// One prologue item (numbering as in the pass: cell, u-face, v-face) at an
-// owned position
-template <bool CL, bool EX, bool TV>
+// One prologue item of kind KIND (0 cell, 1 u-face, 2 v-face) at position q
+// (numbering as in the pass), if that position is owned
+template <int KIND, bool CL, bool EX, bool TV>
 __device__ __forceinline__ void prologue_item(const Lds &s, const Params &P,
-                                              const Consts &C, int v, int x0,
+                                              const Consts &C, int q, int x0,
                                               int y0) {
-  const int kind = v / NT, q = v - kind * NT;
+  constexpr int kind = KIND;
   const int i = q % BX - 1, j = q / BX - 1;
   const int gi = x0 + i, gj = y0 + j;
   if (i < 0 || i >= TX || j < 0 || j >= TY || gi >= P.nx || gj >= P.ny) return;
@@ -988,10 +1361,20 @@ __device__ void prologue_body(Lds &s, const Params &P, const Consts C, int x0,
     }
     __syncthreads();
   }
-  // the items in rounds, one kind per wave and round
-#pragma unroll
-  for (int r = 0; r < Items<NTH>::rounds; r++)
-    prologue_item<CL, EX, TV>(s, P, C, Items<NTH>::item(threadIdx.x, r), x0, y0);
+  // the items in rounds, one kind per wave and round; with NT threads each
+  // thread takes its cell and the two faces on its low side
+  const int t = threadIdx.x;
+  if constexpr (NTH == NT) {
+    prologue_item<0, CL, EX, TV>(s, P, C, t, x0, y0);
+    prologue_item<1, CL, EX, TV>(s, P, C, t, x0, y0);
+    prologue_item<2, CL, EX, TV>(s, P, C, t, x0, y0);
+  } else {
+    static_assert(NTH == NTP, "two rounds");
+    if (t < NT) prologue_item<0, CL, EX, TV>(s, P, C, t, x0, y0);
+    else prologue_item<1, CL, EX, TV>(s, P, C, t - NT, x0, y0);
+    if (t < NTP - NT) prologue_item<1, CL, EX, TV>(s, P, C, t + NTP - NT, x0, y0);
+    else prologue_item<2, CL, EX, TV>(s, P, C, t + NTP - 2 * NT, x0, y0);
+  }
 }
 
 // Two blocks share a CU (LDS bound); the explicit TVD terms need more
@@ -1075,19 +1458,28 @@ void launch_prologue(const Params &P, State m, Consts C, int scheme,
 
 void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
                  const Resid *last, hipStream_t st) {
-  const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0;
+  const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0, mx = (scheme & 4) != 0;
   dim3 g(ntiles(P));
   const Resid X = last ? *last : Resid{nullptr, nullptr, nullptr};
-#define STS_PASS(IM_, TV_)                                                              \
-  do {                                                                                  \
-    constexpr int nth = IM_ ? NT : NTP;                                                 \
-    if (last) hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true>), g, dim3(nth), 0, st, P, o, n, C, X); \
-    else hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false>), g, dim3(nth), 0, st, P, o, n, C, X);     \
+#define STS_PASS(IM_, TV_, MX_)                                                             \
+  do {                                                                                      \
+    constexpr int nth = (IM_ || (MX_ && TV_)) ? NT : NTP;                                   \
+    if (last)                                                                               \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true, MX_>), g, dim3(nth), 0, st, P, o, n, C, X); \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_>), g, dim3(nth), 0, st, P, o, n, C, X); \
   } while (0)
-  if (im && tv) STS_PASS(true, true);
-  else if (im) STS_PASS(true, false);
-  else if (tv) STS_PASS(false, true);
-  else STS_PASS(false, false);
+  if (mx) {
+    if (im && tv) STS_PASS(true, true, true);
+    else if (im) STS_PASS(true, false, true);
+    else if (tv) STS_PASS(false, true, true);
+    else STS_PASS(false, false, true);
+  } else {
+    if (im && tv) STS_PASS(true, true, false);
+    else if (im) STS_PASS(true, false, false);
+    else if (tv) STS_PASS(false, true, false);
+    else STS_PASS(false, false, false);
+  }
 #undef STS_PASS
 }
 

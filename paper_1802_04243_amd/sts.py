@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsts.so")
 
 STS_OK, STS_EINVAL, STS_ENOMEM, STS_EDEVICE, STS_ENONFINITE, STS_ESTATE = 0, -1, -2, -3, -4, -5
-EXPLICIT, IMPLICIT, UPWIND, TVD = 0, 1, 0, 2
+EXPLICIT, IMPLICIT, UPWIND, TVD, MIXED = 0, 1, 0, 2, 4
 
 # every symbol the header declares
 EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_residuals", "sts_fields",

@@ -22,6 +22,7 @@ import numpy as np
 
 EXPLICIT, IMPLICIT = 0, 1
 UPWIND, TVD = 0, 2
+MIXED = 4  # mixed-precision form of any of the four variants
 SCHEMES = {
     "explicit_upwind": EXPLICIT | UPWIND,
     "explicit_tvd": EXPLICIT | TVD,

@@ -19,3 +19,14 @@ def oracle_lib():
     if not os.path.exists(O._LIB_PATH):
         O.build()
     return O
+
+
+@pytest.fixture(scope="session")
+def sts_mod():
+    """The HIP library's binding (skips without a GPU)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_04243_amd import sts
+    sts.lib()
+    return sts

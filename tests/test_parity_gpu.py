@@ -18,15 +18,6 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
-@pytest.fixture(scope="module")
-def sts_mod():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_1802_04243_amd import sts
-    sts.lib()
-    return sts
-
 
 def normdiff(a, b):
     den = np.abs(b).max()
