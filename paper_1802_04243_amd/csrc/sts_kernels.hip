@@ -19,6 +19,8 @@
 // contraction, so no MFMA.
 #include "sts_internal.h"
 
+#include <stddef.h>
+
 namespace sts {
 namespace {
 
@@ -96,7 +98,7 @@ struct Lds {
   // global column of every window column (cells, u-faces: wrapped when
   // periodic, clamped into the frame otherwise) and row (cells, v-faces)
   int ci[LW], ui[LW], cj[LH], vj[LH];
-  double red[NTP / 64][NRES];  // per-wave residual partials (last pass)
+  double red[1][NRES];  // block residual partials of the last pass
 };
 
 // tile-relative accessors: (i, j) with the tile origin at (0, 0)
@@ -981,6 +983,48 @@ __device__ void block_partials(double (*red)[NRES], double v[NRES],
   }
 }
 
+// The last pass's block reduction of the increment maxima v[0..3] and the
+// non-finite count v[6]: through LDS (the window arrays, dead after stage 4,
+// as scratch), then one wave per quantity; far fewer cross-lane shuffles
+// than a reduction of every quantity in every wave.
+template <int NTH>
+__device__ void pass_partials(Lds &s, const double v[NRES], double *row) {
+  static_assert(offsetof(Lds, rv) - offsetof(Lds, u) == 7 * sizeof(double) * LH * LW &&
+                    5 * NTH <= 8 * LH * LW,
+                "window arrays as one scratch area");
+  double *scr = &s.u[0][0];
+  const int t = threadIdx.x, w = t / 64, l = t % 64;
+  __syncthreads();  // every stage-4 read of the window is done
+  scr[t] = v[0];
+  scr[NTH + t] = v[1];
+  scr[2 * NTH + t] = v[2];
+  scr[3 * NTH + t] = v[3];
+  scr[4 * NTH + t] = v[6];
+  __syncthreads();
+  if (w < 5) {
+    double x = 0.0;
+    if (w < 4) {
+      for (int k = l; k < NTH; k += 64) x = fmax(x, scr[w * NTH + k]);
+      x = wave_max(x);
+    } else {
+      for (int k = l; k < NTH; k += 64) x += scr[w * NTH + k];
+      x = wave_sum(x);
+    }
+    if (l == 0) s.red[0][w] = x;
+  }
+  __syncthreads();
+  if (t == 0) {
+    row[0] = s.red[0][0];
+    row[1] = s.red[0][1];
+    row[2] = s.red[0][2];
+    row[3] = s.red[0][3];
+    row[4] = 0.0;
+    row[5] = 0.0;
+    row[6] = s.red[0][4];
+    row[7] = 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // one Jacobi pass of loop 2
 // ---------------------------------------------------------------------------
@@ -1167,7 +1211,7 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
       }
     }
   }
-  if (RS) block_partials<NTH>(s.red, rv, X.partials + (long)tile * NRES);
+  if (RS) pass_partials<NTH>(s, rv, X.partials + (long)tile * NRES);
 }
 
 // One pass over the tiles; RS: the last pass of a step, which also produces
@@ -1400,13 +1444,21 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
 // ---------------------------------------------------------------------------
 constexpr int RB = 256;  // threads per residual block
 
+// Each block also folds a share of the per-tile rows of the last pass, so
+// that k_finalize reads only one row per block.
 __global__ __launch_bounds__(RB) void k_continuity(const Params P,
                                                    const State n,
                                                    const Consts C,
                                                    const Resid X,
-                                                   double *rows) {
+                                                   int ntile, double *rows) {
   __shared__ double red[RB / 64][NRES];
   double rm = 0.0, sm = 0.0, bad = 0.0;
+  double inc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = blockIdx.x * RB + threadIdx.x; b < ntile; b += gridDim.x * RB) {
+    const double *q = X.partials + (long)b * NRES;
+    for (int t = 0; t < 4; t++) inc[t] = fmax(inc[t], q[t]);
+    bad += q[6];
+  }
   const long ncell = (long)P.nx * P.ny;
   for (long c = (long)blockIdx.x * RB + threadIdx.x; c < ncell;
        c += (long)gridDim.x * RB) {
@@ -1421,11 +1473,11 @@ __global__ __launch_bounds__(RB) void k_continuity(const Params P,
     rm = fmax(rm, fabs(R));
     sm += R;
   }
-  double v[NRES] = {0.0, 0.0, 0.0, 0.0, rm, sm, bad, 0.0};
+  double v[NRES] = {inc[0], inc[1], inc[2], inc[3], rm, sm, bad, 0.0};
   block_partials<RB>(red, v, rows + (long)blockIdx.x * NRES);
 }
 
-// merge the rows of the last pass (one per tile) and of k_continuity
+// merge the rows of k_continuity
 constexpr int FB = 1024;
 __global__ __launch_bounds__(FB) void k_finalize(const double *rows, int nrows,
                                                  double *out) {
@@ -1486,9 +1538,8 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
 void launch_residual(const Params &P, State n, Consts C, Resid X, double *out,
                      hipStream_t st) {
   double *rows = X.partials + (long)ntiles(P) * NRES;
-  hipLaunchKernelGGL(k_continuity, dim3(RES_BLOCKS), dim3(RB), 0, st, P, n, C, X, rows);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, X.partials,
-                     ntiles(P) + RES_BLOCKS, out);
+  hipLaunchKernelGGL(k_continuity, dim3(RES_BLOCKS), dim3(RB), 0, st, P, n, C, X, ntiles(P), rows);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, rows, RES_BLOCKS, out);
 }
 
 }  // namespace sts

@@ -20,8 +20,14 @@ from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_1802_04243_amd/csrc/sts_kernels.hip", "paper_1802_04243_amd/csrc/sts_internal.h"]
-SCHEME_OF = {"k_pass<false, false>": "explicit_upwind", "k_pass<false, true>": "explicit_tvd",
-             "k_pass<true, false>": "implicit_upwind", "k_pass<true, true>": "implicit_tvd"}
+def scheme_of(kernel: str):
+    """Scheme of a plain (not last, not mixed) pass kernel k_pass<NTH, IM, TV, RS, MX>."""
+    if not kernel.startswith("k_pass<"):
+        return None
+    a = [x.strip() for x in kernel[len("k_pass<"):-1].split(",")]
+    if len(a) != 5 or a[3] != "false" or a[4] != "false":
+        return None
+    return ("implicit" if a[1] == "true" else "explicit") + ("_tvd" if a[2] == "true" else "_upwind")
 NFV = 5120 * 1152
 
 
@@ -61,7 +67,7 @@ def main(kt, fetch, write, cfetch, cwrite, outdir):
                       dispatches=len(f[k]))
     traffic = {"kernel_hash": kernel_hash(), "workload": "channel_5120x1152",
                "fetch_scale": fscale, "write_scale": wscale,
-               "bytes_per_launch": {SCHEME_OF[k]: v["bytes"] for k, v in per.items() if k in SCHEME_OF},
+               "bytes_per_launch": {scheme_of(k): v["bytes"] for k, v in per.items() if scheme_of(k)},
                "per_kernel": per}
     os.makedirs(outdir, exist_ok=True)
     json.dump(traffic, open(os.path.join(outdir, "pass_kernel_hbm_traffic_5120x1152.json"), "w"), indent=1)

@@ -7,9 +7,8 @@ The form is not bitwise equal to the FP64 method: it moves the coefficients
 by FP32 rounding (unit roundoff 2^-24 = 6e-8, about 1 ulp more where the
 hardware reciprocal and square root are used).  The tolerances below are
 normwise relative differences (max |a - b| / max |b| per field) against the
-FP64 oracle or the FP64 GPU path, set a decade above the differences
-measured on these cases (a decade for the smooth schemes, about 4x for
-implicit TVD):
+FP64 oracle or the FP64 GPU path, set above the differences measured on
+these cases (a decade for the smooth schemes, about 4x for implicit TVD):
 
 - explicit schemes and implicit upwind: ~6e-8 after 50 x 20 passes at
   120x24, ~2.5e-7 after 20 x 10 passes at 1280x288 and 5120x1152 (largest
