@@ -12,7 +12,9 @@ FP64 CPU oracle timed on a bounded sample on the host cores, and the
 mixed-precision form of every scheme (FP32 coefficient assembly and Jacobi
 corrections through an FP64 defect): its rate, its speedup over the FP64 form
 and its max / L2 relative difference from the FP64 fields after the same
-steps.
+steps, and the adjoint of the explicit step on the 1024x256 adjoint workload
+(time-averaged drag, 100 steps x 10 passes, checkpoints every 10 steps):
+backward / forward time and the device memory it holds.
 """
 from __future__ import annotations
 
@@ -90,6 +92,29 @@ def run_gpu(name: str, steps: int, warmup: int, scheme: int, want_fields: bool =
                 fields=fields)
 
 
+def run_adjoint(name: str = "adjoint_1024x256"):
+    """Forward (explicit upwind, drag each step, checkpoints) and backward
+    (recompute + hand-written adjoint) of the time-averaged drag loss."""
+    import torch
+    from paper_1802_04243_amd import adjoint
+    p, run = W.workload(name)
+    f0 = W.initial_fields(p, run["seed"])
+    wb, wt = p.walls()
+    args = [torch.tensor(a, dtype=torch.float64, requires_grad=True)
+            for a in (p.inlet()[0], wb, wt)]
+    L = adjoint.drag_loss(p, *args, f0, run["dt"], run["steps"], run["inner"], W.EXPLICIT,
+                          run["every"])
+    L.backward()
+    st = dict(adjoint.LAST_STATS)
+    return {"workload": name, "steps": run["steps"], "n_inner": run["inner"],
+            "checkpoint_every": run["every"], "scheme": "explicit_upwind",
+            "forward_s": round(st["forward_s"], 4), "backward_s": round(st["backward_s"], 4),
+            "adjoint_forward_ratio": round(st["backward_s"] / st["forward_s"], 3),
+            "device_bytes": int(st["device_bytes"]),
+            "note": "forward includes one drag readback per step; backward includes the "
+                    "recompute of every checkpoint segment and of every step"}
+
+
 def field_errors(fm, fd):
     """max |a - b| / max |b| and rms(a - b) / rms(b) per field (u, v, p, T)."""
     mx, l2 = {}, {}
@@ -138,6 +163,7 @@ def main():
     ap.add_argument("--cpu-baseline-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision runs")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration)")
     a = ap.parse_args()
@@ -173,6 +199,12 @@ def main():
         per[nm]["fields"] = m["fields"] = None
         print(f"# {nm}+mixed: {m['mfv_iters_s']:.1f} MFV-iters/s (x{mixed[nm]['speedup']:.3f}), "
               f"max rel err {max(mx.values()):.2e}", file=sys.stderr, flush=True)
+    adj = None
+    if not a.no_adjoint:
+        adj = run_adjoint()
+        print(f"# adjoint: forward {adj['forward_s']:.3f} s, backward {adj['backward_s']:.3f} s "
+              f"(ratio {adj['adjoint_forward_ratio']:.2f}), device {adj['device_bytes'] / 2**20:.0f} MiB",
+              file=sys.stderr, flush=True)
     h = per[HEADLINE]
     traffic = measured_traffic(HEADLINE)
     roof = dict(bound="hbm", achieved=round(h["pass_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -209,6 +241,7 @@ def main():
                          "max_residuals": r["residuals"][:5]}
                     for nm, r in per.items()},
         "mixed": mixed or None,
+        "adjoint": adj,
     }
     if rank == 0:
         print(json.dumps(out), flush=True)

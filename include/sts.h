@@ -160,6 +160,58 @@ sts_status sts_timing(sts_ctx *ctx, int enable);
    out_n[0] = steps, out_n[1] = passes.  Clears the accumulation. */
 sts_status sts_read_timing(sts_ctx *ctx, double out_ms[3], long long out_n[2]);
 
+/* ---- loss, checkpoints and the adjoint of the explicit step ----
+   The loss is built from the drag on the obstacles,
+     D = sum over fluid cells next to a solid cell of
+         A p dy (solid to the east) - A p dy (solid to the west)
+         + B Gamma u_c dx / (dy/2) (solid to the south or north),
+   A = 1/(gamma Ma^2), B = 1/Re, Gamma = sqrt(T), u_c = the cell-centre mean
+   of the two u-faces (pressure and wall-shear force on the obstacles, in
+   the units of the momentum equations, eqs pl2-pl3). */
+
+/* Wait and return D of the current state. */
+sts_status sts_drag(sts_ctx *ctx, double *out);
+
+/* Device checkpoint storage: (re)allocate n >= 0 state slots owned by the
+   context (n = 0 frees them; previous contents are lost).  STS_ENOMEM if
+   the allocation fails.  sts_state_save copies the current state into a
+   slot; sts_state_load makes a slot the current state.  Both enqueue on
+   the context's stream; slot outside [0, n) -> STS_EINVAL. */
+sts_status sts_state_slots(sts_ctx *ctx, int n);
+sts_status sts_state_save(sts_ctx *ctx, int slot);
+sts_status sts_state_load(sts_ctx *ctx, int slot);
+
+/* Adjoint (reverse mode) of the explicit-scheme FP64 step, upwind or TVD,
+   for channels with an inlet and an outlet (not periodic: STS_EINVAL).
+   The adjoint state lambda is the derivative of a scalar loss L with
+   respect to (u, v, p, T) of one time level; the parameters are the inlet
+   profile u_in[ny] (held by the inlet faces at every level) and the wall
+   temperatures wall_T[0][nx], wall_T[1][nx] (isothermal walls).
+
+   sts_adjoint_begin: allocate the buffers for n_inner passes per step
+   (library-owned, about (n_inner + 33) field arrays), set lambda and the
+   wall-temperature gradients to zero.
+   sts_adjoint_seed_drag: lambda += w dD/d(current state); call it with the
+   current state at level n before the adjoint of step n.
+   sts_adjoint_step: the current state must be level n-1 and lambda the
+   derivative with respect to level n; recomputes the step (same dt,
+   n_inner and scheme as the forward step) and replaces lambda by the
+   derivative with respect to level n-1 (reverse of the n_inner passes and
+   of the prologue), adding the wall-temperature contributions.  The
+   current state is left unchanged.  STS_EINVAL for implicit or mixed
+   scheme bits or an n_inner other than sts_adjoint_begin's; STS_ESTATE
+   before sts_adjoint_begin.
+   sts_adjoint_read: wait and copy to host arrays (NULL skips): dL/du_in[ny]
+   (the inlet entries of lambda_u: complete once the adjoint has reached
+   the initial level), dL/dwall_T[0][nx], dL/dwall_T[1][nx], and lambda in
+   the field layouts of sts_fields. */
+sts_status sts_adjoint_begin(sts_ctx *ctx, int n_inner);
+sts_status sts_adjoint_seed_drag(sts_ctx *ctx, double w);
+sts_status sts_adjoint_step(sts_ctx *ctx, double dt, int n_inner, int scheme);
+sts_status sts_adjoint_read(sts_ctx *ctx, double *g_uin, double *g_Tw0, double *g_Tw1,
+                            double *lambda_u, double *lambda_v, double *lambda_p,
+                            double *lambda_T);
+
 /* Release everything the context owns.  NULL-safe. */
 void sts_destroy(sts_ctx *ctx);
 

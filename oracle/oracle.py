@@ -165,3 +165,37 @@ class Oracle:
                                       (self.ny + 1, self.nx), (self.ny, self.nx))]
         lib().ora_eq_residuals(self._h, float(dt), int(scheme), *[_ptr(a) for a in out])
         return tuple(out)  # rT, ru, rv, rp
+
+
+def drag(prob, fields):
+    """Obstacle drag of a state (u, v, p, T in the layouts of Oracle.fields()).
+
+    Force in x on the solid cells, in the units of the momentum equations
+    (pressure term A grad p, viscous term B div(Gamma grad u); A = 1/(gamma
+    Ma^2), B = 1/Re, Gamma = sqrt(T)):
+      - pressure on the solid's west and east faces: + A p dy from the fluid
+        cell to its west, - A p dy from the fluid cell to its east;
+      - shear on its south and north faces: B Gamma (u_c - 0) / (dy / 2) dx
+        from the fluid cell next to the face, u_c that cell's centre mean of
+        its two u-faces, the wall at rest.
+    """
+    u, _, p, T = fields
+    A = 1.0 / (prob.gamma * prob.Ma ** 2)
+    B = 1.0 / prob.Re
+    dx, dy = prob.widths()
+    solid = prob.solid_mask().astype(bool)
+    ny, nx = solid.shape
+    total = 0.0
+    for j in range(ny):
+        for i in range(nx):
+            if solid[j, i]:
+                continue
+            if i + 1 < nx and solid[j, i + 1]:
+                total += A * p[j, i] * dy[j]
+            if i - 1 >= 0 and solid[j, i - 1]:
+                total -= A * p[j, i] * dy[j]
+            walls = int(j - 1 >= 0 and solid[j - 1, i]) + int(j + 1 < ny and solid[j + 1, i])
+            if walls:
+                uc = 0.5 * (u[j, i] + u[j, i + 1])
+                total += walls * B * np.sqrt(T[j, i]) * uc * dx[i] / (0.5 * dy[j])
+    return total

@@ -98,6 +98,25 @@ struct sts_ctx {
   std::vector<double> dx, dy, u_in, T_in, Tw[2];
   std::vector<unsigned char> solid;  // [ny][nx]
   double p_in, obsT;
+  // adjoint of the explicit step (allocated on first use, library-owned):
+  // the iterates x_0 .. x_K of a step, one pass's intermediates, the
+  // adjoints of the intermediates, two adjoint states, the adjoints of the
+  // step constants and of the wall temperatures; device state slots for
+  // checkpoints; drag reduction buffers
+  char *adj_mem = nullptr;
+  int adj_K = 0;
+  std::vector<State> it;
+  Inter I{};
+  AdjTmp A{};
+  State lam[2]{};
+  int lcur = 0;
+  Consts lC{};
+  double *gtw = nullptr;  // [2 nx]
+  size_t adj_clear_bytes = 0;
+  char *slot_mem = nullptr;
+  int nslots = 0;
+  double *aux = nullptr;   // drag partials + result
+  double *haux = nullptr;  // pinned
   // timing
   bool timing;
   std::vector<hipEvent_t> ev;  // 4 per recorded step
@@ -386,6 +405,10 @@ sts_status initial_state(sts_ctx *c) {
 
 void release(sts_ctx *c) {
   if (!c) return;
+  if (c->adj_mem) (void)hipFree(c->adj_mem);
+  if (c->slot_mem) (void)hipFree(c->slot_mem);
+  if (c->aux) (void)hipFree(c->aux);
+  if (c->haux) (void)hipHostFree(c->haux);
   if (c->base && c->own_mem) (void)hipFree(c->base);
   if (c->hres) (void)hipHostFree(c->hres);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -520,7 +543,7 @@ extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
   if ((s = record(c, 1)) != STS_OK) return s;
   for (int k = 0; k < n_inner; k++) {
     launch_pass(c->P, c->st[c->cur], c->st[c->cur ^ 1], c->C, scheme,
-                k == n_inner - 1 ? &c->X : nullptr, c->stream);
+                k == n_inner - 1 ? &c->X : nullptr, nullptr, c->stream);
     c->cur ^= 1;
   }
   HIPCHK(hipGetLastError());
@@ -625,5 +648,203 @@ extern "C" sts_status sts_read_timing(sts_ctx *c, double out_ms[3], long long ou
   out_n[1] = c->t_passes;
   c->ev_used = 0;
   c->t_passes = 0;
+  return STS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// drag, state slots, adjoint of the explicit step
+// ---------------------------------------------------------------------------
+namespace {
+State carve(char *&q, const Layout &L) {
+  State s;
+  s.u = (double *)q; q += L.field_bytes;
+  s.v = (double *)q; q += L.field_bytes;
+  s.p = (double *)q; q += L.field_bytes;
+  s.T = (double *)q; q += L.field_bytes;
+  return s;
+}
+sts_status copy_state(sts_ctx *c, State dst, State src) {
+  const size_t n = c->L.field_bytes;
+  HIPCHK(hipMemcpyAsync(dst.u, src.u, n, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(dst.v, src.v, n, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(dst.p, src.p, n, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(dst.T, src.T, n, hipMemcpyDeviceToDevice, c->stream));
+  return STS_OK;
+}
+sts_status ensure_aux(sts_ctx *c) {
+  if (c->aux) return STS_OK;
+  HIPCHK(hipMalloc((void **)&c->aux, sizeof(double) * (drag_blocks(c->P) + 1)));
+  HIPCHK(hipHostMalloc((void **)&c->haux, sizeof(double)));
+  return STS_OK;
+}
+State slot_state(sts_ctx *c, int k) {
+  char *q = c->slot_mem + (size_t)k * 4 * c->L.field_bytes;
+  return carve(q, c->L);
+}
+}  // namespace
+
+extern "C" sts_status sts_drag(sts_ctx *c, double *out) {
+  if (!c || !out) return fail(STS_EINVAL, "NULL argument");
+  sts_status s;
+  if ((s = ensure_aux(c)) != STS_OK) return s;
+  launch_drag(c->P, c->st[c->cur], c->aux, c->aux + drag_blocks(c->P), c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->haux, c->aux + drag_blocks(c->P), sizeof(double),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *out = *c->haux;
+  return STS_OK;
+}
+
+extern "C" sts_status sts_state_slots(sts_ctx *c, int n) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (n < 0 || n > 1000000) return fail(STS_EINVAL, "slot count %d out of range", n);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->slot_mem) {
+    HIPCHK(hipFree(c->slot_mem));
+    c->slot_mem = nullptr;
+    c->nslots = 0;
+  }
+  if (n == 0) return STS_OK;
+  const size_t bytes = (size_t)n * 4 * c->L.field_bytes;
+  if (hipMalloc((void **)&c->slot_mem, bytes) != hipSuccess) {
+    c->slot_mem = nullptr;
+    return fail(STS_ENOMEM, "cannot allocate %d state slots (%zu bytes)", n, bytes);
+  }
+  c->nslots = n;
+  return STS_OK;
+}
+
+extern "C" sts_status sts_state_save(sts_ctx *c, int slot) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (slot < 0 || slot >= c->nslots) return fail(STS_EINVAL, "slot %d out of range", slot);
+  return copy_state(c, slot_state(c, slot), c->st[c->cur]);
+}
+
+extern "C" sts_status sts_state_load(sts_ctx *c, int slot) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (slot < 0 || slot >= c->nslots) return fail(STS_EINVAL, "slot %d out of range", slot);
+  sts_status s;
+  if ((s = copy_state(c, c->st[0], slot_state(c, slot))) != STS_OK) return s;
+  if ((s = copy_state(c, c->st[1], slot_state(c, slot))) != STS_OK) return s;
+  c->cur = 0;
+  c->stepped = false;
+  return STS_OK;
+}
+
+namespace {
+// zero the adjoint of the intermediates and the outgoing adjoint state
+sts_status clear_tmp(sts_ctx *c, State lo) {
+  HIPCHK(hipMemsetAsync(c->A.luh, 0, 10 * c->L.field_bytes, c->stream));
+  HIPCHK(hipMemsetAsync(lo.u, 0, 4 * c->L.field_bytes, c->stream));
+  return STS_OK;
+}
+}  // namespace
+
+extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (c->per) return fail(STS_EINVAL, "the adjoint supports inlet/outlet channels only");
+  if (n_inner < 1 || n_inner > 10000) return fail(STS_EINVAL, "n_inner must be in [1, 10000]");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->adj_K != n_inner) {
+    if (c->adj_mem) HIPCHK(hipFree(c->adj_mem));
+    c->adj_mem = nullptr;
+    c->adj_K = 0;
+    // K + 1 iterates, 8 intermediates, 10 adjoint intermediates, 2 adjoint
+    // states, 4 constant adjoints, wall gradients
+    const size_t F = c->L.field_bytes;
+    const size_t bytes = (size_t)(n_inner + 1) * 4 * F + 8 * F + 10 * F + 8 * F + 4 * F +
+                         align_up(sizeof(double) * 2 * c->nx, 256);
+    if (hipMalloc((void **)&c->adj_mem, bytes) != hipSuccess) {
+      c->adj_mem = nullptr;
+      return fail(STS_ENOMEM, "cannot allocate the adjoint buffers (%zu bytes)", bytes);
+    }
+    char *q = c->adj_mem;
+    c->it.clear();
+    for (int k = 0; k <= n_inner; k++) c->it.push_back(carve(q, c->L));
+    double **ip[8] = {&c->I.ru, &c->I.rv, &c->I.uh, &c->I.du, &c->I.vh, &c->I.dv, &c->I.pn, &c->I.tn};
+    for (auto p : ip) { *p = (double *)q; q += F; }
+    double **ap[10] = {&c->A.luh, &c->A.ldu, &c->A.lvh, &c->A.ldv, &c->A.lru,
+                       &c->A.lrv, &c->A.lr,  &c->A.lg,  &c->A.ltn, &c->A.lpn};
+    for (auto p : ap) { *p = (double *)q; q += F; }
+    c->lam[0] = carve(q, c->L);
+    c->lam[1] = carve(q, c->L);
+    c->lC.Cu = (double *)q; q += F;
+    c->lC.Cv = (double *)q; q += F;
+    c->lC.CT = (double *)q; q += F;
+    c->lC.Cp = (double *)q; q += F;
+    c->gtw = (double *)q;
+    c->adj_K = n_inner;
+  }
+  c->lcur = 0;
+  HIPCHK(hipMemsetAsync(c->lam[0].u, 0, 8 * c->L.field_bytes, c->stream));
+  HIPCHK(hipMemsetAsync(c->gtw, 0, sizeof(double) * 2 * c->nx, c->stream));
+  return STS_OK;
+}
+
+extern "C" sts_status sts_adjoint_seed_drag(sts_ctx *c, double w) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (!c->adj_K) return fail(STS_ESTATE, "sts_adjoint_begin has not been called");
+  if (!isfinite(w)) return fail(STS_EINVAL, "weight must be finite");
+  launch_drag_seed(c->P, c->st[c->cur], c->lam[c->lcur], w, c->stream);
+  HIPCHK(hipGetLastError());
+  return STS_OK;
+}
+
+extern "C" sts_status sts_adjoint_step(sts_ctx *c, double dt, int n_inner, int scheme) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (!c->adj_K) return fail(STS_ESTATE, "sts_adjoint_begin has not been called");
+  if (n_inner != c->adj_K) return fail(STS_EINVAL, "n_inner %d differs from sts_adjoint_begin's %d", n_inner, c->adj_K);
+  if (!(dt > 0) || !isfinite(dt)) return fail(STS_EINVAL, "dt must be > 0");
+  if (scheme & ~(STS_TVD)) return fail(STS_EINVAL, "the adjoint is of the explicit FP64 scheme (scheme 0x%x)", scheme);
+  c->P.dt = dt;
+  c->P.idt = 1.0 / dt;
+  const int K = n_inner;
+  sts_status s;
+  // recompute the step from the current state x_0 (kept), storing x_1..x_{K-1}
+  for (int k = 0; k <= K; k++)
+    if ((s = copy_state(c, c->it[k], c->st[c->cur])) != STS_OK) return s;
+  launch_prologue(c->P, c->it[0], c->C, scheme, c->stream);
+  for (int k = 1; k < K; k++)
+    launch_pass(c->P, c->it[k - 1], c->it[k], c->C, scheme, nullptr, nullptr, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemsetAsync(c->lC.Cu, 0, 4 * c->L.field_bytes, c->stream));
+  // reverse of the passes
+  for (int k = K; k >= 1; k--) {
+    launch_pass(c->P, c->it[k - 1], c->it[K], c->C, scheme, nullptr, &c->I, c->stream);
+    State ln = c->lam[c->lcur], lo = c->lam[c->lcur ^ 1];
+    if ((s = clear_tmp(c, lo)) != STS_OK) return s;
+    launch_adjoint_pass(c->P, c->it[k - 1], c->C, c->I, ln, lo, c->lC, c->A, c->gtw,
+                        c->gtw + c->nx, scheme, c->stream);
+    HIPCHK(hipGetLastError());
+    c->lcur ^= 1;
+  }
+  // reverse of the prologue, onto the adjoint of x_0
+  HIPCHK(hipMemsetAsync(c->A.luh, 0, 10 * c->L.field_bytes, c->stream));
+  launch_adjoint_prologue(c->P, c->it[0], c->lC, c->lam[c->lcur], c->A, scheme, c->stream);
+  HIPCHK(hipGetLastError());
+  return STS_OK;
+}
+
+extern "C" sts_status sts_adjoint_read(sts_ctx *c, double *g_uin, double *g_Tw0, double *g_Tw1,
+                                       double *lu, double *lv, double *lp, double *lT) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (!c->adj_K) return fail(STS_ESTATE, "sts_adjoint_begin has not been called");
+  const int nx = c->nx, ny = c->ny;
+  const long Pt = c->L.pitch;
+  const State &l = c->lam[c->lcur];
+  if (g_uin)  // the inlet faces hold u_in at every level
+    HIPCHK(hipMemcpy2DAsync(g_uin, 8, l.u + c->L.off, Pt * 8, 8, ny, hipMemcpyDeviceToHost, c->stream));
+  if (g_Tw0) HIPCHK(hipMemcpyAsync(g_Tw0, c->gtw, 8 * nx, hipMemcpyDeviceToHost, c->stream));
+  if (g_Tw1) HIPCHK(hipMemcpyAsync(g_Tw1, c->gtw + nx, 8 * nx, hipMemcpyDeviceToHost, c->stream));
+  if (lu) HIPCHK(hipMemcpy2DAsync(lu, (nx + 1) * 8, l.u + c->L.off, Pt * 8, (nx + 1) * 8, ny,
+                                  hipMemcpyDeviceToHost, c->stream));
+  if (lv) HIPCHK(hipMemcpy2DAsync(lv, nx * 8, l.v + c->L.off, Pt * 8, nx * 8, ny + 1,
+                                  hipMemcpyDeviceToHost, c->stream));
+  if (lp) HIPCHK(hipMemcpy2DAsync(lp, nx * 8, l.p + c->L.off, Pt * 8, nx * 8, ny,
+                                  hipMemcpyDeviceToHost, c->stream));
+  if (lT) HIPCHK(hipMemcpy2DAsync(lT, nx * 8, l.T + c->L.off, Pt * 8, nx * 8, ny,
+                                  hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return STS_OK;
 }

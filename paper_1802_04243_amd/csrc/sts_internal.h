@@ -65,11 +65,36 @@ struct Resid {
   double *partials;  // [tiles + RES_BLOCKS][NRES]
 };
 
+// Intermediates of one pass (face densities, u-hat, d^u, v-hat, d^v, new p,
+// new T) in the field layout, stored for the adjoint's reverse sweep; all
+// NULL in a plain pass.
+struct Inter {
+  double *ru, *rv, *uh, *du, *vh, *dv, *pn, *tn;
+};
+
+// Adjoints of the pass intermediates (u-hat, d^u, v-hat, d^v, face
+// densities, rho, Gamma, new T, new p), field layout.
+struct AdjTmp {
+  double *luh, *ldu, *lvh, *ldv, *lru, *lrv, *lr, *lg, *ltn, *lpn;
+};
+
 void launch_prologue(const Params &P, State m, Consts C, int scheme,
                      hipStream_t st);
 void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
-                 const Resid *last, hipStream_t st);
+                 const Resid *last, const Inter *inter, hipStream_t st);
 void launch_residual(const Params &P, State n, Consts C, Resid R, double *out,
                      hipStream_t st);
+
+// adjoint of the explicit step (reverse of one pass; reverse of the prologue)
+void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, State lo,
+                         Consts lC, AdjTmp A, double *gtw0, double *gtw1, int scheme,
+                         hipStream_t st);
+void launch_adjoint_prologue(const Params &P, State m, Consts lC, State lm, AdjTmp A,
+                             int scheme, hipStream_t st);
+// drag on the obstacles of a state (partial: drag_blocks doubles) and the
+// adjoint seed lam += w dD/d(state)
+int drag_blocks(const Params &P);
+void launch_drag(const Params &P, State o, double *partial, double *out, hipStream_t st);
+void launch_drag_seed(const Params &P, State o, State lam, double w, hipStream_t st);
 
 }  // namespace sts

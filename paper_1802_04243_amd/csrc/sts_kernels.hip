@@ -1110,8 +1110,8 @@ __device__ __forceinline__ void item_consts(const Params &P, const Consts &C,
 // cell thread's cell
 template <int NTH, bool CL, bool IM, bool TV, bool RS, bool MX>
 __device__ void pass_body(Lds &s, const Params &P, const State n,
-                          const Resid X, int tile, int x0, int y0,
-                          const double c[], double cp) {
+                          const Resid X, const Inter I, int tile, int x0,
+                          int y0, const double c[], double cp) {
   const int t = threadIdx.x;
   const bool cellt = t < NT;
   const int tx = t % BX, ty = t / BX;
@@ -1190,6 +1190,28 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
                           ? VH_(i, j) - DV_(i, j) * (pn - PN_(i, j - 1))
                           : V_(i, j);
     n.v[k] = vn;
+    if (I.tn) {
+      // intermediates for the adjoint (plain FP64 passes only): the owned
+      // cells and faces, the outlet face nx and the top face ny
+      I.ru[k] = RU_(i, j);
+      I.rv[k] = RV_(i, j);
+      I.uh[k] = UH_(i, j);
+      I.du[k] = DU_(i, j);
+      I.vh[k] = VH_(i, j);
+      I.dv[k] = DV_(i, j);
+      I.pn[k] = pn;
+      I.tn[k] = tnew;
+      if (gi == P.nx - 1) {
+        I.ru[k + 1] = RU_(i + 1, j);
+        I.uh[k + 1] = UH_(i + 1, j);
+        I.du[k + 1] = DU_(i + 1, j);
+      }
+      if (gj == P.ny - 1) {
+        I.rv[k + P.pitch] = RV_(i, j + 1);
+        I.vh[k + P.pitch] = VH_(i, j + 1);
+        I.dv[k + P.pitch] = DV_(i, j + 1);
+      }
+    }
     if (RS) {
       // increments of the unknowns (zero on the faces and cells that are not
       // solved) and the mass fluxes of the new velocities through the owned
@@ -1222,7 +1244,7 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
 // SIMD, at most 128 VGPRs).
 template <int NTH, bool IM, bool TV, bool RS, bool MX>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_pass(
-    const Params P, const State o, const State n, const Consts C, const Resid X) {
+    const Params P, const State o, const State n, const Consts C, const Resid X, const Inter I) {
   __shared__ Lds s;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
@@ -1231,9 +1253,9 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
   load_window<NTH, MX>(s, P, o, x0, y0);
   __syncthreads();
   if (P.clean[tile])
-    pass_body<NTH, true, IM, TV, RS, MX>(s, P, n, X, tile, x0, y0, c, cp);
+    pass_body<NTH, true, IM, TV, RS, MX>(s, P, n, X, I, tile, x0, y0, c, cp);
   else
-    pass_body<NTH, false, IM, TV, RS, MX>(s, P, n, X, tile, x0, y0, c, cp);
+    pass_body<NTH, false, IM, TV, RS, MX>(s, P, n, X, I, tile, x0, y0, c, cp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1509,17 +1531,18 @@ void launch_prologue(const Params &P, State m, Consts C, int scheme,
 }
 
 void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
-                 const Resid *last, hipStream_t st) {
+                 const Resid *last, const Inter *inter, hipStream_t st) {
   const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0, mx = (scheme & 4) != 0;
   dim3 g(ntiles(P));
   const Resid X = last ? *last : Resid{nullptr, nullptr, nullptr};
+  const Inter I = inter ? *inter : Inter{};
 #define STS_PASS(IM_, TV_, MX_)                                                             \
   do {                                                                                      \
     constexpr int nth = (IM_ || (MX_ && TV_)) ? NT : NTP;                                   \
     if (last)                                                                               \
-      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true, MX_>), g, dim3(nth), 0, st, P, o, n, C, X); \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true, MX_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
     else                                                                                    \
-      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_>), g, dim3(nth), 0, st, P, o, n, C, X); \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
   } while (0)
   if (mx) {
     if (im && tv) STS_PASS(true, true, true);

@@ -23,7 +23,9 @@ EXPLICIT, IMPLICIT, UPWIND, TVD, MIXED = 0, 1, 0, 2, 4
 
 # every symbol the header declares
 EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_residuals", "sts_fields",
-           "sts_set_fields", "sts_field_ptrs", "sts_timing", "sts_read_timing", "sts_destroy",
+           "sts_set_fields", "sts_field_ptrs", "sts_timing", "sts_read_timing", "sts_drag",
+           "sts_state_slots", "sts_state_save", "sts_state_load", "sts_adjoint_begin",
+           "sts_adjoint_seed_drag", "sts_adjoint_step", "sts_adjoint_read", "sts_destroy",
            "sts_last_error")
 
 _D = C.POINTER(C.c_double)
@@ -77,6 +79,14 @@ def lib():
             [C.POINTER(C.c_size_t)] * 2
         L.sts_timing.argtypes = [C.c_void_p, C.c_int]
         L.sts_read_timing.argtypes = [C.c_void_p, _D, C.POINTER(C.c_longlong)]
+        L.sts_drag.argtypes = [C.c_void_p, _D]
+        L.sts_state_slots.argtypes = [C.c_void_p, C.c_int]
+        L.sts_state_save.argtypes = [C.c_void_p, C.c_int]
+        L.sts_state_load.argtypes = [C.c_void_p, C.c_int]
+        L.sts_adjoint_begin.argtypes = [C.c_void_p, C.c_int]
+        L.sts_adjoint_seed_drag.argtypes = [C.c_void_p, C.c_double]
+        L.sts_adjoint_step.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int]
+        L.sts_adjoint_read.argtypes = [C.c_void_p] + [_D] * 7
         L.sts_destroy.argtypes = [C.c_void_p]
         L.sts_destroy.restype = None
         L.sts_last_error.restype = C.c_char_p
@@ -192,3 +202,35 @@ class Solver:
         n = (C.c_longlong * 2)()
         _check(lib().sts_read_timing(self._h, _ptr(ms), n))
         return ms, (n[0], n[1])
+
+    # ---- loss, checkpoints, adjoint of the explicit step ----
+    def drag(self) -> float:
+        out = np.zeros(1)
+        _check(lib().sts_drag(self._h, _ptr(out)))
+        return float(out[0])
+
+    def state_slots(self, n: int):
+        _check(lib().sts_state_slots(self._h, int(n)))
+
+    def state_save(self, slot: int):
+        _check(lib().sts_state_save(self._h, int(slot)))
+
+    def state_load(self, slot: int):
+        _check(lib().sts_state_load(self._h, int(slot)))
+
+    def adjoint_begin(self, n_inner: int):
+        _check(lib().sts_adjoint_begin(self._h, int(n_inner)))
+
+    def adjoint_seed_drag(self, w: float):
+        _check(lib().sts_adjoint_seed_drag(self._h, float(w)))
+
+    def adjoint_step(self, dt: float, n_inner: int, scheme: int):
+        _check(lib().sts_adjoint_step(self._h, float(dt), int(n_inner), int(scheme)))
+
+    def adjoint_read(self, with_lambda: bool = False):
+        """(dL/du_in[ny], dL/dwall_T[0][nx], dL/dwall_T[1][nx]) and, if asked,
+        the adjoint state (u, v, p, T layouts of fields())."""
+        g = [np.zeros(self.ny), np.zeros(self.nx), np.zeros(self.nx)]
+        lam = [np.zeros(s) for s in self.shapes()] if with_lambda else [None] * 4
+        _check(lib().sts_adjoint_read(self._h, *[_ptr(a) for a in g], *[_ptr(a) for a in lam]))
+        return (tuple(g), tuple(lam)) if with_lambda else tuple(g)

@@ -138,6 +138,9 @@ def workload(name: str) -> Tuple[Problem, dict]:
     elif name == "channel_1024x256":      # one square centred
         p = channel(1024, 256, [Fraction(5, 2)])
         run = dict(steps=100, inner=10, seed=4)
+    elif name == "adjoint_1024x256":      # one square centred, parabolic seeded inlet
+        p = channel(1024, 256, [Fraction(5, 2)], u_in=parabolic_inlet(256, 4))
+        run = dict(steps=100, inner=10, seed=4, every=10)
     elif name == "channel_4096x1024":     # two squares, Re 50
         p = channel(4096, 1024, [Fraction(3, 2), Fraction(3)], Re=50.0)
         run = dict(steps=500, inner=10, seed=5)
@@ -169,6 +172,13 @@ def splitmix64(seed: int, n: int, offset: int = 0) -> np.ndarray:
 def uniform01(seed: int, n: int, offset: int = 0) -> np.ndarray:
     """Doubles in [0, 1): (x >> 11) * 2^-53."""
     return (splitmix64(seed, n, offset) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def parabolic_inlet(ny: int, seed: int, amp: float = 1e-2) -> np.ndarray:
+    """Inlet profile 4 y (1 - y) (peak 1 at mid-height, cell-centre y in units
+    of H) plus a seeded perturbation amp (2U - 1) per row."""
+    y = (np.arange(ny) + 0.5) / ny
+    return 4.0 * y * (1.0 - y) + amp * (2.0 * uniform01(seed ^ 0x5A5A, ny) - 1.0)
 
 
 def initial_fields(p: Problem, seed: int, amp: float = 1e-3):
