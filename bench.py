@@ -164,11 +164,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision runs")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint timing and print its JSON (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration)")
     a = ap.parse_args()
     if a.copy_probe:
         copy_probe()
+        return
+    if a.adjoint_only:
+        print(json.dumps(run_adjoint()), flush=True)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "

@@ -1195,11 +1195,18 @@ __global__ __launch_bounds__(AB) void k_drag(const Params P, const State o, doub
     out[blockIdx.x] = r;
   }
 }
+// sum of n partials in a fixed order (one block)
 __global__ __launch_bounds__(AB) void k_sum(const double *in, int n, double *out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double r = 0.0;
-    for (int q = 0; q < n; q++) r += in[q];
-    *out = r;
+  __shared__ double red[AB / 64];
+  double r = 0.0;
+  for (int q = threadIdx.x; q < n; q += AB) r += in[q];
+  for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < AB / 64; w++) t += red[w];
+    *out = t;
   }
 }
 __global__ __launch_bounds__(AB) void k_drag_seed(const Params P, const State o, const State lam,
