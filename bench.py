@@ -11,10 +11,15 @@ second), the pass kernel's achieved bandwidth against the HBM roofline, the
 FP64 CPU oracle timed on a bounded sample on the host cores, and the
 mixed-precision form of every scheme (FP32 coefficient assembly and Jacobi
 corrections through an FP64 defect): its rate, its speedup over the FP64 form
-and its max / L2 relative difference from the FP64 fields after the same
-steps, and the adjoint of the explicit step on the 1024x256 adjoint workload
-(time-averaged drag, 100 steps x 10 passes, checkpoints every 10 steps):
-backward / forward time and the device memory it holds.
+and its max / L2 relative difference from the FP64 fields after the
+configured 200 steps; the four FP64 schemes on the 3000x600 channel; the
+adjoint of the explicit step on the 1024x256 adjoint workload (time-averaged
+drag, 100 steps x 10 passes, checkpoints every 10 steps): backward / forward
+time and the device memory it holds; and the combined run on the 4096x1024
+channel (Re 50, 500 steps x 10 passes): mixed-precision forward, FP64
+adjoint, checkpoints every ceil(sqrt(500)) = 23 steps, with its peak device
+memory, backward / forward time and the gradient's difference from the one
+taken through the FP64 forward.
 """
 from __future__ import annotations
 
@@ -59,7 +64,9 @@ def measured_traffic(scheme_name: str):
     return d.get("bytes_per_launch", {}).get(scheme_name)
 
 
-def run_gpu(name: str, steps: int, warmup: int, scheme: int, want_fields: bool = False):
+def run_gpu(name: str, steps: int, warmup: int, scheme: int, fields_after: int = 0):
+    """Timed steps; with fields_after > 0 the run continues (untimed) to that
+    many steps in all and returns the fields."""
     import torch
     from paper_1802_04243_amd import sts
 
@@ -80,7 +87,9 @@ def run_gpu(name: str, steps: int, warmup: int, scheme: int, want_fields: bool =
     res = g.residuals()
     ms, n = g.read_timing()
     g.timing(False)
-    fields = g.fields() if want_fields else None
+    for _ in range(warmup + steps, fields_after):
+        g.step(dt, inner, scheme)
+    fields = g.fields() if fields_after else None
     g.close()
     wall = t1 - t0
     fv_iters = p.n_fv * inner * steps
@@ -113,6 +122,63 @@ def run_adjoint(name: str = "adjoint_1024x256"):
             "device_bytes": int(st["device_bytes"]),
             "note": "forward includes one drag readback per step; backward includes the "
                     "recompute of every checkpoint segment and of every step"}
+
+
+def _drag_grad(p, f0, run, scheme):
+    import torch
+    from paper_1802_04243_amd import adjoint
+    wb, wt = p.walls()
+    args = [torch.tensor(a, dtype=torch.float64, requires_grad=True)
+            for a in (p.inlet()[0], wb, wt)]
+    ft = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in f0]
+    L = adjoint.drag_loss(p, *args, ft, run["dt"], run["steps"], run["inner"], scheme,
+                          run["every"])
+    L.backward()
+    grads = [a.grad.numpy() for a in args + ft]
+    return float(L.detach()), grads, dict(adjoint.LAST_STATS)
+
+
+def run_combined(name: str = "combined_4096x1024", scheme: int = W.EXPLICIT | W.TVD):
+    """Mixed-precision forward with the FP64 adjoint under sqrt(N)
+    checkpoints, and the gradient of the same loss through the FP64 forward
+    and adjoint as the reference."""
+    p, run = W.workload(name)
+    f0 = W.initial_fields(p, run["seed"])
+    Lm, gm, sm = _drag_grad(p, f0, run, scheme | W.MIXED)
+    Lf, gf, sf = _drag_grad(p, f0, run, scheme)
+    names = ["u_in", "wall_T0", "wall_T1", "u0", "v0", "p0", "T0"]
+    mx, l2 = {}, {}
+    for nm, a, b in zip(names, gm, gf):
+        den = np.abs(b).max()
+        if den == 0:
+            continue    # no dependence at FP64 resolution within the horizon
+        mx[nm] = float(f"{np.abs(a - b).max() / den:.3e}")
+        l2[nm] = float(f"{np.sqrt(np.mean((a - b) ** 2) / np.mean(b * b)):.3e}")
+    return {"workload": name, "grid": f"{p.nx}x{p.ny}", "steps": run["steps"],
+            "n_inner": run["inner"], "checkpoint_every": sm["every"],
+            "checkpoint_slots": sm["slots"], "scheme": "explicit_tvd", "forward": "mixed",
+            "forward_s": round(sm["forward_s"], 4), "backward_s": round(sm["backward_s"], 4),
+            "adjoint_forward_ratio": round(sm["backward_s"] / sm["forward_s"], 3),
+            "peak_device_bytes": int(sm["device_bytes"]),
+            "fp64_reference": {"forward_s": round(sf["forward_s"], 4),
+                               "backward_s": round(sf["backward_s"], 4),
+                               "adjoint_forward_ratio": round(sf["backward_s"] / sf["forward_s"], 3)},
+            "loss": Lm, "loss_rel_err_vs_fp64": float(f"{abs(Lm - Lf) / abs(Lf):.3e}"),
+            "grad_max_rel_err_vs_fp64": mx, "grad_l2_rel_err_vs_fp64": l2,
+            "grad_zero_in_fp64": [nm for nm, b in zip(names, gf) if not np.abs(b).max() > 0]}
+
+
+def run_other_grid(name: str, steps: int, warmup: int):
+    """FP64 throughput of every scheme on another configured grid."""
+    out = {}
+    for nm, sch in W.SCHEMES.items():
+        r = run_gpu(name, steps, warmup, sch)
+        out[nm] = {"mfv_iters_s": round(r["mfv_iters_s"], 2), "pass_ms": round(r["pass_ms"], 5),
+                   "hbm_frac": round(r["pass_gbs"] / HBM_PEAK_GBS, 4),
+                   "ms_per_step": round(r["ms_per_step"], 4)}
+        print(f"# {name} {nm}: {r['mfv_iters_s']:.1f} MFV-iters/s, pass {r['pass_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+    return out
 
 
 def field_errors(fm, fd):
@@ -164,6 +230,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision runs")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-combined", action="store_true",
+                    help="skip the combined run (mixed forward + FP64 adjoint, 4096x1024)")
+    ap.add_argument("--other-grids", default="channel_3000x600",
+                    help="comma list of further grids timed with every FP64 scheme ('' = none)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint timing and print its JSON (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -186,21 +256,23 @@ def main():
         names.remove(HEADLINE)
     names = [HEADLINE] + names
     per, mixed = {}, {}
+    # the mixed-form errors are taken after the configured step count
+    fields_after = 0 if a.no_mixed else max(W.workload(a.workload)[1]["steps"], a.warmup + a.steps)
     for nm in names:
-        per[nm] = run_gpu(a.workload, a.steps, a.warmup, W.SCHEMES[nm], want_fields=not a.no_mixed)
+        per[nm] = run_gpu(a.workload, a.steps, a.warmup, W.SCHEMES[nm], fields_after)
         print(f"# {nm}: {per[nm]['mfv_iters_s']:.1f} MFV-iters/s, pass {per[nm]['pass_ms']:.3f} ms "
               f"({per[nm]['pass_gbs']:.0f} GB/s algorithmic), step {per[nm]['ms_per_step']:.2f} ms",
               file=sys.stderr, flush=True)
         if a.no_mixed:
             continue
-        m = run_gpu(a.workload, a.steps, a.warmup, W.SCHEMES[nm] | W.MIXED, want_fields=True)
+        m = run_gpu(a.workload, a.steps, a.warmup, W.SCHEMES[nm] | W.MIXED, fields_after)
         mx, l2 = field_errors(m["fields"], per[nm]["fields"])
         mixed[nm] = {"mfv_iters_s": round(m["mfv_iters_s"], 2),
                      "speedup": round(m["mfv_iters_s"] / per[nm]["mfv_iters_s"], 4),
                      "pass_ms": round(m["pass_ms"], 5),
                      "max_rel_err_vs_fp64": {k: float(f"{v:.3e}") for k, v in mx.items()},
                      "l2_rel_err_vs_fp64": {k: float(f"{v:.3e}") for k, v in l2.items()},
-                     "after_steps": a.warmup + a.steps}
+                     "after_steps": fields_after}
         per[nm]["fields"] = m["fields"] = None
         print(f"# {nm}+mixed: {m['mfv_iters_s']:.1f} MFV-iters/s (x{mixed[nm]['speedup']:.3f}), "
               f"max rel err {max(mx.values()):.2e}", file=sys.stderr, flush=True)
@@ -210,6 +282,13 @@ def main():
         print(f"# adjoint: forward {adj['forward_s']:.3f} s, backward {adj['backward_s']:.3f} s "
               f"(ratio {adj['adjoint_forward_ratio']:.2f}), device {adj['device_bytes'] / 2**20:.0f} MiB",
               file=sys.stderr, flush=True)
+    comb = None
+    if not a.no_combined:
+        comb = run_combined()
+        print(f"# combined: forward {comb['forward_s']:.3f} s, backward {comb['backward_s']:.3f} s "
+              f"(ratio {comb['adjoint_forward_ratio']:.2f}), peak {comb['peak_device_bytes'] / 2**30:.2f} GiB, "
+              f"grad err {comb['grad_max_rel_err_vs_fp64']}", file=sys.stderr, flush=True)
+    others = {g: run_other_grid(g, a.steps, a.warmup) for g in a.other_grids.split(",") if g}
     h = per[HEADLINE]
     traffic = measured_traffic(HEADLINE)
     roof = dict(bound="hbm", achieved=round(h["pass_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -245,8 +324,10 @@ def main():
                          "residual_ms": round(r["residual_ms"], 4),
                          "max_residuals": r["residuals"][:5]}
                     for nm, r in per.items()},
+        "other_grids": others or None,
         "mixed": mixed or None,
         "adjoint": adj,
+        "combined": comb,
     }
     if rank == 0:
         print(json.dumps(out), flush=True)

@@ -198,9 +198,11 @@ sts_status sts_state_load(sts_ctx *ctx, int slot);
    n_inner and scheme as the forward step) and replaces lambda by the
    derivative with respect to level n-1 (reverse of the n_inner passes and
    of the prologue), adding the wall-temperature contributions.  The
-   current state is left unchanged.  STS_EINVAL for implicit or mixed
-   scheme bits or an n_inner other than sts_adjoint_begin's; STS_ESTATE
-   before sts_adjoint_begin.
+   current state is left unchanged.  With STS_MIXED the iterates are
+   recomputed by the mixed-precision pass (the forward that produced the
+   states) and the reverse is the FP64 step's transpose evaluated at them.
+   STS_EINVAL for the implicit scheme bit or an n_inner other than
+   sts_adjoint_begin's; STS_ESTATE before sts_adjoint_begin.
    sts_adjoint_read: wait and copy to host arrays (NULL skips): dL/du_in[ny]
    (the inlet entries of lambda_u: complete once the adjoint has reached
    the initial level), dL/dwall_T[0][nx], dL/dwall_T[1][nx], and lambda in

@@ -15,6 +15,12 @@ level mapped through the boundary-value projection of sts_set_fields
 (entries the projection overwrites get 0; the outlet face copies face
 nx-1).
 
+With scheme bit MIXED the forward (and every recompute) runs the
+mixed-precision pass and the backward applies the FP64 step's transpose at
+those states.  every=None takes the two-level sqrt(N) schedule: checkpoints
+every ceil(sqrt(N)) steps, so that the slots held at once (segment starts
+plus the states of one segment) number about 2 sqrt(N).
+
 Every step of the path runs in the library; this module only orders calls.
 """
 from __future__ import annotations
@@ -90,8 +96,10 @@ class DragLoss(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u_in, Tw0, Tw1, u0, v0, p0, T0, base, dt, steps, inner, scheme, every):
-        if scheme & (sts.IMPLICIT | sts.MIXED):
-            raise ValueError("the adjoint is of the explicit FP64 scheme")
+        if scheme & sts.IMPLICIT:
+            raise ValueError("the adjoint is of the explicit scheme")
+        if every is None:
+            every = max(1, math.ceil(math.sqrt(steps)))
         p = _problem(base, u_in.detach().cpu().numpy(), Tw0.detach().cpu().numpy(),
                      Tw1.detach().cpu().numpy())
         _sync()
@@ -110,7 +118,8 @@ class DragLoss(torch.autograd.Function):
             acc += g.drag()
         _sync()
         LAST_STATS.clear()
-        LAST_STATS.update(forward_s=time.perf_counter() - t0, used0=used0)
+        LAST_STATS.update(forward_s=time.perf_counter() - t0, used0=used0, every=every,
+                          slots=nseg + every)
         ctx.g, ctx.meta = g, (dt, steps, inner, scheme, every, nseg)
         ctx.dev = u_in.device
         return torch.tensor(acc / steps, dtype=torch.float64, device=u_in.device)
@@ -150,10 +159,11 @@ class DragLoss(torch.autograd.Function):
 
 def drag_loss(base: W.Problem, u_in: torch.Tensor, Tw0: torch.Tensor, Tw1: torch.Tensor,
               f0, dt: float, steps: int, inner: int, scheme: int = sts.EXPLICIT,
-              every: int = 10) -> torch.Tensor:
+              every=10) -> torch.Tensor:
     """Time-averaged drag as a differentiable function of (u_in, Tw0, Tw1)
     and of the initial fields f0 = (u0, v0, p0, T0) (numpy arrays or
-    tensors; tensors with requires_grad receive the initial-state gradient)."""
+    tensors; tensors with requires_grad receive the initial-state gradient).
+    every: checkpoint interval in steps, or None for ceil(sqrt(steps))."""
     f0 = [a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a), dtype=torch.float64)
           for a in f0]
     return DragLoss.apply(u_in, Tw0, Tw1, *f0, base, dt, steps, inner, scheme, every)

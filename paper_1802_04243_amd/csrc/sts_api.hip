@@ -796,12 +796,15 @@ extern "C" sts_status sts_adjoint_step(sts_ctx *c, double dt, int n_inner, int s
   if (!c->adj_K) return fail(STS_ESTATE, "sts_adjoint_begin has not been called");
   if (n_inner != c->adj_K) return fail(STS_EINVAL, "n_inner %d differs from sts_adjoint_begin's %d", n_inner, c->adj_K);
   if (!(dt > 0) || !isfinite(dt)) return fail(STS_EINVAL, "dt must be > 0");
-  if (scheme & ~(STS_TVD)) return fail(STS_EINVAL, "the adjoint is of the explicit FP64 scheme (scheme 0x%x)", scheme);
+  if (scheme & ~(STS_TVD | STS_MIXED))
+    return fail(STS_EINVAL, "the adjoint is of the explicit scheme (scheme 0x%x)", scheme);
   c->P.dt = dt;
   c->P.idt = 1.0 / dt;
   const int K = n_inner;
   sts_status s;
-  // recompute the step from the current state x_0 (kept), storing x_1..x_{K-1}
+  // recompute the step from the current state x_0 (kept), storing
+  // x_1..x_{K-1}, with the form that produced the state (FP64 or mixed); the
+  // reverse below is the FP64 step's transpose at these iterates
   for (int k = 0; k <= K; k++)
     if ((s = copy_state(c, c->it[k], c->st[c->cur])) != STS_OK) return s;
   launch_prologue(c->P, c->it[0], c->C, scheme, c->stream);

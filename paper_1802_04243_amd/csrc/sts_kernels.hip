@@ -1108,7 +1108,7 @@ __device__ __forceinline__ void item_consts(const Params &P, const Consts &C,
 
 // c: the step constants of the thread's items (item_consts); cp: C_p of a
 // cell thread's cell
-template <int NTH, bool CL, bool IM, bool TV, bool RS, bool MX>
+template <int NTH, bool CL, bool IM, bool TV, bool RS, bool MX, bool IN>
 __device__ void pass_body(Lds &s, const Params &P, const State n,
                           const Resid X, const Inter I, int tile, int x0,
                           int y0, const double c[], double cp) {
@@ -1190,9 +1190,9 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
                           ? VH_(i, j) - DV_(i, j) * (pn - PN_(i, j - 1))
                           : V_(i, j);
     n.v[k] = vn;
-    if (I.tn) {
-      // intermediates for the adjoint (plain FP64 passes only): the owned
-      // cells and faces, the outlet face nx and the top face ny
+    if constexpr (IN) {
+      // intermediates for the adjoint's reverse sweep: the owned cells and
+      // faces, the outlet face nx and the top face ny
       I.ru[k] = RU_(i, j);
       I.rv[k] = RV_(i, j);
       I.uh[k] = UH_(i, j);
@@ -1237,12 +1237,14 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
 }
 
 // One pass over the tiles; RS: the last pass of a step, which also produces
-// the residual inputs; MX: the mixed-precision form of the T, u, v updates.
+// the residual inputs; MX: the mixed-precision form of the T, u, v updates;
+// IN: also store the pass intermediates (the adjoint's recompute; a
+// template flag so that the plain pass holds none of their pointers).
 // Two blocks share a CU (LDS bound).  The explicit schemes use NTP threads
 // (6 waves per SIMD, at most 80 VGPRs); the implicit ones and the mixed
 // explicit TVD pass need more registers and use NT threads (4 waves per
 // SIMD, at most 128 VGPRs).
-template <int NTH, bool IM, bool TV, bool RS, bool MX>
+template <int NTH, bool IM, bool TV, bool RS, bool MX, bool IN>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_pass(
     const Params P, const State o, const State n, const Consts C, const Resid X, const Inter I) {
   __shared__ Lds s;
@@ -1253,9 +1255,9 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
   load_window<NTH, MX>(s, P, o, x0, y0);
   __syncthreads();
   if (P.clean[tile])
-    pass_body<NTH, true, IM, TV, RS, MX>(s, P, n, X, I, tile, x0, y0, c, cp);
+    pass_body<NTH, true, IM, TV, RS, MX, IN>(s, P, n, X, I, tile, x0, y0, c, cp);
   else
-    pass_body<NTH, false, IM, TV, RS, MX>(s, P, n, X, I, tile, x0, y0, c, cp);
+    pass_body<NTH, false, IM, TV, RS, MX, IN>(s, P, n, X, I, tile, x0, y0, c, cp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1536,13 +1538,17 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
   dim3 g(ntiles(P));
   const Resid X = last ? *last : Resid{nullptr, nullptr, nullptr};
   const Inter I = inter ? *inter : Inter{};
+  // intermediates are stored only by the explicit scheme's plain passes (the
+  // adjoint's recompute); the caller guarantees !im && !last with inter
 #define STS_PASS(IM_, TV_, MX_)                                                             \
   do {                                                                                      \
     constexpr int nth = (IM_ || (MX_ && TV_)) ? NT : NTP;                                   \
     if (last)                                                                               \
-      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true, MX_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true, MX_, false>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
+    else if (inter && !IM_)                                                                 \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_, !IM_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
     else                                                                                    \
-      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_, false>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
   } while (0)
   if (mx) {
     if (im && tv) STS_PASS(true, true, true);

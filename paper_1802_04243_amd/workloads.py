@@ -144,6 +144,9 @@ def workload(name: str) -> Tuple[Problem, dict]:
     elif name == "channel_4096x1024":     # two squares, Re 50
         p = channel(4096, 1024, [Fraction(3, 2), Fraction(3)], Re=50.0)
         run = dict(steps=500, inner=10, seed=5)
+    elif name == "combined_4096x1024":    # mixed forward + FP64 adjoint, sqrt(N) checkpoints
+        p = channel(4096, 1024, [Fraction(3, 2), Fraction(3)], Re=50.0)
+        run = dict(steps=500, inner=10, seed=5, every=None)
     else:
         raise KeyError(name)
     run["dt"] = p.cfl_dt()

@@ -82,12 +82,13 @@ def test_mixed_vs_oracle_120x24(sts_mod, oracle_lib, name, scheme):
     assert np.isfinite(rm).all()
 
 
-@pytest.mark.parametrize("name", ["explicit_tvd", "implicit_tvd"])
+@pytest.mark.parametrize("name", list(W.SCHEMES))
 def test_mixed_vs_oracle_1280x288(sts_mod, oracle_lib, name):
+    # the configured 200 steps x 10 passes
     scheme = W.SCHEMES[name]
     p, run = W.workload("channel_1280x288")
     f0 = W.initial_fields(p, run["seed"])
-    steps = 20
+    steps = run["steps"]
     print(f"case mixed 1280x288 {name} {steps}x{run['inner']}", flush=True)
     o = oracle_lib.Oracle(p)
     o.set_fields(*f0)
@@ -104,7 +105,7 @@ def test_mixed_vs_fp64_gpu_5120x1152(sts_mod, name, scheme):
     # GPU path (itself bitwise equal to the oracle on every parity case)
     p, run = W.workload("channel_5120x1152")
     f0 = W.initial_fields(p, run["seed"])
-    steps = 20
+    steps = run["steps"]
     print(f"case mixed 5120x1152 {name} {steps}x{run['inner']}", flush=True)
     fd, _ = run_gpu(sts_mod, p, f0, run["dt"], steps, run["inner"], scheme)
     fm, _ = run_gpu(sts_mod, p, f0, run["dt"], steps, run["inner"], scheme | W.MIXED)

@@ -118,11 +118,14 @@ def test_channel_1280x288_few_steps(sts_mod, oracle_lib, scheme):
              label="channel_1280x288")
 
 
-@pytest.mark.parametrize("scheme", [W.EXPLICIT | W.TVD, W.IMPLICIT | W.TVD])
-def test_full_size_step_from_gpu_state(sts_mod, oracle_lib, scheme):
-    # 5120x1152 in the launch configuration the benchmark uses: advance on the
-    # GPU, then take one step on both from the same state.
-    p, run = W.workload("channel_5120x1152")
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+@pytest.mark.parametrize("wl", ["channel_3000x600", "channel_5120x1152"])
+def test_full_size_step_from_gpu_state(sts_mod, oracle_lib, wl, name, scheme):
+    # the two throughput grids in the launch configuration the benchmark
+    # uses: advance 3 steps on the GPU, then take one step on both from the
+    # same state
+    p, run = W.workload(wl)
+    print(f"case {wl}/{name}: 3 GPU steps, then one step on both", flush=True)
     g = sts_mod.Solver(p)
     g.set_fields(*W.initial_fields(p, run["seed"]))
     for _ in range(3):
@@ -133,7 +136,7 @@ def test_full_size_step_from_gpu_state(sts_mod, oracle_lib, scheme):
     o.set_fields(*state)
     g.step(run["dt"], run["inner"], scheme)
     o.step(run["dt"], run["inner"], scheme)
-    compare(g, o, "channel_5120x1152")
+    compare(g, o, f"{wl}/{name}")
     g.close()
 
 
