@@ -45,6 +45,9 @@ struct ora_ctx {
   double wu[2];
   double *wT[2];
   double obsT;
+  int otype;
+  /* slip and jump coefficients (pl38, pl39): zeta = kz/rho, tau = kt/rho */
+  double kz, kt;
   /* state: old iterate (u..T), new iterate (un..Tn), time level n-1 (um..Tm) */
   double *u, *v, *p, *T;
   double *un, *vn, *pn, *Tn;
@@ -415,19 +418,37 @@ typedef struct {
   double a0, src, texp, unst;
 } tco;
 
+/* Velocity-slip / temperature-jump walls (pl38, pl39).  With the normal
+   derivative taken between the wall and the node at distance d/2, pl38
+   reads u_s - u_w = zeta (u_P - u_s) / (d/2): the gas velocity at the wall
+   is u_s = (u_w d/2 + zeta u_P) / (d/2 + zeta) and the wall shear
+   mu (u_P - u_s) / (d/2) = mu (u_P - u_w) / (d/2 + zeta), i.e. the no-slip
+   half-cell conductance with the distance d/2 + zeta.  pl39 gives the same
+   for the conduction with tau.  zeta = 1.1466 Kn / rho, tau = 2.1904 Kn /
+   rho, rho the density of the node next to the wall (the cell for T, the
+   face node for u and v). */
+static double iwall(double d, double k, double rho) {
+  return 1.0 / (0.5 * d + k / rho);
+}
+static double slip_vel(double uw, double uP, double d, double zeta) {
+  return (uw * (0.5 * d) + zeta * uP) / (0.5 * d + zeta);
+}
+
 /* face-centre velocities for the dissipation term (Sec. 3.2 after pl29):
    v at (x^f_{i+1}, y^v_j) and (x^f_i, y^v_j), u at (x^v_i, y^f_{j+1}) and
    (x^v_i, y^f_j), bilinear between the four nearest nodes; a point on a
-   wall takes the wall velocity, the inlet v is 0, the outlet has zero
-   gradient. */
+   wall takes the wall velocity (the slip velocity at a slip / jump wall,
+   with the cell-centre value as the node value), the inlet v is 0, the
+   outlet has zero gradient. */
 static void face_centre_vel(const ora_ctx *c, int i, int j, double *vE,
                             double *vW, double *uN, double *uS) {
   const double *u = c->u, *v = c->v;
+  const double zP = c->kz / c->rho[IC(c, i, j)];
   double vc = 0.5 * (v[IV(c, i, j)] + v[IV(c, i, j + 1)]);
   if (!c->per && i == c->nx - 1) {
     *vE = vc;
   } else if (solid(c, i + 1, j)) {
-    *vE = 0.0;
+    *vE = (c->otype == 2) ? slip_vel(0.0, vc, c->dx[i], zP) : 0.0;
   } else {
     int r = cw(c, i + 1), k = fwx(c, i + 1);
     *vE = c->wlx[k] * vc + c->wrx[k] * (0.5 * (v[IV(c, r, j)] + v[IV(c, r, j + 1)]));
@@ -435,24 +456,28 @@ static void face_centre_vel(const ora_ctx *c, int i, int j, double *vE,
   if (!c->per && i == 0) {
     *vW = 0.0;
   } else if (solid(c, i - 1, j)) {
-    *vW = 0.0;
+    *vW = (c->otype == 2) ? slip_vel(0.0, vc, c->dx[i], zP) : 0.0;
   } else {
     int l = cw(c, i - 1), k = fwx(c, i);
     *vW = c->wlx[k] * (0.5 * (v[IV(c, l, j)] + v[IV(c, l, j + 1)])) + c->wrx[k] * vc;
   }
   double uc = 0.5 * (Uat(c, u, i, j) + Uat(c, u, i + 1, j));
   if (j == c->ny - 1) {
-    *uN = (c->wtype[1] == 0) ? c->wu[1] : uc;
+    *uN = (c->wtype[1] == 0)   ? c->wu[1]
+          : (c->wtype[1] == 2) ? slip_vel(c->wu[1], uc, c->dy[j], zP)
+                               : uc;
   } else if (solid(c, i, j + 1)) {
-    *uN = 0.0;
+    *uN = (c->otype == 2) ? slip_vel(0.0, uc, c->dy[j], zP) : 0.0;
   } else {
     *uN = c->wly[j + 1] * uc +
           c->wry[j + 1] * (0.5 * (Uat(c, u, i, j + 1) + Uat(c, u, i + 1, j + 1)));
   }
   if (j == 0) {
-    *uS = (c->wtype[0] == 0) ? c->wu[0] : uc;
+    *uS = (c->wtype[0] == 0)   ? c->wu[0]
+          : (c->wtype[0] == 2) ? slip_vel(c->wu[0], uc, c->dy[j], zP)
+                               : uc;
   } else if (solid(c, i, j - 1)) {
-    *uS = 0.0;
+    *uS = (c->otype == 2) ? slip_vel(0.0, uc, c->dy[j], zP) : 0.0;
   } else {
     *uS = c->wly[j] * (0.5 * (Uat(c, u, i, j - 1) + Uat(c, u, i + 1, j - 1))) +
           c->wry[j] * uc;
@@ -465,6 +490,11 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   tco q;
   double dxi = c->dx[i], dyj = c->dy[j], dV = dxi * dyj;
   double gP = gam[IC(c, i, j)], TP = T[IC(c, i, j)];
+  double rhoP = c->rho[IC(c, i, j)];
+  /* a face on an obstacle: half-cell conductance with the harmonic mean of
+     the cell's and the surface's Gamma (no-slip isothermal), or with the
+     cell's Gamma over the distance d/2 + tau (temperature jump) */
+  const int jump = (c->otype == 2);
   double D[4], F[4], psi[4] = {0, 0, 0, 0};
   /* west face x^f_i */
   if (!c->per && i == 0) { /* inlet: T_in on the face, half cell away */
@@ -474,7 +504,8 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     int l = cw(c, i - 1);
     q.nb[0] = T[IC(c, l, j)];
     if (c->solid[IC(c, l, j)])
-      D[0] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj * c->ihx[i];
+      D[0] = jump ? c->C1 * gP * dyj * iwall(dxi, c->kt, rhoP)
+                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj * c->ihx[i];
     else
       D[0] = c->C1 * gam_harm(c->dx[l], gam[IC(c, l, j)], dxi, gP) * dyj *
              c->icx[fwx(c, i)];
@@ -487,7 +518,8 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     int r = cw(c, i + 1);
     q.nb[1] = T[IC(c, r, j)];
     if (c->solid[IC(c, r, j)])
-      D[1] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj * c->ihx[i];
+      D[1] = jump ? c->C1 * gP * dyj * iwall(dxi, c->kt, rhoP)
+                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj * c->ihx[i];
     else
       D[1] = c->C1 * gam_harm(dxi, gP, c->dx[r], gam[IC(c, r, j)]) * dyj *
              c->icx[fwx(c, i + 1)];
@@ -497,6 +529,9 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     if (c->wtype[0] == 0) {
       q.nb[2] = c->wT[0][i];
       D[2] = c->C1 * gam_harm2(gP, sqrt(c->wT[0][i])) * dxi * c->ihy[j];
+    } else if (c->wtype[0] == 2) {
+      q.nb[2] = c->wT[0][i];
+      D[2] = c->C1 * gP * dxi * iwall(dyj, c->kt, rhoP);
     } else {
       q.nb[2] = TP;
       D[2] = 0.0;
@@ -504,7 +539,8 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   } else {
     q.nb[2] = T[IC(c, i, j - 1)];
     if (c->solid[IC(c, i, j - 1)])
-      D[2] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi * c->ihy[j];
+      D[2] = jump ? c->C1 * gP * dxi * iwall(dyj, c->kt, rhoP)
+                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi * c->ihy[j];
     else
       D[2] = c->C1 * gam_harm(c->dy[j - 1], gam[IC(c, i, j - 1)], dyj, gP) *
              dxi * c->icy[j];
@@ -514,6 +550,9 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     if (c->wtype[1] == 0) {
       q.nb[3] = c->wT[1][i];
       D[3] = c->C1 * gam_harm2(gP, sqrt(c->wT[1][i])) * dxi * c->ihy[j];
+    } else if (c->wtype[1] == 2) {
+      q.nb[3] = c->wT[1][i];
+      D[3] = c->C1 * gP * dxi * iwall(dyj, c->kt, rhoP);
     } else {
       q.nb[3] = TP;
       D[3] = 0.0;
@@ -521,7 +560,8 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   } else {
     q.nb[3] = T[IC(c, i, j + 1)];
     if (c->solid[IC(c, i, j + 1)])
-      D[3] = c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi * c->ihy[j];
+      D[3] = jump ? c->C1 * gP * dxi * iwall(dyj, c->kt, rhoP)
+                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi * c->ihy[j];
     else
       D[3] = c->C1 * gam_harm(dyj, gP, c->dy[j + 1], gam[IC(c, i, j + 1)]) *
              dxi * c->icy[j + 1];
@@ -530,7 +570,6 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   F[1] = c->Fx[IU(c, i + 1, j)];
   F[2] = c->Fy[IV(c, i, j)];
   F[3] = c->Fy[IV(c, i, j + 1)];
-  double rhoP = c->rho[IC(c, i, j)];
   if (implicit) {
     if (tvd) {
       double uW = c->u[IU(c, i, j)], uE = c->u[IU(c, i + 1, j)];
@@ -594,13 +633,19 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   double M = (rn * dyn + rs * dys) * dxi / 2.0;
   double len = 0.5 * (dys + dyn);
   double gnode = c->wly[j] * gs + c->wry[j] * gn;
+  /* a face on an obstacle in x: half-cell shear with the mean of the
+     node's and the surface's Gamma (no slip), or with the node's Gamma over
+     the distance d/2 + zeta, zeta from the node density (velocity slip) */
+  const int slip = (c->otype == 2);
+  const double rnode = c->wly[j] * rs + c->wry[j] * rn;
   double DW, DE;
   if (!c->per && i == 0) {
     DW = c->B * 0.5 * (gnode + gam_corner(c, gam, 0, j)) * len * c->ihx[i];
   } else {
     int l = cw(c, i - 1);
     if (solid(c, l, j - 1) && solid(c, l, j))
-      DW = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihx[i];
+      DW = slip ? c->B * gnode * len * iwall(dxi, c->kz, rnode)
+                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihx[i];
     else
       DW = c->B * gam_corner(c, gam, i, j) * c->sy[j] * c->isx[fwx(c, i)];
   }
@@ -609,7 +654,8 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   } else {
     int r = cw(c, i + 1);
     if (solid(c, r, j - 1) && solid(c, r, j))
-      DE = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihx[i];
+      DE = slip ? c->B * gnode * len * iwall(dxi, c->kz, rnode)
+                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihx[i];
     else
       DE = c->B * gam_corner(c, gam, i + 1, j) * c->sy[j] * c->isx[fwx(c, i + 1)];
   }
@@ -688,10 +734,17 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   double M = (rr * dxr + rl * dxl) * dyj / 2.0;
   double len = 0.5 * (dxl + dxr);
   double gnode = c->wlx[fwx(c, i)] * gl + c->wrx[fwx(c, i)] * gr;
+  /* node density for the slip length of pl38; obstacle faces in y as in
+     v_coefs */
+  const int slip = (c->otype == 2);
+  const double rnode = c->wlx[fwx(c, i)] * rl + c->wrx[fwx(c, i)] * rr;
   if (j == 0) {
     if (c->wtype[0] == 0) {
       uS = c->wu[0];
       DS = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 0, i))) * len * c->ihy[j];
+    } else if (c->wtype[0] == 2) {
+      uS = c->wu[0];
+      DS = c->B * gnode * len * iwall(dyj, c->kz, rnode);
     } else {
       uS = uP;
       DS = 0.0;
@@ -699,7 +752,8 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   } else {
     uS = u[IU(c, r, j - 1)];
     if (solid(c, l, j - 1) && solid(c, r, j - 1))
-      DS = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihy[j];
+      DS = slip ? c->B * gnode * len * iwall(dyj, c->kz, rnode)
+                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihy[j];
     else
       DS = c->B * gam_corner(c, gam, i, j) * c->sx[fwx(c, i)] * c->isy[j];
   }
@@ -707,6 +761,9 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     if (c->wtype[1] == 0) {
       uN = c->wu[1];
       DN = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 1, i))) * len * c->ihy[j];
+    } else if (c->wtype[1] == 2) {
+      uN = c->wu[1];
+      DN = c->B * gnode * len * iwall(dyj, c->kz, rnode);
     } else {
       uN = uP;
       DN = 0.0;
@@ -714,7 +771,8 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   } else {
     uN = u[IU(c, r, j + 1)];
     if (solid(c, l, j + 1) && solid(c, r, j + 1))
-      DN = c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihy[j];
+      DN = slip ? c->B * gnode * len * iwall(dyj, c->kz, rnode)
+                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihy[j];
     else
       DN = c->B * gam_corner(c, gam, i, j + 1) * c->sx[fwx(c, i)] * c->isy[j + 1];
   }
@@ -912,6 +970,9 @@ ora_ctx *ora_create(const ora_setup *s) {
       c->wT[w][i] = s->wall_T[w] ? s->wall_T[w][i] : 1.0;
   }
   c->obsT = s->obstacle_T;
+  c->otype = s->obstacle_type;
+  c->kz = 1.1466 * s->kn;
+  c->kt = 2.1904 * s->kn;
   size_t nu = (size_t)(nx + 1) * ny, nv = (size_t)nx * (ny + 1),
          nc = (size_t)nx * ny;
   c->u = dalloc(nu);

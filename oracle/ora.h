@@ -35,11 +35,15 @@ typedef struct {
   const double *u_in, *T_in;  /* [ny] inlet-face u and T                    */
   double p_in;                /* inlet pressure                             */
   int wall_type[2];           /* [0] bottom y=0, [1] top y=Ly:
-                                 0 no-slip isothermal, 1 slip adiabatic     */
-  double wall_u[2];           /* tangential wall velocity (no-slip walls)   */
+                                 0 no-slip isothermal, 1 slip adiabatic,
+                                 2 velocity slip + temperature jump        */
+  double wall_u[2];           /* tangential wall velocity (types 0 and 2)   */
   const double *wall_T[2];    /* [nx] wall temperature per cell column      */
   double obstacle_T;          /* surface temperature of the obstacles       */
   double gx, gy;              /* body force per unit mass                   */
+  int obstacle_type;          /* 0 no-slip isothermal, 2 slip + jump        */
+  double kn;                  /* Knudsen number of the slip / jump walls
+                                 (pl38, pl39), in the grid's length unit   */
 } ora_setup;
 
 enum { ORA_EXPLICIT = 0, ORA_IMPLICIT = 1, ORA_UPWIND = 0, ORA_TVD = 2 };

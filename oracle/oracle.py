@@ -39,6 +39,7 @@ class _Setup(C.Structure):
         ("u_in", _D), ("T_in", _D), ("p_in", C.c_double),
         ("wall_type", C.c_int * 2), ("wall_u", C.c_double * 2), ("wall_T", _D * 2),
         ("obstacle_T", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
+        ("obstacle_type", C.c_int), ("kn", C.c_double),
     ]
 
 
@@ -117,6 +118,7 @@ class Oracle:
         s.wall_u[0], s.wall_u[1] = prob.wall_u
         s.wall_T[0], s.wall_T[1] = _ptr(wb), _ptr(wt)
         s.obstacle_T, s.gx, s.gy = prob.obstacle_T, prob.gx, prob.gy
+        s.obstacle_type, s.kn = prob.obstacle_type, prob.kn
         h = L.ora_create(C.byref(s))
         if not h:
             raise ValueError("ora_create rejected the problem")

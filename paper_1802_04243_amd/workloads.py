@@ -29,7 +29,7 @@ SCHEMES = {
     "implicit_upwind": IMPLICIT | UPWIND,
     "implicit_tvd": IMPLICIT | TVD,
 }
-WALL_NOSLIP_ISOTHERMAL, WALL_SLIP_ADIABATIC = 0, 1
+WALL_NOSLIP_ISOTHERMAL, WALL_SLIP_ADIABATIC, WALL_SLIP_JUMP = 0, 1, 2
 
 
 @dataclasses.dataclass
@@ -55,6 +55,8 @@ class Problem:
     obstacle_T: float = 1.0
     gx: float = 0.0
     gy: float = 0.0
+    obstacle_type: int = WALL_NOSLIP_ISOTHERMAL  # or WALL_SLIP_JUMP
+    kn: float = 0.0                              # Knudsen number of slip / jump surfaces
 
     def widths(self) -> Tuple[np.ndarray, np.ndarray]:
         dx = self.dx if self.dx is not None else np.full(self.nx, self.lx / self.nx)

@@ -1,0 +1,153 @@
+"""Pins of the oracle's velocity-slip / temperature-jump walls (eqs pl38,
+pl39; CPU only).
+
+Discretisation (the oracle's reading): the normal derivative at the wall is
+taken over the half cell between the wall and the nearest node, so a slip /
+jump surface is the no-slip half-cell conductance with the distance d/2
+replaced by d/2 + zeta (velocity, zeta = 1.1466 Kn / rho) or d/2 + tau
+(temperature, tau = 2.1904 Kn / rho), with Gamma and rho of that node; the
+gas velocity at the wall (dissipation term) is the slip velocity that
+satisfies pl38 with the same half-cell derivative.
+
+- Couette flow between a resting and a moving slip wall in the isothermal
+  limit: the exact profile u = U (y + zeta) / (H + 2 zeta) is linear, which
+  the discrete equations reproduce exactly when rho and Gamma are uniform;
+  the small Mach number leaves only the viscous heating (T varies by 1e-4)
+  as a difference.  Run at two pressures, so rho = 1 and rho = 2 give two
+  slip lengths: pins 1.1466, the d/2 + zeta form and the 1/rho.
+- Steady conduction between jump walls at different temperatures in a
+  closed box: the exact solution (Kirchhoff variable (2/3) T^(3/2) linear in
+  y, jump conditions at both walls with tau from the surface density, the
+  pressure from the conserved mass) solved independently; the discrete
+  profile converges to it (first order: the node's Gamma and rho stand for
+  the surface's).  Pins 2.1904, the sign of the jump and its 1/rho.
+- A uniform stream between slip / jump walls that move with it at the wall
+  temperature is preserved bitwise (every wall term vanishes).
+- Mirror symmetry of every discrete equation with slip / jump walls and a
+  slip / jump obstacle (index and sign bookkeeping of the new branches).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import fsolve
+
+from paper_1802_04243_amd import workloads as W
+
+SJ = W.WALL_SLIP_JUMP
+
+
+def _zeros_state(p, pr0, T0):
+    ny, nx = p.ny, p.nx
+    u, v = np.zeros((ny, nx + 1)), np.zeros((ny + 1, nx))
+    return u, v, np.full((ny, nx), pr0), np.full((ny, nx), T0)
+
+
+@pytest.mark.parametrize("p0", [1.0, 2.0])
+def test_slip_couette_isothermal_limit(oracle_lib, p0):
+    ny, kn, U = 16, 0.1 / 1.1466 * 2.0, 1.0
+    p = W.Problem(nx=4, ny=ny, lx=4.0 / ny, ly=1.0, periodic=True, Ma=0.05, Re=10.0, p_in=p0,
+                  wall_type=(SJ, SJ), wall_u=(0.0, U), kn=kn)
+    o = oracle_lib.Oracle(p)
+    o.set_fields(*_zeros_state(p, p0, 1.0))
+    dt = p.cfl_dt()
+    for _ in range(3000):
+        o.step(dt, 4, W.IMPLICIT | W.UPWIND)
+    u, v, pr, T = o.fields()
+    y = (np.arange(ny) + 0.5) / ny
+    zeta = 1.1466 * kn / p0          # rho = p / T = p0
+    exact = U * (y + zeta) / (1.0 + 2.0 * zeta)
+    err = np.abs(u[:, 1] - exact).max()
+    assert np.abs(T - 1.0).max() < 2e-4      # the isothermal limit holds
+    assert err <= 5e-5, err
+    # the slip is resolved: the no-slip profile is far away
+    assert np.abs(u[:, 1] - U * y).max() > 100 * err
+
+
+def _jump_conduction_exact(Tb, Tt, kn, T0, C1):
+    """(T(y), p) of steady conduction with lambda ~ sqrt(T) between jump
+    walls, H = 1, mass of the state p = 1, T = T0."""
+    yq, wq = np.polynomial.legendre.leggauss(64)
+    yq, wq = 0.5 * (yq + 1.0), 0.5 * wq
+
+    def prof(Ts0, TsH, y):
+        ph0, phH = 2.0 / 3.0 * Ts0 ** 1.5, 2.0 / 3.0 * TsH ** 1.5
+        return (1.5 * (ph0 + (phH - ph0) * y)) ** (2.0 / 3.0)
+
+    def F(x):
+        Ts0, TsH, pr = x
+        g = 2.0 / 3.0 * (TsH ** 1.5 - Ts0 ** 1.5)       # q / C1 over H = 1
+        d0, dH = g / math.sqrt(Ts0), g / math.sqrt(TsH)  # T'(0), T'(H)
+        tau0, tauH = 2.1904 * kn * Ts0 / pr, 2.1904 * kn * TsH / pr
+        # T_s - T_w = tau dT/dn, n into the gas (+y at y = 0, -y at y = H)
+        return [Ts0 - Tb - tau0 * d0, TsH - Tt + tauH * dH,
+                pr * np.sum(wq / prof(Ts0, TsH, yq)) - 1.0 / T0]
+
+    Ts0, TsH, pr = fsolve(F, [Tb, Tt, 1.0], xtol=1e-14)
+    assert np.max(np.abs(F([Ts0, TsH, pr]))) < 1e-13
+    return (lambda y: prof(Ts0, TsH, y)), pr, (Ts0, TsH)
+
+
+def test_temperature_jump_conduction_converges(oracle_lib):
+    Tb, Tt, kn, T0 = 1.0, 1.5, 0.04, 1.25
+    Re, Pr, gamma = 10.0, 0.7, 1.4
+    f, pex, (Ts0, TsH) = _jump_conduction_exact(Tb, Tt, kn, T0, gamma / (Re * Pr))
+    assert Ts0 - Tb > 0.03 and Tt - TsH > 0.03   # a resolved jump at both walls
+    errs = []
+    for ny, steps in ((8, 4000), (16, 8000), (32, 16000)):
+        p = W.Problem(nx=4, ny=ny, lx=4.0 / ny, ly=1.0, periodic=True, Ma=0.5, Re=Re, Pr=Pr,
+                      gamma=gamma, wall_type=(SJ, SJ), kn=kn,
+                      wall_T=(np.full(4, Tb), np.full(4, Tt)))
+        o = oracle_lib.Oracle(p)
+        o.set_fields(*_zeros_state(p, 1.0, T0))
+        dt = p.cfl_dt()
+        for _ in range(steps):
+            o.step(dt, 4, W.IMPLICIT | W.UPWIND)
+        u, v, pr, T = o.fields()
+        assert np.abs(o.residuals()[:4]).max() < 1e-12   # steady
+        y = (np.arange(ny) + 0.5) / ny
+        errs.append(np.abs(T[:, 0] - f(y)).max())
+        assert abs(pr[0, 0] - pex) < 1e-3
+    order = math.log2(errs[1] / errs[2])
+    assert errs[0] > errs[1] > errs[2], errs
+    assert 0.6 <= order <= 2.5, (errs, order)
+    assert errs[2] <= 3e-4, errs
+
+
+@pytest.mark.parametrize("scheme", list(W.SCHEMES.values()))
+def test_free_stream_between_moving_slip_jump_walls_is_preserved_bitwise(oracle_lib, scheme):
+    rng = np.random.default_rng(5)
+    p = W.Problem(nx=24, ny=8, dx=rng.uniform(0.05, 0.15, 24), dy=rng.uniform(0.05, 0.15, 8),
+                  wall_type=(SJ, SJ), wall_u=(1.0, 1.0), kn=0.02)
+    o = oracle_lib.Oracle(p)
+    f0 = o.fields()
+    for _ in range(20):
+        o.step(0.01, 6, scheme)
+    for a, b in zip(o.fields(), f0):
+        assert np.array_equal(a, b)
+    assert np.all(o.residuals() == 0.0)
+
+
+@pytest.mark.parametrize("scheme", list(W.SCHEMES.values()))
+def test_mirror_symmetry_with_slip_jump_surfaces(oracle_lib, scheme):
+    p = W.channel(40, 12, [2.5], wall_type=(SJ, SJ), wall_u=(0.3, 0.3), obstacle_type=SJ,
+                  kn=0.01)
+    rng = np.random.default_rng(1)
+    shapes = ((p.ny, p.nx + 1), (p.ny + 1, p.nx), (p.ny, p.nx), (p.ny, p.nx))
+    u, v, pr, T = [rng.uniform(-0.2, 0.2, s) for s in shapes]
+    pr, T, u = 1.0 + pr, 1.0 + T, 1.0 + u
+    u, pr, T, v = 0.5 * (u + u[::-1]), 0.5 * (pr + pr[::-1]), 0.5 * (T + T[::-1]), 0.5 * (v - v[::-1])
+    o = oracle_lib.Oracle(p)
+    o.set_fields(u, v, pr, T)
+    rT, ru, rv, rp = o.eq_residuals(0.01, scheme)
+    for r, sgn in ((rT, 1), (ru, 1), (rv, -1), (rp, 1)):
+        assert np.abs(r - sgn * r[::-1]).max() <= 1e-13 * np.abs(r).max()
+    # the slip / jump branches are active: the same state with no-slip
+    # surfaces gives other residuals
+    q = W.channel(40, 12, [2.5], wall_u=(0.3, 0.3))
+    o2 = oracle_lib.Oracle(q)
+    o2.set_fields(u, v, pr, T)
+    rT2, ru2, rv2, rp2 = o2.eq_residuals(0.01, scheme)
+    assert np.abs(rT - rT2).max() > 1e-6 and np.abs(ru - ru2).max() > 1e-6
