@@ -12,7 +12,9 @@ FP64 CPU oracle timed on a bounded sample on the host cores, and the
 mixed-precision form of every scheme (FP32 coefficient assembly and Jacobi
 corrections through an FP64 defect): its rate, its speedup over the FP64 form
 and its max / L2 relative difference from the FP64 fields after the
-configured 200 steps; the four FP64 schemes on the 3000x600 channel; the
+configured 200 steps; the four FP64 schemes on the 3000x600 channel and on
+the paper's own meshes (4032 x 200 ... 4000, Kn = 0.001, velocity-slip /
+temperature-jump walls and square, particle frame); the
 adjoint of the explicit step on the 1024x256 adjoint workload (time-averaged
 drag, 100 steps x 10 passes, checkpoints every 10 steps): backward / forward
 time and the device memory it holds; and the combined run on the 4096x1024
@@ -64,7 +66,7 @@ def measured_traffic(scheme_name: str):
     return d.get("bytes_per_launch", {}).get(scheme_name)
 
 
-def run_gpu(name: str, steps: int, warmup: int, scheme: int, fields_after: int = 0):
+def run_gpu(name: str, steps: int, warmup: int, scheme: int, fields_after: int = 0, f0=None):
     """Timed steps; with fields_after > 0 the run continues (untimed) to that
     many steps in all and returns the fields."""
     import torch
@@ -72,7 +74,7 @@ def run_gpu(name: str, steps: int, warmup: int, scheme: int, fields_after: int =
 
     p, run = W.workload(name)
     g = sts.Solver(p)
-    g.set_fields(*W.initial_fields(p, run["seed"]))
+    g.set_fields(*(f0 if f0 is not None else W.initial_fields(p, run["seed"])))
     dt, inner = run["dt"], run["inner"]
     for _ in range(warmup):
         g.step(dt, inner, scheme)
@@ -171,8 +173,10 @@ def run_combined(name: str = "combined_4096x1024", scheme: int = W.EXPLICIT | W.
 def run_other_grid(name: str, steps: int, warmup: int):
     """FP64 throughput of every scheme on another configured grid."""
     out = {}
+    p, run = W.workload(name)
+    f0 = W.initial_fields(p, run["seed"])
     for nm, sch in W.SCHEMES.items():
-        r = run_gpu(name, steps, warmup, sch)
+        r = run_gpu(name, steps, warmup, sch, f0=f0)
         out[nm] = {"mfv_iters_s": round(r["mfv_iters_s"], 2), "pass_ms": round(r["pass_ms"], 5),
                    "hbm_frac": round(r["pass_gbs"] / HBM_PEAK_GBS, 4),
                    "ms_per_step": round(r["ms_per_step"], 4)}
@@ -232,7 +236,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined run (mixed forward + FP64 adjoint, 4096x1024)")
-    ap.add_argument("--other-grids", default="channel_3000x600",
+    ap.add_argument("--other-grids",
+                    default="channel_3000x600,paper_4032x200,paper_4032x400,paper_4032x2000,paper_4032x4000",
                     help="comma list of further grids timed with every FP64 scheme ('' = none)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint timing and print its JSON (profiling)")

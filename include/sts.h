@@ -60,18 +60,29 @@ typedef struct {
 } sts_obstacles;
 
 enum { STS_X_INLET_OUTLET = 0, STS_X_PERIODIC = 1 };
-enum { STS_WALL_NOSLIP_ISOTHERMAL = 0, STS_WALL_SLIP_ADIABATIC = 1 };
+enum { STS_WALL_NOSLIP_ISOTHERMAL = 0, STS_WALL_SLIP_ADIABATIC = 1, STS_WALL_SLIP_JUMP = 2 };
 
-/* Boundary conditions (test case of Sec. 4 in convective units; the walls
-   are eqs pl38/pl39 with zero slip and jump lengths, or slip and adiabatic).
-     x_mode      inlet at x = 0 and outlet at x = Lx, or periodic in x.
-     u_in, T_in  [ny] inlet-face u and T (NULL -> 1); inlet v = 0.
-     p_in        inlet pressure (sets the inflow density p_in/T_in).
-     wall_type   [0] bottom wall y = 0, [1] top wall y = Ly.
-     wall_u      tangential velocity of each no-slip wall.
-     wall_T      [nx] wall temperature per cell column (NULL -> 1).
-     obstacle_T  surface temperature of the obstacles (no-slip, isothermal).
-     gx, gy      body force per unit mass (rho g in eqs pl2, pl3).
+/* Boundary conditions (test case of Sec. 4).  Wall and obstacle surfaces:
+     STS_WALL_NOSLIP_ISOTHERMAL  eqs pl38/pl39 with zero slip and jump lengths;
+     STS_WALL_SLIP_ADIABATIC     no shear, no heat flux;
+     STS_WALL_SLIP_JUMP          velocity slip (pl38, zeta = 1.1466 kn / rho)
+                                 and temperature jump (pl39, tau = 2.1904 kn
+                                 / rho), rho of the node next to the surface;
+                                 the normal derivative is taken over the half
+                                 cell, so the wall conductance is that node's
+                                 Gamma over d/2 + zeta (d/2 + tau).
+     x_mode        inlet at x = 0 and outlet at x = Lx, or periodic in x.
+     u_in, T_in    [ny] inlet-face u and T (NULL -> 1); inlet v = 0.
+     p_in          inlet pressure (sets the inflow density p_in/T_in).
+     wall_type     [0] bottom wall y = 0, [1] top wall y = Ly.
+     wall_u        tangential velocity of each wall (no-slip and slip-jump;
+                   moving walls of the particle frame, Sec. 4).
+     wall_T        [nx] wall temperature per cell column (NULL -> 1).
+     obstacle_T    surface temperature of the obstacles (at rest).
+     gx, gy        body force per unit mass (rho g in eqs pl2, pl3).
+     obstacle_type STS_WALL_NOSLIP_ISOTHERMAL or STS_WALL_SLIP_JUMP.
+     kn            Knudsen number of the slip-jump surfaces, in the grid's
+                   length unit (>= 0; unused by the other types).
    Arrays are copied. */
 typedef struct {
   int x_mode;
@@ -82,6 +93,8 @@ typedef struct {
   const double *wall_T[2];
   double obstacle_T;
   double gx, gy;
+  int obstacle_type;
+  double kn;
 } sts_bc;
 
 /* scheme bits for sts_step: convective terms explicit (Forward Euler) or

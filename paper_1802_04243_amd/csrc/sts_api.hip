@@ -98,6 +98,8 @@ struct sts_ctx {
   std::vector<double> dx, dy, u_in, T_in, Tw[2];
   std::vector<unsigned char> solid;  // [ny][nx]
   double p_in, obsT;
+  int otype = STS_WALL_NOSLIP_ISOTHERMAL;
+  bool slip_jump = false;  // some wall or obstacle surface is slip-jump
   // adjoint of the explicit step (allocated on first use, library-owned):
   // the iterates x_0 .. x_K of a step, one pass's intermediates, the
   // adjoints of the intermediates, two adjoint states, the adjoints of the
@@ -157,8 +159,12 @@ sts_status validate(const sts_grid *g, const sts_obstacles *ob, double Ma,
     return fail(STS_EINVAL, "unknown x_mode %d", bc->x_mode);
   for (int w = 0; w < 2; w++)
     if (bc->wall_type[w] != STS_WALL_NOSLIP_ISOTHERMAL &&
-        bc->wall_type[w] != STS_WALL_SLIP_ADIABATIC)
+        bc->wall_type[w] != STS_WALL_SLIP_ADIABATIC && bc->wall_type[w] != STS_WALL_SLIP_JUMP)
       return fail(STS_EINVAL, "unknown wall_type[%d] = %d", w, bc->wall_type[w]);
+  if (bc->obstacle_type != STS_WALL_NOSLIP_ISOTHERMAL && bc->obstacle_type != STS_WALL_SLIP_JUMP)
+    return fail(STS_EINVAL, "obstacle_type must be no-slip isothermal or slip-jump (%d)",
+                bc->obstacle_type);
+  if (!(bc->kn >= 0 && isfinite(bc->kn))) return fail(STS_EINVAL, "kn must be >= 0 and finite");
   if (!(bc->p_in > 0 && isfinite(bc->p_in))) return fail(STS_EINVAL, "p_in must be > 0");
   if (!(bc->obstacle_T > 0 && isfinite(bc->obstacle_T)))
     return fail(STS_EINVAL, "obstacle_T must be > 0");
@@ -380,6 +386,8 @@ sts_status build(sts_ctx *c, const sts_bc *bc) {
   P.gy = bc->gy;
   P.obsT = c->obsT;
   P.sq_obsT = sqrt(c->obsT);
+  P.otype = c->otype;
+  P.sj = c->slip_jump ? 1 : 0;
   HIPCHK(hipStreamSynchronize(c->stream));
   return fill_frames(c);
 }
@@ -455,6 +463,12 @@ extern "C" sts_status sts_create(const sts_grid *grid, const sts_obstacles *obst
           c->solid[(size_t)j * nx + i] = 1;
   c->p_in = bc->p_in;
   c->obsT = bc->obstacle_T;
+  c->otype = bc->obstacle_type;
+  c->slip_jump = bc->obstacle_type == STS_WALL_SLIP_JUMP || bc->wall_type[0] == STS_WALL_SLIP_JUMP ||
+                 bc->wall_type[1] == STS_WALL_SLIP_JUMP;
+  // slip and jump lengths per unit 1/rho (eqs pl38, pl39)
+  c->P.kz = 1.1466 * bc->kn;
+  c->P.kt = 2.1904 * bc->kn;
   // coefficients of eqs pl2-pl6 in convective scaling: A = 1/(gamma Ma^2),
   // B = 1/Re, energy equation in internal-energy form (the discrete source
   // carries p div u): C1 = gamma/(Re Pr), C2 = gamma(gamma-1)Ma^2/Re,
@@ -685,6 +699,8 @@ State slot_state(sts_ctx *c, int k) {
 
 extern "C" sts_status sts_drag(sts_ctx *c, double *out) {
   if (!c || !out) return fail(STS_EINVAL, "NULL argument");
+  if (c->otype != STS_WALL_NOSLIP_ISOTHERMAL)
+    return fail(STS_EINVAL, "the drag is defined for no-slip obstacle surfaces");
   sts_status s;
   if ((s = ensure_aux(c)) != STS_OK) return s;
   launch_drag(c->P, c->st[c->cur], c->aux, c->aux + drag_blocks(c->P), c->stream);
@@ -744,6 +760,7 @@ sts_status clear_tmp(sts_ctx *c, State lo) {
 extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
   if (!c) return fail(STS_EINVAL, "ctx is NULL");
   if (c->per) return fail(STS_EINVAL, "the adjoint supports inlet/outlet channels only");
+  if (c->slip_jump) return fail(STS_EINVAL, "the adjoint supports no slip-jump surfaces");
   if (n_inner < 1 || n_inner > 10000) return fail(STS_EINVAL, "n_inner must be in [1, 10000]");
   HIPCHK(hipStreamSynchronize(c->stream));
   if (c->adj_K != n_inner) {

@@ -38,8 +38,13 @@ struct Params {
   long pitch;  // doubles per row
   long off;    // element index of (0,0)
   double dt, idt, A, B, C1, C2, C3, gx, gy, obsT, sq_obsT;
-  int wtype0, wtype1;
+  int wtype0, wtype1;  // STS_WALL_* of the bottom and top walls
+  int otype;           // STS_WALL_* of the obstacle surfaces
+  int sj;              // some surface is slip-jump (selects the kernel instances)
   double wu0, wu1;
+  // slip / jump length times rho of the slip-jump surfaces (eqs pl38, pl39):
+  // zeta = kz / rho, tau = kt / rho
+  double kz, kt;
   // geometry per column i (index i + XPAD, wrapped or clamped outside the
   // domain): [0] dx_i, [1] 1/dx_i; per x-face i (between cells i-1 and i):
   // [2] s = dx_{i-1} + dx_i, [3] 1/s, [4] dx_i/s (weight of cell i-1),

@@ -349,9 +349,24 @@ __device__ double gam_c(const Lds &s, const Params &P, int i, int j, int gi,
 }
 
 // ---------------------------------------------------------------------------
+// velocity-slip / temperature-jump surfaces (eqs pl38, pl39)
+// ---------------------------------------------------------------------------
+// The normal derivative at the surface is taken over the half cell between
+// the surface and the nearest node: the wall conductance is the node's Gamma
+// over d/2 + k/rho (k = 1.1466 Kn for the velocity slip, 2.1904 Kn for the
+// temperature jump, rho of that node), and the gas velocity at the surface
+// is (u_w d/2 + zeta u_P) / (d/2 + zeta).
+__device__ __forceinline__ double iwall(double d, double k, double rho) {
+  return 1.0 / (0.5 * d + k / rho);
+}
+__device__ __forceinline__ double slip_vel(double uw, double uP, double d, double zeta) {
+  return (uw * (0.5 * d) + zeta * uP) / (0.5 * d + zeta);
+}
+
+// ---------------------------------------------------------------------------
 // energy equation (eqs pl30-pl33, pl28, pl29) for a fluid cell
 // ---------------------------------------------------------------------------
-template <bool CL, bool IM, bool TV>
+template <bool CL, bool SJ, bool IM, bool TV>
 __device__ double t_update(const Lds &s, const Params &P, int i, int j,
                            int gi, int gj, double CT) {
   const double dxi = DX_(i), dyj = DY_(j), dV = dxi * dyj;
@@ -363,7 +378,8 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   } else {
     nW = T_(i - 1, j);
     if (!CL && !FL_(i - 1, j))
-      DW = P.C1 * hmean2(gP, P.sq_obsT) * dyj * (2.0 * IDX_(i));
+      DW = ((SJ && P.otype == 2)) ? P.C1 * gP * dyj * iwall(dxi, P.kt, R_(i, j))
+                          : P.C1 * hmean2(gP, P.sq_obsT) * dyj * (2.0 * IDX_(i));
     else
       DW = P.C1 * hmean(DX_(i - 1), G_(i - 1, j), dxi, gP) * dyj * (2.0 * ISX_(i));
   }
@@ -373,7 +389,8 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   } else {
     nE = T_(i + 1, j);
     if (!CL && !FL_(i + 1, j))
-      DE = P.C1 * hmean2(gP, P.sq_obsT) * dyj * (2.0 * IDX_(i));
+      DE = ((SJ && P.otype == 2)) ? P.C1 * gP * dyj * iwall(dxi, P.kt, R_(i, j))
+                          : P.C1 * hmean2(gP, P.sq_obsT) * dyj * (2.0 * IDX_(i));
     else
       DE = P.C1 * hmean(dxi, gP, DX_(i + 1), G_(i + 1, j)) * dyj * (2.0 * ISX_(i + 1));
   }
@@ -381,6 +398,9 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
     if (P.wtype0 == 0) {
       nS = P.Tw0[wall_c(s, P, i)];
       DS = P.C1 * hmean2(gP, P.sq_Tw0[wall_c(s, P, i)]) * dxi * (2.0 * IDY_(j));
+    } else if ((SJ && P.wtype0 == 2)) {
+      nS = P.Tw0[wall_c(s, P, i)];
+      DS = P.C1 * gP * dxi * iwall(dyj, P.kt, R_(i, j));
     } else {
       nS = TP;
       DS = 0.0;
@@ -388,7 +408,8 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   } else {
     nS = T_(i, j - 1);
     if (!CL && !FL_(i, j - 1))
-      DS = P.C1 * hmean2(gP, P.sq_obsT) * dxi * (2.0 * IDY_(j));
+      DS = ((SJ && P.otype == 2)) ? P.C1 * gP * dxi * iwall(dyj, P.kt, R_(i, j))
+                          : P.C1 * hmean2(gP, P.sq_obsT) * dxi * (2.0 * IDY_(j));
     else
       DS = P.C1 * hmean(DY_(j - 1), G_(i, j - 1), dyj, gP) * dxi * (2.0 * ISY_(j));
   }
@@ -396,6 +417,9 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
     if (P.wtype1 == 0) {
       nN = P.Tw1[wall_c(s, P, i)];
       DN = P.C1 * hmean2(gP, P.sq_Tw1[wall_c(s, P, i)]) * dxi * (2.0 * IDY_(j));
+    } else if ((SJ && P.wtype1 == 2)) {
+      nN = P.Tw1[wall_c(s, P, i)];
+      DN = P.C1 * gP * dxi * iwall(dyj, P.kt, R_(i, j));
     } else {
       nN = TP;
       DN = 0.0;
@@ -403,7 +427,8 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   } else {
     nN = T_(i, j + 1);
     if (!CL && !FL_(i, j + 1))
-      DN = P.C1 * hmean2(gP, P.sq_obsT) * dxi * (2.0 * IDY_(j));
+      DN = ((SJ && P.otype == 2)) ? P.C1 * gP * dxi * iwall(dyj, P.kt, R_(i, j))
+                          : P.C1 * hmean2(gP, P.sq_obsT) * dxi * (2.0 * IDY_(j));
     else
       DN = P.C1 * hmean(dyj, gP, DY_(j + 1), G_(i, j + 1)) * dxi * (2.0 * ISY_(j + 1));
   }
@@ -441,19 +466,29 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   const double uc = 0.5 * (U_(i, j) + U_(i + 1, j));
   double vE, vW, uN, uS;
   if (!CL && !P.per && gi == P.nx - 1) vE = vc;
-  else if (!CL && !FL_(i + 1, j)) vE = 0.0;
+  else if (!CL && !FL_(i + 1, j))
+    vE = ((SJ && P.otype == 2)) ? slip_vel(0.0, vc, DX_(i), P.kz / R_(i, j)) : 0.0;
   else
     vE = WLX_(i + 1) * vc + WRX_(i + 1) * (0.5 * (V_(i + 1, j) + V_(i + 1, j + 1)));
   if (!CL && !P.per && gi == 0) vW = 0.0;
-  else if (!CL && !FL_(i - 1, j)) vW = 0.0;
+  else if (!CL && !FL_(i - 1, j))
+    vW = ((SJ && P.otype == 2)) ? slip_vel(0.0, vc, DX_(i), P.kz / R_(i, j)) : 0.0;
   else
     vW = WLX_(i) * (0.5 * (V_(i - 1, j) + V_(i - 1, j + 1))) + WRX_(i) * vc;
-  if (!CL && gj == P.ny - 1) uN = (P.wtype1 == 0) ? P.wu1 : uc;
-  else if (!CL && !FL_(i, j + 1)) uN = 0.0;
+  if (!CL && gj == P.ny - 1)
+    uN = (P.wtype1 == 0)   ? P.wu1
+         : ((SJ && P.wtype1 == 2)) ? slip_vel(P.wu1, uc, DY_(j), P.kz / R_(i, j))
+                           : uc;
+  else if (!CL && !FL_(i, j + 1))
+    uN = ((SJ && P.otype == 2)) ? slip_vel(0.0, uc, DY_(j), P.kz / R_(i, j)) : 0.0;
   else
     uN = WLY_(j + 1) * uc + WRY_(j + 1) * (0.5 * (U_(i, j + 1) + U_(i + 1, j + 1)));
-  if (!CL && gj == 0) uS = (P.wtype0 == 0) ? P.wu0 : uc;
-  else if (!CL && !FL_(i, j - 1)) uS = 0.0;
+  if (!CL && gj == 0)
+    uS = (P.wtype0 == 0)   ? P.wu0
+         : ((SJ && P.wtype0 == 2)) ? slip_vel(P.wu0, uc, DY_(j), P.kz / R_(i, j))
+                           : uc;
+  else if (!CL && !FL_(i, j - 1))
+    uS = ((SJ && P.otype == 2)) ? slip_vel(0.0, uc, DY_(j), P.kz / R_(i, j)) : 0.0;
   else
     uS = WLY_(j) * (0.5 * (U_(i, j - 1) + U_(i + 1, j - 1))) + WRY_(j) * uc;
   const double ux = (U_(i + 1, j) - U_(i, j)) * IDX_(i);
@@ -471,7 +506,7 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
 // ---------------------------------------------------------------------------
 // u-momentum (x<->y mirror of the printed v-equation) for a solved u-face
 // ---------------------------------------------------------------------------
-template <bool CL, bool IM, bool TV>
+template <bool CL, bool SJ, bool IM, bool TV>
 __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
                          int gj, double Cu, double &uh, double &du) {
   const double dxl = DX_(i - 1), dxr = DX_(i), dyj = DY_(j);
@@ -485,6 +520,9 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
     if (P.wtype0 == 0) {
       uS = P.wu0;
       DS = P.B * 0.5 * (gnode + P.sq_Twu0[wall_u(s, P, i)]) * len * (2.0 * IDY_(j));
+    } else if ((SJ && P.wtype0 == 2)) {
+      uS = P.wu0;
+      DS = P.B * gnode * len * iwall(dyj, P.kz, WLX_(i) * rl + WRX_(i) * rr);
     } else {
       uS = uP;
       DS = 0.0;
@@ -492,7 +530,8 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   } else {
     uS = U_(i, j - 1);
     if (!CL && !FL_(i - 1, j - 1) && !FL_(i, j - 1))
-      DS = P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDY_(j));
+      DS = ((SJ && P.otype == 2)) ? P.B * gnode * len * iwall(dyj, P.kz, WLX_(i) * rl + WRX_(i) * rr)
+                          : P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDY_(j));
     else
       DS = P.B * gam_c<CL>(s, P, i, j, gi, gj) * SX_(i) * ISY_(j);
   }
@@ -500,6 +539,9 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
     if (P.wtype1 == 0) {
       uN = P.wu1;
       DN = P.B * 0.5 * (gnode + P.sq_Twu1[wall_u(s, P, i)]) * len * (2.0 * IDY_(j));
+    } else if ((SJ && P.wtype1 == 2)) {
+      uN = P.wu1;
+      DN = P.B * gnode * len * iwall(dyj, P.kz, WLX_(i) * rl + WRX_(i) * rr);
     } else {
       uN = uP;
       DN = 0.0;
@@ -507,7 +549,8 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   } else {
     uN = U_(i, j + 1);
     if (!CL && !FL_(i - 1, j + 1) && !FL_(i, j + 1))
-      DN = P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDY_(j));
+      DN = ((SJ && P.otype == 2)) ? P.B * gnode * len * iwall(dyj, P.kz, WLX_(i) * rl + WRX_(i) * rr)
+                          : P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDY_(j));
     else
       DN = P.B * gam_c<CL>(s, P, i, j + 1, gi, gj + 1) * SX_(i) * ISY_(j + 1);
   }
@@ -561,7 +604,7 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
 // ---------------------------------------------------------------------------
 // v-momentum (eqs pl14-pl16, pl15, pl21) for a solved v-face
 // ---------------------------------------------------------------------------
-template <bool CL, bool IM, bool TV>
+template <bool CL, bool SJ, bool IM, bool TV>
 __device__ void v_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
                          int gj, double Cv, double &vh, double &dv) {
   const double dxi = DX_(i), dys = DY_(j - 1), dyn = DY_(j);
@@ -576,13 +619,15 @@ __device__ void v_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   if (!CL && !P.per && gi == 0)
     DW = P.B * 0.5 * (gnode + gam_c<CL>(s, P, i, j, gi, gj)) * len * (2.0 * IDX_(i));
   else if (!CL && !FL_(i - 1, j - 1) && !FL_(i - 1, j))
-    DW = P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDX_(i));
+    DW = ((SJ && P.otype == 2)) ? P.B * gnode * len * iwall(dxi, P.kz, WLY_(j) * rs + WRY_(j) * rn)
+                        : P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDX_(i));
   else
     DW = P.B * gam_c<CL>(s, P, i, j, gi, gj) * SY_(j) * ISX_(i);
   if (!CL && !P.per && gi == P.nx - 1)
     DE = 0.0;
   else if (!CL && !FL_(i + 1, j - 1) && !FL_(i + 1, j))
-    DE = P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDX_(i));
+    DE = ((SJ && P.otype == 2)) ? P.B * gnode * len * iwall(dxi, P.kz, WLY_(j) * rs + WRY_(j) * rn)
+                        : P.B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * IDX_(i));
   else
     DE = P.B * gam_c<CL>(s, P, i + 1, j, gi + 1, gj) * SY_(j) * ISX_(i + 1);
   const double DS = P.B * gs * dxi * IDY_(j - 1), DN = P.B * gn * dxi * IDY_(j);
@@ -647,6 +692,11 @@ __device__ void v_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
 // the FP32-assembled operator.  FP32 divisions and square roots use the
 // hardware reciprocal / square root (about 1 ulp), and FP32 products may be
 // fused.
+__device__ __forceinline__ float iwall_f(float d, float k, float rho) {
+#pragma clang fp contract(fast)
+  return frcp(0.5f * d + k * frcp(rho));
+}
+
 template <bool CL>
 __device__ float gam_c_f(const Lds &s, const Params &P, int i, int j, int gi,
                          int gj) {
@@ -662,7 +712,7 @@ __device__ float gam_c_f(const Lds &s, const Params &P, int i, int j, int gi,
          wn * (wl * F_(G_(i - 1, j)) + wr * F_(G_(i, j)));
 }
 
-template <bool CL, bool IM, bool TV>
+template <bool CL, bool SJ, bool IM, bool TV>
 __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
                               int gi, int gj, double CT) {
 #pragma clang fp contract(fast)
@@ -677,7 +727,8 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
   } else {
     nW = T_(i - 1, j);
     if (!CL && !FL_(i - 1, j))
-      DW = C1 * hmean2_f(gP, obs) * dyj * (2.0f * F_(IDX_(i)));
+      DW = ((SJ && P.otype == 2)) ? C1 * gP * dyj * iwall_f(dxi, F_(P.kt), F_(R_(i, j)))
+                          : C1 * hmean2_f(gP, obs) * dyj * (2.0f * F_(IDX_(i)));
     else
       DW = C1 * hmean_f(F_(DX_(i - 1)), F_(G_(i - 1, j)), dxi, gP) * dyj * (2.0f * F_(ISX_(i)));
   }
@@ -687,7 +738,8 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
   } else {
     nE = T_(i + 1, j);
     if (!CL && !FL_(i + 1, j))
-      DE = C1 * hmean2_f(gP, obs) * dyj * (2.0f * F_(IDX_(i)));
+      DE = ((SJ && P.otype == 2)) ? C1 * gP * dyj * iwall_f(dxi, F_(P.kt), F_(R_(i, j)))
+                          : C1 * hmean2_f(gP, obs) * dyj * (2.0f * F_(IDX_(i)));
     else
       DE = C1 * hmean_f(dxi, gP, F_(DX_(i + 1)), F_(G_(i + 1, j))) * dyj * (2.0f * F_(ISX_(i + 1)));
   }
@@ -695,6 +747,9 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
     if (P.wtype0 == 0) {
       nS = P.Tw0[wall_c(s, P, i)];
       DS = C1 * hmean2_f(gP, F_(P.sq_Tw0[wall_c(s, P, i)])) * dxi * (2.0f * F_(IDY_(j)));
+    } else if ((SJ && P.wtype0 == 2)) {
+      nS = P.Tw0[wall_c(s, P, i)];
+      DS = C1 * gP * dxi * iwall_f(dyj, F_(P.kt), F_(R_(i, j)));
     } else {
       nS = TP;
       DS = 0.0f;
@@ -702,7 +757,8 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
   } else {
     nS = T_(i, j - 1);
     if (!CL && !FL_(i, j - 1))
-      DS = C1 * hmean2_f(gP, obs) * dxi * (2.0f * F_(IDY_(j)));
+      DS = ((SJ && P.otype == 2)) ? C1 * gP * dxi * iwall_f(dyj, F_(P.kt), F_(R_(i, j)))
+                          : C1 * hmean2_f(gP, obs) * dxi * (2.0f * F_(IDY_(j)));
     else
       DS = C1 * hmean_f(F_(DY_(j - 1)), F_(G_(i, j - 1)), dyj, gP) * dxi * (2.0f * F_(ISY_(j)));
   }
@@ -710,6 +766,9 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
     if (P.wtype1 == 0) {
       nN = P.Tw1[wall_c(s, P, i)];
       DN = C1 * hmean2_f(gP, F_(P.sq_Tw1[wall_c(s, P, i)])) * dxi * (2.0f * F_(IDY_(j)));
+    } else if ((SJ && P.wtype1 == 2)) {
+      nN = P.Tw1[wall_c(s, P, i)];
+      DN = C1 * gP * dxi * iwall_f(dyj, F_(P.kt), F_(R_(i, j)));
     } else {
       nN = TP;
       DN = 0.0f;
@@ -717,7 +776,8 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
   } else {
     nN = T_(i, j + 1);
     if (!CL && !FL_(i, j + 1))
-      DN = C1 * hmean2_f(gP, obs) * dxi * (2.0f * F_(IDY_(j)));
+      DN = ((SJ && P.otype == 2)) ? C1 * gP * dxi * iwall_f(dyj, F_(P.kt), F_(R_(i, j)))
+                          : C1 * hmean2_f(gP, obs) * dxi * (2.0f * F_(IDY_(j)));
     else
       DN = C1 * hmean_f(dyj, gP, F_(DY_(j + 1)), F_(G_(i, j + 1))) * dxi * (2.0f * F_(ISY_(j + 1)));
   }
@@ -749,19 +809,29 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
   const double uc = 0.5 * (U_(i, j) + U_(i + 1, j));
   double vE, vW, uN, uS;
   if (!CL && !P.per && gi == P.nx - 1) vE = vc;
-  else if (!CL && !FL_(i + 1, j)) vE = 0.0;
+  else if (!CL && !FL_(i + 1, j))
+    vE = ((SJ && P.otype == 2)) ? slip_vel(0.0, vc, DX_(i), P.kz / R_(i, j)) : 0.0;
   else
     vE = WLX_(i + 1) * vc + WRX_(i + 1) * (0.5 * (V_(i + 1, j) + V_(i + 1, j + 1)));
   if (!CL && !P.per && gi == 0) vW = 0.0;
-  else if (!CL && !FL_(i - 1, j)) vW = 0.0;
+  else if (!CL && !FL_(i - 1, j))
+    vW = ((SJ && P.otype == 2)) ? slip_vel(0.0, vc, DX_(i), P.kz / R_(i, j)) : 0.0;
   else
     vW = WLX_(i) * (0.5 * (V_(i - 1, j) + V_(i - 1, j + 1))) + WRX_(i) * vc;
-  if (!CL && gj == P.ny - 1) uN = (P.wtype1 == 0) ? P.wu1 : uc;
-  else if (!CL && !FL_(i, j + 1)) uN = 0.0;
+  if (!CL && gj == P.ny - 1)
+    uN = (P.wtype1 == 0)   ? P.wu1
+         : ((SJ && P.wtype1 == 2)) ? slip_vel(P.wu1, uc, DY_(j), P.kz / R_(i, j))
+                           : uc;
+  else if (!CL && !FL_(i, j + 1))
+    uN = ((SJ && P.otype == 2)) ? slip_vel(0.0, uc, DY_(j), P.kz / R_(i, j)) : 0.0;
   else
     uN = WLY_(j + 1) * uc + WRY_(j + 1) * (0.5 * (U_(i, j + 1) + U_(i + 1, j + 1)));
-  if (!CL && gj == 0) uS = (P.wtype0 == 0) ? P.wu0 : uc;
-  else if (!CL && !FL_(i, j - 1)) uS = 0.0;
+  if (!CL && gj == 0)
+    uS = (P.wtype0 == 0)   ? P.wu0
+         : ((SJ && P.wtype0 == 2)) ? slip_vel(P.wu0, uc, DY_(j), P.kz / R_(i, j))
+                           : uc;
+  else if (!CL && !FL_(i, j - 1))
+    uS = ((SJ && P.otype == 2)) ? slip_vel(0.0, uc, DY_(j), P.kz / R_(i, j)) : 0.0;
   else
     uS = WLY_(j) * (0.5 * (U_(i, j - 1) + U_(i + 1, j - 1))) + WRY_(j) * uc;
   const float idx = F_(IDX_(i)), idy = F_(IDY_(j)), dVf = dxi * dyj;
@@ -782,7 +852,7 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
   return TP + (double)(F_(r) * frcp(F_(a0)));
 }
 
-template <bool CL, bool IM, bool TV>
+template <bool CL, bool SJ, bool IM, bool TV>
 __device__ void u_pseudo_mx(const Lds &s, const Params &P, int i, int j,
                             int gi, int gj, double Cu, double &uh, double &du) {
 #pragma clang fp contract(fast)
@@ -799,6 +869,9 @@ __device__ void u_pseudo_mx(const Lds &s, const Params &P, int i, int j,
     if (P.wtype0 == 0) {
       uS = P.wu0;
       DS = B * 0.5f * (gnode + F_(P.sq_Twu0[wall_u(s, P, i)])) * len * (2.0f * F_(IDY_(j)));
+    } else if ((SJ && P.wtype0 == 2)) {
+      uS = P.wu0;
+      DS = B * gnode * len * iwall_f(dyj, F_(P.kz), F_(WLX_(i) * R_(i - 1, j) + WRX_(i) * R_(i, j)));
     } else {
       uS = uP;
       DS = 0.0f;
@@ -806,7 +879,9 @@ __device__ void u_pseudo_mx(const Lds &s, const Params &P, int i, int j,
   } else {
     uS = U_(i, j - 1);
     if (!CL && !FL_(i - 1, j - 1) && !FL_(i, j - 1))
-      DS = B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDY_(j)));
+      DS = ((SJ && P.otype == 2))
+               ? B * gnode * len * iwall_f(dyj, F_(P.kz), F_(WLX_(i) * R_(i - 1, j) + WRX_(i) * R_(i, j)))
+               : B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDY_(j)));
     else
       DS = B * gcS * F_(SX_(i)) * F_(ISY_(j));
   }
@@ -814,6 +889,9 @@ __device__ void u_pseudo_mx(const Lds &s, const Params &P, int i, int j,
     if (P.wtype1 == 0) {
       uN = P.wu1;
       DN = B * 0.5f * (gnode + F_(P.sq_Twu1[wall_u(s, P, i)])) * len * (2.0f * F_(IDY_(j)));
+    } else if ((SJ && P.wtype1 == 2)) {
+      uN = P.wu1;
+      DN = B * gnode * len * iwall_f(dyj, F_(P.kz), F_(WLX_(i) * R_(i - 1, j) + WRX_(i) * R_(i, j)));
     } else {
       uN = uP;
       DN = 0.0f;
@@ -821,7 +899,9 @@ __device__ void u_pseudo_mx(const Lds &s, const Params &P, int i, int j,
   } else {
     uN = U_(i, j + 1);
     if (!CL && !FL_(i - 1, j + 1) && !FL_(i, j + 1))
-      DN = B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDY_(j)));
+      DN = ((SJ && P.otype == 2))
+               ? B * gnode * len * iwall_f(dyj, F_(P.kz), F_(WLX_(i) * R_(i - 1, j) + WRX_(i) * R_(i, j)))
+               : B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDY_(j)));
     else
       DN = B * gcN * F_(SX_(i)) * F_(ISY_(j + 1));
   }
@@ -869,7 +949,7 @@ __device__ void u_pseudo_mx(const Lds &s, const Params &P, int i, int j,
   du = (double)(F_(P.A) * dyj * ia0);
 }
 
-template <bool CL, bool IM, bool TV>
+template <bool CL, bool SJ, bool IM, bool TV>
 __device__ void v_pseudo_mx(const Lds &s, const Params &P, int i, int j,
                             int gi, int gj, double Cv, double &vh, double &dv) {
 #pragma clang fp contract(fast)
@@ -886,13 +966,17 @@ __device__ void v_pseudo_mx(const Lds &s, const Params &P, int i, int j,
   if (!CL && !P.per && gi == 0)
     DW = B * 0.5f * (gnode + gcW) * len * (2.0f * F_(IDX_(i)));
   else if (!CL && !FL_(i - 1, j - 1) && !FL_(i - 1, j))
-    DW = B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDX_(i)));
+    DW = ((SJ && P.otype == 2))
+             ? B * gnode * len * iwall_f(dxi, F_(P.kz), F_(WLY_(j) * R_(i, j - 1) + WRY_(j) * R_(i, j)))
+             : B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDX_(i)));
   else
     DW = B * gcW * F_(SY_(j)) * F_(ISX_(i));
   if (!CL && !P.per && gi == P.nx - 1)
     DE = 0.0f;
   else if (!CL && !FL_(i + 1, j - 1) && !FL_(i + 1, j))
-    DE = B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDX_(i)));
+    DE = ((SJ && P.otype == 2))
+             ? B * gnode * len * iwall_f(dxi, F_(P.kz), F_(WLY_(j) * R_(i, j - 1) + WRY_(j) * R_(i, j)))
+             : B * 0.5f * (gnode + F_(P.sq_obsT)) * len * (2.0f * F_(IDX_(i)));
   else
     DE = B * gcE * F_(SY_(j)) * F_(ISX_(i + 1));
   const float DS = B * gs * dxi * F_(IDY_(j - 1)), DN = B * gn * dxi * F_(IDY_(j));
@@ -1042,29 +1126,29 @@ __device__ __forceinline__ long item_index(const Params &P, int q, int x0,
   return P.off + (long)win_cj(P, y0, j + HB) * P.pitch + win_ui(P, x0, i + HB);
 }
 
-template <bool CL, bool IM, bool TV, bool MX>
+template <bool CL, bool SJ, bool IM, bool TV, bool MX>
 __device__ __forceinline__ void u_item(Lds &s, const Params &P, int q, int x0,
                                        int y0, double cu) {
   const int i = q % BX - 1, j = q / BX - 1;
   if (j <= TY - 1) {
     double uh = U_(i, j), du = 0.0;
     if (u_solved(s, P, i, j, x0 + i)) {
-      if (MX) u_pseudo_mx<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cu, uh, du);
-      else u_pseudo<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cu, uh, du);
+      if (MX) u_pseudo_mx<CL, SJ, IM, TV>(s, P, i, j, x0 + i, y0 + j, cu, uh, du);
+      else u_pseudo<CL, SJ, IM, TV>(s, P, i, j, x0 + i, y0 + j, cu, uh, du);
     }
     UH_(i, j) = uh;
     DU_(i, j) = du;
   }
 }
-template <bool CL, bool IM, bool TV, bool MX>
+template <bool CL, bool SJ, bool IM, bool TV, bool MX>
 __device__ __forceinline__ void v_item(Lds &s, const Params &P, int q, int x0,
                                        int y0, double cv) {
   const int i = q % BX - 1, j = q / BX - 1;
   if (i <= TX - 1) {
     double vh = V_(i, j), dv = 0.0;
     if (v_solved(s, P, i, j, y0 + j)) {
-      if (MX) v_pseudo_mx<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cv, vh, dv);
-      else v_pseudo<CL, IM, TV>(s, P, i, j, x0 + i, y0 + j, cv, vh, dv);
+      if (MX) v_pseudo_mx<CL, SJ, IM, TV>(s, P, i, j, x0 + i, y0 + j, cv, vh, dv);
+      else v_pseudo<CL, SJ, IM, TV>(s, P, i, j, x0 + i, y0 + j, cv, vh, dv);
     }
     VH_(i, j) = vh;
     DV_(i, j) = dv;
@@ -1108,7 +1192,7 @@ __device__ __forceinline__ void item_consts(const Params &P, const Consts &C,
 
 // c: the step constants of the thread's items (item_consts); cp: C_p of a
 // cell thread's cell
-template <int NTH, bool CL, bool IM, bool TV, bool RS, bool MX, bool IN>
+template <int NTH, bool CL, bool SJ, bool IM, bool TV, bool RS, bool MX, bool IN>
 __device__ void pass_body(Lds &s, const Params &P, const State n,
                           const Resid X, const Inter I, int tile, int x0,
                           int y0, const double c[], double cp) {
@@ -1138,19 +1222,19 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
   if (cellt) {
     tnew = T_(i, j);
     if (i <= TX - 1 && j <= TY - 1 && FL_(i, j))
-      tnew = MX ? t_update_mx<CL, IM, TV>(s, P, i, j, gi, gj, c[0])
-                : t_update<CL, IM, TV>(s, P, i, j, gi, gj, c[0]);
+      tnew = MX ? t_update_mx<CL, SJ, IM, TV>(s, P, i, j, gi, gj, c[0])
+                : t_update<CL, SJ, IM, TV>(s, P, i, j, gi, gj, c[0]);
   }
   if constexpr (NTH == NT) {
-    u_item<CL, IM, TV, MX>(s, P, t, x0, y0, c[1]);
-    v_item<CL, IM, TV, MX>(s, P, t, x0, y0, c[2]);
+    u_item<CL, SJ, IM, TV, MX>(s, P, t, x0, y0, c[1]);
+    v_item<CL, SJ, IM, TV, MX>(s, P, t, x0, y0, c[2]);
   } else {
     static_assert(NTH == NTP, "two rounds");
-    if (!cellt) u_item<CL, IM, TV, MX>(s, P, t - NT, x0, y0, c[0]);
+    if (!cellt) u_item<CL, SJ, IM, TV, MX>(s, P, t - NT, x0, y0, c[0]);
     if (t < NTP - NT)
-      u_item<CL, IM, TV, MX>(s, P, t + NTP - NT, x0, y0, c[1]);
+      u_item<CL, SJ, IM, TV, MX>(s, P, t + NTP - NT, x0, y0, c[1]);
     else
-      v_item<CL, IM, TV, MX>(s, P, t + NTP - 2 * NT, x0, y0, c[1]);
+      v_item<CL, SJ, IM, TV, MX>(s, P, t + NTP - 2 * NT, x0, y0, c[1]);
   }
   __syncthreads();
 
@@ -1239,12 +1323,15 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
 // One pass over the tiles; RS: the last pass of a step, which also produces
 // the residual inputs; MX: the mixed-precision form of the T, u, v updates;
 // IN: also store the pass intermediates (the adjoint's recompute; a
-// template flag so that the plain pass holds none of their pointers).
+// template flag so that the plain pass holds none of their pointers); SJ:
+// the problem has velocity-slip / temperature-jump surfaces (their branches
+// are compiled only into these instances, which keeps the register
+// allocation of the others as it is without them).
 // Two blocks share a CU (LDS bound).  The explicit schemes use NTP threads
 // (6 waves per SIMD, at most 80 VGPRs); the implicit ones and the mixed
 // explicit TVD pass need more registers and use NT threads (4 waves per
 // SIMD, at most 128 VGPRs).
-template <int NTH, bool IM, bool TV, bool RS, bool MX, bool IN>
+template <int NTH, bool IM, bool TV, bool RS, bool MX, bool IN, bool SJ>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_pass(
     const Params P, const State o, const State n, const Consts C, const Resid X, const Inter I) {
   __shared__ Lds s;
@@ -1255,9 +1342,9 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
   load_window<NTH, MX>(s, P, o, x0, y0);
   __syncthreads();
   if (P.clean[tile])
-    pass_body<NTH, true, IM, TV, RS, MX, IN>(s, P, n, X, I, tile, x0, y0, c, cp);
+    pass_body<NTH, true, false, IM, TV, RS, MX, IN>(s, P, n, X, I, tile, x0, y0, c, cp);
   else
-    pass_body<NTH, false, IM, TV, RS, MX, IN>(s, P, n, X, I, tile, x0, y0, c, cp);
+    pass_body<NTH, false, SJ, IM, TV, RS, MX, IN>(s, P, n, X, I, tile, x0, y0, c, cp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1540,15 +1627,20 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
   const Inter I = inter ? *inter : Inter{};
   // intermediates are stored only by the explicit scheme's plain passes (the
   // adjoint's recompute); the caller guarantees !im && !last with inter
-#define STS_PASS(IM_, TV_, MX_)                                                             \
+#define STS_PASS_SJ(IM_, TV_, MX_, SJ_)                                                     \
   do {                                                                                      \
     constexpr int nth = (IM_ || (MX_ && TV_)) ? NT : NTP;                                   \
     if (last)                                                                               \
-      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true, MX_, false>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
-    else if (inter && !IM_)                                                                 \
-      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_, !IM_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true, MX_, false, SJ_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
+    else if (inter && !IM_ && !SJ_)                                                         \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_, !IM_ && !SJ_, SJ_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
     else                                                                                    \
-      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_, false>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_, false, SJ_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
+  } while (0)
+#define STS_PASS(IM_, TV_, MX_)                \
+  do {                                         \
+    if (P.sj) STS_PASS_SJ(IM_, TV_, MX_, true); \
+    else STS_PASS_SJ(IM_, TV_, MX_, false);     \
   } while (0)
   if (mx) {
     if (im && tv) STS_PASS(true, true, true);
@@ -1562,6 +1654,7 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
     else STS_PASS(false, false, false);
   }
 #undef STS_PASS
+#undef STS_PASS_SJ
 }
 
 void launch_residual(const Params &P, State n, Consts C, Resid X, double *out,

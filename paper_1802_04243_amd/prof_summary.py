@@ -21,12 +21,12 @@ from collections import defaultdict
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_1802_04243_amd/csrc/sts_kernels.hip", "paper_1802_04243_amd/csrc/sts_internal.h"]
 def scheme_of(kernel: str):
-    """Scheme of a plain (not last, not mixed, no intermediates) pass kernel
-    k_pass<NTH, IM, TV, RS, MX, IN>."""
+    """Scheme of a plain (not last, not mixed, no intermediates, no
+    slip-jump surfaces) pass kernel k_pass<NTH, IM, TV, RS, MX, IN, SJ>."""
     if not kernel.startswith("k_pass<"):
         return None
     a = [x.strip() for x in kernel[len("k_pass<"):-1].split(",")]
-    if len(a) != 6 or a[3] != "false" or a[4] != "false" or a[5] != "false":
+    if len(a) != 7 or any(x != "false" for x in a[3:]):
         return None
     return ("implicit" if a[1] == "true" else "explicit") + ("_tvd" if a[2] == "true" else "_upwind")
 NFV = 5120 * 1152

@@ -50,7 +50,8 @@ class _Obst(C.Structure):
 class _Bc(C.Structure):
     _fields_ = [("x_mode", C.c_int), ("u_in", _D), ("T_in", _D), ("p_in", C.c_double),
                 ("wall_type", C.c_int * 2), ("wall_u", C.c_double * 2), ("wall_T", _D * 2),
-                ("obstacle_T", C.c_double), ("gx", C.c_double), ("gy", C.c_double)]
+                ("obstacle_T", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
+                ("obstacle_type", C.c_int), ("kn", C.c_double)]
 
 
 _lib = None
@@ -132,6 +133,7 @@ class Solver:
         bc.wall_u[0], bc.wall_u[1] = prob.wall_u
         bc.wall_T[0], bc.wall_T[1] = _ptr(wb), _ptr(wt)
         bc.obstacle_T, bc.gx, bc.gy = prob.obstacle_T, prob.gx, prob.gy
+        bc.obstacle_type, bc.kn = prob.obstacle_type, prob.kn
         nbytes = C.c_size_t()
         _check(L.sts_workspace_bytes(C.byref(g), C.byref(nbytes)))
         self.workspace_bytes = nbytes.value

@@ -121,6 +121,30 @@ def channel(nx: int, ny: int, centres: Sequence[Fraction], Re: float = 20.0, **k
     return Problem(nx=nx, ny=ny, lx=5.0, ly=1.0, obstacles=obst, Re=Re, **kw)
 
 
+def paper_channel(ny: int, kn: float = 0.001, Ma: float = 2.43) -> Problem:
+    """The test case of Sec. 4 in the paper's own units (length: the square
+    side a; velocity: the thermal speed V_th = sqrt(2 R T_0); T_0 the wall
+    temperature, p_0 the inflow pressure): uniform grid spacing 0.05, channel
+    length 201.6 (4032 cells), height ny * 0.05, one square of side 1 whose
+    front face is 5.5 behind the inlet, centred in y; hard-sphere gas with
+    gamma = 5/3, Pr = 2/3 and the pl37 coefficients (A = 1/2,
+    B = 5 sqrt(pi) Kn / 16), i.e. a reference Mach number sqrt(2/gamma) and a
+    reference Reynolds number 16 / (5 sqrt(pi) Kn); inflow at Mach Ma, i.e.
+    u = Ma sqrt(gamma/2) in V_th units; particle frame: the channel walls move
+    with the inflow speed; velocity-slip / temperature-jump walls and square
+    (pl38, pl39) at T = 1."""
+    nx, d = 4032, 0.05
+    gamma = 5.0 / 3.0
+    U = Ma * math.sqrt(gamma / 2.0)
+    i0 = 110                           # 5.5 / 0.05
+    j0 = ny // 2 - 10
+    return Problem(nx=nx, ny=ny, lx=nx * d, ly=ny * d, obstacles=[(i0, j0, i0 + 19, j0 + 19)],
+                   Ma=math.sqrt(2.0 / gamma), Re=16.0 / (5.0 * math.sqrt(math.pi) * kn),
+                   Pr=2.0 / 3.0, gamma=gamma, u_in=np.full(ny, U),
+                   wall_type=(WALL_SLIP_JUMP, WALL_SLIP_JUMP), wall_u=(U, U),
+                   obstacle_type=WALL_SLIP_JUMP, kn=kn)
+
+
 # named workloads ------------------------------------------------------------
 def workload(name: str) -> Tuple[Problem, dict]:
     """Problem plus run parameters (steps, inner iterations, dt, seed)."""
@@ -149,6 +173,10 @@ def workload(name: str) -> Tuple[Problem, dict]:
     elif name == "combined_4096x1024":    # mixed forward + FP64 adjoint, sqrt(N) checkpoints
         p = channel(4096, 1024, [Fraction(3, 2), Fraction(3)], Re=50.0)
         run = dict(steps=500, inner=10, seed=5, every=None)
+    elif name.startswith("paper_4032x") and name[len("paper_4032x"):] in ("200", "400", "2000", "4000"):
+        # the paper's meshes (Sec. 4): channel heights 10, 20, 100, 200
+        p = paper_channel(int(name[len("paper_4032x"):]))
+        run = dict(steps=200, inner=10, seed=6)
     else:
         raise KeyError(name)
     run["dt"] = p.cfl_dt()
