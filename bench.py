@@ -194,17 +194,24 @@ def field_errors(fm, fd):
     return mx, l2
 
 
-def run_cpu_baseline(name: str, scheme: int, steps: int):
-    """The FP64 oracle as it stands, on the host cores, on a bounded sample."""
+def run_cpu_baseline(name: str, scheme: int, steps: int, threads: int = 0):
+    """The FP64 oracle as it stands, on the host cores (all of them, or
+    `threads`), on a bounded sample."""
     from oracle import oracle as O
     p, run = W.workload(name)
     o = O.Oracle(p)
     o.set_fields(*W.initial_fields(p, run["seed"]))
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        o.step(run["dt"], run["inner"], scheme)
-    t = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    default = O.max_threads()
+    if threads:
+        O.set_threads(threads)
+    cores = O.max_threads()
+    try:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            o.step(run["dt"], run["inner"], scheme)
+        t = time.perf_counter() - t0
+    finally:
+        O.set_threads(default)
     return dict(value=p.n_fv * run["inner"] * steps / t / 1e6, unit="MFV-iters/s", cores=cores,
                 kind="oracle",
                 sample=f"{steps} step(s) x {run['inner']} passes of {name} ({p.n_fv} FV), "
@@ -305,6 +312,10 @@ def main():
     if rank == 0 and not a.no_cpu_baseline:
         cpu = run_cpu_baseline(a.workload, W.SCHEMES[HEADLINE], a.cpu_baseline_steps)
         cpu["value"] = round(cpu["value"], 3)
+        cpu["gpu_speedup"] = round(h["mfv_iters_s"] / cpu["value"], 1)
+        one = run_cpu_baseline(a.workload, W.SCHEMES[HEADLINE], a.cpu_baseline_steps, threads=1)
+        cpu["single_core"] = {"value": round(one["value"], 3), "cores": 1, "sample": one["sample"],
+                              "gpu_speedup": round(h["mfv_iters_s"] / one["value"], 1)}
     out = {
         "metric": "MFV-iters/s (FP64 SIMPLE-TS step)",
         "value": round(h["mfv_iters_s"], 2),

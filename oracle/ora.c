@@ -23,6 +23,7 @@
 #include "ora.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -194,6 +195,9 @@ double ora_psi_c(double f1, double f2, double f3, double f4, double d1,
    form (the discrete source pl29 carries p div(u), not Dp/Dt):
    C^{T1}_f = gamma/(Re Pr), C^{T2}_f = gamma(gamma-1)Ma^2/Re,
    C^{T3}_f = -(gamma-1). */
+void ora_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int ora_max_threads(void) { return omp_get_max_threads(); }
+
 void ora_params(double Ma, double Re, double Pr, double g, double out[5]) {
   out[0] = 1.0 / (g * Ma * Ma);
   out[1] = 1.0 / Re;

@@ -68,6 +68,9 @@ void ora_mass(const ora_ctx *c, double out[3]);
 
 /* ---- pieces exposed for pin tests ---- */
 /* A, B, C^{T1}_f, C^{T2}_f, C^{T3}_f for (Ma, Re, Pr, gamma). */
+/* OpenMP threads of the row loops (the results do not depend on it). */
+void ora_set_threads(int n);
+int ora_max_threads(void);
 void ora_params(double Ma, double Re, double Pr, double gamma, double out[5]);
 /* van Leer limiter psi(r) of r = a/b, division-safe. */
 double ora_vanleer(double a, double b);

@@ -58,6 +58,8 @@ def lib():
         L.ora_residuals.argtypes = [C.c_void_p, _D]
         L.ora_mass.argtypes = [C.c_void_p, _D]
         L.ora_params.argtypes = [C.c_double] * 4 + [_D]
+        L.ora_set_threads.argtypes = [C.c_int]
+        L.ora_max_threads.restype = C.c_int
         L.ora_vanleer.restype = C.c_double
         L.ora_vanleer.argtypes = [C.c_double, C.c_double]
         L.ora_psi_s.restype = C.c_double
@@ -201,3 +203,12 @@ def drag(prob, fields):
                 uc = 0.5 * (u[j, i] + u[j, i + 1])
                 total += walls * B * np.sqrt(T[j, i]) * uc * dx[i] / (0.5 * dy[j])
     return total
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's row loops in this process."""
+    lib().ora_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().ora_max_threads())

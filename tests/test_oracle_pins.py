@@ -307,6 +307,35 @@ def test_couette_with_heat_conduction_converges_at_second_order(oracle_lib):
     assert e[-1, 0] < 2e-7 and e[-1, 1] < 5e-5, e[-1]
 
 
+def stretched_faces(N: int, a: float = 0.6) -> np.ndarray:
+    """Face positions y = eta - a sin(2 pi eta) / (2 pi), eta = k / N: a smooth
+    mapping that clusters cells at both walls (width ratio (1+a)/(1-a))."""
+    eta = np.arange(N + 1) / N
+    return eta - a / (2 * math.pi) * np.sin(2 * math.pi * eta)
+
+
+def test_couette_on_stretched_grid_converges_at_second_order(oracle_lib):
+    # the same closed form on smoothly stretched cells (4x width ratio): the
+    # non-uniform-grid factors keep the scheme second order
+    Ma, Re, Pr, g, Uw, Tb, Tt = 1.0, 5.0, 0.7, 1.4, 1.0, 1.0, 1.2
+    K = (g - 1) * Ma ** 2 * Pr
+    errs = []
+    for N in (8, 16, 32):
+        nx, yf = 4, stretched_faces(N)
+        y = 0.5 * (yf[:-1] + yf[1:])
+        p = W.Problem(nx=nx, ny=N, dx=np.full(nx, 0.5 / nx), dy=np.diff(yf), periodic=True, Ma=Ma,
+                      Re=Re, Pr=Pr, gamma=g, wall_u=(0.0, Uw), wall_T=(np.full(nx, Tb), np.full(nx, Tt)))
+        o = _steady(oracle_lib, p, np.repeat((Uw * y)[:, None], nx + 1, 1),
+                    np.repeat((Tb + (Tt - Tb) * y)[:, None], nx, 1), dt=0.01, max_steps=20000)
+        u, v, pr, T = o.fields()
+        ex = _couette_exact(y, Uw, Tb, Tt, K)
+        errs.append((np.abs(u[:, 0] - ex[:, 0]).max(), np.abs(T[:, 0] - ex[:, 1]).max()))
+    e = np.array(errs)
+    orders = np.log2(e[:-1] / e[1:])
+    assert np.all(orders > 1.85) and np.all(orders < 2.15), orders
+    assert e[-1, 0] < 5e-5 and e[-1, 1] < 1.5e-4, e[-1]
+
+
 # ---------------------------------------------------------------------------
 # P3: Poiseuille flow driven by a body force, with viscous heating
 # ---------------------------------------------------------------------------

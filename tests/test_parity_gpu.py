@@ -119,6 +119,24 @@ def test_channel_1280x288_few_steps(sts_mod, oracle_lib, scheme):
 
 
 @pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_stretched_grid_channel(sts_mod, oracle_lib, name, scheme):
+    # smoothly stretched cells: y clustered at both walls, x clustered around
+    # the square at the channel centre (width ratios 4 and 3)
+    import math
+    nx, ny = 150, 48
+    ex = np.arange(nx + 1) / nx
+    xf = 5.0 * (ex + 0.5 / (2 * math.pi) * np.sin(2 * math.pi * ex))
+    ey = np.arange(ny + 1) / ny
+    yf = ey - 0.6 / (2 * math.pi) * np.sin(2 * math.pi * ey)
+    xc, yc = 0.5 * (xf[1:] + xf[:-1]), 0.5 * (yf[1:] + yf[:-1])
+    ii = np.nonzero(np.abs(xc - 2.5) <= 0.125)[0]
+    jj = np.nonzero(np.abs(yc - 0.5) <= 0.125)[0]
+    p = W.Problem(nx=nx, ny=ny, dx=np.diff(xf), dy=np.diff(yf),
+                  obstacles=[(int(ii[0]), int(jj[0]), int(ii[-1]), int(jj[-1]))])
+    run_pair(sts_mod, oracle_lib, p, p.cfl_dt(), 20, 10, scheme, 13, label=f"stretched 150x48/{name}")
+
+
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
 @pytest.mark.parametrize("wl", ["channel_3000x600", "channel_5120x1152"])
 def test_full_size_step_from_gpu_state(sts_mod, oracle_lib, wl, name, scheme):
     # the two throughput grids in the launch configuration the benchmark
