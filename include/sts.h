@@ -202,8 +202,11 @@ sts_status sts_state_load(sts_ctx *ctx, int slot);
    temperatures wall_T[0][nx], wall_T[1][nx] (isothermal walls).
 
    sts_adjoint_begin: allocate the buffers for n_inner passes per step
-   (library-owned, about (n_inner + 33) field arrays), set lambda and the
-   wall-temperature gradients to zero.
+   (library-owned, 12 n_inner + 22 field arrays: the iterates and the
+   intermediates of every pass of one step, the adjoint temporaries and
+   states), set lambda and the wall-temperature gradients to zero.  The
+   adjoint supports inlet/outlet channels without slip-jump surfaces
+   (STS_EINVAL otherwise).
    sts_adjoint_seed_drag: lambda += w dD/d(current state); call it with the
    current state at level n before the adjoint of step n.
    sts_adjoint_step: the current state must be level n-1 and lambda the

@@ -169,99 +169,149 @@ __device__ __forceinline__ bool elem(const Params &P, int &i, int &j) {
 }
 
 // ---------------------------------------------------------------------------
-// (4) velocity update and the cell outputs
+// (4) velocity update and the cell outputs, gather form (no atomics)
 // ---------------------------------------------------------------------------
-// cells: the adjoints of the new T and p seed those of T-new and p-new
-// (fluid) or pass to the old values (solid cells are copied)
-__global__ __launch_bounds__(AB) void k_adj_cells_out(const Params P, const State ln,
-                                                      const State lo, const AdjTmp A) {
-  int i, j;
-  if (!elem(P, i, j) || i >= P.nx || j >= P.ny) return;
+// Element (i, j) handles u-face (i, j), v-face (i, j) and cell (i, j).
+// Faces: u = u-hat - d^u (p_P - p_W) on solved faces, else a copy of the old
+// value; the outlet face takes the new value of face nx-1.  Cells: the
+// adjoints of the new T and p seed those of T-new and p-new (fluid), the new
+// p collecting its part of the four velocity updates around the cell, or
+// pass to the old values (solid cells are copied).
+__device__ __forceinline__ double lam_u(const Params &P, const State &ln, int i, int j) {
   const long k = ix(P, i, j);
-  if (fl(P, i, j)) {
-    A.ltn[k] = ln.T[k];
-    A.lpn[k] = ln.p[k];
-  } else {
-    lo.T[k] += ln.T[k];
-    lo.p[k] += ln.p[k];
-  }
+  return i == P.nx - 1 ? ln.u[k] + ln.u[k + 1] : ln.u[k];
 }
-// faces: u = u-hat - d^u (p_P - p_W) on solved faces, else a copy of the old
-// value; the outlet face takes the new value of face nx-1
-__global__ __launch_bounds__(AB) void k_adj_velocity(const Params P, const State ln,
-                                                     const State lo, const Inter I,
-                                                     const AdjTmp A) {
+__global__ __launch_bounds__(AB) void k_adj_outputs(const Params P, const State ln,
+                                                    const State lo, const Inter I,
+                                                    const AdjTmp A) {
   int i, j;
   if (!elem(P, i, j)) return;
+  const long k = ix(P, i, j);
   if (j < P.ny && i < P.nx) {  // u-face (i, j); face nx is the outlet copy
-    const long k = ix(P, i, j);
-    double l = ln.u[k];
-    if (i == P.nx - 1) l += ln.u[k + 1];
+    const double l = lam_u(P, ln, i, j);
     if (u_solved(P, i, j)) {
       A.luh[k] += l;
       A.ldu[k] += -l * (I.pn[k] - I.pn[k - 1]);
-      aadd(A.lpn, P, i, j, -l * I.du[k]);
-      aadd(A.lpn, P, i - 1, j, l * I.du[k]);
     } else {
       lo.u[k] += l;
     }
   }
   if (i < P.nx && j <= P.ny) {  // v-face (i, j)
-    const long k = ix(P, i, j);
     const double l = ln.v[k];
     if (v_solved(P, i, j)) {
       A.lvh[k] += l;
       A.ldv[k] += -l * (I.pn[k] - I.pn[k - P.pitch]);
-      aadd(A.lpn, P, i, j, -l * I.dv[k]);
-      aadd(A.lpn, P, i, j - 1, l * I.dv[k]);
     } else {
       lo.v[k] += l;
+    }
+  }
+  if (i < P.nx && j < P.ny) {  // cell (i, j)
+    if (fl(P, i, j)) {
+      double lp = ln.p[k];
+      if (u_solved(P, i, j)) lp += -lam_u(P, ln, i, j) * I.du[k];
+      if (u_solved(P, i + 1, j)) lp += lam_u(P, ln, i + 1, j) * I.du[k + 1];
+      if (v_solved(P, i, j)) lp += -ln.v[k] * I.dv[k];
+      if (v_solved(P, i, j + 1)) lp += ln.v[k + P.pitch] * I.dv[k + P.pitch];
+      A.ltn[k] = ln.T[k];
+      A.lpn[k] = lp;
+    } else {
+      lo.T[k] += ln.T[k];
+      lo.p[k] += ln.p[k];
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// (3) pressure equation of a fluid cell
+// (3) pressure equation of a fluid cell, gather form (no atomics)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(AB) void k_adj_pressure(const Params P, const State o,
-                                                     const State lo, const Consts C,
-                                                     const Consts lC, const Inter I,
-                                                     const AdjTmp A) {
+// p = N / a0 with N = (sum a_nb p_nb) dt + C_p - (bE - bW + bN - bS) dt,
+// a0 = dV/T + (sum a_nb) dt, a_W = rho^u d^u dy and b_W = rho^u u-hat dy on
+// the faces.  First per cell: lN = lambda/a0 and la0 = -lambda p/a0 (kept in
+// the scratch arrays; 0 for solid cells), the T-new and C_p adjoints.  Then
+// per element: the old pressure of cell (i, j) collects lN a dt of its four
+// neighbours' equations, and each face the a- and b-adjoints of the (at most
+// two) cells it borders.
+__global__ __launch_bounds__(AB) void k_adj_pressure_cells(const Params P, const Consts lC,
+                                                           const Inter I, const AdjTmp A) {
   int i, j;
-  if (!elem(P, i, j) || i >= P.nx || j >= P.ny || !fl(P, i, j)) return;
-  const long k = ix(P, i, j), kE = k + 1, kN = k + P.pitch;
+  if (!elem(P, i, j) || i >= P.nx || j >= P.ny) return;
+  const long k = ix(P, i, j);
+  if (!fl(P, i, j)) {
+    A.q0[k] = 0.0;
+    A.q1[k] = 0.0;
+    return;
+  }
+  const long kE = k + 1, kN = k + P.pitch;
   const double dxi = gx(P, 0, i), dyj = gy(P, 0, j), dV = dxi * dyj, dt = P.dt;
   const double aW = I.ru[k] * I.du[k] * dyj, aE = I.ru[kE] * I.du[kE] * dyj;
   const double aS = I.rv[k] * I.dv[k] * dxi, aN = I.rv[kN] * I.dv[kN] * dxi;
   const double tn = I.tn[k], pn = I.pn[k];
   const double a0 = dV / tn + (aW + aE + aS + aN) * dt;
-  const double pW = at(o.p, P, i - 1, j), pE = at(o.p, P, i + 1, j);
-  const double pS = at(o.p, P, i, j - 1), pN = at(o.p, P, i, j + 1);
   const double l = A.lpn[k];
-  // p = N / a0, N = (sum a p_nb) dt + C_p - (bE - bW + bN - bS) dt
   const double lN = l / a0, la0 = -l * pn / a0;
   A.ltn[k] += la0 * (-dV / (tn * tn));
   lC.Cp[k] += lN;
-  if (aW != 0.0) aadd(lo.p, P, i - 1, j, lN * aW * dt);
-  if (aE != 0.0) aadd(lo.p, P, i + 1, j, lN * aE * dt);
-  if (aS != 0.0) aadd(lo.p, P, i, j - 1, lN * aS * dt);
-  if (aN != 0.0) aadd(lo.p, P, i, j + 1, lN * aN * dt);
-  const double laW = lN * pW * dt + la0 * dt, laE = lN * pE * dt + la0 * dt;
-  const double laS = lN * pS * dt + la0 * dt, laN = lN * pN * dt + la0 * dt;
-  const double lbW = lN * dt, lbE = -lN * dt, lbS = lN * dt, lbN = -lN * dt;
-  // a_W = rho^u d^u dy, b_W = rho^u u-hat dy (faces shared with the neighbour)
-  unsafeAtomicAdd(A.lru + k, (laW * I.du[k] + lbW * I.uh[k]) * dyj);
-  unsafeAtomicAdd(A.ldu + k, laW * I.ru[k] * dyj);
-  unsafeAtomicAdd(A.luh + k, lbW * I.ru[k] * dyj);
-  unsafeAtomicAdd(A.lru + kE, (laE * I.du[kE] + lbE * I.uh[kE]) * dyj);
-  unsafeAtomicAdd(A.ldu + kE, laE * I.ru[kE] * dyj);
-  unsafeAtomicAdd(A.luh + kE, lbE * I.ru[kE] * dyj);
-  unsafeAtomicAdd(A.lrv + k, (laS * I.dv[k] + lbS * I.vh[k]) * dxi);
-  unsafeAtomicAdd(A.ldv + k, laS * I.rv[k] * dxi);
-  unsafeAtomicAdd(A.lvh + k, lbS * I.rv[k] * dxi);
-  unsafeAtomicAdd(A.lrv + kN, (laN * I.dv[kN] + lbN * I.vh[kN]) * dxi);
-  unsafeAtomicAdd(A.ldv + kN, laN * I.rv[kN] * dxi);
-  unsafeAtomicAdd(A.lvh + kN, lbN * I.rv[kN] * dxi);
+  A.q0[k] = lN;
+  A.q1[k] = la0;
+}
+__global__ __launch_bounds__(AB) void k_adj_pressure_faces(const Params P, const State o,
+                                                           const State lo, const Inter I,
+                                                           const AdjTmp A) {
+  int i, j;
+  if (!elem(P, i, j)) return;
+  const long k = ix(P, i, j);
+  const double dt = P.dt;
+  if (i < P.nx && j < P.ny) {  // old pressure of cell (i, j)
+    const double dxi = gx(P, 0, i), dyj = gy(P, 0, j);
+    double s = 0.0;
+    if (i >= 1) s += A.q0[k - 1] * (I.ru[k] * I.du[k] * dyj) * dt;
+    if (i + 1 < P.nx) s += A.q0[k + 1] * (I.ru[k + 1] * I.du[k + 1] * dyj) * dt;
+    if (j >= 1) s += A.q0[k - P.pitch] * (I.rv[k] * I.dv[k] * dxi) * dt;
+    if (j + 1 < P.ny) s += A.q0[k + P.pitch] * (I.rv[k + P.pitch] * I.dv[k + P.pitch] * dxi) * dt;
+    lo.p[k] += s;
+  }
+  if (j < P.ny) {  // u-face (i, j): west face of cell (i, j), east face of cell (i-1, j)
+    const double dyj = gy(P, 0, j);
+    double lru = 0.0, ldu = 0.0, luh = 0.0;
+    if (i < P.nx && fl(P, i, j)) {
+      const double lN = A.q0[k];
+      const double laW = lN * at(o.p, P, i - 1, j) * dt + A.q1[k] * dt, lbW = lN * dt;
+      lru += (laW * I.du[k] + lbW * I.uh[k]) * dyj;
+      ldu += laW * I.ru[k] * dyj;
+      luh += lbW * I.ru[k] * dyj;
+    }
+    if (i >= 1 && i - 1 < P.nx && fl(P, i - 1, j)) {
+      const double lN = A.q0[k - 1];
+      const double laE = lN * at(o.p, P, i, j) * dt + A.q1[k - 1] * dt, lbE = -lN * dt;
+      lru += (laE * I.du[k] + lbE * I.uh[k]) * dyj;
+      ldu += laE * I.ru[k] * dyj;
+      luh += lbE * I.ru[k] * dyj;
+    }
+    A.lru[k] += lru;
+    A.ldu[k] += ldu;
+    A.luh[k] += luh;
+  }
+  if (i < P.nx) {  // v-face (i, j): south face of cell (i, j), north face of cell (i, j-1)
+    const double dxi = gx(P, 0, i);
+    double lrv = 0.0, ldv = 0.0, lvh = 0.0;
+    if (j < P.ny && fl(P, i, j)) {
+      const double lN = A.q0[k];
+      const double laS = lN * at(o.p, P, i, j - 1) * dt + A.q1[k] * dt, lbS = lN * dt;
+      lrv += (laS * I.dv[k] + lbS * I.vh[k]) * dxi;
+      ldv += laS * I.rv[k] * dxi;
+      lvh += lbS * I.rv[k] * dxi;
+    }
+    if (j >= 1 && j - 1 < P.ny && fl(P, i, j - 1)) {
+      const double lN = A.q0[k - P.pitch];
+      const double laN = lN * at(o.p, P, i, j) * dt + A.q1[k - P.pitch] * dt, lbN = -lN * dt;
+      lrv += (laN * I.dv[k] + lbN * I.vh[k]) * dxi;
+      ldv += laN * I.rv[k] * dxi;
+      lvh += lbN * I.rv[k] * dxi;
+    }
+    A.lrv[k] += lrv;
+    A.ldv[k] += ldv;
+    A.lvh[k] += lvh;
+  }
 }
 
 // u-hat / v-hat of faces that are not solved are copies of the old value
@@ -1234,9 +1284,9 @@ void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, 
                          Consts lC, AdjTmp A, double *gtw0, double *gtw1, int scheme,
                          hipStream_t st) {
   const dim3 g = agrid(P), b(AB);
-  hipLaunchKernelGGL(k_adj_cells_out, g, b, 0, st, P, ln, lo, A);
-  hipLaunchKernelGGL(k_adj_velocity, g, b, 0, st, P, ln, lo, I, A);
-  hipLaunchKernelGGL(k_adj_pressure, g, b, 0, st, P, o, lo, C, lC, I, A);
+  hipLaunchKernelGGL(k_adj_outputs, g, b, 0, st, P, ln, lo, I, A);
+  hipLaunchKernelGGL(k_adj_pressure_cells, g, b, 0, st, P, lC, I, A);
+  hipLaunchKernelGGL(k_adj_pressure_faces, g, b, 0, st, P, o, lo, I, A);
   hipLaunchKernelGGL(k_adj_energy, g, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
   hipLaunchKernelGGL(k_adj_uhat, g, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
   hipLaunchKernelGGL(k_adj_vhat, g, b, 0, st, P, o, lo, C, lC, I, A);

@@ -107,8 +107,9 @@ struct sts_ctx {
   // checkpoints; drag reduction buffers
   char *adj_mem = nullptr;
   int adj_K = 0;
-  std::vector<State> it;
-  Inter I{};
+  bool adj_frames = false;  // iterate buffers hold the boundary values
+  std::vector<State> it;   // it[1..K]: the iterates of a step (it[0] unused)
+  std::vector<Inter> Iv;   // Iv[1..K]: the intermediates of each pass
   AdjTmp A{};
   State lam[2]{};
   int lcur = 0;
@@ -767,23 +768,31 @@ extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
     if (c->adj_mem) HIPCHK(hipFree(c->adj_mem));
     c->adj_mem = nullptr;
     c->adj_K = 0;
-    // K + 1 iterates, 8 intermediates, 10 adjoint intermediates, 2 adjoint
-    // states, 4 constant adjoints, wall gradients
+    // K iterates, 8 intermediates per pass, 10 adjoint intermediates and 2
+    // scratch arrays, 2 adjoint states, 4 constant adjoints, wall gradients
     const size_t F = c->L.field_bytes;
-    const size_t bytes = (size_t)(n_inner + 1) * 4 * F + 8 * F + 10 * F + 8 * F + 4 * F +
-                         align_up(sizeof(double) * 2 * c->nx, 256);
+    const size_t bytes = (size_t)n_inner * 4 * F + (size_t)n_inner * 8 * F + 12 * F + 8 * F +
+                         4 * F + align_up(sizeof(double) * 2 * c->nx, 256);
     if (hipMalloc((void **)&c->adj_mem, bytes) != hipSuccess) {
       c->adj_mem = nullptr;
       return fail(STS_ENOMEM, "cannot allocate the adjoint buffers (%zu bytes)", bytes);
     }
     char *q = c->adj_mem;
-    c->it.clear();
-    for (int k = 0; k <= n_inner; k++) c->it.push_back(carve(q, c->L));
-    double **ip[8] = {&c->I.ru, &c->I.rv, &c->I.uh, &c->I.du, &c->I.vh, &c->I.dv, &c->I.pn, &c->I.tn};
-    for (auto p : ip) { *p = (double *)q; q += F; }
+    c->it.assign(1, State{});
+    c->Iv.assign(1, Inter{});
+    for (int k = 1; k <= n_inner; k++) c->it.push_back(carve(q, c->L));
+    for (int k = 1; k <= n_inner; k++) {
+      Inter I;
+      double **ip[8] = {&I.ru, &I.rv, &I.uh, &I.du, &I.vh, &I.dv, &I.pn, &I.tn};
+      for (auto p : ip) { *p = (double *)q; q += F; }
+      c->Iv.push_back(I);
+    }
+    c->adj_frames = false;
     double **ap[10] = {&c->A.luh, &c->A.ldu, &c->A.lvh, &c->A.ldv, &c->A.lru,
                        &c->A.lrv, &c->A.lr,  &c->A.lg,  &c->A.ltn, &c->A.lpn};
     for (auto p : ap) { *p = (double *)q; q += F; }
+    c->A.q0 = (double *)q; q += F;
+    c->A.q1 = (double *)q; q += F;
     c->lam[0] = carve(q, c->L);
     c->lam[1] = carve(q, c->L);
     c->lC.Cu = (double *)q; q += F;
@@ -819,29 +828,36 @@ extern "C" sts_status sts_adjoint_step(sts_ctx *c, double dt, int n_inner, int s
   c->P.idt = 1.0 / dt;
   const int K = n_inner;
   sts_status s;
-  // recompute the step from the current state x_0 (kept), storing
-  // x_1..x_{K-1}, with the form that produced the state (FP64 or mixed); the
-  // reverse below is the FP64 step's transpose at these iterates
-  for (int k = 0; k <= K; k++)
-    if ((s = copy_state(c, c->it[k], c->st[c->cur])) != STS_OK) return s;
-  launch_prologue(c->P, c->it[0], c->C, scheme, c->stream);
-  for (int k = 1; k < K; k++)
-    launch_pass(c->P, c->it[k - 1], c->it[k], c->C, scheme, nullptr, nullptr, c->stream);
+  // recompute the step from the current state x_0 (read in place), storing
+  // the iterates x_1..x_K and every pass's intermediates, with the form that
+  // produced the state (FP64 or mixed); the reverse below is the FP64 step's
+  // transpose at these iterates.  A pass writes every cell and face of its
+  // output except the constant boundary entries (top wall faces, frame), so
+  // the iterate buffers take those once from a copy of the state.
+  const State x0 = c->st[c->cur];
+  if (!c->adj_frames) {
+    for (int k = 1; k <= K; k++)
+      if ((s = copy_state(c, c->it[k], x0)) != STS_OK) return s;
+    c->adj_frames = true;
+  }
+  auto iterate = [&](int k) { return k == 0 ? x0 : c->it[k]; };
+  launch_prologue(c->P, x0, c->C, scheme, c->stream);
+  for (int k = 1; k <= K; k++)
+    launch_pass(c->P, iterate(k - 1), c->it[k], c->C, scheme, nullptr, &c->Iv[k], c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemsetAsync(c->lC.Cu, 0, 4 * c->L.field_bytes, c->stream));
   // reverse of the passes
   for (int k = K; k >= 1; k--) {
-    launch_pass(c->P, c->it[k - 1], c->it[K], c->C, scheme, nullptr, &c->I, c->stream);
     State ln = c->lam[c->lcur], lo = c->lam[c->lcur ^ 1];
     if ((s = clear_tmp(c, lo)) != STS_OK) return s;
-    launch_adjoint_pass(c->P, c->it[k - 1], c->C, c->I, ln, lo, c->lC, c->A, c->gtw,
+    launch_adjoint_pass(c->P, iterate(k - 1), c->C, c->Iv[k], ln, lo, c->lC, c->A, c->gtw,
                         c->gtw + c->nx, scheme, c->stream);
     HIPCHK(hipGetLastError());
     c->lcur ^= 1;
   }
   // reverse of the prologue, onto the adjoint of x_0
   HIPCHK(hipMemsetAsync(c->A.luh, 0, 10 * c->L.field_bytes, c->stream));
-  launch_adjoint_prologue(c->P, c->it[0], c->lC, c->lam[c->lcur], c->A, scheme, c->stream);
+  launch_adjoint_prologue(c->P, x0, c->lC, c->lam[c->lcur], c->A, scheme, c->stream);
   HIPCHK(hipGetLastError());
   return STS_OK;
 }

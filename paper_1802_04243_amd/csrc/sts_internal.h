@@ -81,6 +81,9 @@ struct Inter {
 // densities, rho, Gamma, new T, new p), field layout.
 struct AdjTmp {
   double *luh, *ldu, *lvh, *ldv, *lru, *lrv, *lr, *lg, *ltn, *lpn;
+  // per-cell scratch of the pressure reverse (adjoints of the numerator and
+  // of the diagonal of each cell's equation); written before being read
+  double *q0, *q1;
 };
 
 void launch_prologue(const Params &P, State m, Consts C, int scheme,
