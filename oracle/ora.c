@@ -1273,6 +1273,25 @@ void ora_step(ora_ctx *c, double dt, int n_inner, int scheme) {
   for (int k = 0; k < n_inner; k++) pass(c, dt, scheme);
 }
 
+/* Loop 2 with its convergence test (Sec. 3.1, the algorithm figures: the
+   inner iterations repeat until the solution of the step has converged; the
+   paper reads the maximal residuals back after every iteration, Sec. 5).
+   The test: max(max|du|, max|dv|, max|dT|, max|dp| / p_in) <= tol over the
+   unknowns, after each pass; at most max_inner passes.  Returns the number
+   of passes taken. */
+int ora_step_tol(ora_ctx *c, double dt, int max_inner, double tol, int scheme) {
+  c->idt = 1.0 / dt;
+  prologue(c, scheme);
+  int k = 0;
+  while (k < max_inner) {
+    pass(c, dt, scheme);
+    k++;
+    double r = dmax(dmax(c->res[0], c->res[1]), dmax(c->res[3], c->res[2] / c->p_in));
+    if (r <= tol) break;
+  }
+  return k;
+}
+
 void ora_eq_residuals(ora_ctx *c, double dt, int scheme, double *rT,
                       double *ru, double *rv, double *rp) {
   const int nx = c->nx, ny = c->ny;

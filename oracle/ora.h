@@ -59,6 +59,10 @@ void ora_get_fields(const ora_ctx *c, double *u, double *v, double *p,
                     double *T);
 /* One time step: prologue, then n_inner Jacobi passes. */
 void ora_step(ora_ctx *c, double dt, int n_inner, int scheme);
+/* One time step whose loop 2 stops after the first pass with
+   max(max|du|, max|dv|, max|dT|, max|dp|/p_in) <= tol, or after max_inner
+   passes; returns the passes taken. */
+int ora_step_tol(ora_ctx *c, double dt, int max_inner, double tol, int scheme);
 /* Residuals of the last pass: max|du|, max|dv|, max|dp|, max|dT|,
    max|R_mass|, sum R_mass. */
 void ora_residuals(const ora_ctx *c, double out[6]);

@@ -55,6 +55,8 @@ def lib():
         L.ora_set_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
         L.ora_get_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
         L.ora_step.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int]
+        L.ora_step_tol.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_int]
+        L.ora_step_tol.restype = C.c_int
         L.ora_residuals.argtypes = [C.c_void_p, _D]
         L.ora_mass.argtypes = [C.c_void_p, _D]
         L.ora_params.argtypes = [C.c_double] * 4 + [_D]
@@ -153,6 +155,10 @@ class Oracle:
 
     def step(self, dt, n_inner, scheme):
         lib().ora_step(self._h, float(dt), int(n_inner), int(scheme))
+
+    def step_tol(self, dt, max_inner, tol, scheme) -> int:
+        """One step whose loop 2 stops at the tolerance; returns the passes taken."""
+        return int(lib().ora_step_tol(self._h, float(dt), int(max_inner), float(tol), int(scheme)))
 
     def residuals(self):
         out = np.zeros(6)

@@ -11,10 +11,12 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
 #include "../../include/sts.h"
+
 #include "sts_internal.h"
 
 using namespace sts;
@@ -574,6 +576,41 @@ extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
   }
   c->stepped = true;
   c->last_scheme = scheme;
+  return STS_OK;
+}
+
+// Loop 2 with its convergence test: every pass produces its residuals (the
+// last-pass kernel variant), which are reduced and read back before the next
+// pass is launched, as the paper's GPU algorithm does (Sec. 5).
+extern "C" sts_status sts_step_tol(sts_ctx *c, double dt, int max_inner, double tol, int scheme,
+                                   int *n_inner) {
+  if (!c || !n_inner) return fail(STS_EINVAL, "NULL argument");
+  if (!(dt > 0) || !isfinite(dt)) return fail(STS_EINVAL, "dt must be > 0");
+  if (max_inner < 1) return fail(STS_EINVAL, "max_inner must be >= 1");
+  if (!(tol >= 0) || !isfinite(tol)) return fail(STS_EINVAL, "tol must be >= 0 and finite");
+  if (scheme & ~STS_SCHEME_MASK) return fail(STS_EINVAL, "unknown scheme bits 0x%x", scheme);
+  c->P.dt = dt;
+  c->P.idt = 1.0 / dt;
+  launch_prologue(c->P, c->st[c->cur], c->C, scheme, c->stream);
+  HIPCHK(hipGetLastError());
+  int k = 0;
+  c->stepped = true;
+  c->last_scheme = scheme;
+  while (k < max_inner) {
+    launch_pass(c->P, c->st[c->cur], c->st[c->cur ^ 1], c->C, scheme, &c->X, nullptr, c->stream);
+    c->cur ^= 1;
+    k++;
+    launch_residual(c->P, c->st[c->cur], c->C, c->X, c->dres, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->hres, c->dres, NRES * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const double *r = c->hres;
+    if (r[6] != 0.0) break;  // non-finite: reported by sts_residuals
+    const double crit = std::max(std::max(r[0], r[1]), std::max(r[3], r[2] / c->p_in));
+    if (crit <= tol) break;
+  }
+  *n_inner = k;
   return STS_OK;
 }
 

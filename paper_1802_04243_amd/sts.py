@@ -22,7 +22,7 @@ STS_OK, STS_EINVAL, STS_ENOMEM, STS_EDEVICE, STS_ENONFINITE, STS_ESTATE = 0, -1,
 EXPLICIT, IMPLICIT, UPWIND, TVD, MIXED = 0, 1, 0, 2, 4
 
 # every symbol the header declares
-EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_residuals", "sts_fields",
+EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_step_tol", "sts_residuals", "sts_fields",
            "sts_set_fields", "sts_field_ptrs", "sts_timing", "sts_read_timing", "sts_drag",
            "sts_state_slots", "sts_state_save", "sts_state_load", "sts_adjoint_begin",
            "sts_adjoint_seed_drag", "sts_adjoint_step", "sts_adjoint_read", "sts_destroy",
@@ -73,6 +73,8 @@ def lib():
                                  C.c_double, C.c_double, C.POINTER(_Bc), C.c_void_p, C.c_void_p,
                                  C.c_size_t, C.POINTER(C.c_void_p)]
         L.sts_step.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int]
+        L.sts_step_tol.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_int,
+                                   C.POINTER(C.c_int)]
         L.sts_residuals.argtypes = [C.c_void_p, _D]
         L.sts_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
         L.sts_set_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
@@ -168,6 +170,13 @@ class Solver:
 
     def step(self, dt: float, n_inner: int, scheme: int):
         _check(lib().sts_step(self._h, float(dt), int(n_inner), int(scheme)))
+
+    def step_tol(self, dt: float, max_inner: int, tol: float, scheme: int) -> int:
+        """One step with loop 2 stopped at the tolerance; returns the passes taken."""
+        n = C.c_int(0)
+        _check(lib().sts_step_tol(self._h, float(dt), int(max_inner), float(tol), int(scheme),
+                                  C.byref(n)))
+        return n.value
 
     def residuals(self) -> np.ndarray:
         out = np.zeros(6)

@@ -213,3 +213,48 @@ def test_deterministic_and_resumable(sts_mod):
         assert np.array_equal(a, b)
     g.close()
     g2.close()
+
+
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_tolerance_exit_matches_oracle(sts_mod, oracle_lib, name, scheme):
+    # loop 2 with its convergence test: the same number of passes in every
+    # step and the same fields as the oracle (the decisions are taken on
+    # bitwise-equal residual maxima)
+    p, run = W.workload("channel_120x24")
+    tol = 1e-4 if scheme == W.IMPLICIT | W.TVD else 1e-9
+    print(f"case tolerance exit 120x24/{name} tol {tol:g}", flush=True)
+    g = sts_mod.Solver(p)
+    o = oracle_lib.Oracle(p)
+    f0 = W.initial_fields(p, run["seed"])
+    g.set_fields(*f0)
+    o.set_fields(*f0)
+    counts = []
+    for _ in range(8):
+        ng = g.step_tol(run["dt"], 40, tol, scheme)
+        no = o.step_tol(run["dt"], 40, tol, scheme)
+        assert ng == no, (ng, no)
+        counts.append(ng)
+    print(f"passes per step {counts}", flush=True)
+    assert min(counts) < 40
+    compare(g, o, f"tolerance exit 120x24/{name}")
+    g.close()
+
+
+def test_tolerance_exit_zero_tol_is_fixed_count(sts_mod):
+    p, run = W.workload("channel_120x24")
+    f0 = W.initial_fields(p, 3)
+    a, b = sts_mod.Solver(p), sts_mod.Solver(p)
+    a.set_fields(*f0)
+    b.set_fields(*f0)
+    for _ in range(3):
+        assert a.step_tol(run["dt"], 6, 0.0, W.EXPLICIT | W.TVD) == 6
+        b.step(run["dt"], 6, W.EXPLICIT | W.TVD)
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.residuals(), b.residuals())
+    for bad in ((0.0, 6, 0.0), (run["dt"], 0, 0.0), (run["dt"], 6, -1.0), (run["dt"], 6, float("nan"))):
+        with pytest.raises(sts_mod.StsError) as e:
+            a.step_tol(*bad, W.EXPLICIT)
+        assert e.value.code == sts_mod.STS_EINVAL
+    a.close()
+    b.close()
