@@ -221,21 +221,24 @@ def test_tolerance_exit_matches_oracle(sts_mod, oracle_lib, name, scheme):
     # step and the same fields as the oracle (the decisions are taken on
     # bitwise-equal residual maxima)
     p, run = W.workload("channel_120x24")
-    tol = 1e-4 if scheme == W.IMPLICIT | W.TVD else 1e-9
+    tol = 1e-4 if scheme == W.IMPLICIT | W.TVD else 1e-8
     print(f"case tolerance exit 120x24/{name} tol {tol:g}", flush=True)
     g = sts_mod.Solver(p)
     o = oracle_lib.Oracle(p)
     f0 = W.initial_fields(p, run["seed"])
     g.set_fields(*f0)
     o.set_fields(*f0)
+    for _ in range(3):  # past the initial noise
+        g.step(run["dt"], 20, scheme)
+        o.step(run["dt"], 20, scheme)
     counts = []
     for _ in range(8):
-        ng = g.step_tol(run["dt"], 40, tol, scheme)
-        no = o.step_tol(run["dt"], 40, tol, scheme)
+        ng = g.step_tol(run["dt"], 60, tol, scheme)
+        no = o.step_tol(run["dt"], 60, tol, scheme)
         assert ng == no, (ng, no)
         counts.append(ng)
     print(f"passes per step {counts}", flush=True)
-    assert min(counts) < 40
+    assert max(counts) < 60 and len(set(counts)) > 1
     compare(g, o, f"tolerance exit 120x24/{name}")
     g.close()
 
