@@ -48,6 +48,17 @@ __device__ __forceinline__ double rho(const Params &P, const State &o, int i, in
 __device__ __forceinline__ double gam(const Params &P, const State &o, int i, int j) {
   return sqrt(at(o.T, P, i, j));
 }
+// rho and Gamma of a state's cells computed once (k_cell_cache) and read by
+// the stages that need them many times per item; the same values as above
+struct Cache {
+  const double *r, *g;
+};
+__device__ __forceinline__ double rho(const Params &P, const Cache &c, int i, int j) {
+  return at(c.r, P, i, j);
+}
+__device__ __forceinline__ double gam(const Params &P, const Cache &c, int i, int j) {
+  return at(c.g, P, i, j);
+}
 __device__ __forceinline__ bool u_solved(const Params &P, int i, int j) {
   return i >= 1 && i <= P.nx - 1 && fl(P, i - 1, j) && fl(P, i, j);
 }
@@ -128,7 +139,8 @@ __device__ __forceinline__ double hmean2_d(double a, double b, double &da, doubl
 }
 
 // Gamma at the corner (x^f_i, y^f_j) and its adjoint
-__device__ double gamc(const Params &P, const State &o, int i, int j) {
+template <class Src>
+__device__ double gamc(const Params &P, const Src &o, int i, int j) {
   if (j <= 0 || j >= P.ny) return 0.0;
   const double ws = gy(P, 4, j), wn = gy(P, 5, j);
   if (i == 0) return ws * P.sq_T_in[j - 1] + wn * P.sq_T_in[j];
@@ -137,19 +149,20 @@ __device__ double gamc(const Params &P, const State &o, int i, int j) {
   return ws * (wl * gam(P, o, i - 1, j - 1) + wr * gam(P, o, i, j - 1)) +
          wn * (wl * gam(P, o, i - 1, j) + wr * gam(P, o, i, j));
 }
-__device__ void gamc_adj(const Params &P, double *lg, int i, int j, double l) {
+template <class S>
+__device__ void gamc_adj(S &sk, int slot, const Params &P, int i, int j, double l) {
   if (l == 0.0 || j <= 0 || j >= P.ny || i == 0) return;
   const double ws = gy(P, 4, j), wn = gy(P, 5, j);
   if (i == P.nx) {
-    aadd(lg, P, i - 1, j - 1, l * ws);
-    aadd(lg, P, i - 1, j, l * wn);
+    sk.add(slot, P, i - 1, j - 1, l * ws);
+    sk.add(slot, P, i - 1, j, l * wn);
     return;
   }
   const double wl = gx(P, 4, i), wr = gx(P, 5, i);
-  aadd(lg, P, i - 1, j - 1, l * ws * wl);
-  aadd(lg, P, i, j - 1, l * ws * wr);
-  aadd(lg, P, i - 1, j, l * wn * wl);
-  aadd(lg, P, i, j, l * wn * wr);
+  sk.add(slot, P, i - 1, j - 1, l * ws * wl);
+  sk.add(slot, P, i, j - 1, l * ws * wr);
+  sk.add(slot, P, i - 1, j, l * wn * wl);
+  sk.add(slot, P, i, j, l * wn * wr);
 }
 // d sqrt(Tw at u-face i) / d Tw of the two neighbouring columns
 __device__ void sqtwu_adj(const Params &P, const double *sqtwu, double *gtw, int i, double l) {
@@ -166,6 +179,62 @@ __device__ __forceinline__ bool elem(const Params &P, int &i, int &j) {
   i = (int)(t % (P.nx + 1));
   j = (int)(t / (P.nx + 1));
   return true;
+}
+
+// Scatter with block-level pre-summation.  A block takes a TW x TH tile of
+// the element space; a reverse kernel adds lambda_out * d(out)/d(in) to the
+// adjoints of inputs within R elements of the output (R = 1 for the energy,
+// u-hat and v-hat stages, 2 for the face densities).  Contributions to NA
+// registered arrays inside the tile grown by R are summed in LDS (FP64 LDS
+// atomics); then every nonzero entry goes to global memory once: entries at
+// least R inside the tile receive contributions from this block only and are
+// added with a plain read-modify-write (EXCL; not when blocks of several
+// stages of one launch add to the same arrays), the others with a hardware
+// FP64 atomic.  Targets outside the window (none for the stencils here) are added
+// directly.  Like the plain scatter, the result is exact up to the order of
+// the sums.
+constexpr int TW = 32, TH = 8;
+static_assert(TW * TH == AB, "one element per thread");
+typedef __attribute__((address_space(3))) double lds_double;
+template <int NA, int R, bool EXCL = true>
+struct Tiled {
+  static constexpr int WW = TW + 2 * R, WH = TH + 2 * R, WN = WW * WH;
+  lds_double *w;     // LDS [NA][WH][WW]
+  double *a[NA];     // the registered arrays (field layout)
+  int x0, y0;        // tile origin
+  __device__ void begin(const Params &P, int &i, int &j) {
+    const int ntx = (P.nx + 1 + TW - 1) / TW;
+    x0 = (int)(blockIdx.x % ntx) * TW;
+    y0 = (int)(blockIdx.x / ntx) * TH;
+    i = x0 + (int)threadIdx.x % TW;
+    j = y0 + (int)threadIdx.x / TW;
+    for (int e = threadIdx.x; e < NA * WN; e += AB) w[e] = 0.0;
+    __syncthreads();
+  }
+  __device__ __forceinline__ void add(int s, const Params &P, int i, int j, double x) {
+    const int wi = i - x0 + R, wj = j - y0 + R;
+    if ((unsigned)wi < (unsigned)WW && (unsigned)wj < (unsigned)WH)
+      __hip_atomic_fetch_add(w + (s * WH + wj) * WW + wi, x, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+      unsafeAtomicAdd(a[s] + ix(P, i, j), x);
+  }
+  __device__ void end(const Params &P) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NA; s++)
+      for (int r = threadIdx.x; r < WN; r += AB) {
+        const double v = w[s * WN + r];
+        if (v == 0.0) continue;
+        const int wj = r / WW, wi = r % WW;
+        double *q = a[s] + ix(P, x0 - R + wi, y0 - R + wj);
+        if (EXCL && wi >= 2 * R && wi < TW && wj >= 2 * R && wj < TH) *q += v;
+        else unsafeAtomicAdd(q, v);
+      }
+  }
+};
+static dim3 tgrid(const Params &P) {
+  return dim3((unsigned)(((P.nx + 1 + TW - 1) / TW) * ((P.ny + 1 + TH - 1) / TH)));
 }
 
 // ---------------------------------------------------------------------------
@@ -327,19 +396,17 @@ __global__ __launch_bounds__(AB) void k_adj_hat_copies(const Params P, const Sta
 // ---------------------------------------------------------------------------
 // (2) energy equation of a fluid cell (explicit scheme)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(AB) void k_adj_energy(const Params P, const State o,
-                                                   const State lo, const Consts C,
-                                                   const Consts lC, const Inter I,
-                                                   const AdjTmp A, double *gtw0,
-                                                   double *gtw1) {
-  int i, j;
-  if (!elem(P, i, j) || i >= P.nx || j >= P.ny || !fl(P, i, j)) return;
+template <class S>
+__device__ void energy_item(const Params &P, const State o, const Cache cc, const State lo, const Consts C,
+                            const Consts lC, const Inter I, const AdjTmp A, double *gtw0,
+                            double *gtw1, int i, int j, S &sk) {
+  if (i >= P.nx || j >= P.ny || !fl(P, i, j)) return;
   const long k = ix(P, i, j);
   const double l = A.ltn[k];
   if (l == 0.0) return;
   const double dxi = gx(P, 0, i), dyj = gy(P, 0, j), dV = dxi * dyj, dt = P.dt;
   const double idx = gx(P, 1, i), idy = gy(P, 1, j);
-  const double gP = gam(P, o, i, j), TP = at(o.T, P, i, j);
+  const double gP = gam(P, cc, i, j), TP = at(o.T, P, i, j);
   // conductances and neighbour values (the forward's rules), with the
   // partials of each conductance in Gamma_P, Gamma_nb and the wall sqrt(T)
   double nW, nE, nS, nN, DW, DE, DS, DN;
@@ -358,7 +425,7 @@ __global__ __launch_bounds__(AB) void k_adj_energy(const Params P, const State o
       dWP *= K;
     } else {
       const double K = P.C1 * dyj * (2.0 * gx(P, 3, i));
-      DW = K * hmean_d(gx(P, 0, i - 1), gam(P, o, i - 1, j), dxi, gP, dWn, dWP);
+      DW = K * hmean_d(gx(P, 0, i - 1), gam(P, cc, i - 1, j), dxi, gP, dWn, dWP);
       dWn *= K;
       dWP *= K;
     }
@@ -374,7 +441,7 @@ __global__ __launch_bounds__(AB) void k_adj_energy(const Params P, const State o
       dEP *= K;
     } else {
       const double K = P.C1 * dyj * (2.0 * gx(P, 3, i + 1));
-      DE = K * hmean_d(dxi, gP, gx(P, 0, i + 1), gam(P, o, i + 1, j), dEP, dEn);
+      DE = K * hmean_d(dxi, gP, gx(P, 0, i + 1), gam(P, cc, i + 1, j), dEP, dEn);
       dEP *= K;
       dEn *= K;
     }
@@ -398,7 +465,7 @@ __global__ __launch_bounds__(AB) void k_adj_energy(const Params P, const State o
       dSP *= K;
     } else {
       const double K = P.C1 * dxi * (2.0 * gy(P, 3, j));
-      DS = K * hmean_d(gy(P, 0, j - 1), gam(P, o, i, j - 1), dyj, gP, dSn, dSP);
+      DS = K * hmean_d(gy(P, 0, j - 1), gam(P, cc, i, j - 1), dyj, gP, dSn, dSP);
       dSn *= K;
       dSP *= K;
     }
@@ -422,49 +489,49 @@ __global__ __launch_bounds__(AB) void k_adj_energy(const Params P, const State o
       dNP *= K;
     } else {
       const double K = P.C1 * dxi * (2.0 * gy(P, 3, j + 1));
-      DN = K * hmean_d(dyj, gP, gy(P, 0, j + 1), gam(P, o, i, j + 1), dNP, dNn);
+      DN = K * hmean_d(dyj, gP, gy(P, 0, j + 1), gam(P, cc, i, j + 1), dNP, dNn);
       dNP *= K;
       dNn *= K;
     }
   }
-  const double rP = rho(P, o, i, j);
+  const double rP = rho(P, cc, i, j);
   const double a0 = dt * (DW + DE + DS + DN) + rP * dV;
   const double tn = I.tn[k];
   // T = (dt (sum D n + Sc) + C_T) / a0
   const double lnum = l / a0, la0 = -l * tn / a0;
   lC.CT[k] += lnum;
-  unsafeAtomicAdd(A.lr + k, la0 * dV);
+  unsafeAtomicAdd(A.lr + k, la0 * dV);  // u-hat, v-hat, rho faces add to A.lr too
   const double lDW = lnum * dt * nW + la0 * dt, lDE = lnum * dt * nE + la0 * dt;
   const double lDS = lnum * dt * nS + la0 * dt, lDN = lnum * dt * nN + la0 * dt;
   double lgP = lDW * dWP + lDE * dEP + lDS * dSP + lDN * dNP;
   if (i > 0) {
-    aadd(lo.T, P, i - 1, j, lnum * dt * DW);
-    if (dWn != 0.0) aadd(A.lg, P, i - 1, j, lDW * dWn);
+    sk.add(0, P, i - 1, j, lnum * dt * DW);
+    if (dWn != 0.0) sk.add(1, P, i - 1, j, lDW * dWn);
   }
-  if (i == P.nx - 1) aadd(lo.T, P, i, j, lnum * dt * DE);
+  if (i == P.nx - 1) sk.add(0, P, i, j, lnum * dt * DE);
   else {
-    aadd(lo.T, P, i + 1, j, lnum * dt * DE);
-    if (dEn != 0.0) aadd(A.lg, P, i + 1, j, lDE * dEn);
+    sk.add(0, P, i + 1, j, lnum * dt * DE);
+    if (dEn != 0.0) sk.add(1, P, i + 1, j, lDE * dEn);
   }
   if (j == 0) {
     if (P.wtype0 == 0) {
       unsafeAtomicAdd(gtw0 + i, lnum * dt * DS + lDS * dSw / (2.0 * P.sq_Tw0[i]));
     } else {
-      aadd(lo.T, P, i, j, lnum * dt * DS);
+      sk.add(0, P, i, j, lnum * dt * DS);
     }
   } else {
-    aadd(lo.T, P, i, j - 1, lnum * dt * DS);
-    if (dSn != 0.0) aadd(A.lg, P, i, j - 1, lDS * dSn);
+    sk.add(0, P, i, j - 1, lnum * dt * DS);
+    if (dSn != 0.0) sk.add(1, P, i, j - 1, lDS * dSn);
   }
   if (j == P.ny - 1) {
     if (P.wtype1 == 0) {
       unsafeAtomicAdd(gtw1 + i, lnum * dt * DN + lDN * dNw / (2.0 * P.sq_Tw1[i]));
     } else {
-      aadd(lo.T, P, i, j, lnum * dt * DN);
+      sk.add(0, P, i, j, lnum * dt * DN);
     }
   } else {
-    aadd(lo.T, P, i, j + 1, lnum * dt * DN);
-    if (dNn != 0.0) aadd(A.lg, P, i, j + 1, lDN * dNn);
+    sk.add(0, P, i, j + 1, lnum * dt * DN);
+    if (dNn != 0.0) sk.add(1, P, i, j + 1, lDN * dNn);
   }
   // source: dissipation and pressure work
   const double lSc = lnum * dt;
@@ -505,7 +572,7 @@ __global__ __launch_bounds__(AB) void k_adj_energy(const Params P, const State o
   const double S1 = 2.0 * (ux * ux + vy * vy) + (vx + uy) * (vx + uy) - 2.0 / 3.0 * dv * dv;
   const double pP = at(o.p, P, i, j);
   lgP += lSc * P.C2 * S1 * dV;
-  aadd(lo.p, P, i, j, lSc * P.C3 * dv * dV);
+  lo.p[k] += lSc * P.C3 * dv * dV;  // this cell only
   const double lS1 = lSc * P.C2 * gP * dV;
   const double ldv = lSc * P.C3 * pP * dV - lS1 * (4.0 / 3.0) * dv;
   const double lux = lS1 * 4.0 * ux + ldv, lvy = lS1 * 4.0 * vy + ldv;
@@ -517,56 +584,54 @@ __global__ __launch_bounds__(AB) void k_adj_energy(const Params P, const State o
   else if (cvE == 2) {
     lvc += lvE * gx(P, 4, i + 1);
     const double q = lvE * gx(P, 5, i + 1) * 0.5;
-    aadd(lo.v, P, i + 1, j, q);
-    aadd(lo.v, P, i + 1, j + 1, q);
+    sk.add(3, P, i + 1, j, q);
+    sk.add(3, P, i + 1, j + 1, q);
   }
   if (cvW == 2) {
     const double q = lvW * gx(P, 4, i) * 0.5;
-    aadd(lo.v, P, i - 1, j, q);
-    aadd(lo.v, P, i - 1, j + 1, q);
+    sk.add(3, P, i - 1, j, q);
+    sk.add(3, P, i - 1, j + 1, q);
     lvc += lvW * gx(P, 5, i);
   }
   if (cuN == 1) luc += luN;
   else if (cuN == 2) {
     luc += luN * gy(P, 4, j + 1);
     const double q = luN * gy(P, 5, j + 1) * 0.5;
-    aadd(lo.u, P, i, j + 1, q);
-    aadd(lo.u, P, i + 1, j + 1, q);
+    sk.add(2, P, i, j + 1, q);
+    sk.add(2, P, i + 1, j + 1, q);
   }
   if (cuS == 1) luc += luS;
   else if (cuS == 2) {
     const double q = luS * gy(P, 4, j) * 0.5;
-    aadd(lo.u, P, i, j - 1, q);
-    aadd(lo.u, P, i + 1, j - 1, q);
+    sk.add(2, P, i, j - 1, q);
+    sk.add(2, P, i + 1, j - 1, q);
     luc += luS * gy(P, 5, j);
   }
   lV0 += 0.5 * lvc;
   lV1 += 0.5 * lvc;
   lU0 += 0.5 * luc;
   lU1 += 0.5 * luc;
-  aadd(lo.u, P, i, j, lU0);
-  aadd(lo.u, P, i + 1, j, lU1);
-  aadd(lo.v, P, i, j, lV0);
-  aadd(lo.v, P, i, j + 1, lV1);
-  aadd(A.lg, P, i, j, lgP);
+  sk.add(2, P, i, j, lU0);
+  sk.add(2, P, i + 1, j, lU1);
+  sk.add(3, P, i, j, lV0);
+  sk.add(3, P, i, j + 1, lV1);
+  sk.add(1, P, i, j, lgP);
 }
 
 // ---------------------------------------------------------------------------
 // (2) u-hat, d^u of a solved u-face (explicit scheme)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(AB) void k_adj_uhat(const Params P, const State o,
-                                                 const State lo, const Consts C,
-                                                 const Consts lC, const Inter I,
-                                                 const AdjTmp A, double *gtw0,
-                                                 double *gtw1) {
-  int i, j;
-  if (!elem(P, i, j) || j >= P.ny || !u_solved(P, i, j)) return;
+template <class S>
+__device__ void uhat_item(const Params &P, const State o, const Cache cc, const State lo, const Consts C,
+                          const Consts lC, const Inter I, const AdjTmp A, double *gtw0,
+                          double *gtw1, int i, int j, S &sk) {
+  if (j >= P.ny || !u_solved(P, i, j)) return;
   const long k = ix(P, i, j);
   const double luh = A.luh[k], ldu = A.ldu[k];
   if (luh == 0.0 && ldu == 0.0) return;
   const double B = P.B;
   const double dxl = gx(P, 0, i - 1), dxr = gx(P, 0, i), dyj = gy(P, 0, j), idy = gy(P, 1, j);
-  const double gl = gam(P, o, i - 1, j), gr = gam(P, o, i, j);
+  const double gl = gam(P, cc, i - 1, j), gr = gam(P, cc, i, j);
   const double uP = at(o.u, P, i, j), uW = at(o.u, P, i - 1, j), uE = at(o.u, P, i + 1, j);
   const double len = 0.5 * (dxl + dxr);
   const double gnode = gx(P, 4, i) * gl + gx(P, 5, i) * gr;
@@ -583,7 +648,7 @@ __global__ __launch_bounds__(AB) void k_adj_uhat(const Params P, const State o,
     if (!fl(P, i - 1, j - 1) && !fl(P, i, j - 1)) {
       dS = 2; DS = B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * idy);
     } else {
-      dS = 3; DS = B * gamc(P, o, i, j) * gx(P, 2, i) * gy(P, 3, j);
+      dS = 3; DS = B * gamc(P, cc, i, j) * gx(P, 2, i) * gy(P, 3, j);
     }
   }
   if (j == P.ny - 1) {
@@ -596,14 +661,14 @@ __global__ __launch_bounds__(AB) void k_adj_uhat(const Params P, const State o,
     if (!fl(P, i - 1, j + 1) && !fl(P, i, j + 1)) {
       dN = 2; DN = B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * idy);
     } else {
-      dN = 3; DN = B * gamc(P, o, i, j + 1) * gx(P, 2, i) * gy(P, 3, j + 1);
+      dN = 3; DN = B * gamc(P, cc, i, j + 1) * gx(P, 2, i) * gy(P, 3, j + 1);
     }
   }
   const double DW = B * gl * dyj * gx(P, 1, i - 1), DE = B * gr * dyj * gx(P, 1, i);
   const double aS = DS, aN = DN, aW = 4.0 / 3.0 * DW, aE = 4.0 / 3.0 * DE;
-  const double M = (rho(P, o, i, j) * dxr + rho(P, o, i - 1, j) * dxl) * dyj / 2.0;
+  const double M = (rho(P, cc, i, j) * dxr + rho(P, cc, i - 1, j) * dxl) * dyj / 2.0;
   const double a0 = aS + aN + aW + aE + 0.0 + M * P.idt;
-  const double gcN = gamc(P, o, i, j + 1), gcS = gamc(P, o, i, j);
+  const double gcN = gamc(P, cc, i, j + 1), gcS = gamc(P, cc, i, j);
   const double v00 = at(o.v, P, i - 1, j), v10 = at(o.v, P, i, j);
   const double v01 = at(o.v, P, i - 1, j + 1), v11 = at(o.v, P, i, j + 1);
   const double X = gcN * (v11 - v01) - gcS * (v10 - v00) - 2.0 / 3.0 * gr * (v11 - v10) +
@@ -614,14 +679,14 @@ __global__ __launch_bounds__(AB) void k_adj_uhat(const Params P, const State o,
   const double lnum = luh / a0, la0 = -(luh * uh + ldu * du) / a0;
   lC.Cu[k] += lnum;
   // neighbour values
-  aadd(lo.u, P, i - 1, j, lnum * aW);
-  aadd(lo.u, P, i + 1, j, lnum * aE);
+  sk.add(0, P, i - 1, j, lnum * aW);
+  sk.add(0, P, i + 1, j, lnum * aE);
   double lself = 0.0;
   if (kS == 1) lself += lnum * aS;
-  else if (kS == 2) aadd(lo.u, P, i, j - 1, lnum * aS);
+  else if (kS == 2) sk.add(0, P, i, j - 1, lnum * aS);
   if (kN == 1) lself += lnum * aN;
-  else if (kN == 2) aadd(lo.u, P, i, j + 1, lnum * aN);
-  if (lself != 0.0) aadd(lo.u, P, i, j, lself);
+  else if (kN == 2) sk.add(0, P, i, j + 1, lnum * aN);
+  if (lself != 0.0) sk.add(0, P, i, j, lself);
   // coefficients
   const double laS = lnum * uS + la0, laN = lnum * uN + la0;
   const double laW = lnum * uW + la0, laE = lnum * uE + la0;
@@ -645,46 +710,44 @@ __global__ __launch_bounds__(AB) void k_adj_uhat(const Params P, const State o,
   lgr += lgn * gx(P, 5, i);
   // M = (rho_P dxr + rho_W dxl) dy / 2
   const double lM = la0 * P.idt;
-  aadd(A.lr, P, i, j, lM * dxr * dyj / 2.0);
-  aadd(A.lr, P, i - 1, j, lM * dxl * dyj / 2.0);
+  sk.add(2, P, i, j, lM * dxr * dyj / 2.0);
+  sk.add(2, P, i - 1, j, lM * dxl * dyj / 2.0);
   // cross-diffusion X
   const double lX = lnum * B;
   lgcN += lX * (v11 - v01);
   lgcS += -lX * (v10 - v00);
   lgr += -lX * 2.0 / 3.0 * (v11 - v10);
   lgl += lX * 2.0 / 3.0 * (v01 - v00);
-  aadd(lo.v, P, i, j + 1, lX * (gcN - 2.0 / 3.0 * gr));
-  aadd(lo.v, P, i - 1, j + 1, lX * (-gcN + 2.0 / 3.0 * gl));
-  aadd(lo.v, P, i, j, lX * (-gcS + 2.0 / 3.0 * gr));
-  aadd(lo.v, P, i - 1, j, lX * (gcS - 2.0 / 3.0 * gl));
-  gamc_adj(P, A.lg, i, j, lgcS);
-  gamc_adj(P, A.lg, i, j + 1, lgcN);
-  aadd(A.lg, P, i - 1, j, lgl);
-  aadd(A.lg, P, i, j, lgr);
+  sk.add(1, P, i, j + 1, lX * (gcN - 2.0 / 3.0 * gr));
+  sk.add(1, P, i - 1, j + 1, lX * (-gcN + 2.0 / 3.0 * gl));
+  sk.add(1, P, i, j, lX * (-gcS + 2.0 / 3.0 * gr));
+  sk.add(1, P, i - 1, j, lX * (gcS - 2.0 / 3.0 * gl));
+  gamc_adj(sk, 3, P, i, j, lgcS);
+  gamc_adj(sk, 3, P, i, j + 1, lgcN);
+  sk.add(3, P, i - 1, j, lgl);
+  sk.add(3, P, i, j, lgr);
 }
 
 // ---------------------------------------------------------------------------
 // (2) v-hat, d^v of a solved v-face (explicit scheme)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(AB) void k_adj_vhat(const Params P, const State o,
-                                                 const State lo, const Consts C,
-                                                 const Consts lC, const Inter I,
-                                                 const AdjTmp A) {
-  int i, j;
-  if (!elem(P, i, j) || i >= P.nx || !v_solved(P, i, j)) return;
+template <class S>
+__device__ void vhat_item(const Params &P, const State o, const Cache cc, const State lo, const Consts C,
+                          const Consts lC, const Inter I, const AdjTmp A, int i, int j, S &sk) {
+  if (i >= P.nx || !v_solved(P, i, j)) return;
   const long k = ix(P, i, j);
   const double lvh = A.lvh[k], ldv = A.ldv[k];
   if (lvh == 0.0 && ldv == 0.0) return;
   const double B = P.B;
   const double dxi = gx(P, 0, i), dys = gy(P, 0, j - 1), dyn = gy(P, 0, j), idx = gx(P, 1, i);
-  const double gs = gam(P, o, i, j - 1), gn = gam(P, o, i, j);
+  const double gs = gam(P, cc, i, j - 1), gn = gam(P, cc, i, j);
   const double vP = at(o.v, P, i, j), vS = at(o.v, P, i, j - 1), vN = at(o.v, P, i, j + 1);
   const bool inl = i == 0, outl = i == P.nx - 1;
   const double vW = inl ? 0.0 : at(o.v, P, i - 1, j);
   const double vE = outl ? vP : at(o.v, P, i + 1, j);
   const double len = 0.5 * (dys + dyn);
   const double gnode = gy(P, 4, j) * gs + gy(P, 5, j) * gn;
-  const double gcW = gamc(P, o, i, j), gcE = gamc(P, o, i + 1, j);
+  const double gcW = gamc(P, cc, i, j), gcE = gamc(P, cc, i + 1, j);
   double DW, DE;
   int dW, dE;  // 1 inlet, 2 obstacle, 3 corner; 0 none
   if (inl) { dW = 1; DW = B * 0.5 * (gnode + gcW) * len * (2.0 * idx); }
@@ -697,7 +760,7 @@ __global__ __launch_bounds__(AB) void k_adj_vhat(const Params P, const State o,
   } else { dE = 3; DE = B * gcE * gy(P, 2, j) * gx(P, 3, i + 1); }
   const double DS = B * gs * dxi * gy(P, 1, j - 1), DN = B * gn * dxi * gy(P, 1, j);
   const double aW = DW, aE = DE, aS = 4.0 / 3.0 * DS, aN = 4.0 / 3.0 * DN;
-  const double M = (rho(P, o, i, j) * dyn + rho(P, o, i, j - 1) * dys) * dxi / 2.0;
+  const double M = (rho(P, cc, i, j) * dyn + rho(P, cc, i, j - 1) * dys) * dxi / 2.0;
   const double a0 = aW + aE + aS + aN + 0.0 + M * P.idt;
   const double u00 = at(o.u, P, i, j - 1), u10 = at(o.u, P, i + 1, j - 1);
   const double u01 = at(o.u, P, i, j), u11 = at(o.u, P, i + 1, j);
@@ -708,11 +771,11 @@ __global__ __launch_bounds__(AB) void k_adj_vhat(const Params P, const State o,
   const double vh = num / a0, dv = P.A * dxi / a0;
   const double lnum = lvh / a0, la0 = -(lvh * vh + ldv * dv) / a0;
   lC.Cv[k] += lnum;
-  if (!inl) aadd(lo.v, P, i - 1, j, lnum * aW);
-  if (outl) aadd(lo.v, P, i, j, lnum * aE);
-  else aadd(lo.v, P, i + 1, j, lnum * aE);
-  aadd(lo.v, P, i, j - 1, lnum * aS);
-  aadd(lo.v, P, i, j + 1, lnum * aN);
+  if (!inl) sk.add(1, P, i - 1, j, lnum * aW);
+  if (outl) sk.add(1, P, i, j, lnum * aE);
+  else sk.add(1, P, i + 1, j, lnum * aE);
+  sk.add(1, P, i, j - 1, lnum * aS);
+  sk.add(1, P, i, j + 1, lnum * aN);
   const double laW = lnum * vW + la0, laE = lnum * vE + la0;
   const double laS = lnum * vS + la0, laN = lnum * vN + la0;
   double lgs = laS * 4.0 / 3.0 * B * dxi * gy(P, 1, j - 1);
@@ -729,52 +792,49 @@ __global__ __launch_bounds__(AB) void k_adj_vhat(const Params P, const State o,
   lgs += lgnode * gy(P, 4, j);
   lgn_ += lgnode * gy(P, 5, j);
   const double lM = la0 * P.idt;
-  aadd(A.lr, P, i, j, lM * dyn * dxi / 2.0);
-  aadd(A.lr, P, i, j - 1, lM * dys * dxi / 2.0);
+  sk.add(2, P, i, j, lM * dyn * dxi / 2.0);
+  sk.add(2, P, i, j - 1, lM * dys * dxi / 2.0);
   const double lX = lnum * B;
   lgcE += lX * (u11 - u10);
   lgcW += -lX * (u01 - u00);
   lgn_ += -lX * 2.0 / 3.0 * (u11 - u01);
   lgs += lX * 2.0 / 3.0 * (u10 - u00);
-  aadd(lo.u, P, i + 1, j, lX * (gcE - 2.0 / 3.0 * gn));
-  aadd(lo.u, P, i + 1, j - 1, lX * (-gcE + 2.0 / 3.0 * gs));
-  aadd(lo.u, P, i, j, lX * (-gcW + 2.0 / 3.0 * gn));
-  aadd(lo.u, P, i, j - 1, lX * (gcW - 2.0 / 3.0 * gs));
-  gamc_adj(P, A.lg, i, j, lgcW);
-  gamc_adj(P, A.lg, i + 1, j, lgcE);
-  aadd(A.lg, P, i, j - 1, lgs);
-  aadd(A.lg, P, i, j, lgn_);
+  sk.add(0, P, i + 1, j, lX * (gcE - 2.0 / 3.0 * gn));
+  sk.add(0, P, i + 1, j - 1, lX * (-gcE + 2.0 / 3.0 * gs));
+  sk.add(0, P, i, j, lX * (-gcW + 2.0 / 3.0 * gn));
+  sk.add(0, P, i, j - 1, lX * (gcW - 2.0 / 3.0 * gs));
+  gamc_adj(sk, 3, P, i, j, lgcW);
+  gamc_adj(sk, 3, P, i + 1, j, lgcE);
+  sk.add(3, P, i, j - 1, lgs);
+  sk.add(3, P, i, j, lgn_);
 }
 
 // ---------------------------------------------------------------------------
 // (1) face densities (upwind value + TVD correction x jump)
 // ---------------------------------------------------------------------------
-template <bool TV>
-__global__ __launch_bounds__(AB) void k_adj_rho_faces(const Params P, const State o,
-                                                      const double *lru, const double *lrv,
-                                                      double *lr) {
-  int i, j;
-  if (!elem(P, i, j)) return;
+template <bool TV, class S>
+__device__ void rho_faces_item(const Params &P, const State &o, const Cache cc, const double *lru,
+                               const double *lrv, int i, int j, S &sk) {
   if (j < P.ny) {  // u-face
     const double l = lru[ix(P, i, j)];
     if (l != 0.0) {
       const double uf = at(o.u, P, i, j);
       if (i == 0) {
-        if (!(uf > 0.0)) aadd(lr, P, 0, j, l);
+        if (!(uf > 0.0)) sk.add(0, P, 0, j, l);
       } else if (i == P.nx) {
-        aadd(lr, P, P.nx - 1, j, l);
+        sk.add(0, P, P.nx - 1, j, l);
       } else {
-        aadd(lr, P, uf > 0.0 ? i - 1 : i, j, l);
+        sk.add(0, P, uf > 0.0 ? i - 1 : i, j, l);
         if (TV && fl(P, i - 2, j) && fl(P, i - 1, j) && fl(P, i, j) && fl(P, i + 1, j)) {
-          const double r1 = rho(P, o, i - 2, j), rl = rho(P, o, i - 1, j);
-          const double rr = rho(P, o, i, j), r4 = rho(P, o, i + 1, j);
+          const double r1 = rho(P, cc, i - 2, j), rl = rho(P, cc, i - 1, j);
+          const double rr = rho(P, cc, i, j), r4 = rho(P, cc, i + 1, j);
           double g[4];
           const double ps = psix_d(P, r1, rl, rr, r4, i, uf, g);
           const double lj = l * (rr - rl);
-          aadd(lr, P, i - 2, j, lj * g[0]);
-          aadd(lr, P, i - 1, j, lj * g[1] - l * ps);
-          aadd(lr, P, i, j, lj * g[2] + l * ps);
-          aadd(lr, P, i + 1, j, lj * g[3]);
+          sk.add(0, P, i - 2, j, lj * g[0]);
+          sk.add(0, P, i - 1, j, lj * g[1] - l * ps);
+          sk.add(0, P, i, j, lj * g[2] + l * ps);
+          sk.add(0, P, i + 1, j, lj * g[3]);
         }
       }
     }
@@ -782,24 +842,73 @@ __global__ __launch_bounds__(AB) void k_adj_rho_faces(const Params P, const Stat
   if (i < P.nx) {  // v-face
     const double l = lrv[ix(P, i, j)];
     if (l != 0.0) {
-      if (j == 0) aadd(lr, P, i, 0, l);
-      else if (j == P.ny) aadd(lr, P, i, P.ny - 1, l);
+      if (j == 0) sk.add(0, P, i, 0, l);
+      else if (j == P.ny) sk.add(0, P, i, P.ny - 1, l);
       else {
         const double vf = at(o.v, P, i, j);
-        aadd(lr, P, i, vf > 0.0 ? j - 1 : j, l);
+        sk.add(0, P, i, vf > 0.0 ? j - 1 : j, l);
         if (TV && fl(P, i, j - 2) && fl(P, i, j - 1) && fl(P, i, j) && fl(P, i, j + 1)) {
-          const double r1 = rho(P, o, i, j - 2), rs = rho(P, o, i, j - 1);
-          const double rn = rho(P, o, i, j), r4 = rho(P, o, i, j + 1);
+          const double r1 = rho(P, cc, i, j - 2), rs = rho(P, cc, i, j - 1);
+          const double rn = rho(P, cc, i, j), r4 = rho(P, cc, i, j + 1);
           double g[4];
           const double ps = psiy_d(P, r1, rs, rn, r4, j, vf, g);
           const double lj = l * (rn - rs);
-          aadd(lr, P, i, j - 2, lj * g[0]);
-          aadd(lr, P, i, j - 1, lj * g[1] - l * ps);
-          aadd(lr, P, i, j, lj * g[2] + l * ps);
-          aadd(lr, P, i, j + 1, lj * g[3]);
+          sk.add(0, P, i, j - 2, lj * g[0]);
+          sk.add(0, P, i, j - 1, lj * g[1] - l * ps);
+          sk.add(0, P, i, j, lj * g[2] + l * ps);
+          sk.add(0, P, i, j + 1, lj * g[3]);
         }
       }
     }
+  }
+}
+
+template <bool TV>
+__global__ __launch_bounds__(AB) void k_adj_rho_faces(const Params P, const State o,
+                                                      const Cache cc, const double *lru,
+                                                      const double *lrv, double *lr) {
+  __shared__ double wl[Tiled<1, 2>::WN];
+  Tiled<1, 2> sk{(lds_double *)wl, {lr}};
+  int i, j;
+  sk.begin(P, i, j);
+  if (i <= P.nx && j <= P.ny) rho_faces_item<TV>(P, o, cc, lru, lrv, i, j, sk);
+  sk.end(P);
+}
+
+
+// The energy, u-hat, v-hat and face-density stages read disjoint adjoint
+// inputs and add into shared targets, so one launch runs them side by side
+// (blockIdx.y selects the stage): four times the blocks of one stage, which
+// keeps the CUs busy on grids whose single stage would leave them half idle.
+template <bool TV>
+__global__ __launch_bounds__(AB) void k_adj_stage2(const Params P, const State o,
+                                                   const State lo, const Consts C,
+                                                   const Consts lC, const Inter I,
+                                                   const AdjTmp A, double *gtw0, double *gtw1) {
+  __shared__ double wl[4 * Tiled<4, 1, false>::WN];
+  static_assert(Tiled<1, 2, false>::WN <= 4 * Tiled<4, 1, false>::WN, "LDS");
+  const Cache cc{A.q0, A.q1};
+  int i, j;
+  if (blockIdx.y == 0) {
+    Tiled<4, 1, false> sk{(lds_double *)wl, {lo.T, A.lg, lo.u, lo.v}};
+    sk.begin(P, i, j);
+    if (i <= P.nx && j <= P.ny) energy_item(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
+    sk.end(P);
+  } else if (blockIdx.y == 1) {
+    Tiled<4, 1, false> sk{(lds_double *)wl, {lo.u, lo.v, A.lr, A.lg}};
+    sk.begin(P, i, j);
+    if (i <= P.nx && j <= P.ny) uhat_item(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
+    sk.end(P);
+  } else if (blockIdx.y == 2) {
+    Tiled<4, 1, false> sk{(lds_double *)wl, {lo.u, lo.v, A.lr, A.lg}};
+    sk.begin(P, i, j);
+    if (i <= P.nx && j <= P.ny) vhat_item(P, o, cc, lo, C, lC, I, A, i, j, sk);
+    sk.end(P);
+  } else {
+    Tiled<1, 2, false> sk{(lds_double *)wl, {A.lr}};
+    sk.begin(P, i, j);
+    if (i <= P.nx && j <= P.ny) rho_faces_item<TV>(P, o, cc, A.lru, A.lrv, i, j, sk);
+    sk.end(P);
   }
 }
 
@@ -1280,6 +1389,22 @@ static dim3 agrid(const Params &P) {
   return dim3((unsigned)(((long)(P.nx + 1) * (P.ny + 1) + AB - 1) / AB));
 }
 
+// rho = p/T and Gamma = sqrt(T) of a state's cells and of the first two
+// frame layers around them (the values the stencils read there)
+__global__ __launch_bounds__(AB) void k_cell_cache(const Params P, const State o, double *r,
+                                                   double *g) {
+  const long t = (long)blockIdx.x * AB + threadIdx.x;
+  const int W = P.nx + 4, H = P.ny + 4;
+  if (t >= (long)W * H) return;
+  const int i = (int)(t % W) - 2, j = (int)(t / W) - 2;
+  const long k = ix(P, i, j);
+  r[k] = o.p[k] / o.T[k];
+  g[k] = sqrt(o.T[k]);
+}
+static dim3 cgrid(const Params &P) {
+  return dim3((unsigned)(((long)(P.nx + 4) * (P.ny + 4) + AB - 1) / AB));
+}
+
 void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, State lo,
                          Consts lC, AdjTmp A, double *gtw0, double *gtw1, int scheme,
                          hipStream_t st) {
@@ -1287,14 +1412,14 @@ void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, 
   hipLaunchKernelGGL(k_adj_outputs, g, b, 0, st, P, ln, lo, I, A);
   hipLaunchKernelGGL(k_adj_pressure_cells, g, b, 0, st, P, lC, I, A);
   hipLaunchKernelGGL(k_adj_pressure_faces, g, b, 0, st, P, o, lo, I, A);
-  hipLaunchKernelGGL(k_adj_energy, g, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
-  hipLaunchKernelGGL(k_adj_uhat, g, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
-  hipLaunchKernelGGL(k_adj_vhat, g, b, 0, st, P, o, lo, C, lC, I, A);
+  // the pressure stage's scratch is free from here on: rho, Gamma of o
+  hipLaunchKernelGGL(k_cell_cache, cgrid(P), b, 0, st, P, o, A.q0, A.q1);
   hipLaunchKernelGGL(k_adj_hat_copies, g, b, 0, st, P, lo, A);
+  const dim3 g4(tgrid(P).x, 4);
   if (scheme & 2)
-    hipLaunchKernelGGL((k_adj_rho_faces<true>), g, b, 0, st, P, o, A.lru, A.lrv, A.lr);
+    hipLaunchKernelGGL((k_adj_stage2<true>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
   else
-    hipLaunchKernelGGL((k_adj_rho_faces<false>), g, b, 0, st, P, o, A.lru, A.lrv, A.lr);
+    hipLaunchKernelGGL((k_adj_stage2<false>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
   hipLaunchKernelGGL(k_adj_cell_props, g, b, 0, st, P, o, lo, A.lr, A.lg);
 }
 
@@ -1312,8 +1437,13 @@ void launch_adjoint_prologue(const Params &P, State m, Consts lC, State lm, AdjT
   else
     hipLaunchKernelGGL((k_adj_prologue<false>), g, b, 0, st, P, m, lC, lm, A.luh, A.lvh, A.lru,
                        A.lrv, A.lr);
-  if (tv) hipLaunchKernelGGL((k_adj_rho_faces<true>), g, b, 0, st, P, m, A.lru, A.lrv, A.lr);
-  else hipLaunchKernelGGL((k_adj_rho_faces<false>), g, b, 0, st, P, m, A.lru, A.lrv, A.lr);
+  hipLaunchKernelGGL(k_cell_cache, cgrid(P), b, 0, st, P, m, A.q0, A.q1);
+  if (tv)
+    hipLaunchKernelGGL((k_adj_rho_faces<true>), tgrid(P), b, 0, st, P, m, Cache{A.q0, A.q1},
+                       A.lru, A.lrv, A.lr);
+  else
+    hipLaunchKernelGGL((k_adj_rho_faces<false>), tgrid(P), b, 0, st, P, m, Cache{A.q0, A.q1},
+                       A.lru, A.lrv, A.lr);
   hipLaunchKernelGGL(k_adj_cell_props, g, b, 0, st, P, m, lm, A.lr, A.lg);
 }
 
