@@ -253,41 +253,42 @@ __device__ __forceinline__ double lam_u(const Params &P, const State &ln, int i,
 __global__ __launch_bounds__(AB) void k_adj_outputs(const Params P, const State ln,
                                                     const State lo, const Inter I,
                                                     const AdjTmp A) {
+  // The first kernel of the reverse of a pass: it assigns every entry of
+  // the element (i, j) in the adjoint temporaries and in the adjoint of the
+  // old iterate that a later stage adds to, so nothing needs clearing
+  // before the pass.  u-face (i, j) (face nx is the outlet copy):
   int i, j;
   if (!elem(P, i, j)) return;
   const long k = ix(P, i, j);
-  if (j < P.ny && i < P.nx) {  // u-face (i, j); face nx is the outlet copy
-    const double l = lam_u(P, ln, i, j);
-    if (u_solved(P, i, j)) {
-      A.luh[k] += l;
-      A.ldu[k] += -l * (I.pn[k] - I.pn[k - 1]);
-    } else {
-      lo.u[k] += l;
-    }
+  const bool uf = j < P.ny && i < P.nx, us = uf && u_solved(P, i, j);
+  const double lu = uf ? lam_u(P, ln, i, j) : 0.0;
+  A.luh[k] = us ? lu : 0.0;
+  A.ldu[k] = us ? -lu * (I.pn[k] - I.pn[k - 1]) : 0.0;
+  lo.u[k] = us ? 0.0 : lu;
+  // v-face (i, j)
+  const bool vf = i < P.nx && j <= P.ny, vs = vf && v_solved(P, i, j);
+  const double lv = vf ? ln.v[k] : 0.0;
+  A.lvh[k] = vs ? lv : 0.0;
+  A.ldv[k] = vs ? -lv * (I.pn[k] - I.pn[k - P.pitch]) : 0.0;
+  lo.v[k] = vs ? 0.0 : lv;
+  // cell (i, j): the new T and p seed T-new and p-new (fluid), the new p
+  // collecting its part of the four velocity updates around the cell, or
+  // pass to the old values (solid cells are copied)
+  const bool cell = i < P.nx && j < P.ny, fluid = cell && fl(P, i, j);
+  double lp = 0.0;
+  if (fluid) {
+    lp = ln.p[k];
+    if (u_solved(P, i, j)) lp += -lam_u(P, ln, i, j) * I.du[k];
+    if (u_solved(P, i + 1, j)) lp += lam_u(P, ln, i + 1, j) * I.du[k + 1];
+    if (v_solved(P, i, j)) lp += -ln.v[k] * I.dv[k];
+    if (v_solved(P, i, j + 1)) lp += ln.v[k + P.pitch] * I.dv[k + P.pitch];
   }
-  if (i < P.nx && j <= P.ny) {  // v-face (i, j)
-    const double l = ln.v[k];
-    if (v_solved(P, i, j)) {
-      A.lvh[k] += l;
-      A.ldv[k] += -l * (I.pn[k] - I.pn[k - P.pitch]);
-    } else {
-      lo.v[k] += l;
-    }
-  }
-  if (i < P.nx && j < P.ny) {  // cell (i, j)
-    if (fl(P, i, j)) {
-      double lp = ln.p[k];
-      if (u_solved(P, i, j)) lp += -lam_u(P, ln, i, j) * I.du[k];
-      if (u_solved(P, i + 1, j)) lp += lam_u(P, ln, i + 1, j) * I.du[k + 1];
-      if (v_solved(P, i, j)) lp += -ln.v[k] * I.dv[k];
-      if (v_solved(P, i, j + 1)) lp += ln.v[k + P.pitch] * I.dv[k + P.pitch];
-      A.ltn[k] = ln.T[k];
-      A.lpn[k] = lp;
-    } else {
-      lo.T[k] += ln.T[k];
-      lo.p[k] += ln.p[k];
-    }
-  }
+  A.ltn[k] = fluid ? ln.T[k] : 0.0;
+  A.lpn[k] = lp;
+  lo.T[k] = cell && !fluid ? ln.T[k] : 0.0;
+  lo.p[k] = cell && !fluid ? ln.p[k] : 0.0;
+  A.lr[k] = 0.0;
+  A.lg[k] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(AB) void k_adj_pressure_faces(const Params P, const
       ldu += laE * I.ru[k] * dyj;
       luh += lbE * I.ru[k] * dyj;
     }
-    A.lru[k] += lru;
+    A.lru[k] = lru;  // first writer of the pass
     A.ldu[k] += ldu;
     A.luh[k] += luh;
   }
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(AB) void k_adj_pressure_faces(const Params P, const
       ldv += laN * I.rv[k] * dxi;
       lvh += lbN * I.rv[k] * dxi;
     }
-    A.lrv[k] += lrv;
+    A.lrv[k] = lrv;  // first writer of the pass
     A.ldv[k] += ldv;
     A.lvh[k] += lvh;
   }

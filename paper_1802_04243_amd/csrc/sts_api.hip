@@ -778,22 +778,13 @@ extern "C" sts_status sts_state_save(sts_ctx *c, int slot) {
 extern "C" sts_status sts_state_load(sts_ctx *c, int slot) {
   if (!c) return fail(STS_EINVAL, "ctx is NULL");
   if (slot < 0 || slot >= c->nslots) return fail(STS_EINVAL, "slot %d out of range", slot);
+  // into the current buffer only: a pass writes every entry of its output
+  // buffer except the boundary entries, which are the same in every state
   sts_status s;
-  if ((s = copy_state(c, c->st[0], slot_state(c, slot))) != STS_OK) return s;
-  if ((s = copy_state(c, c->st[1], slot_state(c, slot))) != STS_OK) return s;
-  c->cur = 0;
+  if ((s = copy_state(c, c->st[c->cur], slot_state(c, slot))) != STS_OK) return s;
   c->stepped = false;
   return STS_OK;
 }
-
-namespace {
-// zero the adjoint of the intermediates and the outgoing adjoint state
-sts_status clear_tmp(sts_ctx *c, State lo) {
-  HIPCHK(hipMemsetAsync(c->A.luh, 0, 10 * c->L.field_bytes, c->stream));
-  HIPCHK(hipMemsetAsync(lo.u, 0, 4 * c->L.field_bytes, c->stream));
-  return STS_OK;
-}
-}  // namespace
 
 extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
   if (!c) return fail(STS_EINVAL, "ctx is NULL");
@@ -886,7 +877,7 @@ extern "C" sts_status sts_adjoint_step(sts_ctx *c, double dt, int n_inner, int s
   // reverse of the passes
   for (int k = K; k >= 1; k--) {
     State ln = c->lam[c->lcur], lo = c->lam[c->lcur ^ 1];
-    if ((s = clear_tmp(c, lo)) != STS_OK) return s;
+    // (the reverse of the pass assigns its temporaries before adding to them)
     launch_adjoint_pass(c->P, iterate(k - 1), c->C, c->Iv[k], ln, lo, c->lC, c->A, c->gtw,
                         c->gtw + c->nx, scheme, c->stream);
     HIPCHK(hipGetLastError());
