@@ -250,9 +250,9 @@ __device__ __forceinline__ double lam_u(const Params &P, const State &ln, int i,
   const long k = ix(P, i, j);
   return i == P.nx - 1 ? ln.u[k] + ln.u[k + 1] : ln.u[k];
 }
-__global__ __launch_bounds__(AB) void k_adj_outputs(const Params P, const State ln,
-                                                    const State lo, const Inter I,
-                                                    const AdjTmp A) {
+__global__ __launch_bounds__(AB) void k_adj_outputs(const Params P, const State o,
+                                                    const State ln, const State lo,
+                                                    const Inter I, const AdjTmp A) {
   // The first kernel of the reverse of a pass: it assigns every entry of
   // the element (i, j) in the adjoint temporaries and in the adjoint of the
   // old iterate that a later stage adds to, so nothing needs clearing
@@ -289,6 +289,10 @@ __global__ __launch_bounds__(AB) void k_adj_outputs(const Params P, const State 
   lo.p[k] = cell && !fluid ? ln.p[k] : 0.0;
   A.lr[k] = 0.0;
   A.lg[k] = 0.0;
+  if (cell) {  // rho and Gamma of the iterate, for the later stages
+    A.cr[k] = o.p[k] / o.T[k];
+    A.cg[k] = sqrt(o.T[k]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -360,6 +364,8 @@ __global__ __launch_bounds__(AB) void k_adj_pressure_faces(const Params P, const
     A.lru[k] = lru;  // first writer of the pass
     A.ldu[k] += ldu;
     A.luh[k] += luh;
+    // u-hat of a face that is not solved is a copy of the old value
+    if (!u_solved(P, i, j)) lo.u[k] += A.luh[k];
   }
   if (i < P.nx) {  // v-face (i, j): south face of cell (i, j), north face of cell (i, j-1)
     const double dxi = gx(P, 0, i);
@@ -381,17 +387,8 @@ __global__ __launch_bounds__(AB) void k_adj_pressure_faces(const Params P, const
     A.lrv[k] = lrv;  // first writer of the pass
     A.ldv[k] += ldv;
     A.lvh[k] += lvh;
+    if (!v_solved(P, i, j)) lo.v[k] += A.lvh[k];
   }
-}
-
-// u-hat / v-hat of faces that are not solved are copies of the old value
-__global__ __launch_bounds__(AB) void k_adj_hat_copies(const Params P, const State lo,
-                                                       const AdjTmp A) {
-  int i, j;
-  if (!elem(P, i, j)) return;
-  const long k = ix(P, i, j);
-  if (j < P.ny && !u_solved(P, i, j)) lo.u[k] += A.luh[k];
-  if (i < P.nx && !v_solved(P, i, j)) lo.v[k] += A.lvh[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -888,7 +885,7 @@ __global__ __launch_bounds__(AB) void k_adj_stage2(const Params P, const State o
                                                    const AdjTmp A, double *gtw0, double *gtw1) {
   __shared__ double wl[4 * Tiled<4, 1, false>::WN];
   static_assert(Tiled<1, 2, false>::WN <= 4 * Tiled<4, 1, false>::WN, "LDS");
-  const Cache cc{A.q0, A.q1};
+  const Cache cc{A.cr, A.cg};
   int i, j;
   if (blockIdx.y == 0) {
     Tiled<4, 1, false> sk{(lds_double *)wl, {lo.T, A.lg, lo.u, lo.v}};
@@ -1406,16 +1403,17 @@ static dim3 cgrid(const Params &P) {
   return dim3((unsigned)(((long)(P.nx + 4) * (P.ny + 4) + AB - 1) / AB));
 }
 
+void launch_cell_cache(const Params &P, State o, double *r, double *g, hipStream_t st) {
+  hipLaunchKernelGGL(k_cell_cache, cgrid(P), dim3(AB), 0, st, P, o, r, g);
+}
+
 void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, State lo,
                          Consts lC, AdjTmp A, double *gtw0, double *gtw1, int scheme,
                          hipStream_t st) {
   const dim3 g = agrid(P), b(AB);
-  hipLaunchKernelGGL(k_adj_outputs, g, b, 0, st, P, ln, lo, I, A);
+  hipLaunchKernelGGL(k_adj_outputs, g, b, 0, st, P, o, ln, lo, I, A);
   hipLaunchKernelGGL(k_adj_pressure_cells, g, b, 0, st, P, lC, I, A);
   hipLaunchKernelGGL(k_adj_pressure_faces, g, b, 0, st, P, o, lo, I, A);
-  // the pressure stage's scratch is free from here on: rho, Gamma of o
-  hipLaunchKernelGGL(k_cell_cache, cgrid(P), b, 0, st, P, o, A.q0, A.q1);
-  hipLaunchKernelGGL(k_adj_hat_copies, g, b, 0, st, P, lo, A);
   const dim3 g4(tgrid(P).x, 4);
   if (scheme & 2)
     hipLaunchKernelGGL((k_adj_stage2<true>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
@@ -1438,12 +1436,12 @@ void launch_adjoint_prologue(const Params &P, State m, Consts lC, State lm, AdjT
   else
     hipLaunchKernelGGL((k_adj_prologue<false>), g, b, 0, st, P, m, lC, lm, A.luh, A.lvh, A.lru,
                        A.lrv, A.lr);
-  hipLaunchKernelGGL(k_cell_cache, cgrid(P), b, 0, st, P, m, A.q0, A.q1);
+  hipLaunchKernelGGL(k_cell_cache, cgrid(P), b, 0, st, P, m, A.cr, A.cg);
   if (tv)
-    hipLaunchKernelGGL((k_adj_rho_faces<true>), tgrid(P), b, 0, st, P, m, Cache{A.q0, A.q1},
+    hipLaunchKernelGGL((k_adj_rho_faces<true>), tgrid(P), b, 0, st, P, m, Cache{A.cr, A.cg},
                        A.lru, A.lrv, A.lr);
   else
-    hipLaunchKernelGGL((k_adj_rho_faces<false>), tgrid(P), b, 0, st, P, m, Cache{A.q0, A.q1},
+    hipLaunchKernelGGL((k_adj_rho_faces<false>), tgrid(P), b, 0, st, P, m, Cache{A.cr, A.cg},
                        A.lru, A.lrv, A.lr);
   hipLaunchKernelGGL(k_adj_cell_props, g, b, 0, st, P, m, lm, A.lr, A.lg);
 }

@@ -796,10 +796,10 @@ extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
     if (c->adj_mem) HIPCHK(hipFree(c->adj_mem));
     c->adj_mem = nullptr;
     c->adj_K = 0;
-    // K iterates, 8 intermediates per pass, 10 adjoint intermediates and 2
+    // K iterates, 8 intermediates per pass, 10 adjoint intermediates and 4
     // scratch arrays, 2 adjoint states, 4 constant adjoints, wall gradients
     const size_t F = c->L.field_bytes;
-    const size_t bytes = (size_t)n_inner * 4 * F + (size_t)n_inner * 8 * F + 12 * F + 8 * F +
+    const size_t bytes = (size_t)n_inner * 4 * F + (size_t)n_inner * 8 * F + 14 * F + 8 * F +
                          4 * F + align_up(sizeof(double) * 2 * c->nx, 256);
     if (hipMalloc((void **)&c->adj_mem, bytes) != hipSuccess) {
       c->adj_mem = nullptr;
@@ -821,6 +821,8 @@ extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
     for (auto p : ap) { *p = (double *)q; q += F; }
     c->A.q0 = (double *)q; q += F;
     c->A.q1 = (double *)q; q += F;
+    c->A.cr = (double *)q; q += F;
+    c->A.cg = (double *)q; q += F;
     c->lam[0] = carve(q, c->L);
     c->lam[1] = carve(q, c->L);
     c->lC.Cu = (double *)q; q += F;
@@ -831,6 +833,10 @@ extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
     c->adj_K = n_inner;
   }
   c->lcur = 0;
+  // rho, Gamma of a state including the frame (the cells are recomputed for
+  // every iterate by the reverse kernels; the frame is the same in all)
+  launch_cell_cache(c->P, c->st[c->cur], c->A.cr, c->A.cg, c->stream);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipMemsetAsync(c->lam[0].u, 0, 8 * c->L.field_bytes, c->stream));
   HIPCHK(hipMemsetAsync(c->gtw, 0, sizeof(double) * 2 * c->nx, c->stream));
   return STS_OK;

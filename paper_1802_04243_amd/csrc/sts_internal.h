@@ -84,6 +84,9 @@ struct AdjTmp {
   // per-cell scratch of the pressure reverse (adjoints of the numerator and
   // of the diagonal of each cell's equation); written before being read
   double *q0, *q1;
+  // rho = p/T and Gamma = sqrt(T) of the iterate being reversed (its frame
+  // entries hold the values of the constant ghost state)
+  double *cr, *cg;
 };
 
 void launch_prologue(const Params &P, State m, Consts C, int scheme,
@@ -97,6 +100,7 @@ void launch_residual(const Params &P, State n, Consts C, Resid R, double *out,
 void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, State lo,
                          Consts lC, AdjTmp A, double *gtw0, double *gtw1, int scheme,
                          hipStream_t st);
+void launch_cell_cache(const Params &P, State o, double *r, double *g, hipStream_t st);
 void launch_adjoint_prologue(const Params &P, State m, Consts lC, State lm, AdjTmp A,
                              int scheme, hipStream_t st);
 // drag on the obstacles of a state (partial: drag_blocks doubles) and the
