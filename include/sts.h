@@ -216,7 +216,7 @@ sts_status sts_state_load(sts_ctx *ctx, int slot);
    temperatures wall_T[0][nx], wall_T[1][nx] (isothermal walls).
 
    sts_adjoint_begin: allocate the buffers for n_inner passes per step
-   (library-owned, 12 n_inner + 22 field arrays: the iterates and the
+   (library-owned, 12 n_inner + 23 field arrays: the iterates and the
    intermediates of every pass of one step, the adjoint temporaries and
    states), set lambda and the wall-temperature gradients to zero.  The
    adjoint supports inlet/outlet channels without slip-jump surfaces

@@ -238,156 +238,177 @@ static dim3 tgrid(const Params &P) {
 }
 
 // ---------------------------------------------------------------------------
-// (4) velocity update and the cell outputs, gather form (no atomics)
+// (4) velocity update and cell outputs, and (3) the pressure equation:
+// gather form, one launch (no atomics)
 // ---------------------------------------------------------------------------
-// Element (i, j) handles u-face (i, j), v-face (i, j) and cell (i, j).
-// Faces: u = u-hat - d^u (p_P - p_W) on solved faces, else a copy of the old
-// value; the outlet face takes the new value of face nx-1.  Cells: the
-// adjoints of the new T and p seed those of T-new and p-new (fluid), the new
-// p collecting its part of the four velocity updates around the cell, or
-// pass to the old values (solid cells are copied).
+// Velocity update: u = u-hat - d^u (p_P - p_W) on solved faces, else a copy
+// of the old value; the outlet face takes the new value of face nx-1.  Cell
+// outputs: the adjoints of the new T and p seed those of T-new and p-new
+// (fluid), the new p collecting its part of the four velocity updates around
+// the cell, or pass to the old values (solid cells are copied).
+// Pressure: p = N / a0 with N = (sum a_nb p_nb) dt + C_p - (bE - bW + bN -
+// bS) dt, a0 = dV/T + (sum a_nb) dt, a_W = rho^u d^u dy and b_W = rho^u
+// u-hat dy on the faces.  Per fluid cell lN = lambda/a0 and la0 = -lambda
+// p/a0; the old pressure of a cell collects lN a dt of its four neighbours'
+// equations, each face the a- and b-adjoints of the (at most two) cells it
+// borders.
 __device__ __forceinline__ double lam_u(const Params &P, const State &ln, int i, int j) {
   const long k = ix(P, i, j);
   return i == P.nx - 1 ? ln.u[k] + ln.u[k + 1] : ln.u[k];
 }
-__global__ __launch_bounds__(AB) void k_adj_outputs(const Params P, const State o,
-                                                    const State ln, const State lo,
-                                                    const Inter I, const AdjTmp A) {
-  // The first kernel of the reverse of a pass: it assigns every entry of
-  // the element (i, j) in the adjoint temporaries and in the adjoint of the
-  // old iterate that a later stage adds to, so nothing needs clearing
-  // before the pass.  u-face (i, j) (face nx is the outlet copy):
-  int i, j;
-  if (!elem(P, i, j)) return;
-  const long k = ix(P, i, j);
-  const bool uf = j < P.ny && i < P.nx, us = uf && u_solved(P, i, j);
-  const double lu = uf ? lam_u(P, ln, i, j) : 0.0;
-  A.luh[k] = us ? lu : 0.0;
-  A.ldu[k] = us ? -lu * (I.pn[k] - I.pn[k - 1]) : 0.0;
-  lo.u[k] = us ? 0.0 : lu;
-  // v-face (i, j)
-  const bool vf = i < P.nx && j <= P.ny, vs = vf && v_solved(P, i, j);
-  const double lv = vf ? ln.v[k] : 0.0;
-  A.lvh[k] = vs ? lv : 0.0;
-  A.ldv[k] = vs ? -lv * (I.pn[k] - I.pn[k - P.pitch]) : 0.0;
-  lo.v[k] = vs ? 0.0 : lv;
-  // cell (i, j): the new T and p seed T-new and p-new (fluid), the new p
-  // collecting its part of the four velocity updates around the cell, or
-  // pass to the old values (solid cells are copied)
-  const bool cell = i < P.nx && j < P.ny, fluid = cell && fl(P, i, j);
-  double lp = 0.0;
-  if (fluid) {
-    lp = ln.p[k];
-    if (u_solved(P, i, j)) lp += -lam_u(P, ln, i, j) * I.du[k];
-    if (u_solved(P, i + 1, j)) lp += lam_u(P, ln, i + 1, j) * I.du[k + 1];
-    if (v_solved(P, i, j)) lp += -ln.v[k] * I.dv[k];
-    if (v_solved(P, i, j + 1)) lp += ln.v[k + P.pitch] * I.dv[k + P.pitch];
+// adjoint of the new p of fluid cell (i, j) (its own output and the four
+// velocity updates around it)
+__device__ __forceinline__ double lam_pnew(const Params &P, const State &ln, const Inter &I,
+                                           int i, int j, long k) {
+  double lp = ln.p[k];
+  if (u_solved(P, i, j)) lp += -lam_u(P, ln, i, j) * I.du[k];
+  if (u_solved(P, i + 1, j)) lp += lam_u(P, ln, i + 1, j) * I.du[k + 1];
+  if (v_solved(P, i, j)) lp += -ln.v[k] * I.dv[k];
+  if (v_solved(P, i, j + 1)) lp += ln.v[k + P.pitch] * I.dv[k + P.pitch];
+  return lp;
+}
+// lN, la0 of fluid cell (i, j) from the adjoint l of its new p; tn, dV out
+__device__ __forceinline__ void press_adj(const Params &P, const Inter &I, int i, int j, long k,
+                                          double l, double &lN, double &la0, double &tn,
+                                          double &dV) {
+  const long kE = k + 1, kN = k + P.pitch;
+  const double dxi = gx(P, 0, i), dyj = gy(P, 0, j), dt = P.dt;
+  dV = dxi * dyj;
+  const double aW = I.ru[k] * I.du[k] * dyj, aE = I.ru[kE] * I.du[kE] * dyj;
+  const double aS = I.rv[k] * I.dv[k] * dxi, aN = I.rv[kN] * I.dv[kN] * dxi;
+  tn = I.tn[k];
+  const double pn = I.pn[k];
+  const double a0 = dV / tn + (aW + aE + aS + aN) * dt;
+  lN = l / a0;
+  la0 = -l * pn / a0;
+}
+
+// One block per TW x TH tile of elements (u-face, v-face and cell (i, j)).
+// Phase 1: lN, la0 of the tile's cells and of the ring of cells around it
+// (the ring recomputed by both neighbouring blocks), kept in LDS.  Phase 2:
+// every element assigns the entries of the temporaries and of the outgoing
+// adjoint state that it or a later stage adds to (nothing is cleared before
+// a pass), and ρ = p/T, Γ = √T of the iterate for the later stages.
+constexpr int CW = TW + 2, CH = TH + 2;
+__global__ __launch_bounds__(AB) void k_adj_front(const Params P, const State o,
+                                                  const State ln, const State lo,
+                                                  const Consts lC, const Inter I,
+                                                  const AdjTmp A) {
+  __shared__ double sq0[CH * CW], sq1[CH * CW];
+  const int ntx = (P.nx + 1 + TW - 1) / TW;
+  const int x0 = (int)(blockIdx.x % ntx) * TW, y0 = (int)(blockIdx.x / ntx) * TH;
+  for (int c = threadIdx.x; c < CW * CH; c += AB) {
+    const int ci = x0 - 1 + c % CW, cj = y0 - 1 + c / CW;
+    double lN = 0.0, la0 = 0.0;
+    if (ci >= 0 && ci < P.nx && cj >= 0 && cj < P.ny && fl(P, ci, cj)) {
+      const long k = ix(P, ci, cj);
+      double tn, dV;
+      press_adj(P, I, ci, cj, k, lam_pnew(P, ln, I, ci, cj, k), lN, la0, tn, dV);
+    }
+    sq0[c] = lN;
+    sq1[c] = la0;
   }
-  A.ltn[k] = fluid ? ln.T[k] : 0.0;
-  A.lpn[k] = lp;
-  lo.T[k] = cell && !fluid ? ln.T[k] : 0.0;
-  lo.p[k] = cell && !fluid ? ln.p[k] : 0.0;
-  A.lr[k] = 0.0;
-  A.lg[k] = 0.0;
-  if (cell) {  // rho and Gamma of the iterate, for the later stages
+  __syncthreads();
+  const int i = x0 + (int)threadIdx.x % TW, j = y0 + (int)threadIdx.x / TW;
+  if (i > P.nx || j > P.ny) return;
+  const long k = ix(P, i, j);
+  const int c = (j - y0 + 1) * CW + (i - x0 + 1);  // cell (i, j) in the LDS ring layout
+  const double dt = P.dt;
+
+  // cell (i, j)
+  const bool cell = i < P.nx && j < P.ny, fluid = cell && fl(P, i, j);
+  double lTn = 0.0;
+  if (fluid) {
+    double lN, la0, tn, dV;
+    press_adj(P, I, i, j, k, lam_pnew(P, ln, I, i, j, k), lN, la0, tn, dV);
+    lTn = ln.T[k] + la0 * (-dV / (tn * tn));
+    lC.Cp[k] += lN;
+  }
+  A.ltn[k] = lTn;
+  double lpo = cell && !fluid ? ln.p[k] : 0.0;  // old pressure
+  if (cell) {
+    const double dxi = gx(P, 0, i), dyj = gy(P, 0, j);
+    double s = 0.0;
+    if (i >= 1) s += sq0[c - 1] * (I.ru[k] * I.du[k] * dyj) * dt;
+    if (i + 1 < P.nx) s += sq0[c + 1] * (I.ru[k + 1] * I.du[k + 1] * dyj) * dt;
+    if (j >= 1) s += sq0[c - CW] * (I.rv[k] * I.dv[k] * dxi) * dt;
+    if (j + 1 < P.ny) s += sq0[c + CW] * (I.rv[k + P.pitch] * I.dv[k + P.pitch] * dxi) * dt;
+    lpo += s;
     A.cr[k] = o.p[k] / o.T[k];
     A.cg[k] = sqrt(o.T[k]);
   }
-}
+  lo.p[k] = lpo;
+  lo.T[k] = cell && !fluid ? ln.T[k] : 0.0;
+  A.lr[k] = 0.0;
+  A.lg[k] = 0.0;
 
-// ---------------------------------------------------------------------------
-// (3) pressure equation of a fluid cell, gather form (no atomics)
-// ---------------------------------------------------------------------------
-// p = N / a0 with N = (sum a_nb p_nb) dt + C_p - (bE - bW + bN - bS) dt,
-// a0 = dV/T + (sum a_nb) dt, a_W = rho^u d^u dy and b_W = rho^u u-hat dy on
-// the faces.  First per cell: lN = lambda/a0 and la0 = -lambda p/a0 (kept in
-// the scratch arrays; 0 for solid cells), the T-new and C_p adjoints.  Then
-// per element: the old pressure of cell (i, j) collects lN a dt of its four
-// neighbours' equations, and each face the a- and b-adjoints of the (at most
-// two) cells it borders.
-__global__ __launch_bounds__(AB) void k_adj_pressure_cells(const Params P, const Consts lC,
-                                                           const Inter I, const AdjTmp A) {
-  int i, j;
-  if (!elem(P, i, j) || i >= P.nx || j >= P.ny) return;
-  const long k = ix(P, i, j);
-  if (!fl(P, i, j)) {
-    A.q0[k] = 0.0;
-    A.q1[k] = 0.0;
-    return;
-  }
-  const long kE = k + 1, kN = k + P.pitch;
-  const double dxi = gx(P, 0, i), dyj = gy(P, 0, j), dV = dxi * dyj, dt = P.dt;
-  const double aW = I.ru[k] * I.du[k] * dyj, aE = I.ru[kE] * I.du[kE] * dyj;
-  const double aS = I.rv[k] * I.dv[k] * dxi, aN = I.rv[kN] * I.dv[kN] * dxi;
-  const double tn = I.tn[k], pn = I.pn[k];
-  const double a0 = dV / tn + (aW + aE + aS + aN) * dt;
-  const double l = A.lpn[k];
-  const double lN = l / a0, la0 = -l * pn / a0;
-  A.ltn[k] += la0 * (-dV / (tn * tn));
-  lC.Cp[k] += lN;
-  A.q0[k] = lN;
-  A.q1[k] = la0;
-}
-__global__ __launch_bounds__(AB) void k_adj_pressure_faces(const Params P, const State o,
-                                                           const State lo, const Inter I,
-                                                           const AdjTmp A) {
-  int i, j;
-  if (!elem(P, i, j)) return;
-  const long k = ix(P, i, j);
-  const double dt = P.dt;
-  if (i < P.nx && j < P.ny) {  // old pressure of cell (i, j)
-    const double dxi = gx(P, 0, i), dyj = gy(P, 0, j);
-    double s = 0.0;
-    if (i >= 1) s += A.q0[k - 1] * (I.ru[k] * I.du[k] * dyj) * dt;
-    if (i + 1 < P.nx) s += A.q0[k + 1] * (I.ru[k + 1] * I.du[k + 1] * dyj) * dt;
-    if (j >= 1) s += A.q0[k - P.pitch] * (I.rv[k] * I.dv[k] * dxi) * dt;
-    if (j + 1 < P.ny) s += A.q0[k + P.pitch] * (I.rv[k + P.pitch] * I.dv[k + P.pitch] * dxi) * dt;
-    lo.p[k] += s;
-  }
-  if (j < P.ny) {  // u-face (i, j): west face of cell (i, j), east face of cell (i-1, j)
+  // u-face (i, j): velocity update, then the west face of cell (i, j) and
+  // the east face of cell (i-1, j) in the pressure equation; an unsolved
+  // face passes its u-hat adjoint to the old velocity
+  if (j < P.ny) {
+    const bool us = i < P.nx && u_solved(P, i, j);
+    const double lu = i < P.nx ? lam_u(P, ln, i, j) : 0.0;
+    double luh = us ? lu : 0.0, ldu = us ? -lu * (I.pn[k] - I.pn[k - 1]) : 0.0, lru = 0.0;
     const double dyj = gy(P, 0, j);
-    double lru = 0.0, ldu = 0.0, luh = 0.0;
+    double pl = 0.0, pd = 0.0, ph = 0.0;
     if (i < P.nx && fl(P, i, j)) {
-      const double lN = A.q0[k];
-      const double laW = lN * at(o.p, P, i - 1, j) * dt + A.q1[k] * dt, lbW = lN * dt;
-      lru += (laW * I.du[k] + lbW * I.uh[k]) * dyj;
-      ldu += laW * I.ru[k] * dyj;
-      luh += lbW * I.ru[k] * dyj;
+      const double lN = sq0[c];
+      const double laW = lN * at(o.p, P, i - 1, j) * dt + sq1[c] * dt, lbW = lN * dt;
+      pl += (laW * I.du[k] + lbW * I.uh[k]) * dyj;
+      pd += laW * I.ru[k] * dyj;
+      ph += lbW * I.ru[k] * dyj;
     }
-    if (i >= 1 && i - 1 < P.nx && fl(P, i - 1, j)) {
-      const double lN = A.q0[k - 1];
-      const double laE = lN * at(o.p, P, i, j) * dt + A.q1[k - 1] * dt, lbE = -lN * dt;
-      lru += (laE * I.du[k] + lbE * I.uh[k]) * dyj;
-      ldu += laE * I.ru[k] * dyj;
-      luh += lbE * I.ru[k] * dyj;
+    if (i >= 1 && fl(P, i - 1, j)) {
+      const double lN = sq0[c - 1];
+      const double laE = lN * at(o.p, P, i, j) * dt + sq1[c - 1] * dt, lbE = -lN * dt;
+      pl += (laE * I.du[k] + lbE * I.uh[k]) * dyj;
+      pd += laE * I.ru[k] * dyj;
+      ph += lbE * I.ru[k] * dyj;
     }
-    A.lru[k] = lru;  // first writer of the pass
-    A.ldu[k] += ldu;
-    A.luh[k] += luh;
-    // u-hat of a face that is not solved is a copy of the old value
-    if (!u_solved(P, i, j)) lo.u[k] += A.luh[k];
+    lru = pl;
+    ldu += pd;
+    luh += ph;
+    A.lru[k] = lru;
+    A.ldu[k] = ldu;
+    A.luh[k] = luh;
+    lo.u[k] = us ? 0.0 : (i < P.nx ? lu : 0.0) + luh;
+  } else {
+    A.luh[k] = 0.0;
+    A.ldu[k] = 0.0;
+    lo.u[k] = 0.0;
   }
-  if (i < P.nx) {  // v-face (i, j): south face of cell (i, j), north face of cell (i, j-1)
+  // v-face (i, j): the same with the south face of cell (i, j) and the
+  // north face of cell (i, j-1)
+  if (i < P.nx) {
+    const bool vs = v_solved(P, i, j);
+    const double lv = ln.v[k];
+    double lvh = vs ? lv : 0.0, ldv = vs ? -lv * (I.pn[k] - I.pn[k - P.pitch]) : 0.0;
     const double dxi = gx(P, 0, i);
-    double lrv = 0.0, ldv = 0.0, lvh = 0.0;
+    double pl = 0.0, pd = 0.0, ph = 0.0;
     if (j < P.ny && fl(P, i, j)) {
-      const double lN = A.q0[k];
-      const double laS = lN * at(o.p, P, i, j - 1) * dt + A.q1[k] * dt, lbS = lN * dt;
-      lrv += (laS * I.dv[k] + lbS * I.vh[k]) * dxi;
-      ldv += laS * I.rv[k] * dxi;
-      lvh += lbS * I.rv[k] * dxi;
+      const double lN = sq0[c];
+      const double laS = lN * at(o.p, P, i, j - 1) * dt + sq1[c] * dt, lbS = lN * dt;
+      pl += (laS * I.dv[k] + lbS * I.vh[k]) * dxi;
+      pd += laS * I.rv[k] * dxi;
+      ph += lbS * I.rv[k] * dxi;
     }
-    if (j >= 1 && j - 1 < P.ny && fl(P, i, j - 1)) {
-      const double lN = A.q0[k - P.pitch];
-      const double laN = lN * at(o.p, P, i, j) * dt + A.q1[k - P.pitch] * dt, lbN = -lN * dt;
-      lrv += (laN * I.dv[k] + lbN * I.vh[k]) * dxi;
-      ldv += laN * I.rv[k] * dxi;
-      lvh += lbN * I.rv[k] * dxi;
+    if (j >= 1 && fl(P, i, j - 1)) {
+      const double lN = sq0[c - CW];
+      const double laN = lN * at(o.p, P, i, j) * dt + sq1[c - CW] * dt, lbN = -lN * dt;
+      pl += (laN * I.dv[k] + lbN * I.vh[k]) * dxi;
+      pd += laN * I.rv[k] * dxi;
+      ph += lbN * I.rv[k] * dxi;
     }
-    A.lrv[k] = lrv;  // first writer of the pass
-    A.ldv[k] += ldv;
-    A.lvh[k] += lvh;
-    if (!v_solved(P, i, j)) lo.v[k] += A.lvh[k];
+    ldv += pd;
+    lvh += ph;
+    A.lrv[k] = pl;
+    A.ldv[k] = ldv;
+    A.lvh[k] = lvh;
+    lo.v[k] = vs ? 0.0 : lv + lvh;
+  } else {
+    A.lvh[k] = 0.0;
+    A.ldv[k] = 0.0;
+    lo.v[k] = 0.0;
   }
 }
 
@@ -1411,9 +1432,7 @@ void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, 
                          Consts lC, AdjTmp A, double *gtw0, double *gtw1, int scheme,
                          hipStream_t st) {
   const dim3 g = agrid(P), b(AB);
-  hipLaunchKernelGGL(k_adj_outputs, g, b, 0, st, P, o, ln, lo, I, A);
-  hipLaunchKernelGGL(k_adj_pressure_cells, g, b, 0, st, P, lC, I, A);
-  hipLaunchKernelGGL(k_adj_pressure_faces, g, b, 0, st, P, o, lo, I, A);
+  hipLaunchKernelGGL(k_adj_front, tgrid(P), b, 0, st, P, o, ln, lo, lC, I, A);
   const dim3 g4(tgrid(P).x, 4);
   if (scheme & 2)
     hipLaunchKernelGGL((k_adj_stage2<true>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);

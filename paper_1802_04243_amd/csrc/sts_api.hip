@@ -796,10 +796,10 @@ extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
     if (c->adj_mem) HIPCHK(hipFree(c->adj_mem));
     c->adj_mem = nullptr;
     c->adj_K = 0;
-    // K iterates, 8 intermediates per pass, 10 adjoint intermediates and 4
-    // scratch arrays, 2 adjoint states, 4 constant adjoints, wall gradients
+    // K iterates, 8 intermediates per pass, 9 adjoint intermediates and 2
+    // cached arrays, 2 adjoint states, 4 constant adjoints, wall gradients
     const size_t F = c->L.field_bytes;
-    const size_t bytes = (size_t)n_inner * 4 * F + (size_t)n_inner * 8 * F + 14 * F + 8 * F +
+    const size_t bytes = (size_t)n_inner * 4 * F + (size_t)n_inner * 8 * F + 11 * F + 8 * F +
                          4 * F + align_up(sizeof(double) * 2 * c->nx, 256);
     if (hipMalloc((void **)&c->adj_mem, bytes) != hipSuccess) {
       c->adj_mem = nullptr;
@@ -816,11 +816,9 @@ extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
       c->Iv.push_back(I);
     }
     c->adj_frames = false;
-    double **ap[10] = {&c->A.luh, &c->A.ldu, &c->A.lvh, &c->A.ldv, &c->A.lru,
-                       &c->A.lrv, &c->A.lr,  &c->A.lg,  &c->A.ltn, &c->A.lpn};
+    double **ap[9] = {&c->A.luh, &c->A.ldu, &c->A.lvh, &c->A.ldv, &c->A.lru,
+                      &c->A.lrv, &c->A.lr,  &c->A.lg,  &c->A.ltn};
     for (auto p : ap) { *p = (double *)q; q += F; }
-    c->A.q0 = (double *)q; q += F;
-    c->A.q1 = (double *)q; q += F;
     c->A.cr = (double *)q; q += F;
     c->A.cg = (double *)q; q += F;
     c->lam[0] = carve(q, c->L);
@@ -890,7 +888,7 @@ extern "C" sts_status sts_adjoint_step(sts_ctx *c, double dt, int n_inner, int s
     c->lcur ^= 1;
   }
   // reverse of the prologue, onto the adjoint of x_0
-  HIPCHK(hipMemsetAsync(c->A.luh, 0, 10 * c->L.field_bytes, c->stream));
+  HIPCHK(hipMemsetAsync(c->A.luh, 0, 9 * c->L.field_bytes, c->stream));
   launch_adjoint_prologue(c->P, x0, c->lC, c->lam[c->lcur], c->A, scheme, c->stream);
   HIPCHK(hipGetLastError());
   return STS_OK;

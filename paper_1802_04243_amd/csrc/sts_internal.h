@@ -78,12 +78,9 @@ struct Inter {
 };
 
 // Adjoints of the pass intermediates (u-hat, d^u, v-hat, d^v, face
-// densities, rho, Gamma, new T, new p), field layout.
+// densities, rho, Gamma, new T), field layout.
 struct AdjTmp {
-  double *luh, *ldu, *lvh, *ldv, *lru, *lrv, *lr, *lg, *ltn, *lpn;
-  // per-cell scratch of the pressure reverse (adjoints of the numerator and
-  // of the diagonal of each cell's equation); written before being read
-  double *q0, *q1;
+  double *luh, *ldu, *lvh, *ldv, *lru, *lrv, *lr, *lg, *ltn;
   // rho = p/T and Gamma = sqrt(T) of the iterate being reversed (its frame
   // entries hold the values of the constant ghost state)
   double *cr, *cg;
