@@ -140,15 +140,18 @@ sts_status sts_step(sts_ctx *ctx, double dt, int n_inner, int scheme);
 
 /* One time step whose loop 2 runs until convergence (Sec. 3.1: the inner
    iterations repeat until the step's solution has converged; Sec. 5: the
-   maximal residuals are read back after every iteration): after each pass
-   the residuals of sts_residuals are reduced on the device and read back,
-   and loop 2 stops at the first pass with
+   maximal residuals are checked after every iteration): after each pass the
+   residuals of sts_residuals are reduced on the device, and loop 2 stops at
+   the first pass with
      max(max|du|, max|dv|, max|dT|, max|dp| / p_in) <= tol,
    or after max_inner passes, or at a non-finite value (sts_residuals then
-   returns STS_ENONFINITE).  *n_inner receives the passes taken.  Waits for
-   the stream after every pass; every pass is the residual-producing
-   variant.  STS_EINVAL for dt <= 0, max_inner < 1, tol < 0 or not finite,
-   unknown scheme bits, NULL n_inner (state unchanged). */
+   returns STS_ENONFINITE).  *n_inner receives the passes taken.  Every pass
+   is the residual-producing variant.  The decision is taken on the device:
+   passes queued after the converged one return without work, and the host
+   waits for the stream only every second pass and once at the end (the
+   call returns after the step is complete).  STS_EINVAL for dt <= 0,
+   max_inner < 1, tol < 0 or not finite, unknown scheme bits, NULL n_inner
+   (state unchanged). */
 sts_status sts_step_tol(sts_ctx *ctx, double dt, int max_inner, double tol, int scheme,
                         int *n_inner);
 

@@ -71,7 +71,7 @@ Sizes make_sizes(int nx, int ny, const Layout &L) {
                      256) +
             align_up(tiles, 256);
   S.partials = align_up(sizeof(double) * NRES * (tiles + RES_BLOCKS), 256);
-  S.res = 256;
+  S.res = 256;  // NRES doubles, then the loop-2 control block at RES_CTL
   S.total = S.state + S.consts + S.mask + S.small + S.partials + S.res;
   return S;
 }
@@ -92,8 +92,9 @@ struct sts_ctx {
   int cur;
   Consts C;
   Resid X;
-  double *dres;
-  double *hres;  // pinned
+  double *dres;   // NRES residuals; at RES_CTL the loop-2 control block
+  double *hres;   // pinned: NRES residuals; at RES_CTL host copies of it
+  hipEvent_t l2ev[2] = {nullptr, nullptr};
   bool stepped;
   int last_scheme;
   // host copies of the boundary data
@@ -423,6 +424,8 @@ void release(sts_ctx *c) {
   if (c->base && c->own_mem) (void)hipFree(c->base);
   if (c->hres) (void)hipHostFree(c->hres);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->l2ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -516,6 +519,12 @@ extern "C" sts_status sts_create(const sts_grid *grid, const sts_obstacles *obst
     return fail(STS_ENOMEM, "pinned host allocation failed");
   }
   memset(c->hres, 0, 256);
+  for (hipEvent_t &e : c->l2ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      release(c);
+      return fail(STS_ENOMEM, "event creation failed");
+    }
   if ((s = build(c, bc)) != STS_OK || (s = initial_state(c)) != STS_OK) {
     std::string msg = g_err;
     release(c);
@@ -579,9 +588,19 @@ extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
   return STS_OK;
 }
 
-// Loop 2 with its convergence test: every pass produces its residuals (the
-// last-pass kernel variant), which are reduced and read back before the next
-// pass is launched, as the paper's GPU algorithm does (Sec. 5).
+// Loop 2 with its convergence test.  Every pass produces its increment
+// maxima (the last-pass kernel variant); one small reduction over its tile
+// rows takes the convergence decision on the device (a flag and a pass count,
+// Loop2), and once the flag is set the passes and reductions still queued
+// return at once.  The continuity residual is reduced once, for the last
+// pass run.  The host launches
+// passes in groups of L2_GROUP, copies the flag back after each group and
+// waits only for the group before the one just queued, so the device never
+// runs dry; at most two groups of empty launches follow the converged pass.
+// The paper's GPU algorithm reads the residuals back after every pass
+// (Sec. 5); the passes taken and the state reached are the same.
+constexpr int L2_GROUP = 2;
+
 extern "C" sts_status sts_step_tol(sts_ctx *c, double dt, int max_inner, double tol, int scheme,
                                    int *n_inner) {
   if (!c || !n_inner) return fail(STS_EINVAL, "NULL argument");
@@ -592,24 +611,45 @@ extern "C" sts_status sts_step_tol(sts_ctx *c, double dt, int max_inner, double 
   c->P.dt = dt;
   c->P.idt = 1.0 / dt;
   launch_prologue(c->P, c->st[c->cur], c->C, scheme, c->stream);
+  int *ctl = (int *)(c->dres + RES_CTL);
+  int *hctl = (int *)(c->hres + RES_CTL);  // [3][2]: two group slots, the final copy
+  launch_loop2_reset(ctl, c->stream);
   HIPCHK(hipGetLastError());
-  int k = 0;
+  Resid X = c->X;
+  X.stop = ctl;
+  Loop2 L{ctl, tol, c->p_in, 0};
+  const int cur0 = c->cur;
   c->stepped = true;
   c->last_scheme = scheme;
-  while (k < max_inner) {
-    launch_pass(c->P, c->st[c->cur], c->st[c->cur ^ 1], c->C, scheme, &c->X, nullptr, c->stream);
-    c->cur ^= 1;
-    k++;
-    launch_residual(c->P, c->st[c->cur], c->C, c->X, c->dres, c->stream);
+  int slot = 0, waiting = -1;
+  for (int k = 0; k < max_inner;) {
+    for (const int e = std::min(k + L2_GROUP, max_inner); k < e; k++) {
+      const int a = cur0 ^ (k & 1);
+      launch_pass(c->P, c->st[a], c->st[a ^ 1], c->C, scheme, &X, nullptr, c->stream);
+      L.k = k + 1;
+      launch_loop2_check(c->P, X, c->dres, L, c->stream);
+    }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(c->hres, c->dres, NRES * sizeof(double), hipMemcpyDeviceToHost,
+    if (k == max_inner) break;
+    HIPCHK(hipMemcpyAsync(hctl + 2 * slot, ctl, 2 * sizeof(int), hipMemcpyDeviceToHost,
                           c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    const double *r = c->hres;
-    if (r[6] != 0.0) break;  // non-finite: reported by sts_residuals
-    const double crit = std::max(std::max(r[0], r[1]), std::max(r[3], r[2] / c->p_in));
-    if (crit <= tol) break;
+    HIPCHK(hipEventRecord(c->l2ev[slot], c->stream));
+    if (waiting >= 0) {
+      HIPCHK(hipEventSynchronize(c->l2ev[waiting]));
+      if (hctl[2 * waiting]) break;
+    }
+    waiting = slot;
+    slot ^= 1;
   }
+  launch_loop2_final(c->P, c->st[cur0], c->st[cur0 ^ 1], c->C, c->X, c->dres, ctl, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(hctl + 4, ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(c->hres, c->dres, NRES * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const int k = hctl[5];
+  if (k < 1 || k > max_inner) return fail(STS_EDEVICE, "loop 2 control block reads %d passes", k);
+  c->cur = cur0 ^ (k & 1);
   *n_inner = k;
   return STS_OK;
 }

@@ -60,14 +60,29 @@ struct Params {
 // residual partial per block: max|du|, max|dv|, max|dp|, max|dT|, max|R|,
 // sum R, non-finite count
 constexpr int NRES = 8;
+// offset (in doubles) of the loop-2 control block in the residual buffer
+constexpr int RES_CTL = 16;
 constexpr int RES_BLOCKS = 2048;  // blocks of the continuity-residual kernel
 
 // Outputs of the last pass of a step used by the residual reduction: the
 // face mass fluxes rho^u u dy (u-face layout) and rho^v v dx (v-face layout)
-// of the new velocities, and one row of NRES partials per tile.
+// of the new velocities, and one row of NRES partials per tile.  stop: NULL,
+// or the device flag of a loop 2 run to convergence (Loop2); once it is set,
+// the residual-producing pass and the reduction kernels return at once.
 struct Resid {
   double *gu, *gv;
   double *partials;  // [tiles + RES_BLOCKS][NRES]
+  const int *stop;
+};
+
+// Device-side convergence control of loop 2: ctl[0] = stop flag, ctl[1] =
+// passes run.  The reduction after pass k writes ctl[1] = k and sets the flag
+// when max(max|du|, max|dv|, max|dT|, max|dp| / p_in) <= tol or some value is
+// non-finite (some pass's per-tile non-finite count is not zero).
+struct Loop2 {
+  int *ctl;
+  double tol, p_in;
+  int k;
 };
 
 // Intermediates of one pass (face densities, u-hat, d^u, v-hat, d^v, new p,
@@ -92,6 +107,14 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
                  const Resid *last, const Inter *inter, hipStream_t st);
 void launch_residual(const Params &P, State n, Consts C, Resid R, double *out,
                      hipStream_t st);
+// loop 2 run to convergence: clear the control block; after pass L.k, fold
+// the pass's per-tile rows and take the decision (returns at once once the
+// flag is set); at the end, the residuals of the last pass run, whose state
+// is `even` or `odd` as ctl[1] is
+void launch_loop2_reset(int *ctl, hipStream_t st);
+void launch_loop2_check(const Params &P, Resid R, double *out, const Loop2 &L, hipStream_t st);
+void launch_loop2_final(const Params &P, State even, State odd, Consts C, Resid R, double *out,
+                        const int *ctl, hipStream_t st);
 
 // adjoint of the explicit step (reverse of one pass; reverse of the prologue)
 void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, State lo,

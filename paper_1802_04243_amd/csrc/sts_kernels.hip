@@ -1335,6 +1335,7 @@ template <int NTH, bool IM, bool TV, bool RS, bool MX, bool IN, bool SJ>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_pass(
     const Params P, const State o, const State n, const Consts C, const Resid X, const Inter I) {
   __shared__ Lds s;
+  if (RS && X.stop && *X.stop) return;  // loop 2 has converged
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
   double c[Items<NTH>::rounds], cp;
@@ -1557,12 +1558,17 @@ constexpr int RB = 256;  // threads per residual block
 
 // Each block also folds a share of the per-tile rows of the last pass, so
 // that k_finalize reads only one row per block.
+// PICK: the state is n or n1 as the pass count kc of a loop 2 run to
+// convergence is even or odd (the buffer its last pass wrote).
+template <bool PICK>
 __global__ __launch_bounds__(RB) void k_continuity(const Params P,
-                                                   const State n,
+                                                   State n, const State n1,
                                                    const Consts C,
                                                    const Resid X,
-                                                   int ntile, double *rows) {
+                                                   int ntile, double *rows,
+                                                   const int *kc) {
   __shared__ double red[RB / 64][NRES];
+  if (PICK && (*kc & 1)) n = n1;
   double rm = 0.0, sm = 0.0, bad = 0.0;
   double inc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = blockIdx.x * RB + threadIdx.x; b < ntile; b += gridDim.x * RB) {
@@ -1588,11 +1594,15 @@ __global__ __launch_bounds__(RB) void k_continuity(const Params P,
   block_partials<RB>(red, v, rows + (long)blockIdx.x * NRES);
 }
 
-// merge the rows of k_continuity
+// merge rows of partials (those of k_continuity, or the per-tile rows of a
+// pass); with a loop-2 control block, also take the convergence decision of
+// pass L.k (Sec. 3.1: loop 2 ends when the iterate no longer changes beyond
+// the tolerance)
 constexpr int FB = 1024;
 __global__ __launch_bounds__(FB) void k_finalize(const double *rows, int nrows,
-                                                 double *out) {
+                                                 double *out, const Loop2 L) {
   __shared__ double red[FB / 64][NRES];
+  if (L.ctl && L.ctl[0]) return;
   double v[NRES] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nrows; b += FB) {
     const double *q = rows + (long)b * NRES;
@@ -1601,6 +1611,15 @@ __global__ __launch_bounds__(FB) void k_finalize(const double *rows, int nrows,
     v[6] += q[6];
   }
   block_partials<FB>(red, v, out);
+  if (L.ctl && threadIdx.x == 0) {
+    const double crit = fmax(fmax(out[0], out[1]), fmax(out[3], out[2] / L.p_in));
+    L.ctl[1] = L.k;
+    if (out[6] != 0.0 || crit <= L.tol) L.ctl[0] = 1;
+  }
+}
+
+__global__ void k_loop2_reset(int *ctl) {
+  if (threadIdx.x < 2) ctl[threadIdx.x] = 0;
 }
 
 }  // namespace
@@ -1623,7 +1642,7 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
                  const Resid *last, const Inter *inter, hipStream_t st) {
   const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0, mx = (scheme & 4) != 0;
   dim3 g(ntiles(P));
-  const Resid X = last ? *last : Resid{nullptr, nullptr, nullptr};
+  const Resid X = last ? *last : Resid{nullptr, nullptr, nullptr, nullptr};
   const Inter I = inter ? *inter : Inter{};
   // intermediates are stored only by the explicit scheme's plain passes (the
   // adjoint's recompute); the caller guarantees !im && !last with inter
@@ -1660,8 +1679,31 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
 void launch_residual(const Params &P, State n, Consts C, Resid X, double *out,
                      hipStream_t st) {
   double *rows = X.partials + (long)ntiles(P) * NRES;
-  hipLaunchKernelGGL(k_continuity, dim3(RES_BLOCKS), dim3(RB), 0, st, P, n, C, X, ntiles(P), rows);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, rows, RES_BLOCKS, out);
+  const Loop2 L{nullptr, 0.0, 1.0, 0};
+  hipLaunchKernelGGL(k_continuity<false>, dim3(RES_BLOCKS), dim3(RB), 0, st, P, n, n, C, X,
+                     ntiles(P), rows, nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, rows, RES_BLOCKS, out, L);
+}
+
+void launch_loop2_reset(int *ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_loop2_reset, dim3(1), dim3(64), 0, st, ctl);
+}
+
+void launch_loop2_check(const Params &P, Resid X, double *out, const Loop2 &L,
+                        hipStream_t st) {
+  // the per-tile rows of the pass hold the increment maxima and the
+  // non-finite count; the continuity sum is not needed for the decision
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, X.partials, ntiles(P), out, L);
+}
+
+void launch_loop2_final(const Params &P, State even, State odd, Consts C, Resid X, double *out,
+                        const int *ctl, hipStream_t st) {
+  double *rows = X.partials + (long)ntiles(P) * NRES;
+  const Loop2 L{nullptr, 0.0, 1.0, 0};
+  X.stop = nullptr;
+  hipLaunchKernelGGL(k_continuity<true>, dim3(RES_BLOCKS), dim3(RB), 0, st, P, even, odd, C, X,
+                     ntiles(P), rows, ctl + 1);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, rows, RES_BLOCKS, out, L);
 }
 
 }  // namespace sts

@@ -243,6 +243,63 @@ def test_tolerance_exit_matches_oracle(sts_mod, oracle_lib, name, scheme):
     g.close()
 
 
+def test_tolerance_exit_stops_at_every_position(sts_mod, oracle_lib):
+    # the convergence decision is taken on the device and the host polls it
+    # every second pass: stop loop 2 at each pass position (tolerance = the
+    # criterion after m passes, known from fixed-count oracle steps) and at
+    # odd and even pass limits; passes taken, fields and residuals as the
+    # oracle's
+    p, run = W.workload("channel_120x24")
+    scheme, dt = W.EXPLICIT | W.TVD, run["dt"]
+    o = oracle_lib.Oracle(p)
+    o.set_fields(*W.initial_fields(p, 4))
+    for _ in range(3):
+        o.step(dt, 20, scheme)
+    state = o.fields()
+    crit = []
+    for m in range(1, 8):
+        q = oracle_lib.Oracle(p)
+        q.set_fields(*state)
+        q.step(dt, m, scheme)
+        r = q.residuals()
+        crit.append(max(r[0], r[1], r[3], r[2] / p.p_in))
+    print("criterion after 1..7 passes " + " ".join(f"{c:.3e}" for c in crit), flush=True)
+    cases = [(9, c) for c in crit] + [(mi, 0.0) for mi in (1, 2, 3, 5)]
+    seen = set()
+    for max_inner, tol in cases:
+        q = oracle_lib.Oracle(p)
+        q.set_fields(*state)
+        g = sts_mod.Solver(p)
+        g.set_fields(*state)
+        no = q.step_tol(dt, max_inner, tol, scheme)
+        ng = g.step_tol(dt, max_inner, tol, scheme)
+        print(f"case stop position max_inner {max_inner} tol {tol:.3e}: gpu {ng} oracle {no}",
+              flush=True)
+        assert ng == no
+        seen.add(ng)
+        compare(g, q, f"stop after {ng}")
+        # the context goes on from the right buffer
+        g.step(dt, 3, scheme)
+        q.step(dt, 3, scheme)
+        compare(g, q, f"step after a stop after {ng}")
+        g.close()
+    assert seen >= {1, 2, 3, 4, 5, 6}, seen
+
+
+def test_tolerance_exit_stops_at_non_finite(sts_mod):
+    p, run = W.workload("channel_120x24")
+    u, v, pr, T = W.initial_fields(p, 4)
+    T = T.copy()
+    T[7, 50] = np.nan
+    g = sts_mod.Solver(p)
+    g.set_fields(u, v, pr, T)
+    assert g.step_tol(run["dt"], 9, 1e-8, W.EXPLICIT | W.TVD) == 1
+    with pytest.raises(sts_mod.StsError) as e:
+        g.residuals()
+    assert e.value.code == sts_mod.STS_ENONFINITE
+    g.close()
+
+
 def test_tolerance_exit_zero_tol_is_fixed_count(sts_mod):
     p, run = W.workload("channel_120x24")
     f0 = W.initial_fields(p, 3)

@@ -6,9 +6,10 @@ asserted: normwise relative difference <= 1e-10 per field.  Cases: a small
 channel with slip-jump walls moving with the flow and a slip-jump square
 (all four schemes, and the mixed-precision form within its FP32 tolerance);
 a ragged non-uniform grid mixing wall types, heated walls and a body force;
-a periodic channel; and one step of every scheme on the paper's 4032x200
-mesh (Kn = 0.001, Ma 2.43, particle frame) from a GPU-advanced state, in
-the launch configuration the benchmark times.  Plus the argument checks of
+a periodic channel; one step of every scheme on the paper's 4032x200 mesh
+(Kn = 0.001, Ma 2.43, particle frame) from a GPU-advanced state, in the
+launch configuration the benchmark times; and the whole 200-step run of
+that workload, whose increments must stay bounded.  Plus the argument checks of
 the new fields and the calls that reject slip-jump surfaces.
 """
 from __future__ import annotations
@@ -91,6 +92,26 @@ def test_paper_mesh_4032x200_step_from_gpu_state(sts_mod, oracle_lib, name, sche
     o.step(run["dt"], run["inner"], scheme)
     compare(g, o, f"paper_4032x200/{name}")
     g.close()
+
+
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_paper_mesh_4032x200_run_stays_bounded(sts_mod, name, scheme):
+    # the workload as the benchmark runs it (200 steps of 10 passes at its
+    # time step): loop 2's last-pass increments stay small and finite in
+    # every scheme (at twice this time step the explicit TVD run diverges)
+    p, run = W.workload("paper_4032x200")
+    print(f"case paper_4032x200/{name}: {run['steps']} steps", flush=True)
+    g = sts_mod.Solver(p)
+    g.set_fields(*W.initial_fields(p, run["seed"]))
+    worst = 0.0
+    for s in range(run["steps"]):
+        g.step(run["dt"], run["inner"], scheme)
+        if s % 20 == 19:
+            r = g.residuals()   # raises on a non-finite value
+            worst = max(worst, r[0], r[1], r[3], r[2] / p.p_in)
+    print(f"largest last-pass increment {worst:.2e}", flush=True)
+    g.close()
+    assert worst < 2e-5, worst
 
 
 def test_slip_jump_argument_checks(sts_mod):
