@@ -221,11 +221,17 @@ sts_status sts_state_load(sts_ctx *ctx, int slot);
    sts_adjoint_begin: allocate the buffers for n_inner passes per step
    (library-owned, 12 n_inner + 23 field arrays: the iterates and the
    intermediates of every pass of one step, the adjoint temporaries and
-   states), set lambda and the wall-temperature gradients to zero.  The
-   adjoint supports inlet/outlet channels without slip-jump surfaces
-   (STS_EINVAL otherwise).
+   states), set lambda and the wall-temperature gradients to zero.  Every
+   wall and obstacle type is supported, velocity-slip / temperature-jump
+   surfaces (eqs pl38, pl39) included: their conductances and slip
+   velocities are differentiated in the node's Gamma and rho.
    sts_adjoint_seed_drag: lambda += w dD/d(current state); call it with the
-   current state at level n before the adjoint of step n.
+   current state at level n before the adjoint of step n.  The drag is that
+   of no-slip obstacle surfaces (STS_EINVAL for slip-jump obstacles).
+   sts_adjoint_seed: lambda += the host arrays w_u, w_v, w_p, w_T (layouts
+   of sts_fields; NULL skips a field), i.e. the derivative of the loss
+   term sum w . state of the current level; waits for the stream.
+   STS_EINVAL for a non-finite entry (lambda unchanged).
    sts_adjoint_step: the current state must be level n-1 and lambda the
    derivative with respect to level n; recomputes the step (same dt,
    n_inner and scheme as the forward step) and replaces lambda by the
@@ -242,6 +248,8 @@ sts_status sts_state_load(sts_ctx *ctx, int slot);
    the field layouts of sts_fields. */
 sts_status sts_adjoint_begin(sts_ctx *ctx, int n_inner);
 sts_status sts_adjoint_seed_drag(sts_ctx *ctx, double w);
+sts_status sts_adjoint_seed(sts_ctx *ctx, const double *w_u, const double *w_v,
+                            const double *w_p, const double *w_T);
 sts_status sts_adjoint_step(sts_ctx *ctx, double dt, int n_inner, int scheme);
 sts_status sts_adjoint_read(sts_ctx *ctx, double *g_uin, double *g_Tw0, double *g_Tw1,
                             double *lambda_u, double *lambda_v, double *lambda_p,

@@ -137,6 +137,25 @@ __device__ __forceinline__ double hmean2_d(double a, double b, double &da, doubl
   db = 2.0 * a * a / (s * s);
   return 2.0 * a * b / s;
 }
+// velocity-slip / temperature-jump surface (eqs pl38, pl39): the conductance
+// K g / (d/2 + k/r) of the half cell to the surface, with node Gamma g and
+// node density r, and its partials in g and r
+__device__ __forceinline__ double jwall_d(double K, double g, double d, double k, double r,
+                                          double &dg, double &dr) {
+  const double w = 1.0 / (0.5 * d + k / r);
+  dg = K * w;
+  dr = K * g * w * w * k / (r * r);
+  return K * g * w;
+}
+// the gas velocity at such a surface, (u_w d/2 + zeta u_P) / (d/2 + zeta) with
+// zeta = k / r, and its partials in u_P and r
+__device__ __forceinline__ double slip_d(double uw, double uP, double d, double k, double r,
+                                         double &du, double &dr) {
+  const double h = 0.5 * d, z = k / r, den = h + z;
+  du = z / den;
+  dr = -(h * (uP - uw) / (den * den)) * z / r;
+  return (uw * h + z * uP) / den;
+}
 
 // Gamma at the corner (x^f_i, y^f_j) and its adjoint
 template <class Src>
@@ -426,10 +445,14 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   const double dxi = gx(P, 0, i), dyj = gy(P, 0, j), dV = dxi * dyj, dt = P.dt;
   const double idx = gx(P, 1, i), idy = gy(P, 1, j);
   const double gP = gam(P, cc, i, j), TP = at(o.T, P, i, j);
+  const double rP = rho(P, cc, i, j);
+  const bool jo = P.otype == 2;  // slip-jump obstacle surfaces
   // conductances and neighbour values (the forward's rules), with the
-  // partials of each conductance in Gamma_P, Gamma_nb and the wall sqrt(T)
+  // partials of each conductance in Gamma_P, Gamma_nb, the wall sqrt(T) and
+  // (slip-jump surfaces) rho_P
   double nW, nE, nS, nN, DW, DE, DS, DN;
   double dWP = 0, dWn = 0, dEP = 0, dEn = 0, dSP = 0, dSn = 0, dNP = 0, dNn = 0, dSw = 0, dNw = 0;
+  double dWr = 0, dEr = 0, dSr = 0, dNr = 0;
   double x;
   if (i == 0) {
     nW = P.T_in[j];
@@ -438,7 +461,9 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
     dWP *= K;
   } else {
     nW = at(o.T, P, i - 1, j);
-    if (!fl(P, i - 1, j)) {
+    if (!fl(P, i - 1, j) && jo) {
+      DW = jwall_d(P.C1 * dyj, gP, dxi, P.kt, rP, dWP, dWr);
+    } else if (!fl(P, i - 1, j)) {
       const double K = P.C1 * dyj * (2.0 * idx);
       DW = K * hmean2_d(gP, P.sq_obsT, dWP, x);
       dWP *= K;
@@ -454,7 +479,9 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
     DE = 0.0;
   } else {
     nE = at(o.T, P, i + 1, j);
-    if (!fl(P, i + 1, j)) {
+    if (!fl(P, i + 1, j) && jo) {
+      DE = jwall_d(P.C1 * dyj, gP, dxi, P.kt, rP, dEP, dEr);
+    } else if (!fl(P, i + 1, j)) {
       const double K = P.C1 * dyj * (2.0 * idx);
       DE = K * hmean2_d(gP, P.sq_obsT, dEP, x);
       dEP *= K;
@@ -472,13 +499,18 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
       DS = K * hmean2_d(gP, P.sq_Tw0[i], dSP, dSw);
       dSP *= K;
       dSw *= K;
+    } else if (P.wtype0 == 2) {
+      nS = P.Tw0[i];
+      DS = jwall_d(P.C1 * dxi, gP, dyj, P.kt, rP, dSP, dSr);
     } else {
       nS = TP;
       DS = 0.0;
     }
   } else {
     nS = at(o.T, P, i, j - 1);
-    if (!fl(P, i, j - 1)) {
+    if (!fl(P, i, j - 1) && jo) {
+      DS = jwall_d(P.C1 * dxi, gP, dyj, P.kt, rP, dSP, dSr);
+    } else if (!fl(P, i, j - 1)) {
       const double K = P.C1 * dxi * (2.0 * idy);
       DS = K * hmean2_d(gP, P.sq_obsT, dSP, x);
       dSP *= K;
@@ -496,13 +528,18 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
       DN = K * hmean2_d(gP, P.sq_Tw1[i], dNP, dNw);
       dNP *= K;
       dNw *= K;
+    } else if (P.wtype1 == 2) {
+      nN = P.Tw1[i];
+      DN = jwall_d(P.C1 * dxi, gP, dyj, P.kt, rP, dNP, dNr);
     } else {
       nN = TP;
       DN = 0.0;
     }
   } else {
     nN = at(o.T, P, i, j + 1);
-    if (!fl(P, i, j + 1)) {
+    if (!fl(P, i, j + 1) && jo) {
+      DN = jwall_d(P.C1 * dxi, gP, dyj, P.kt, rP, dNP, dNr);
+    } else if (!fl(P, i, j + 1)) {
       const double K = P.C1 * dxi * (2.0 * idy);
       DN = K * hmean2_d(gP, P.sq_obsT, dNP, x);
       dNP *= K;
@@ -513,7 +550,6 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
       dNn *= K;
     }
   }
-  const double rP = rho(P, cc, i, j);
   const double a0 = dt * (DW + DE + DS + DN) + rP * dV;
   const double tn = I.tn[k];
   // T = (dt (sum D n + Sc) + C_T) / a0
@@ -523,6 +559,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   const double lDW = lnum * dt * nW + la0 * dt, lDE = lnum * dt * nE + la0 * dt;
   const double lDS = lnum * dt * nS + la0 * dt, lDN = lnum * dt * nN + la0 * dt;
   double lgP = lDW * dWP + lDE * dEP + lDS * dSP + lDN * dNP;
+  double lrw = lDW * dWr + lDE * dEr + lDS * dSr + lDN * dNr;  // more of rho_P's adjoint
   if (i > 0) {
     sk.add(0, P, i - 1, j, lnum * dt * DW);
     if (dWn != 0.0) sk.add(1, P, i - 1, j, lDW * dWn);
@@ -535,6 +572,8 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   if (j == 0) {
     if (P.wtype0 == 0) {
       unsafeAtomicAdd(gtw0 + i, lnum * dt * DS + lDS * dSw / (2.0 * P.sq_Tw0[i]));
+    } else if (P.wtype0 == 2) {
+      unsafeAtomicAdd(gtw0 + i, lnum * dt * DS);
     } else {
       sk.add(0, P, i, j, lnum * dt * DS);
     }
@@ -545,6 +584,8 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   if (j == P.ny - 1) {
     if (P.wtype1 == 0) {
       unsafeAtomicAdd(gtw1 + i, lnum * dt * DN + lDN * dNw / (2.0 * P.sq_Tw1[i]));
+    } else if (P.wtype1 == 2) {
+      unsafeAtomicAdd(gtw1 + i, lnum * dt * DN);
     } else {
       sk.add(0, P, i, j, lnum * dt * DN);
     }
@@ -558,30 +599,39 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   const double V0 = at(o.v, P, i, j), V1 = at(o.v, P, i, j + 1);
   const double vc = 0.5 * (V0 + V1), uc = 0.5 * (U0 + U1);
   double vE, vW, uN, uS;
-  int cvE = 0, cvW = 0, cuN = 0, cuS = 0;  // 0 constant, 1 vc/uc, 2 interpolated
+  // 0 constant, 1 vc/uc, 2 interpolated, 3 slip velocity (partials s* in
+  // vc/uc and r* in rho_P)
+  int cvE = 0, cvW = 0, cuN = 0, cuS = 0;
+  double svE = 0, svW = 0, suN = 0, suS = 0, rvE = 0, rvW = 0, ruN = 0, ruS = 0;
   if (i == P.nx - 1) { vE = vc; cvE = 1; }
+  else if (!fl(P, i + 1, j) && jo) { vE = slip_d(0.0, vc, dxi, P.kz, rP, svE, rvE); cvE = 3; }
   else if (!fl(P, i + 1, j)) vE = 0.0;
   else {
     vE = gx(P, 4, i + 1) * vc + gx(P, 5, i + 1) * (0.5 * (at(o.v, P, i + 1, j) + at(o.v, P, i + 1, j + 1)));
     cvE = 2;
   }
-  if (i == 0 || !fl(P, i - 1, j)) vW = 0.0;
+  if (i > 0 && !fl(P, i - 1, j) && jo) { vW = slip_d(0.0, vc, dxi, P.kz, rP, svW, rvW); cvW = 3; }
+  else if (i == 0 || !fl(P, i - 1, j)) vW = 0.0;
   else {
     vW = gx(P, 4, i) * (0.5 * (at(o.v, P, i - 1, j) + at(o.v, P, i - 1, j + 1))) + gx(P, 5, i) * vc;
     cvW = 2;
   }
   if (j == P.ny - 1) {
     if (P.wtype1 == 0) uN = P.wu1;
+    else if (P.wtype1 == 2) { uN = slip_d(P.wu1, uc, dyj, P.kz, rP, suN, ruN); cuN = 3; }
     else { uN = uc; cuN = 1; }
-  } else if (!fl(P, i, j + 1)) uN = 0.0;
+  } else if (!fl(P, i, j + 1) && jo) { uN = slip_d(0.0, uc, dyj, P.kz, rP, suN, ruN); cuN = 3; }
+  else if (!fl(P, i, j + 1)) uN = 0.0;
   else {
     uN = gy(P, 4, j + 1) * uc + gy(P, 5, j + 1) * (0.5 * (at(o.u, P, i, j + 1) + at(o.u, P, i + 1, j + 1)));
     cuN = 2;
   }
   if (j == 0) {
     if (P.wtype0 == 0) uS = P.wu0;
+    else if (P.wtype0 == 2) { uS = slip_d(P.wu0, uc, dyj, P.kz, rP, suS, ruS); cuS = 3; }
     else { uS = uc; cuS = 1; }
-  } else if (!fl(P, i, j - 1)) uS = 0.0;
+  } else if (!fl(P, i, j - 1) && jo) { uS = slip_d(0.0, uc, dyj, P.kz, rP, suS, ruS); cuS = 3; }
+  else if (!fl(P, i, j - 1)) uS = 0.0;
   else {
     uS = gy(P, 4, j) * (0.5 * (at(o.u, P, i, j - 1) + at(o.u, P, i + 1, j - 1))) + gy(P, 5, j) * uc;
     cuS = 2;
@@ -599,6 +649,10 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   double lU0 = -lux * idx, lU1 = lux * idx, lV0 = -lvy * idy, lV1 = lvy * idy;
   const double lvE = lvx * idx, lvW = -lvx * idx, luN = luy * idy, luS = -luy * idy;
   double lvc = 0.0, luc = 0.0;
+  if (cvE == 3) { lvc += lvE * svE; lrw += lvE * rvE; }
+  if (cvW == 3) { lvc += lvW * svW; lrw += lvW * rvW; }
+  if (cuN == 3) { luc += luN * suN; lrw += luN * ruN; }
+  if (cuS == 3) { luc += luS * suS; lrw += luS * ruS; }
   if (cvE == 1) lvc += lvE;
   else if (cvE == 2) {
     lvc += lvE * gx(P, 4, i + 1);
@@ -635,6 +689,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   sk.add(3, P, i, j, lV0);
   sk.add(3, P, i, j + 1, lV1);
   sk.add(1, P, i, j, lgP);
+  if (lrw != 0.0) unsafeAtomicAdd(A.lr + k, lrw);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,17 +709,28 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
   const double uP = at(o.u, P, i, j), uW = at(o.u, P, i - 1, j), uE = at(o.u, P, i + 1, j);
   const double len = 0.5 * (dxl + dxr);
   const double gnode = gx(P, 4, i) * gl + gx(P, 5, i) * gr;
+  // slip surfaces: the node density interpolated like gnode
+  const double rnode = gx(P, 4, i) * rho(P, cc, i - 1, j) + gx(P, 5, i) * rho(P, cc, i, j);
   double uS, uN, DS, DN;
-  int kS, kN;  // 0 wall (constant u), 1 uP, 2 neighbour; D kinds: 0 none, 1 wall, 2 obstacle, 3 corner
+  // kS, kN: 0 wall (constant u), 1 uP, 2 neighbour; D kinds dS, dN: 0 none,
+  // 1 wall, 2 obstacle, 3 corner, 4 slip wall or obstacle (partials jSg,
+  // jNg in gnode and jSr, jNr in rnode)
+  int kS, kN;
   int dS, dN;
+  double jSg = 0, jSr = 0, jNg = 0, jNr = 0;
   if (j == 0) {
     if (P.wtype0 == 0) {
       uS = P.wu0; kS = 0; dS = 1;
       DS = B * 0.5 * (gnode + P.sq_Twu0[i]) * len * (2.0 * idy);
+    } else if (P.wtype0 == 2) {
+      uS = P.wu0; kS = 0; dS = 4;
+      DS = jwall_d(B * len, gnode, dyj, P.kz, rnode, jSg, jSr);
     } else { uS = uP; kS = 1; dS = 0; DS = 0.0; }
   } else {
     uS = at(o.u, P, i, j - 1); kS = 2;
-    if (!fl(P, i - 1, j - 1) && !fl(P, i, j - 1)) {
+    if (!fl(P, i - 1, j - 1) && !fl(P, i, j - 1) && P.otype == 2) {
+      dS = 4; DS = jwall_d(B * len, gnode, dyj, P.kz, rnode, jSg, jSr);
+    } else if (!fl(P, i - 1, j - 1) && !fl(P, i, j - 1)) {
       dS = 2; DS = B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * idy);
     } else {
       dS = 3; DS = B * gamc(P, cc, i, j) * gx(P, 2, i) * gy(P, 3, j);
@@ -674,10 +740,15 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
     if (P.wtype1 == 0) {
       uN = P.wu1; kN = 0; dN = 1;
       DN = B * 0.5 * (gnode + P.sq_Twu1[i]) * len * (2.0 * idy);
+    } else if (P.wtype1 == 2) {
+      uN = P.wu1; kN = 0; dN = 4;
+      DN = jwall_d(B * len, gnode, dyj, P.kz, rnode, jNg, jNr);
     } else { uN = uP; kN = 1; dN = 0; DN = 0.0; }
   } else {
     uN = at(o.u, P, i, j + 1); kN = 2;
-    if (!fl(P, i - 1, j + 1) && !fl(P, i, j + 1)) {
+    if (!fl(P, i - 1, j + 1) && !fl(P, i, j + 1) && P.otype == 2) {
+      dN = 4; DN = jwall_d(B * len, gnode, dyj, P.kz, rnode, jNg, jNr);
+    } else if (!fl(P, i - 1, j + 1) && !fl(P, i, j + 1)) {
       dN = 2; DN = B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * idy);
     } else {
       dN = 3; DN = B * gamc(P, cc, i, j + 1) * gx(P, 2, i) * gy(P, 3, j + 1);
@@ -711,7 +782,7 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
   const double laW = lnum * uW + la0, laE = lnum * uE + la0;
   double lgl = laW * 4.0 / 3.0 * B * dyj * gx(P, 1, i - 1);
   double lgr = laE * 4.0 / 3.0 * B * dyj * gx(P, 1, i);
-  double lgn = 0.0;  // adjoint of gnode
+  double lgn = 0.0, lrn = 0.0;  // adjoints of gnode, rnode
   double lgcS = 0.0, lgcN = 0.0;
   if (dS == 1) {
     const double q = laS * B * 0.5 * len * (2.0 * idy);
@@ -719,18 +790,20 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
     sqtwu_adj(P, P.sq_Twu0, gtw0, i, q);
   } else if (dS == 2) lgn += laS * B * 0.5 * len * (2.0 * idy);
   else if (dS == 3) lgcS += laS * B * gx(P, 2, i) * gy(P, 3, j);
+  else if (dS == 4) { lgn += laS * jSg; lrn += laS * jSr; }
   if (dN == 1) {
     const double q = laN * B * 0.5 * len * (2.0 * idy);
     lgn += q;
     sqtwu_adj(P, P.sq_Twu1, gtw1, i, q);
   } else if (dN == 2) lgn += laN * B * 0.5 * len * (2.0 * idy);
   else if (dN == 3) lgcN += laN * B * gx(P, 2, i) * gy(P, 3, j + 1);
+  else if (dN == 4) { lgn += laN * jNg; lrn += laN * jNr; }
   lgl += lgn * gx(P, 4, i);
   lgr += lgn * gx(P, 5, i);
   // M = (rho_P dxr + rho_W dxl) dy / 2
   const double lM = la0 * P.idt;
-  sk.add(2, P, i, j, lM * dxr * dyj / 2.0);
-  sk.add(2, P, i - 1, j, lM * dxl * dyj / 2.0);
+  sk.add(2, P, i, j, lM * dxr * dyj / 2.0 + lrn * gx(P, 5, i));
+  sk.add(2, P, i - 1, j, lM * dxl * dyj / 2.0 + lrn * gx(P, 4, i));
   // cross-diffusion X
   const double lX = lnum * B;
   lgcN += lX * (v11 - v01);
@@ -767,14 +840,23 @@ __device__ void vhat_item(const Params &P, const State o, const Cache cc, const 
   const double len = 0.5 * (dys + dyn);
   const double gnode = gy(P, 4, j) * gs + gy(P, 5, j) * gn;
   const double gcW = gamc(P, cc, i, j), gcE = gamc(P, cc, i + 1, j);
+  const double rnode = gy(P, 4, j) * rho(P, cc, i, j - 1) + gy(P, 5, j) * rho(P, cc, i, j);
   double DW, DE;
-  int dW, dE;  // 1 inlet, 2 obstacle, 3 corner; 0 none
+  // 1 inlet, 2 obstacle, 3 corner, 4 slip obstacle (partials j*g in gnode,
+  // j*r in rnode); 0 none
+  int dW, dE;
+  double jWg = 0, jWr = 0, jEg = 0, jEr = 0;
+  const bool so = P.otype == 2;
   if (inl) { dW = 1; DW = B * 0.5 * (gnode + gcW) * len * (2.0 * idx); }
-  else if (!fl(P, i - 1, j - 1) && !fl(P, i - 1, j)) {
+  else if (!fl(P, i - 1, j - 1) && !fl(P, i - 1, j) && so) {
+    dW = 4; DW = jwall_d(B * len, gnode, dxi, P.kz, rnode, jWg, jWr);
+  } else if (!fl(P, i - 1, j - 1) && !fl(P, i - 1, j)) {
     dW = 2; DW = B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * idx);
   } else { dW = 3; DW = B * gcW * gy(P, 2, j) * gx(P, 3, i); }
   if (outl) { dE = 0; DE = 0.0; }
-  else if (!fl(P, i + 1, j - 1) && !fl(P, i + 1, j)) {
+  else if (!fl(P, i + 1, j - 1) && !fl(P, i + 1, j) && so) {
+    dE = 4; DE = jwall_d(B * len, gnode, dxi, P.kz, rnode, jEg, jEr);
+  } else if (!fl(P, i + 1, j - 1) && !fl(P, i + 1, j)) {
     dE = 2; DE = B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * idx);
   } else { dE = 3; DE = B * gcE * gy(P, 2, j) * gx(P, 3, i + 1); }
   const double DS = B * gs * dxi * gy(P, 1, j - 1), DN = B * gn * dxi * gy(P, 1, j);
@@ -799,20 +881,22 @@ __device__ void vhat_item(const Params &P, const State o, const Cache cc, const 
   const double laS = lnum * vS + la0, laN = lnum * vN + la0;
   double lgs = laS * 4.0 / 3.0 * B * dxi * gy(P, 1, j - 1);
   double lgn_ = laN * 4.0 / 3.0 * B * dxi * gy(P, 1, j);
-  double lgnode = 0.0, lgcW = 0.0, lgcE = 0.0;
+  double lgnode = 0.0, lgcW = 0.0, lgcE = 0.0, lrn = 0.0;
   if (dW == 1) {
     const double q = laW * B * 0.5 * len * (2.0 * idx);
     lgnode += q;
     lgcW += q;
   } else if (dW == 2) lgnode += laW * B * 0.5 * len * (2.0 * idx);
-  else lgcW += laW * B * gy(P, 2, j) * gx(P, 3, i);
+  else if (dW == 3) lgcW += laW * B * gy(P, 2, j) * gx(P, 3, i);
+  else { lgnode += laW * jWg; lrn += laW * jWr; }
   if (dE == 2) lgnode += laE * B * 0.5 * len * (2.0 * idx);
   else if (dE == 3) lgcE += laE * B * gy(P, 2, j) * gx(P, 3, i + 1);
+  else if (dE == 4) { lgnode += laE * jEg; lrn += laE * jEr; }
   lgs += lgnode * gy(P, 4, j);
   lgn_ += lgnode * gy(P, 5, j);
   const double lM = la0 * P.idt;
-  sk.add(2, P, i, j, lM * dyn * dxi / 2.0);
-  sk.add(2, P, i, j - 1, lM * dys * dxi / 2.0);
+  sk.add(2, P, i, j, lM * dyn * dxi / 2.0 + lrn * gy(P, 5, j));
+  sk.add(2, P, i, j - 1, lM * dys * dxi / 2.0 + lrn * gy(P, 4, j));
   const double lX = lnum * B;
   lgcE += lX * (u11 - u10);
   lgcW += -lX * (u01 - u00);

@@ -829,7 +829,6 @@ extern "C" sts_status sts_state_load(sts_ctx *c, int slot) {
 extern "C" sts_status sts_adjoint_begin(sts_ctx *c, int n_inner) {
   if (!c) return fail(STS_EINVAL, "ctx is NULL");
   if (c->per) return fail(STS_EINVAL, "the adjoint supports inlet/outlet channels only");
-  if (c->slip_jump) return fail(STS_EINVAL, "the adjoint supports no slip-jump surfaces");
   if (n_inner < 1 || n_inner > 10000) return fail(STS_EINVAL, "n_inner must be in [1, 10000]");
   HIPCHK(hipStreamSynchronize(c->stream));
   if (c->adj_K != n_inner) {
@@ -884,8 +883,43 @@ extern "C" sts_status sts_adjoint_seed_drag(sts_ctx *c, double w) {
   if (!c) return fail(STS_EINVAL, "ctx is NULL");
   if (!c->adj_K) return fail(STS_ESTATE, "sts_adjoint_begin has not been called");
   if (!isfinite(w)) return fail(STS_EINVAL, "weight must be finite");
+  if (c->otype != STS_WALL_NOSLIP_ISOTHERMAL)
+    return fail(STS_EINVAL, "the drag is defined for no-slip obstacle surfaces");
   launch_drag_seed(c->P, c->st[c->cur], c->lam[c->lcur], w, c->stream);
   HIPCHK(hipGetLastError());
+  return STS_OK;
+}
+
+extern "C" sts_status sts_adjoint_seed(sts_ctx *c, const double *wu, const double *wv,
+                                       const double *wp, const double *wT) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (!c->adj_K) return fail(STS_ESTATE, "sts_adjoint_begin has not been called");
+  const int nx = c->nx, ny = c->ny;
+  const long Pt = c->L.pitch;
+  const State &l = c->lam[c->lcur];
+  struct Part {
+    double *dev;
+    const double *w;
+    int width, height;
+  };
+  const Part parts[4] = {{l.u, wu, nx + 1, ny}, {l.v, wv, nx, ny + 1}, {l.p, wp, nx, ny},
+                         {l.T, wT, nx, ny}};
+  for (const Part &q : parts)
+    if (q.w)
+      for (size_t m = 0; m < (size_t)q.width * q.height; m++)
+        if (!isfinite(q.w[m])) return fail(STS_EINVAL, "non-finite seed value");
+  std::vector<double> h;
+  for (const Part &q : parts) {
+    if (!q.w) continue;
+    h.resize((size_t)q.width * q.height);
+    HIPCHK(hipMemcpy2DAsync(h.data(), q.width * 8, q.dev + c->L.off, Pt * 8, q.width * 8, q.height,
+                            hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t m = 0; m < h.size(); m++) h[m] += q.w[m];
+    HIPCHK(hipMemcpy2DAsync(q.dev + c->L.off, Pt * 8, h.data(), q.width * 8, q.width * 8, q.height,
+                            hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
   return STS_OK;
 }
 

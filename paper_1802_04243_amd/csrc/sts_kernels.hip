@@ -1651,8 +1651,8 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
     constexpr int nth = (IM_ || (MX_ && TV_)) ? NT : NTP;                                   \
     if (last)                                                                               \
       hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true, MX_, false, SJ_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
-    else if (inter && !IM_ && !SJ_)                                                         \
-      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_, !IM_ && !SJ_, SJ_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
+    else if (inter && !IM_)                                                                 \
+      hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_, !IM_, SJ_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
     else                                                                                    \
       hipLaunchKernelGGL((k_pass<nth, IM_, TV_, false, MX_, false, SJ_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
   } while (0)

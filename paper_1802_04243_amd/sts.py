@@ -25,7 +25,7 @@ EXPLICIT, IMPLICIT, UPWIND, TVD, MIXED = 0, 1, 0, 2, 4
 EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_step_tol", "sts_residuals", "sts_fields",
            "sts_set_fields", "sts_field_ptrs", "sts_timing", "sts_read_timing", "sts_drag",
            "sts_state_slots", "sts_state_save", "sts_state_load", "sts_adjoint_begin",
-           "sts_adjoint_seed_drag", "sts_adjoint_step", "sts_adjoint_read", "sts_destroy",
+           "sts_adjoint_seed_drag", "sts_adjoint_seed", "sts_adjoint_step", "sts_adjoint_read", "sts_destroy",
            "sts_last_error")
 
 _D = C.POINTER(C.c_double)
@@ -88,6 +88,7 @@ def lib():
         L.sts_state_load.argtypes = [C.c_void_p, C.c_int]
         L.sts_adjoint_begin.argtypes = [C.c_void_p, C.c_int]
         L.sts_adjoint_seed_drag.argtypes = [C.c_void_p, C.c_double]
+        L.sts_adjoint_seed.argtypes = [C.c_void_p] + [_D] * 4
         L.sts_adjoint_step.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int]
         L.sts_adjoint_read.argtypes = [C.c_void_p] + [_D] * 7
         L.sts_destroy.argtypes = [C.c_void_p]
@@ -234,6 +235,17 @@ class Solver:
 
     def adjoint_seed_drag(self, w: float):
         _check(lib().sts_adjoint_seed_drag(self._h, float(w)))
+
+    def adjoint_seed(self, lu=None, lv=None, lp=None, lT=None):
+        """lambda += the given arrays (field shapes; None skips a field)."""
+        arrs = []
+        for a, shp in zip((lu, lv, lp, lT), self.shapes()):
+            if a is not None:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                if a.shape != shp:
+                    raise ValueError(f"seed shape {a.shape}, expected {shp}")
+            arrs.append(a)
+        _check(lib().sts_adjoint_seed(self._h, *[_ptr(a) for a in arrs]))
 
     def adjoint_step(self, dt: float, n_inner: int, scheme: int):
         _check(lib().sts_adjoint_step(self._h, float(dt), int(n_inner), int(scheme)))
