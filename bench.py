@@ -14,7 +14,9 @@ corrections through an FP64 defect): its rate, its speedup over the FP64 form
 and its max / L2 relative difference from the FP64 fields after the
 configured 200 steps; the four FP64 schemes on the 3000x600 channel and on
 the paper's own meshes (4032 x 200 ... 4000, Kn = 0.001, velocity-slip /
-temperature-jump walls and square, particle frame); the
+temperature-jump walls and square, particle frame); loop 2 run to
+convergence (tolerance 1e-6, decided on the device) on the bench workload
+against fixed-count steps of the same passes; the
 adjoint of the explicit step on the 1024x256 adjoint workload (time-averaged
 drag, 100 steps x 10 passes, checkpoints every 10 steps): backward / forward
 time and the device memory it holds; and the combined run on the 4096x1024
@@ -101,6 +103,41 @@ def run_gpu(name: str, steps: int, warmup: int, scheme: int, fields_after: int =
                 pass_gbs=BYTES_PER_FV_PASS * p.n_fv / (pass_ms * 1e-3) / 1e9,
                 residuals=[float(x) for x in res], nx=p.nx, ny=p.ny, dt=dt, inner=inner,
                 fields=fields)
+
+
+def run_loop2(name: str, scheme: int, tol: float, steps: int, warmup: int, max_inner: int = 60):
+    """Loop 2 run to convergence (sts_step_tol, decided on the device) against
+    the fixed-count step of the same workload: passes per step and time."""
+    import torch
+    from paper_1802_04243_amd import sts
+
+    p, run = W.workload(name)
+    g = sts.Solver(p)
+    g.set_fields(*W.initial_fields(p, run["seed"]))
+    dt = run["dt"]
+    for _ in range(warmup):
+        g.step(dt, run["inner"], scheme)
+    g.residuals()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    counts = [g.step_tol(dt, max_inner, tol, scheme) for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.residuals()
+    # the same passes as fixed-count steps, for the per-pass overhead
+    t0 = time.perf_counter()
+    for k in counts:
+        g.step(dt, k, scheme)
+    g.residuals()
+    torch.cuda.synchronize()
+    wall_fixed = time.perf_counter() - t0
+    g.close()
+    npass = sum(counts)
+    return {"workload": name, "tol": tol, "max_inner": max_inner, "steps": steps,
+            "passes_per_step": round(npass / steps, 2), "passes_min_max": [min(counts), max(counts)],
+            "ms_per_step": round(wall / steps * 1e3, 4), "ms_per_pass": round(wall / npass * 1e3, 5),
+            "fixed_count_ms_per_pass": round(wall_fixed / npass * 1e3, 5),
+            "mfv_iters_s": round(p.n_fv * npass / wall / 1e6, 2)}
 
 
 def run_adjoint(name: str = "adjoint_1024x256"):
@@ -241,6 +278,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision runs")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-loop2", action="store_true",
+                    help="skip the loop-2-to-convergence timing (sts_step_tol)")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined run (mixed forward + FP64 adjoint, 4096x1024)")
     ap.add_argument("--other-grids",
@@ -300,6 +339,12 @@ def main():
         print(f"# combined: forward {comb['forward_s']:.3f} s, backward {comb['backward_s']:.3f} s "
               f"(ratio {comb['adjoint_forward_ratio']:.2f}), peak {comb['peak_device_bytes'] / 2**30:.2f} GiB, "
               f"grad err {comb['grad_max_rel_err_vs_fp64']}", file=sys.stderr, flush=True)
+    loop2 = None
+    if not a.no_loop2:
+        loop2 = run_loop2(a.workload, W.SCHEMES[HEADLINE], 1e-6, 10, a.warmup)
+        print(f"# loop 2 to tol 1e-6: {loop2['passes_per_step']} passes/step, "
+              f"{loop2['ms_per_pass']:.4f} ms/pass (fixed count {loop2['fixed_count_ms_per_pass']:.4f})",
+              file=sys.stderr, flush=True)
     others = {g: run_other_grid(g, a.steps, a.warmup) for g in a.other_grids.split(",") if g}
     h = per[HEADLINE]
     traffic = measured_traffic(HEADLINE)
@@ -342,6 +387,7 @@ def main():
                     for nm, r in per.items()},
         "other_grids": others or None,
         "mixed": mixed or None,
+        "loop2_to_convergence": loop2,
         "adjoint": adj,
         "combined": comb,
     }
