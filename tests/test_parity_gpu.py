@@ -286,6 +286,29 @@ def test_tolerance_exit_stops_at_every_position(sts_mod, oracle_lib):
     assert seen >= {1, 2, 3, 4, 5, 6}, seen
 
 
+def test_tolerance_exit_full_size(sts_mod, oracle_lib):
+    # loop 2 to convergence on the bench grid (5120x1152, explicit TVD, the
+    # tolerance and pass limit the benchmark uses) from a GPU-advanced state:
+    # the same pass count as the oracle and bitwise-equal fields
+    p, run = W.workload("channel_5120x1152")
+    scheme = W.EXPLICIT | W.TVD
+    print("case channel_5120x1152 loop 2 to tol 1e-6: 3 GPU steps, then one on both", flush=True)
+    g = sts_mod.Solver(p)
+    g.set_fields(*W.initial_fields(p, run["seed"]))
+    for _ in range(3):
+        g.step(run["dt"], run["inner"], scheme)
+    state = g.fields()
+    g.set_fields(*state)
+    o = oracle_lib.Oracle(p)
+    o.set_fields(*state)
+    ng = g.step_tol(run["dt"], 60, 1e-6, scheme)
+    no = o.step_tol(run["dt"], 60, 1e-6, scheme)
+    print(f"passes gpu {ng} oracle {no}", flush=True)
+    assert ng == no and 1 < ng < 60
+    compare(g, o, "channel_5120x1152 loop 2 to tol 1e-6")
+    g.close()
+
+
 def test_tolerance_exit_stops_at_non_finite(sts_mod):
     p, run = W.workload("channel_120x24")
     u, v, pr, T = W.initial_fields(p, 4)
