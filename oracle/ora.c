@@ -53,6 +53,8 @@ struct ora_ctx {
   double *u, *v, *p, *T;
   double *un, *vn, *pn, *Tn;
   double *um, *vm, *pm, *Tm;
+  /* loop 3: the previous sub-iterate of T and p */
+  double *Ts, *ps;
   /* per-pass work arrays */
   double *rho, *gam, *rhou, *rhov, *Fx, *Fy;
   double *uh, *du, *vh, *dv;
@@ -988,6 +990,8 @@ ora_ctx *ora_create(const ora_setup *s) {
   c->p = dalloc(nc);
   c->pn = dalloc(nc);
   c->pm = dalloc(nc);
+  c->Ts = dalloc(nc);
+  c->ps = dalloc(nc);
   c->T = dalloc(nc);
   c->Tn = dalloc(nc);
   c->Tm = dalloc(nc);
@@ -1026,7 +1030,7 @@ void ora_destroy(ora_ctx *c) {
                     c->p,   c->pn,   c->pm,   c->T,    c->Tn,    c->Tm,
                     c->rho, c->gam,  c->rhou, c->Fx,   c->rhov,  c->Fy,
                     c->uh,  c->du,   c->vh,   c->dv,   c->uexp,  c->vexp,
-                    c->Texp};
+                    c->Texp, c->Ts,  c->ps};
   for (size_t k = 0; k < sizeof(bufs) / sizeof(bufs[0]); k++) free(bufs[k]);
   free(c->solid);
   free(c);
@@ -1103,27 +1107,71 @@ static void prologue(ora_ctx *c, int scheme) {
 /* ------------------------------------------------------------------ */
 /* one pass of loop 2 (Appendix A order)                              */
 /* ------------------------------------------------------------------ */
-static void pass(ora_ctx *c, double dt, int scheme) {
-  const int nx = c->nx, ny = c->ny, tvd = scheme & ORA_TVD;
-  /* 1. rho = p/T, Gamma = sqrt(T) (pl5, pl37), face densities and fluxes */
-  cell_props(c, c->p, c->T);
-  face_fluxes(c, c->u, c->v, tvd);
-
-  /* 2. temperature (pl30), Jacobi: neighbours at the old iterate */
+/* Energy equation (pl30) of one pass, Jacobi: T and p (neighbour values,
+   the cell's own T where a boundary takes it, the pressure work) from the
+   arrays c->T, c->p; rho, Gamma and the face fluxes from the pass's
+   iterate (cell_props, face_fluxes).  Writes Tout. */
+static void T_solve(ora_ctx *c, double dt, int scheme, double *Tout) {
+  const int nx = c->nx, ny = c->ny;
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
       size_t k = IC(c, i, j);
       if (c->solid[k]) {
-        c->Tn[k] = c->T[k];
+        Tout[k] = c->T[k];
         continue;
       }
       tco q = T_coefs(c, i, j, dt, scheme);
-      c->Tn[k] = (dt * (q.a[0] * q.nb[0] + q.a[1] * q.nb[1] +
-                        q.a[2] * q.nb[2] + q.a[3] * q.nb[3] + q.src) +
-                  (q.unst + dt * q.texp)) /
-                 q.a0;
+      Tout[k] = (dt * (q.a[0] * q.nb[0] + q.a[1] * q.nb[1] +
+                       q.a[2] * q.nb[2] + q.a[3] * q.nb[3] + q.src) +
+                 (q.unst + dt * q.texp)) /
+                q.a0;
     }
+}
+
+/* Pressure equation (pl23, pl24) of one pass: the cell's T from Tcell,
+   neighbour (and the cell's own) p from pold; face densities, u-hat, v-hat,
+   d of the pass.  Writes pout. */
+static void p_solve(ora_ctx *c, double dt, const double *pold, const double *Tcell,
+                    double *pout) {
+  const int nx = c->nx, ny = c->ny;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      size_t k = IC(c, i, j);
+      if (c->solid[k]) {
+        pout[k] = pold[k];
+        continue;
+      }
+      double dxi = c->dx[i], dyj = c->dy[j], dV = dxi * dyj;
+      size_t kw = IU(c, i, j), ke = IU(c, i + 1, j), ks = IV(c, i, j),
+             kn = IV(c, i, j + 1);
+      double aW = c->rhou[kw] * c->du[kw] * dyj;
+      double aE = c->rhou[ke] * c->du[ke] * dyj;
+      double aS = c->rhov[ks] * c->dv[ks] * dxi;
+      double aN = c->rhov[kn] * c->dv[kn] * dxi;
+      double bW = c->rhou[kw] * c->uh[kw] * dyj;
+      double bE = c->rhou[ke] * c->uh[ke] * dyj;
+      double bS = c->rhov[ks] * c->vh[ks] * dxi;
+      double bN = c->rhov[kn] * c->vh[kn] * dxi;
+      double pP = pold[k];
+      double pW = (!c->per && i == 0) ? pP : Cat(c, pold, i - 1, j);
+      double pE = (!c->per && i == nx - 1) ? pP : Cat(c, pold, i + 1, j);
+      double pS = (j == 0) ? pP : pold[IC(c, i, j - 1)];
+      double pN = (j == ny - 1) ? pP : pold[IC(c, i, j + 1)];
+      double a0 = dV / Tcell[k] + (aW + aE + aS + aN) * dt;
+      double bp = c->pm[k] / c->Tm[k] * dV - (bE - bW + bN - bS) * dt;
+      pout[k] = ((aW * pW + aE * pE + aS * pS + aN * pN) * dt + bp) / a0;
+    }
+
+}
+
+static void pass(ora_ctx *c, double dt, int scheme, int n3) {
+  const int nx = c->nx, ny = c->ny, tvd = scheme & ORA_TVD;
+  /* 1. rho = p/T, Gamma = sqrt(T) (pl5, pl37), face densities and fluxes */
+  cell_props(c, c->p, c->T);
+  face_fluxes(c, c->u, c->v, tvd);
+
 
   /* 3. pseudo velocities and d (pl18-pl21).  Faces that are not unknowns
      keep their fixed value as u-hat and get d = 0. */
@@ -1159,35 +1207,28 @@ static void pass(ora_ctx *c, double dt, int scheme) {
       }
     }
 
-  /* 4. pressure (pl23, pl24): own-cell T from this pass, neighbour p old */
-#pragma omp parallel for schedule(static)
-  for (int j = 0; j < ny; j++)
-    for (int i = 0; i < nx; i++) {
-      size_t k = IC(c, i, j);
-      if (c->solid[k]) {
-        c->pn[k] = c->p[k];
-        continue;
-      }
-      double dxi = c->dx[i], dyj = c->dy[j], dV = dxi * dyj;
-      size_t kw = IU(c, i, j), ke = IU(c, i + 1, j), ks = IV(c, i, j),
-             kn = IV(c, i, j + 1);
-      double aW = c->rhou[kw] * c->du[kw] * dyj;
-      double aE = c->rhou[ke] * c->du[ke] * dyj;
-      double aS = c->rhov[ks] * c->dv[ks] * dxi;
-      double aN = c->rhov[kn] * c->dv[kn] * dxi;
-      double bW = c->rhou[kw] * c->uh[kw] * dyj;
-      double bE = c->rhou[ke] * c->uh[ke] * dyj;
-      double bS = c->rhov[ks] * c->vh[ks] * dxi;
-      double bN = c->rhov[kn] * c->vh[kn] * dxi;
-      double pP = c->p[k];
-      double pW = (!c->per && i == 0) ? pP : Cat(c, c->p, i - 1, j);
-      double pE = (!c->per && i == nx - 1) ? pP : Cat(c, c->p, i + 1, j);
-      double pS = (j == 0) ? pP : c->p[IC(c, i, j - 1)];
-      double pN = (j == ny - 1) ? pP : c->p[IC(c, i, j + 1)];
-      double a0 = dV / c->Tn[k] + (aW + aE + aS + aN) * dt;
-      double bp = c->pm[k] / c->Tm[k] * dV - (bE - bW + bN - bS) * dt;
-      c->pn[k] = ((aW * pW + aE * pE + aS * pS + aN * pN) * dt + bp) / a0;
+  /* 2.-4. temperature (pl30) and pressure (pl23, pl24), Jacobi in their
+     neighbours.  Loop 3 of the CPU algorithm (Sec. 3, its figure): with
+     the face densities, fluxes, rho, Gamma, u-hat, v-hat and d of this
+     pass fixed, the energy and pressure equations are solved n3 times,
+     each time with T and p from the previous solve (n3 = 1: the pass of
+     the GPU algorithm, T and p at the old iterate). */
+  T_solve(c, dt, scheme, c->Tn);
+  p_solve(c, dt, c->p, c->Tn, c->pn);
+  if (n3 > 1) {
+    double *Told = c->T, *pold = c->p;
+    for (int s = 2; s <= n3; s++) {
+      /* the previous sub-iterate takes the place of the old T and p */
+      memcpy(c->Ts, c->Tn, sizeof(double) * (size_t)nx * ny);
+      memcpy(c->ps, c->pn, sizeof(double) * (size_t)nx * ny);
+      c->T = c->Ts;
+      c->p = c->ps;
+      T_solve(c, dt, scheme, c->Tn);
+      p_solve(c, dt, c->ps, c->Tn, c->pn);
     }
+    c->T = Told;
+    c->p = pold;
+  }
 
   /* 5. velocities (pl18, pl19) with this pass's pressure on both sides */
 #pragma omp parallel for schedule(static)
@@ -1270,7 +1311,15 @@ static void pass(ora_ctx *c, double dt, int scheme) {
 void ora_step(ora_ctx *c, double dt, int n_inner, int scheme) {
   c->idt = 1.0 / dt;
   prologue(c, scheme);
-  for (int k = 0; k < n_inner; k++) pass(c, dt, scheme);
+  for (int k = 0; k < n_inner; k++) pass(c, dt, scheme, 1);
+}
+
+/* A step whose passes each run loop 3 with n3 >= 1 energy-pressure solves
+   (n3 = 1: ora_step). */
+void ora_step_l3(ora_ctx *c, double dt, int n_inner, int n3, int scheme) {
+  c->idt = 1.0 / dt;
+  prologue(c, scheme);
+  for (int k = 0; k < n_inner; k++) pass(c, dt, scheme, n3);
 }
 
 /* Loop 2 with its convergence test (Sec. 3.1, the algorithm figures: the
@@ -1284,7 +1333,7 @@ int ora_step_tol(ora_ctx *c, double dt, int max_inner, double tol, int scheme) {
   prologue(c, scheme);
   int k = 0;
   while (k < max_inner) {
-    pass(c, dt, scheme);
+    pass(c, dt, scheme, 1);
     k++;
     double r = dmax(dmax(c->res[0], c->res[1]), dmax(c->res[3], c->res[2] / c->p_in));
     if (r <= tol) break;

@@ -59,6 +59,9 @@ void ora_get_fields(const ora_ctx *c, double *u, double *v, double *p,
                     double *T);
 /* One time step: prologue, then n_inner Jacobi passes. */
 void ora_step(ora_ctx *c, double dt, int n_inner, int scheme);
+/* One time step whose passes each solve the energy and pressure equations
+   n3 >= 1 times (loop 3 of the CPU algorithm; n3 = 1 is ora_step). */
+void ora_step_l3(ora_ctx *c, double dt, int n_inner, int n3, int scheme);
 /* One time step whose loop 2 stops after the first pass with
    max(max|du|, max|dv|, max|dT|, max|dp|/p_in) <= tol, or after max_inner
    passes; returns the passes taken. */

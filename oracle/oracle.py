@@ -55,6 +55,7 @@ def lib():
         L.ora_set_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
         L.ora_get_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
         L.ora_step.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int]
+        L.ora_step_l3.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_int]
         L.ora_step_tol.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_int]
         L.ora_step_tol.restype = C.c_int
         L.ora_residuals.argtypes = [C.c_void_p, _D]
@@ -155,6 +156,10 @@ class Oracle:
 
     def step(self, dt, n_inner, scheme):
         lib().ora_step(self._h, float(dt), int(n_inner), int(scheme))
+
+    def step_l3(self, dt, n_inner, n3, scheme):
+        """One step whose passes run loop 3 with n3 energy-pressure solves."""
+        lib().ora_step_l3(self._h, float(dt), int(n_inner), int(n3), int(scheme))
 
     def step_tol(self, dt, max_inner, tol, scheme) -> int:
         """One step whose loop 2 stops at the tolerance; returns the passes taken."""

@@ -1,0 +1,98 @@
+"""Pins of loop 3 in the oracle (CPU only): the CPU algorithm's coupled
+energy-pressure solve inside each loop-2 iteration (Sec. 3, the algorithm
+figures; reading: with the face densities, fluxes, rho, Gamma, u-hat, v-hat
+and d of the pass fixed, the energy and pressure equations are solved n3
+times, each with T and p from the previous solve).
+
+- n3 = 1 is the GPU algorithm's pass, bitwise.
+- Loop 3 changes the path of loop 2, not the solution of the time step: after
+  a few passes the fields with n3 = 2, 3 differ from n3 = 1 by ~1e-2, while
+  loop 2 run to convergence reaches the same fields to round-off (the step's
+  solution is the fixed point of the discrete equations, whatever the inner
+  iteration); implicit TVD stalls near 1e-7 (its limiter is discontinuous in
+  the iterate), so only that level is asserted for it.
+- Within one pass the sub-iterations contract: the change from n3 to n3 + 1
+  shrinks geometrically.
+- A uniform stream between walls moving with it is preserved bitwise.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_1802_04243_amd import workloads as W
+
+
+def _start(oracle_lib, p, run, scheme):
+    o = oracle_lib.Oracle(p)
+    o.set_fields(*W.initial_fields(p, 1))
+    o.step(run["dt"], 20, scheme)  # past the initial noise
+    return o.fields()
+
+
+def _run(oracle_lib, p, f, dt, npass, n3, scheme):
+    o = oracle_lib.Oracle(p)
+    o.set_fields(*f)
+    o.step_l3(dt, npass, n3, scheme)
+    return o.fields(), o.residuals()
+
+
+def _rel(a, b):
+    return max(float(np.abs(x - y).max() / np.abs(y).max()) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("scheme", list(W.SCHEMES.values()))
+def test_one_solve_is_the_gpu_pass(oracle_lib, scheme):
+    p, run = W.workload("channel_120x24")
+    f = _start(oracle_lib, p, run, scheme)
+    a = oracle_lib.Oracle(p)
+    b = oracle_lib.Oracle(p)
+    a.set_fields(*f)
+    b.set_fields(*f)
+    for _ in range(3):
+        a.step(run["dt"], 7, scheme)
+        b.step_l3(run["dt"], 7, 1, scheme)
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.residuals(), b.residuals())
+
+
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_loop3_changes_the_path_not_the_solution(oracle_lib, name, scheme):
+    p, run = W.workload("channel_120x24")
+    f = _start(oracle_lib, p, run, scheme)
+    few = {n3: _run(oracle_lib, p, f, run["dt"], 3, n3, scheme)[0] for n3 in (1, 2, 3)}
+    conv = {n3: _run(oracle_lib, p, f, run["dt"], 200, n3, scheme) for n3 in (1, 2, 3)}
+    for n3 in (2, 3):
+        path, sol = _rel(few[n3], few[1]), _rel(conv[n3][0], conv[1][0])
+        print(f"{name} n3={n3}: after 3 passes {path:.2e}, converged {sol:.2e}")
+        assert path > 1e-4
+        if scheme == W.IMPLICIT | W.TVD:
+            assert sol <= 1e-5 and max(conv[n3][1][:4]) <= 1e-5
+        else:
+            assert sol <= 1e-12 and max(conv[n3][1][:4]) <= 1e-13
+
+
+def test_sub_iterations_contract(oracle_lib):
+    p, run = W.workload("channel_120x24")
+    scheme = W.EXPLICIT | W.TVD
+    f = _start(oracle_lib, p, run, scheme)
+    res = [_run(oracle_lib, p, f, run["dt"], 1, n3, scheme)[0] for n3 in range(1, 9)]
+    d = [_rel(res[k + 1], res[k]) for k in range(len(res) - 1)]
+    print("change from n3 to n3+1 in one pass: " + " ".join(f"{x:.1e}" for x in d))
+    assert all(d[k + 1] < 0.7 * d[k] for k in range(len(d) - 1)), d
+    assert d[-1] < 0.05 * d[0]
+
+
+@pytest.mark.parametrize("scheme", list(W.SCHEMES.values()))
+def test_loop3_preserves_a_uniform_stream(oracle_lib, scheme):
+    rng = np.random.default_rng(5)
+    p = W.Problem(nx=24, ny=8, dx=rng.uniform(0.05, 0.15, 24), dy=rng.uniform(0.05, 0.15, 8),
+                  wall_u=(1.0, 1.0))
+    o = oracle_lib.Oracle(p)
+    f0 = o.fields()
+    for _ in range(10):
+        o.step_l3(0.01, 4, 3, scheme)
+    for a, b in zip(o.fields(), f0):
+        assert np.array_equal(a, b)
+    assert np.all(o.residuals() == 0.0)
