@@ -138,6 +138,18 @@ sts_status sts_create(const sts_grid *grid, const sts_obstacles *obstacles,
    and copied to pinned host memory. */
 sts_status sts_step(sts_ctx *ctx, double dt, int n_inner, int scheme);
 
+/* One time step of n_inner passes, each running loop 3 of the CPU
+   algorithm (Sec. 3, its figure): the energy and pressure equations are
+   solved n3 times per pass with the face densities, convective fluxes, rho,
+   Gamma, u-hat, v-hat and d of the pass's iterate fixed, each solve taking T
+   and p (the Jacobi neighbour values, the pressure work, the cell's T in the
+   pressure equation) from the previous one; then the velocities.  n3 = 1 is
+   sts_step (the GPU algorithm's pass).  FP64 schemes only.  Allocates four
+   field arrays on first use with n3 > 1 (STS_ENOMEM if that fails).
+   STS_EINVAL for dt <= 0, n_inner < 1, n3 outside [1, 64], unknown scheme
+   bits or STS_MIXED with n3 > 1 (state unchanged). */
+sts_status sts_step_l3(sts_ctx *ctx, double dt, int n_inner, int n3, int scheme);
+
 /* One time step whose loop 2 runs until convergence (Sec. 3.1: the inner
    iterations repeat until the step's solution has converged; Sec. 5: the
    maximal residuals are checked after every iteration): after each pass the

@@ -121,6 +121,10 @@ struct sts_ctx {
   size_t adj_clear_bytes = 0;
   char *slot_mem = nullptr;
   int nslots = 0;
+  // loop 3: two (T, p) pairs of the energy-pressure solves of a pass
+  // (allocated on first use; frames hold the ghost values p = T = 1)
+  char *l3_mem = nullptr;
+  double *l3T[2] = {nullptr, nullptr}, *l3p[2] = {nullptr, nullptr};
   double *aux = nullptr;   // drag partials + result
   double *haux = nullptr;  // pinned
   // timing
@@ -419,6 +423,7 @@ void release(sts_ctx *c) {
   if (!c) return;
   if (c->adj_mem) (void)hipFree(c->adj_mem);
   if (c->slot_mem) (void)hipFree(c->slot_mem);
+  if (c->l3_mem) (void)hipFree(c->l3_mem);
   if (c->aux) (void)hipFree(c->aux);
   if (c->haux) (void)hipHostFree(c->haux);
   if (c->base && c->own_mem) (void)hipFree(c->base);
@@ -651,6 +656,61 @@ extern "C" sts_status sts_step_tol(sts_ctx *c, double dt, int max_inner, double 
   if (k < 1 || k > max_inner) return fail(STS_EDEVICE, "loop 2 control block reads %d passes", k);
   c->cur = cur0 ^ (k & 1);
   *n_inner = k;
+  return STS_OK;
+}
+
+// Loop 3 of the CPU algorithm inside every pass (n3 energy-pressure solves):
+// the first solve from the pass's iterate, then n3 - 2 solves into the two
+// scratch pairs in turn, then the last, which also updates the velocities
+// and writes the new iterate.  Every solve recomputes the face densities and
+// pseudo-velocities of the pass's iterate (bitwise the same each time) and
+// takes T and p from the previous solve.
+extern "C" sts_status sts_step_l3(sts_ctx *c, double dt, int n_inner, int n3, int scheme) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (!(dt > 0) || !isfinite(dt)) return fail(STS_EINVAL, "dt must be > 0");
+  if (n_inner < 1) return fail(STS_EINVAL, "n_inner must be >= 1");
+  if (n3 < 1 || n3 > 64) return fail(STS_EINVAL, "n3 must be in [1, 64]");
+  if (scheme & ~STS_SCHEME_MASK) return fail(STS_EINVAL, "unknown scheme bits 0x%x", scheme);
+  if (n3 == 1) return sts_step(c, dt, n_inner, scheme);
+  if (scheme & STS_MIXED) return fail(STS_EINVAL, "loop 3 is of the FP64 step (scheme 0x%x)", scheme);
+  if (!c->l3_mem) {
+    const size_t fb = c->L.field_bytes;
+    if (hipMalloc((void **)&c->l3_mem, 4 * fb) != hipSuccess) {
+      c->l3_mem = nullptr;
+      return fail(STS_ENOMEM, "hipMalloc of %zu bytes failed", 4 * fb);
+    }
+    const size_t n = (size_t)c->L.pitch * c->L.rows;
+    std::vector<double> one(n, 1.0);
+    for (int q = 0; q < 2; q++) {
+      c->l3T[q] = (double *)(c->l3_mem + (2 * q) * fb);
+      c->l3p[q] = (double *)(c->l3_mem + (2 * q + 1) * fb);
+      HIPCHK(hipMemcpyAsync(c->l3T[q], one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(c->l3p[q], one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  c->P.dt = dt;
+  c->P.idt = 1.0 / dt;
+  launch_prologue(c->P, c->st[c->cur], c->C, scheme, c->stream);
+  for (int k = 0; k < n_inner; k++) {
+    const State o = c->st[c->cur], nw = c->st[c->cur ^ 1];
+    launch_pass3(c->P, o, nw, c->C, scheme, nullptr, 1, nullptr, nullptr, c->l3T[0], c->l3p[0],
+                 c->stream);
+    int q = 0;  // the pair holding the previous solve
+    for (int sub = 2; sub < n3; sub++, q ^= 1)
+      launch_pass3(c->P, o, nw, c->C, scheme, nullptr, 1, c->l3T[q], c->l3p[q], c->l3T[q ^ 1],
+                   c->l3p[q ^ 1], c->stream);
+    launch_pass3(c->P, o, nw, c->C, scheme, k == n_inner - 1 ? &c->X : nullptr, 2, c->l3T[q],
+                 c->l3p[q], nullptr, nullptr, c->stream);
+    c->cur ^= 1;
+  }
+  HIPCHK(hipGetLastError());
+  launch_residual(c->P, c->st[c->cur], c->C, c->X, c->dres, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->hres, c->dres, NRES * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  c->stepped = true;
+  c->last_scheme = scheme;
   return STS_OK;
 }
 

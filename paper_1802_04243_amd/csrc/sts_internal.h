@@ -105,6 +105,13 @@ void launch_prologue(const Params &P, State m, Consts C, int scheme,
                      hipStream_t st);
 void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
                  const Resid *last, const Inter *inter, hipStream_t st);
+// one energy-pressure solve of a pass with loop 3 (FP64 schemes): L3 = 1 a
+// solve before the last (T, p into To, po; Ts = NULL for the first, whose T
+// and p are the iterate's), 2 the last (Ts, ps: the previous solve; the
+// pass's outputs in n, with the residual inputs when last != NULL)
+void launch_pass3(const Params &P, State o, State n, Consts C, int scheme, const Resid *last,
+                  int L3, const double *Ts, const double *ps, double *To, double *po,
+                  hipStream_t st);
 void launch_residual(const Params &P, State n, Consts C, Resid R, double *out,
                      hipStream_t st);
 // loop 2 run to convergence: clear the control block; after pass L.k, fold

@@ -178,12 +178,15 @@ constexpr int NW = LH * LW;  // cells of the window
 // NTH threads: every global load of the thread is issued before the first
 // LDS store, so that their latencies overlap; the caller synchronises.
 // MX: Gamma is only read by FP32 code (mixed form): FP32 square root.
-template <int NTH, bool MX = false>
+// SUB (loop 3, a solve after the first): rho and Gamma from the pass's
+// iterate o, the T and p values from the previous solve (Ts, ps).
+template <int NTH, bool MX = false, bool SUB = false>
 __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
-                            int y0) {
+                            int y0, const double *Ts = nullptr, const double *ps = nullptr) {
   constexpr int WPT = (NW + NTH - 1) / NTH;  // window cells per thread
   const int t = threadIdx.x;
   double pp[WPT], tt[WPT], uu[WPT], vv[WPT];
+  double sp[WPT], st[WPT];
   unsigned char ff[WPT];
 #pragma unroll
   for (int m = 0; m < WPT; m++) {
@@ -194,6 +197,10 @@ __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
       const long rc = P.off + (long)win_cj(P, y0, b) * P.pitch;
       pp[m] = o.p[rc + ci];
       tt[m] = o.T[rc + ci];
+      if (SUB) {
+        sp[m] = ps[rc + ci];
+        st[m] = Ts[rc + ci];
+      }
       ff[m] = P.fl[rc + ci];
       uu[m] = o.u[rc + win_ui(P, x0, a)];
       vv[m] = o.v[P.off + (long)win_vj(P, y0, b) * P.pitch + ci];
@@ -217,8 +224,8 @@ __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
     const int k = t + m * NTH;
     if (k < NW) {
       const int a = k % LW, b = k / LW;
-      s.p[b][a] = pp[m];
-      s.T[b][a] = tt[m];
+      s.p[b][a] = SUB ? sp[m] : pp[m];
+      s.T[b][a] = SUB ? st[m] : tt[m];
       s.r[b][a] = pp[m] / tt[m];
       s.g[b][a] = MX ? (double)__builtin_amdgcn_sqrtf((float)tt[m]) : sqrt(tt[m]);
       s.fl[b][a] = ff[m];
@@ -1192,10 +1199,16 @@ __device__ __forceinline__ void item_consts(const Params &P, const Consts &C,
 
 // c: the step constants of the thread's items (item_consts); cp: C_p of a
 // cell thread's cell
-template <int NTH, bool CL, bool SJ, bool IM, bool TV, bool RS, bool MX, bool IN>
+// L3 (loop 3): 0 a plain pass; 1 an energy-pressure solve that is not the
+// pass's last (writes T and p to To, po, no velocities); 2 the last solve of
+// a pass (the plain pass's outputs; the increments of the residual-producing
+// variant are taken against the pass's iterate o, as the window holds the
+// previous solve's T and p).
+template <int NTH, bool CL, bool SJ, bool IM, bool TV, bool RS, bool MX, bool IN, int L3 = 0>
 __device__ void pass_body(Lds &s, const Params &P, const State n,
                           const Resid X, const Inter I, int tile, int x0,
-                          int y0, const double c[], double cp) {
+                          int y0, const double c[], double cp, const State o = State{},
+                          double *To = nullptr, double *po = nullptr) {
   const int t = threadIdx.x;
   const bool cellt = t < NT;
   const int tx = t % BX, ty = t / BX;
@@ -1253,7 +1266,15 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
                aN * P_(i, j + 1)) * P.dt + bp) / a0;
     }
     PN_(i, j) = pnew;
+    if constexpr (L3 == 1) {
+      if (i >= 0 && j >= 0 && gi < P.nx && gj < P.ny) {
+        const long k = P.off + (long)gj * P.pitch + gi;
+        To[k] = tnew;
+        po[k] = pnew;
+      }
+    }
   }
+  if constexpr (L3 == 1) return;  // no barrier follows in this variant
   __syncthreads();
 
   // stage 4: velocities (eqs pl18, pl19); write the owned values
@@ -1311,8 +1332,8 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
       rv[1] = fabs(vn - V_(i, j));
       rv[6] = (double)(!isfinite(un)) + (double)(!isfinite(vn));
       if (FL_(i, j)) {
-        rv[2] = fabs(pn - P_(i, j));
-        rv[3] = fabs(tnew - T_(i, j));
+        rv[2] = fabs(pn - (L3 == 2 ? o.p[k] : P_(i, j)));
+        rv[3] = fabs(tnew - (L3 == 2 ? o.T[k] : T_(i, j)));
         rv[6] += (double)(!isfinite(pn)) + (double)(!isfinite(tnew));
       }
     }
@@ -1346,6 +1367,30 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
     pass_body<NTH, true, false, IM, TV, RS, MX, IN>(s, P, n, X, I, tile, x0, y0, c, cp);
   else
     pass_body<NTH, false, SJ, IM, TV, RS, MX, IN>(s, P, n, X, I, tile, x0, y0, c, cp);
+}
+
+// One energy-pressure solve of a pass with loop 3 (FP64): L3 = 1 a solve
+// before the last (T, p to To, po), 2 the last (the pass's outputs in n);
+// SUB: the window's T and p from the previous solve (Ts, ps), rho, Gamma
+// and everything else from the pass's iterate o.
+template <int NTH, bool IM, bool TV, bool RS, bool SJ, int L3, bool SUB>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_pass3(
+    const Params P, const State o, const State n, const Consts C, const Resid X,
+    const double *Ts, const double *ps, double *To, double *po) {
+  __shared__ Lds s;
+  if (RS && X.stop && *X.stop) return;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
+  double c[Items<NTH>::rounds], cp;
+  item_consts<NTH>(P, C, x0, y0, c, cp);
+  load_window<NTH, false, SUB>(s, P, o, x0, y0, Ts, ps);
+  __syncthreads();
+  if (P.clean[tile])
+    pass_body<NTH, true, false, IM, TV, RS, false, false, L3>(s, P, n, X, Inter{}, tile, x0, y0, c,
+                                                              cp, o, To, po);
+  else
+    pass_body<NTH, false, SJ, IM, TV, RS, false, false, L3>(s, P, n, X, Inter{}, tile, x0, y0, c,
+                                                            cp, o, To, po);
 }
 
 // ---------------------------------------------------------------------------
@@ -1674,6 +1719,37 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
   }
 #undef STS_PASS
 #undef STS_PASS_SJ
+}
+
+void launch_pass3(const Params &P, State o, State n, Consts C, int scheme, const Resid *last,
+                  int L3, const double *Ts, const double *ps, double *To, double *po,
+                  hipStream_t st) {
+  const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0;
+  dim3 g(ntiles(P));
+  const Resid X = last ? *last : Resid{nullptr, nullptr, nullptr, nullptr};
+#define STS_P3(IM_, TV_, SJ_)                                                                   \
+  do {                                                                                          \
+    constexpr int nth = IM_ ? NT : NTP;                                                         \
+    if (L3 == 1 && !Ts)                                                                         \
+      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, false, SJ_, 1, false>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
+    else if (L3 == 1)                                                                           \
+      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, false, SJ_, 1, true>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
+    else if (last)                                                                              \
+      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, true, SJ_, 2, true>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, false, SJ_, 2, true>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
+  } while (0)
+#define STS_P3S(IM_, TV_)                 \
+  do {                                    \
+    if (P.sj) STS_P3(IM_, TV_, true);     \
+    else STS_P3(IM_, TV_, false);         \
+  } while (0)
+  if (im && tv) STS_P3S(true, true);
+  else if (im) STS_P3S(true, false);
+  else if (tv) STS_P3S(false, true);
+  else STS_P3S(false, false);
+#undef STS_P3S
+#undef STS_P3
 }
 
 void launch_residual(const Params &P, State n, Consts C, Resid X, double *out,

@@ -1,0 +1,110 @@
+"""Loop 3 (the CPU algorithm's energy-pressure solves inside each pass) on
+the GPU against the FP64 oracle (through the C ABI).
+
+Expected bitwise equal, as the plain pass; asserted: normwise relative
+difference <= 1e-10 per field and the residuals.  Cases: the small channel
+in every scheme with 2 and 3 solves per pass; a ragged non-uniform grid with
+a slip-jump and a no-slip wall, two obstacles, heated walls and a body force;
+a periodic slip-jump channel; the 4x4 grid; one step of the bench grid
+(5120x1152, explicit TVD, 2 solves) from a GPU-advanced state.  Plus: one
+solve is sts_step, and the argument checks.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_1802_04243_amd import workloads as W
+
+from test_parity_gpu import compare
+
+pytestmark = pytest.mark.gpu
+
+SJ = W.WALL_SLIP_JUMP
+
+
+def run_l3(sts_mod, oracle_lib, p, dt, steps, inner, n3, scheme, seed, label):
+    print(f"case loop 3 {label} n3={n3} scheme={scheme} grid={p.nx}x{p.ny} steps={steps}x{inner}",
+          flush=True)
+    g = sts_mod.Solver(p)
+    o = oracle_lib.Oracle(p)
+    f0 = W.initial_fields(p, seed)
+    g.set_fields(*f0)
+    o.set_fields(*f0)
+    for _ in range(steps):
+        g.step_l3(dt, inner, n3, scheme)
+        o.step_l3(dt, inner, n3, scheme)
+    compare(g, o, f"loop 3 {label} n3={n3}")
+    g.close()
+
+
+@pytest.mark.parametrize("n3", [2, 3])
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_loop3_channel_120x24(sts_mod, oracle_lib, name, scheme, n3):
+    p, run = W.workload("channel_120x24")
+    run_l3(sts_mod, oracle_lib, p, run["dt"], 15, 6, n3, scheme, 1, f"120x24/{name}")
+
+
+@pytest.mark.parametrize("scheme", [W.EXPLICIT | W.TVD, W.IMPLICIT | W.UPWIND])
+def test_loop3_ragged_mixed_walls(sts_mod, oracle_lib, scheme):
+    rng = np.random.default_rng(8)
+    nx, ny = 71, 37
+    p = W.Problem(nx=nx, ny=ny, dx=rng.uniform(0.03, 0.08, nx), dy=rng.uniform(0.02, 0.05, ny),
+                  obstacles=[(20, 5, 26, 12), (40, 20, 43, 36)], wall_type=(SJ, W.WALL_NOSLIP_ISOTHERMAL),
+                  wall_u=(0.4, -0.2), wall_T=(rng.uniform(0.9, 1.1, nx), rng.uniform(0.95, 1.2, nx)),
+                  obstacle_type=SJ, obstacle_T=1.1, kn=0.004, gx=0.3, gy=-0.1,
+                  u_in=W.parabolic_inlet(ny, 3))
+    run_l3(sts_mod, oracle_lib, p, p.cfl_dt(), 10, 5, 3, scheme, 5, "ragged 71x37")
+
+
+@pytest.mark.parametrize("scheme", [W.EXPLICIT | W.UPWIND, W.IMPLICIT | W.TVD])
+def test_loop3_periodic_slip_jump(sts_mod, oracle_lib, scheme):
+    p = W.Problem(nx=67, ny=20, lx=3.0, periodic=True, obstacles=[(30, 7, 35, 12)],
+                  wall_type=(SJ, SJ), wall_u=(0.0, 0.5), obstacle_type=SJ, kn=0.02,
+                  wall_T=(np.full(67, 1.0), np.linspace(1.0, 1.2, 67)))
+    run_l3(sts_mod, oracle_lib, p, 0.01, 10, 5, 2, scheme, 9, "periodic 67x20")
+
+
+def test_loop3_tiny_grid(sts_mod, oracle_lib):
+    p = W.Problem(nx=4, ny=4, lx=1.0, ly=1.0)
+    run_l3(sts_mod, oracle_lib, p, p.cfl_dt(), 10, 4, 4, W.EXPLICIT | W.TVD, 2, "4x4")
+
+
+def test_loop3_full_size_step_from_gpu_state(sts_mod, oracle_lib):
+    p, run = W.workload("channel_5120x1152")
+    scheme = W.EXPLICIT | W.TVD
+    print("case loop 3 channel_5120x1152 n3=2: 3 GPU steps, then one step on both", flush=True)
+    g = sts_mod.Solver(p)
+    g.set_fields(*W.initial_fields(p, run["seed"]))
+    for _ in range(3):
+        g.step(run["dt"], run["inner"], scheme)
+    state = g.fields()
+    g.set_fields(*state)
+    o = oracle_lib.Oracle(p)
+    o.set_fields(*state)
+    g.step_l3(run["dt"], run["inner"], 2, scheme)
+    o.step_l3(run["dt"], run["inner"], 2, scheme)
+    compare(g, o, "loop 3 channel_5120x1152 n3=2")
+    g.close()
+
+
+def test_loop3_one_solve_is_the_step_and_argument_checks(sts_mod):
+    p, run = W.workload("channel_120x24")
+    f0 = W.initial_fields(p, 3)
+    a, b = sts_mod.Solver(p), sts_mod.Solver(p)
+    a.set_fields(*f0)
+    b.set_fields(*f0)
+    for _ in range(3):
+        a.step_l3(run["dt"], 6, 1, W.EXPLICIT | W.TVD)
+        b.step(run["dt"], 6, W.EXPLICIT | W.TVD)
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.residuals(), b.residuals())
+    for args in ((run["dt"], 6, 0, W.EXPLICIT), (run["dt"], 6, 65, W.EXPLICIT),
+                 (run["dt"], 0, 2, W.EXPLICIT), (0.0, 6, 2, W.EXPLICIT),
+                 (run["dt"], 6, 2, W.EXPLICIT | W.MIXED)):
+        with pytest.raises(sts_mod.StsError) as e:
+            a.step_l3(*args)
+        assert e.value.code == sts_mod.STS_EINVAL, args
+    a.close()
+    b.close()
