@@ -16,7 +16,8 @@ configured 200 steps; the four FP64 schemes on the 3000x600 channel and on
 the paper's own meshes (4032 x 200 ... 4000, Kn = 0.001, velocity-slip /
 temperature-jump walls and square, particle frame); loop 2 run to
 convergence (tolerance 1e-6, decided on the device) on the bench workload
-against fixed-count steps of the same passes; the
+against fixed-count steps of the same passes; steps with loop 3 (1, 2, 3
+energy-pressure solves per pass) on the bench workload; the
 adjoint of the explicit step on the 1024x256 adjoint workload (time-averaged
 drag, 100 steps x 10 passes, checkpoints every 10 steps): backward / forward
 time and the device memory it holds; and the combined run on the 4096x1024
@@ -138,6 +139,33 @@ def run_loop2(name: str, scheme: int, tol: float, steps: int, warmup: int, max_i
             "ms_per_step": round(wall / steps * 1e3, 4), "ms_per_pass": round(wall / npass * 1e3, 5),
             "fixed_count_ms_per_pass": round(wall_fixed / npass * 1e3, 5),
             "mfv_iters_s": round(p.n_fv * npass / wall / 1e6, 2)}
+
+
+def run_loop3(name: str, scheme: int, steps: int, warmup: int, n3s=(1, 2, 3)):
+    """Steps whose passes run loop 3 (n3 energy-pressure solves, sts_step_l3)
+    on the bench workload: time per step for each n3."""
+    import torch
+    from paper_1802_04243_amd import sts
+
+    p, run = W.workload(name)
+    out = {"workload": name, "n_inner": run["inner"], "steps": steps}
+    for n3 in n3s:
+        g = sts.Solver(p)
+        g.set_fields(*W.initial_fields(p, run["seed"]))
+        for _ in range(warmup):
+            g.step_l3(run["dt"], run["inner"], n3, scheme)
+        g.residuals()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.step_l3(run["dt"], run["inner"], n3, scheme)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        g.residuals()
+        g.close()
+        out[f"n3_{n3}"] = {"ms_per_step": round(wall / steps * 1e3, 4),
+                           "mfv_iters_s": round(p.n_fv * run["inner"] * steps / wall / 1e6, 2)}
+    return out
 
 
 def run_adjoint(name: str = "adjoint_1024x256"):
@@ -280,6 +308,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-loop2", action="store_true",
                     help="skip the loop-2-to-convergence timing (sts_step_tol)")
+    ap.add_argument("--no-loop3", action="store_true",
+                    help="skip the loop-3 timing (sts_step_l3, n3 = 1, 2, 3)")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined run (mixed forward + FP64 adjoint, 4096x1024)")
     ap.add_argument("--other-grids",
@@ -345,6 +375,11 @@ def main():
         print(f"# loop 2 to tol 1e-6: {loop2['passes_per_step']} passes/step, "
               f"{loop2['ms_per_pass']:.4f} ms/pass (fixed count {loop2['fixed_count_ms_per_pass']:.4f})",
               file=sys.stderr, flush=True)
+    loop3 = None
+    if not a.no_loop3:
+        loop3 = run_loop3(a.workload, W.SCHEMES[HEADLINE], 20, a.warmup)
+        print("# loop 3: " + ", ".join(f"{k} {v['ms_per_step']:.3f} ms/step" for k, v in loop3.items()
+                                      if k.startswith("n3_")), file=sys.stderr, flush=True)
     others = {g: run_other_grid(g, a.steps, a.warmup) for g in a.other_grids.split(",") if g}
     h = per[HEADLINE]
     traffic = measured_traffic(HEADLINE)
@@ -388,6 +423,7 @@ def main():
         "other_grids": others or None,
         "mixed": mixed or None,
         "loop2_to_convergence": loop2,
+        "loop3": loop3,
         "adjoint": adj,
         "combined": comb,
     }
