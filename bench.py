@@ -165,6 +165,21 @@ def run_loop3(name: str, scheme: int, steps: int, warmup: int, n3s=(1, 2, 3)):
         g.close()
         out[f"n3_{n3}"] = {"ms_per_step": round(wall / steps * 1e3, 4),
                            "mfv_iters_s": round(p.n_fv * run["inner"] * steps / wall / 1e6, 2)}
+    # loop 2 to convergence (tolerance 1e-6) with one and two solves per pass
+    for n3 in (1, 2):
+        g = sts.Solver(p)
+        g.set_fields(*W.initial_fields(p, run["seed"]))
+        for _ in range(warmup):
+            g.step(run["dt"], run["inner"], scheme)
+        g.residuals()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        counts = [g.step_tol_l3(run["dt"], 60, n3, 1e-6, scheme) for _ in range(5)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        g.close()
+        out[f"to_tol_1e-6_n3_{n3}"] = {"passes_per_step": round(sum(counts) / len(counts), 2),
+                                       "ms_per_step": round(wall / len(counts) * 1e3, 4)}
     return out
 
 
@@ -379,7 +394,7 @@ def main():
     if not a.no_loop3:
         loop3 = run_loop3(a.workload, W.SCHEMES[HEADLINE], 20, a.warmup)
         print("# loop 3: " + ", ".join(f"{k} {v['ms_per_step']:.3f} ms/step" for k, v in loop3.items()
-                                      if k.startswith("n3_")), file=sys.stderr, flush=True)
+                                      if isinstance(v, dict)), file=sys.stderr, flush=True)
     others = {g: run_other_grid(g, a.steps, a.warmup) for g in a.other_grids.split(",") if g}
     h = per[HEADLINE]
     traffic = measured_traffic(HEADLINE)

@@ -167,6 +167,12 @@ sts_status sts_step_l3(sts_ctx *ctx, double dt, int n_inner, int n3, int scheme)
 sts_status sts_step_tol(sts_ctx *ctx, double dt, int max_inner, double tol, int scheme,
                         int *n_inner);
 
+/* sts_step_tol with loop 3 (n3 energy-pressure solves, as sts_step_l3) in
+   every pass; n3 = 1 is sts_step_tol.  STS_EINVAL as sts_step_tol, and for
+   n3 outside [1, 64] or STS_MIXED with n3 > 1; STS_ENOMEM as sts_step_l3. */
+sts_status sts_step_tol_l3(sts_ctx *ctx, double dt, int max_inner, int n3, double tol,
+                           int scheme, int *n_inner);
+
 /* Wait for the stream; out[6] = max|du|, max|dv|, max|dp|, max|dT| of the
    last pass over the unknowns, max|R| and sum R of the discrete continuity
    residual R = ((p/T)_new - (p/T)^{n-1}) dV/dt + net outflow of

@@ -1329,11 +1329,16 @@ void ora_step_l3(ora_ctx *c, double dt, int n_inner, int n3, int scheme) {
    unknowns, after each pass; at most max_inner passes.  Returns the number
    of passes taken. */
 int ora_step_tol(ora_ctx *c, double dt, int max_inner, double tol, int scheme) {
+  return ora_step_tol_l3(c, dt, max_inner, 1, tol, scheme);
+}
+
+/* The same with loop 3 in every pass (n3 energy-pressure solves). */
+int ora_step_tol_l3(ora_ctx *c, double dt, int max_inner, int n3, double tol, int scheme) {
   c->idt = 1.0 / dt;
   prologue(c, scheme);
   int k = 0;
   while (k < max_inner) {
-    pass(c, dt, scheme, 1);
+    pass(c, dt, scheme, n3);
     k++;
     double r = dmax(dmax(c->res[0], c->res[1]), dmax(c->res[3], c->res[2] / c->p_in));
     if (r <= tol) break;

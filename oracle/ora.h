@@ -66,6 +66,8 @@ void ora_step_l3(ora_ctx *c, double dt, int n_inner, int n3, int scheme);
    max(max|du|, max|dv|, max|dT|, max|dp|/p_in) <= tol, or after max_inner
    passes; returns the passes taken. */
 int ora_step_tol(ora_ctx *c, double dt, int max_inner, double tol, int scheme);
+/* ora_step_tol with loop 3 (n3 >= 1 energy-pressure solves) in every pass. */
+int ora_step_tol_l3(ora_ctx *c, double dt, int max_inner, int n3, double tol, int scheme);
 /* Residuals of the last pass: max|du|, max|dv|, max|dp|, max|dT|,
    max|R_mass|, sum R_mass. */
 void ora_residuals(const ora_ctx *c, double out[6]);

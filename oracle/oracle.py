@@ -58,6 +58,8 @@ def lib():
         L.ora_step_l3.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_int]
         L.ora_step_tol.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_int]
         L.ora_step_tol.restype = C.c_int
+        L.ora_step_tol_l3.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_double, C.c_int]
+        L.ora_step_tol_l3.restype = C.c_int
         L.ora_residuals.argtypes = [C.c_void_p, _D]
         L.ora_mass.argtypes = [C.c_void_p, _D]
         L.ora_params.argtypes = [C.c_double] * 4 + [_D]
@@ -160,6 +162,11 @@ class Oracle:
     def step_l3(self, dt, n_inner, n3, scheme):
         """One step whose passes run loop 3 with n3 energy-pressure solves."""
         lib().ora_step_l3(self._h, float(dt), int(n_inner), int(n3), int(scheme))
+
+    def step_tol_l3(self, dt, max_inner, n3, tol, scheme) -> int:
+        """step_tol with loop 3 (n3 energy-pressure solves) in every pass."""
+        return int(lib().ora_step_tol_l3(self._h, float(dt), int(max_inner), int(n3), float(tol),
+                                         int(scheme)))
 
     def step_tol(self, dt, max_inner, tol, scheme) -> int:
         """One step whose loop 2 stops at the tolerance; returns the passes taken."""

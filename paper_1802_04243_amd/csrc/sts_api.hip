@@ -593,6 +593,41 @@ extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
   return STS_OK;
 }
 
+namespace {
+// the scratch (T, p) pairs of loop 3, allocated on first use
+sts_status ensure_l3(sts_ctx *c) {
+  if (c->l3_mem) return STS_OK;
+  const size_t fb = c->L.field_bytes;
+  if (hipMalloc((void **)&c->l3_mem, 4 * fb) != hipSuccess) {
+    c->l3_mem = nullptr;
+    return fail(STS_ENOMEM, "hipMalloc of %zu bytes failed", 4 * fb);
+  }
+  const size_t n = (size_t)c->L.pitch * c->L.rows;
+  std::vector<double> one(n, 1.0);
+  for (int q = 0; q < 2; q++) {
+    c->l3T[q] = (double *)(c->l3_mem + (2 * q) * fb);
+    c->l3p[q] = (double *)(c->l3_mem + (2 * q + 1) * fb);
+    HIPCHK(hipMemcpyAsync(c->l3T[q], one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->l3p[q], one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return STS_OK;
+}
+
+// one pass with loop 3 from iterate o into nw (n3 >= 2 launches); X: the
+// residual inputs of the pass (last pass of a step, or every pass of a loop 2
+// run to convergence, whose stop flag every launch honours), or NULL
+void launch_l3_pass(sts_ctx *c, State o, State nw, int n3, int scheme, const Resid *X) {
+  launch_pass3(c->P, o, nw, c->C, scheme, X, 1, nullptr, nullptr, c->l3T[0], c->l3p[0],
+               c->stream);
+  int q = 0;  // the pair holding the previous solve
+  for (int sub = 2; sub < n3; sub++, q ^= 1)
+    launch_pass3(c->P, o, nw, c->C, scheme, X, 1, c->l3T[q], c->l3p[q], c->l3T[q ^ 1],
+                 c->l3p[q ^ 1], c->stream);
+  launch_pass3(c->P, o, nw, c->C, scheme, X, 2, c->l3T[q], c->l3p[q], nullptr, nullptr, c->stream);
+}
+}  // namespace
+
 // Loop 2 with its convergence test.  Every pass produces its increment
 // maxima (the last-pass kernel variant); one small reduction over its tile
 // rows takes the convergence decision on the device (a flag and a pass count,
@@ -606,13 +641,21 @@ extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
 // (Sec. 5); the passes taken and the state reached are the same.
 constexpr int L2_GROUP = 2;
 
-extern "C" sts_status sts_step_tol(sts_ctx *c, double dt, int max_inner, double tol, int scheme,
-                                   int *n_inner) {
+namespace {
+sts_status step_tol(sts_ctx *c, double dt, int max_inner, int n3, double tol, int scheme,
+                    int *n_inner) {
   if (!c || !n_inner) return fail(STS_EINVAL, "NULL argument");
   if (!(dt > 0) || !isfinite(dt)) return fail(STS_EINVAL, "dt must be > 0");
   if (max_inner < 1) return fail(STS_EINVAL, "max_inner must be >= 1");
   if (!(tol >= 0) || !isfinite(tol)) return fail(STS_EINVAL, "tol must be >= 0 and finite");
   if (scheme & ~STS_SCHEME_MASK) return fail(STS_EINVAL, "unknown scheme bits 0x%x", scheme);
+  if (n3 < 1 || n3 > 64) return fail(STS_EINVAL, "n3 must be in [1, 64]");
+  if (n3 > 1 && (scheme & STS_MIXED))
+    return fail(STS_EINVAL, "loop 3 is of the FP64 step (scheme 0x%x)", scheme);
+  if (n3 > 1) {
+    const sts_status s = ensure_l3(c);
+    if (s != STS_OK) return s;
+  }
   c->P.dt = dt;
   c->P.idt = 1.0 / dt;
   launch_prologue(c->P, c->st[c->cur], c->C, scheme, c->stream);
@@ -630,7 +673,8 @@ extern "C" sts_status sts_step_tol(sts_ctx *c, double dt, int max_inner, double 
   for (int k = 0; k < max_inner;) {
     for (const int e = std::min(k + L2_GROUP, max_inner); k < e; k++) {
       const int a = cur0 ^ (k & 1);
-      launch_pass(c->P, c->st[a], c->st[a ^ 1], c->C, scheme, &X, nullptr, c->stream);
+      if (n3 == 1) launch_pass(c->P, c->st[a], c->st[a ^ 1], c->C, scheme, &X, nullptr, c->stream);
+      else launch_l3_pass(c, c->st[a], c->st[a ^ 1], n3, scheme, &X);
       L.k = k + 1;
       launch_loop2_check(c->P, X, c->dres, L, c->stream);
     }
@@ -658,6 +702,18 @@ extern "C" sts_status sts_step_tol(sts_ctx *c, double dt, int max_inner, double 
   *n_inner = k;
   return STS_OK;
 }
+}  // namespace
+
+extern "C" sts_status sts_step_tol(sts_ctx *c, double dt, int max_inner, double tol, int scheme,
+                                   int *n_inner) {
+  return step_tol(c, dt, max_inner, 1, tol, scheme, n_inner);
+}
+
+extern "C" sts_status sts_step_tol_l3(sts_ctx *c, double dt, int max_inner, int n3, double tol,
+                                      int scheme, int *n_inner) {
+  return step_tol(c, dt, max_inner, n3, tol, scheme, n_inner);
+}
+
 
 // Loop 3 of the CPU algorithm inside every pass (n3 energy-pressure solves):
 // the first solve from the pass's iterate, then n3 - 2 solves into the two
@@ -673,35 +729,14 @@ extern "C" sts_status sts_step_l3(sts_ctx *c, double dt, int n_inner, int n3, in
   if (scheme & ~STS_SCHEME_MASK) return fail(STS_EINVAL, "unknown scheme bits 0x%x", scheme);
   if (n3 == 1) return sts_step(c, dt, n_inner, scheme);
   if (scheme & STS_MIXED) return fail(STS_EINVAL, "loop 3 is of the FP64 step (scheme 0x%x)", scheme);
-  if (!c->l3_mem) {
-    const size_t fb = c->L.field_bytes;
-    if (hipMalloc((void **)&c->l3_mem, 4 * fb) != hipSuccess) {
-      c->l3_mem = nullptr;
-      return fail(STS_ENOMEM, "hipMalloc of %zu bytes failed", 4 * fb);
-    }
-    const size_t n = (size_t)c->L.pitch * c->L.rows;
-    std::vector<double> one(n, 1.0);
-    for (int q = 0; q < 2; q++) {
-      c->l3T[q] = (double *)(c->l3_mem + (2 * q) * fb);
-      c->l3p[q] = (double *)(c->l3_mem + (2 * q + 1) * fb);
-      HIPCHK(hipMemcpyAsync(c->l3T[q], one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
-      HIPCHK(hipMemcpyAsync(c->l3p[q], one.data(), n * 8, hipMemcpyHostToDevice, c->stream));
-    }
-    HIPCHK(hipStreamSynchronize(c->stream));
-  }
+  sts_status s;
+  if ((s = ensure_l3(c)) != STS_OK) return s;
   c->P.dt = dt;
   c->P.idt = 1.0 / dt;
   launch_prologue(c->P, c->st[c->cur], c->C, scheme, c->stream);
   for (int k = 0; k < n_inner; k++) {
-    const State o = c->st[c->cur], nw = c->st[c->cur ^ 1];
-    launch_pass3(c->P, o, nw, c->C, scheme, nullptr, 1, nullptr, nullptr, c->l3T[0], c->l3p[0],
-                 c->stream);
-    int q = 0;  // the pair holding the previous solve
-    for (int sub = 2; sub < n3; sub++, q ^= 1)
-      launch_pass3(c->P, o, nw, c->C, scheme, nullptr, 1, c->l3T[q], c->l3p[q], c->l3T[q ^ 1],
-                   c->l3p[q ^ 1], c->stream);
-    launch_pass3(c->P, o, nw, c->C, scheme, k == n_inner - 1 ? &c->X : nullptr, 2, c->l3T[q],
-                 c->l3p[q], nullptr, nullptr, c->stream);
+    launch_l3_pass(c, c->st[c->cur], c->st[c->cur ^ 1], n3, scheme,
+                   k == n_inner - 1 ? &c->X : nullptr);
     c->cur ^= 1;
   }
   HIPCHK(hipGetLastError());

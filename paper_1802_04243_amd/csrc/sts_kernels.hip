@@ -1378,7 +1378,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
     const Params P, const State o, const State n, const Consts C, const Resid X,
     const double *Ts, const double *ps, double *To, double *po) {
   __shared__ Lds s;
-  if (RS && X.stop && *X.stop) return;
+  if (X.stop && *X.stop) return;  // loop 2 has converged
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
   double c[Items<NTH>::rounds], cp;

@@ -25,7 +25,7 @@ EXPLICIT, IMPLICIT, UPWIND, TVD, MIXED = 0, 1, 0, 2, 4
 EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_step_tol", "sts_residuals", "sts_fields",
            "sts_set_fields", "sts_field_ptrs", "sts_timing", "sts_read_timing", "sts_drag",
            "sts_state_slots", "sts_state_save", "sts_state_load", "sts_adjoint_begin",
-           "sts_adjoint_seed_drag", "sts_adjoint_seed", "sts_adjoint_step", "sts_step_l3", "sts_adjoint_read", "sts_destroy",
+           "sts_adjoint_seed_drag", "sts_adjoint_seed", "sts_adjoint_step", "sts_step_l3", "sts_step_tol_l3", "sts_adjoint_read", "sts_destroy",
            "sts_last_error")
 
 _D = C.POINTER(C.c_double)
@@ -90,6 +90,8 @@ def lib():
         L.sts_adjoint_seed_drag.argtypes = [C.c_void_p, C.c_double]
         L.sts_adjoint_seed.argtypes = [C.c_void_p] + [_D] * 4
         L.sts_step_l3.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_int]
+        L.sts_step_tol_l3.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_double,
+                                      C.c_int, C.POINTER(C.c_int)]
         L.sts_adjoint_step.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int]
         L.sts_adjoint_read.argtypes = [C.c_void_p] + [_D] * 7
         L.sts_destroy.argtypes = [C.c_void_p]
@@ -176,6 +178,13 @@ class Solver:
     def step_l3(self, dt: float, n_inner: int, n3: int, scheme: int):
         """One step whose passes each solve the energy and pressure equations n3 times."""
         _check(lib().sts_step_l3(self._h, float(dt), int(n_inner), int(n3), int(scheme)))
+
+    def step_tol_l3(self, dt: float, max_inner: int, n3: int, tol: float, scheme: int) -> int:
+        """step_tol with loop 3 (n3 energy-pressure solves) in every pass."""
+        n = C.c_int(0)
+        _check(lib().sts_step_tol_l3(self._h, float(dt), int(max_inner), int(n3), float(tol),
+                                     int(scheme), C.byref(n)))
+        return n.value
 
     def step_tol(self, dt: float, max_inner: int, tol: float, scheme: int) -> int:
         """One step with loop 2 stopped at the tolerance; returns the passes taken."""

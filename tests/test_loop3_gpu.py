@@ -6,8 +6,10 @@ difference <= 1e-10 per field and the residuals.  Cases: the small channel
 in every scheme with 2 and 3 solves per pass; a ragged non-uniform grid with
 a slip-jump and a no-slip wall, two obstacles, heated walls and a body force;
 a periodic slip-jump channel; the 4x4 grid; one step of the bench grid
-(5120x1152, explicit TVD, 2 solves) from a GPU-advanced state.  Plus: one
-solve is sts_step, and the argument checks.
+(5120x1152, explicit TVD, 2 solves) from a GPU-advanced state; loop 2 run
+to convergence with two solves per pass (sts_step_tol_l3: the oracle's pass
+counts, every scheme, and the bench grid).  Plus: one solve is sts_step /
+sts_step_tol, and the argument checks.
 """
 from __future__ import annotations
 
@@ -88,6 +90,53 @@ def test_loop3_full_size_step_from_gpu_state(sts_mod, oracle_lib):
     g.close()
 
 
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_loop3_with_tolerance_exit(sts_mod, oracle_lib, name, scheme):
+    # loop 2 to convergence with two solves per pass: the oracle's pass
+    # counts and bitwise-equal fields
+    p, run = W.workload("channel_120x24")
+    tol = 1e-4 if scheme == W.IMPLICIT | W.TVD else 1e-8
+    print(f"case loop 3 + tolerance exit 120x24/{name} tol {tol:g}", flush=True)
+    g = sts_mod.Solver(p)
+    o = oracle_lib.Oracle(p)
+    f0 = W.initial_fields(p, 1)
+    g.set_fields(*f0)
+    o.set_fields(*f0)
+    for _ in range(3):
+        g.step(run["dt"], 20, scheme)
+        o.step(run["dt"], 20, scheme)
+    counts = []
+    for _ in range(5):
+        ng = g.step_tol_l3(run["dt"], 60, 2, tol, scheme)
+        no = o.step_tol_l3(run["dt"], 60, 2, tol, scheme)
+        assert ng == no, (ng, no)
+        counts.append(ng)
+    print(f"passes per step {counts}", flush=True)
+    assert max(counts) < 60
+    compare(g, o, f"loop 3 + tolerance exit 120x24/{name}")
+    g.close()
+
+
+def test_loop3_with_tolerance_exit_full_size(sts_mod, oracle_lib):
+    p, run = W.workload("channel_5120x1152")
+    scheme = W.EXPLICIT | W.TVD
+    print("case loop 3 + tolerance exit channel_5120x1152 n3=2 tol 1e-6", flush=True)
+    g = sts_mod.Solver(p)
+    g.set_fields(*W.initial_fields(p, run["seed"]))
+    for _ in range(3):
+        g.step(run["dt"], run["inner"], scheme)
+    state = g.fields()
+    g.set_fields(*state)
+    o = oracle_lib.Oracle(p)
+    o.set_fields(*state)
+    ng = g.step_tol_l3(run["dt"], 60, 2, 1e-6, scheme)
+    no = o.step_tol_l3(run["dt"], 60, 2, 1e-6, scheme)
+    print(f"passes gpu {ng} oracle {no}", flush=True)
+    assert ng == no and 1 < ng < 60
+    compare(g, o, "loop 3 + tolerance exit channel_5120x1152")
+    g.close()
+
+
 def test_loop3_one_solve_is_the_step_and_argument_checks(sts_mod):
     p, run = W.workload("channel_120x24")
     f0 = W.initial_fields(p, 3)
@@ -106,5 +155,14 @@ def test_loop3_one_solve_is_the_step_and_argument_checks(sts_mod):
         with pytest.raises(sts_mod.StsError) as e:
             a.step_l3(*args)
         assert e.value.code == sts_mod.STS_EINVAL, args
+        with pytest.raises(sts_mod.StsError) as e:
+            a.step_tol_l3(args[0], args[1], args[2], 1e-8, args[3])
+        assert e.value.code == sts_mod.STS_EINVAL, args
+    # one solve per pass is sts_step_tol
+    a.set_fields(*f0)
+    b.set_fields(*f0)
+    assert a.step_tol_l3(run["dt"], 40, 1, 1e-8, W.EXPLICIT) == b.step_tol(run["dt"], 40, 1e-8, W.EXPLICIT)
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
     a.close()
     b.close()

@@ -96,3 +96,30 @@ def test_loop3_preserves_a_uniform_stream(oracle_lib, scheme):
     for a, b in zip(o.fields(), f0):
         assert np.array_equal(a, b)
     assert np.all(o.residuals() == 0.0)
+
+
+@pytest.mark.parametrize("name,scheme", [("explicit_upwind", W.EXPLICIT | W.UPWIND),
+                                         ("explicit_tvd", W.EXPLICIT | W.TVD)])
+def test_loop3_shortens_loop2(oracle_lib, name, scheme):
+    # loop 2 run to convergence: two solves per pass take fewer passes than
+    # one, more solves no fewer than two (the CPU algorithm's "two are
+    # usually enough"); the converged fields agree to the tolerance's level
+    p, run = W.workload("channel_120x24")
+    f = _start(oracle_lib, p, run, scheme)
+    counts, fields = {}, {}
+    for n3 in (1, 2, 3):
+        o = oracle_lib.Oracle(p)
+        o.set_fields(*f)
+        counts[n3] = [o.step_tol_l3(run["dt"], 100, n3, 1e-8, scheme) for _ in range(3)]
+        fields[n3] = o.fields()
+    print(f"{name}: loop-2 passes per step with n3 = 1, 2, 3: {counts}")
+    assert sum(counts[2]) < 0.9 * sum(counts[1])
+    assert sum(counts[3]) >= 0.9 * sum(counts[2])
+    assert _rel(fields[2], fields[1]) < 1e-6 and _rel(fields[3], fields[1]) < 1e-6
+    o = oracle_lib.Oracle(p)
+    o.set_fields(*f)
+    q = oracle_lib.Oracle(p)
+    q.set_fields(*f)
+    assert o.step_tol_l3(run["dt"], 100, 1, 1e-8, scheme) == q.step_tol(run["dt"], 100, 1e-8, scheme)
+    for a, b in zip(o.fields(), q.fields()):
+        assert np.array_equal(a, b)
