@@ -1348,9 +1348,10 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
 // the problem has velocity-slip / temperature-jump surfaces (their branches
 // are compiled only into these instances, which keeps the register
 // allocation of the others as it is without them).
-// Two blocks share a CU (LDS bound).  The explicit schemes use NTP threads
-// (6 waves per SIMD, at most 80 VGPRs); the implicit ones and the mixed
-// explicit TVD pass need more registers and use NT threads (4 waves per
+// Two blocks share a CU (LDS bound).  The explicit schemes and the mixed
+// implicit upwind pass use NTP threads (6 waves per SIMD, at most 80 VGPRs);
+// the FP64 implicit ones, the mixed TVD passes and the explicit TVD pass with
+// slip-jump surfaces need more registers and use NT threads (4 waves per
 // SIMD, at most 128 VGPRs).
 template <int NTH, bool IM, bool TV, bool RS, bool MX, bool IN, bool SJ>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_pass(
@@ -1621,10 +1622,11 @@ __global__ __launch_bounds__(RB) void k_continuity(const Params P,
     for (int t = 0; t < 4; t++) inc[t] = fmax(inc[t], q[t]);
     bad += q[6];
   }
-  const long ncell = (long)P.nx * P.ny;
-  for (long c = (long)blockIdx.x * RB + threadIdx.x; c < ncell;
-       c += (long)gridDim.x * RB) {
-    const int i = (int)(c % P.nx), j = (int)(c / P.nx);
+  // row segments of RB cells: one (block-uniform) division per segment
+  const int nseg = (P.nx + RB - 1) / RB, nunit = nseg * P.ny;
+  for (int q = blockIdx.x; q < nunit; q += gridDim.x) {
+    const int j = q / nseg, i = (q - j * nseg) * RB + threadIdx.x;
+    if (i >= P.nx) continue;
     const long k = P.off + (long)j * P.pitch + i;
     if (!P.fl[k]) continue;
     const double dV = P.gx_[0][i + XPAD] * P.gy_[0][j + XPAD];
@@ -1693,7 +1695,7 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
   // adjoint's recompute); the caller guarantees !im && !last with inter
 #define STS_PASS_SJ(IM_, TV_, MX_, SJ_)                                                     \
   do {                                                                                      \
-    constexpr int nth = (IM_ || (MX_ && TV_)) ? NT : NTP;                                   \
+    constexpr int nth = ((IM_ && !MX_) || (TV_ && (MX_ || SJ_))) ? NT : NTP;                \
     if (last)                                                                               \
       hipLaunchKernelGGL((k_pass<nth, IM_, TV_, true, MX_, false, SJ_>), g, dim3(nth), 0, st, P, o, n, C, X, I); \
     else if (inter && !IM_)                                                                 \
