@@ -434,7 +434,7 @@ __global__ __launch_bounds__(AB) void k_adj_front(const Params P, const State o,
 // ---------------------------------------------------------------------------
 // (2) energy equation of a fluid cell (explicit scheme)
 // ---------------------------------------------------------------------------
-template <class S>
+template <bool SJ, class S>
 __device__ void energy_item(const Params &P, const State o, const Cache cc, const State lo, const Consts C,
                             const Consts lC, const Inter I, const AdjTmp A, double *gtw0,
                             double *gtw1, int i, int j, S &sk) {
@@ -446,7 +446,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   const double idx = gx(P, 1, i), idy = gy(P, 1, j);
   const double gP = gam(P, cc, i, j), TP = at(o.T, P, i, j);
   const double rP = rho(P, cc, i, j);
-  const bool jo = P.otype == 2;  // slip-jump obstacle surfaces
+  const bool jo = SJ && P.otype == 2;  // slip-jump obstacle surfaces
   // conductances and neighbour values (the forward's rules), with the
   // partials of each conductance in Gamma_P, Gamma_nb, the wall sqrt(T) and
   // (slip-jump surfaces) rho_P
@@ -499,7 +499,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
       DS = K * hmean2_d(gP, P.sq_Tw0[i], dSP, dSw);
       dSP *= K;
       dSw *= K;
-    } else if (P.wtype0 == 2) {
+    } else if (SJ && P.wtype0 == 2) {
       nS = P.Tw0[i];
       DS = jwall_d(P.C1 * dxi, gP, dyj, P.kt, rP, dSP, dSr);
     } else {
@@ -528,7 +528,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
       DN = K * hmean2_d(gP, P.sq_Tw1[i], dNP, dNw);
       dNP *= K;
       dNw *= K;
-    } else if (P.wtype1 == 2) {
+    } else if (SJ && P.wtype1 == 2) {
       nN = P.Tw1[i];
       DN = jwall_d(P.C1 * dxi, gP, dyj, P.kt, rP, dNP, dNr);
     } else {
@@ -572,7 +572,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   if (j == 0) {
     if (P.wtype0 == 0) {
       unsafeAtomicAdd(gtw0 + i, lnum * dt * DS + lDS * dSw / (2.0 * P.sq_Tw0[i]));
-    } else if (P.wtype0 == 2) {
+    } else if (SJ && P.wtype0 == 2) {
       unsafeAtomicAdd(gtw0 + i, lnum * dt * DS);
     } else {
       sk.add(0, P, i, j, lnum * dt * DS);
@@ -584,7 +584,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   if (j == P.ny - 1) {
     if (P.wtype1 == 0) {
       unsafeAtomicAdd(gtw1 + i, lnum * dt * DN + lDN * dNw / (2.0 * P.sq_Tw1[i]));
-    } else if (P.wtype1 == 2) {
+    } else if (SJ && P.wtype1 == 2) {
       unsafeAtomicAdd(gtw1 + i, lnum * dt * DN);
     } else {
       sk.add(0, P, i, j, lnum * dt * DN);
@@ -618,7 +618,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   }
   if (j == P.ny - 1) {
     if (P.wtype1 == 0) uN = P.wu1;
-    else if (P.wtype1 == 2) { uN = slip_d(P.wu1, uc, dyj, P.kz, rP, suN, ruN); cuN = 3; }
+    else if (SJ && P.wtype1 == 2) { uN = slip_d(P.wu1, uc, dyj, P.kz, rP, suN, ruN); cuN = 3; }
     else { uN = uc; cuN = 1; }
   } else if (!fl(P, i, j + 1) && jo) { uN = slip_d(0.0, uc, dyj, P.kz, rP, suN, ruN); cuN = 3; }
   else if (!fl(P, i, j + 1)) uN = 0.0;
@@ -628,7 +628,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   }
   if (j == 0) {
     if (P.wtype0 == 0) uS = P.wu0;
-    else if (P.wtype0 == 2) { uS = slip_d(P.wu0, uc, dyj, P.kz, rP, suS, ruS); cuS = 3; }
+    else if (SJ && P.wtype0 == 2) { uS = slip_d(P.wu0, uc, dyj, P.kz, rP, suS, ruS); cuS = 3; }
     else { uS = uc; cuS = 1; }
   } else if (!fl(P, i, j - 1) && jo) { uS = slip_d(0.0, uc, dyj, P.kz, rP, suS, ruS); cuS = 3; }
   else if (!fl(P, i, j - 1)) uS = 0.0;
@@ -695,7 +695,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
 // ---------------------------------------------------------------------------
 // (2) u-hat, d^u of a solved u-face (explicit scheme)
 // ---------------------------------------------------------------------------
-template <class S>
+template <bool SJ, class S>
 __device__ void uhat_item(const Params &P, const State o, const Cache cc, const State lo, const Consts C,
                           const Consts lC, const Inter I, const AdjTmp A, double *gtw0,
                           double *gtw1, int i, int j, S &sk) {
@@ -722,13 +722,13 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
     if (P.wtype0 == 0) {
       uS = P.wu0; kS = 0; dS = 1;
       DS = B * 0.5 * (gnode + P.sq_Twu0[i]) * len * (2.0 * idy);
-    } else if (P.wtype0 == 2) {
+    } else if (SJ && P.wtype0 == 2) {
       uS = P.wu0; kS = 0; dS = 4;
       DS = jwall_d(B * len, gnode, dyj, P.kz, rnode, jSg, jSr);
     } else { uS = uP; kS = 1; dS = 0; DS = 0.0; }
   } else {
     uS = at(o.u, P, i, j - 1); kS = 2;
-    if (!fl(P, i - 1, j - 1) && !fl(P, i, j - 1) && P.otype == 2) {
+    if (!fl(P, i - 1, j - 1) && !fl(P, i, j - 1) && SJ && P.otype == 2) {
       dS = 4; DS = jwall_d(B * len, gnode, dyj, P.kz, rnode, jSg, jSr);
     } else if (!fl(P, i - 1, j - 1) && !fl(P, i, j - 1)) {
       dS = 2; DS = B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * idy);
@@ -740,13 +740,13 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
     if (P.wtype1 == 0) {
       uN = P.wu1; kN = 0; dN = 1;
       DN = B * 0.5 * (gnode + P.sq_Twu1[i]) * len * (2.0 * idy);
-    } else if (P.wtype1 == 2) {
+    } else if (SJ && P.wtype1 == 2) {
       uN = P.wu1; kN = 0; dN = 4;
       DN = jwall_d(B * len, gnode, dyj, P.kz, rnode, jNg, jNr);
     } else { uN = uP; kN = 1; dN = 0; DN = 0.0; }
   } else {
     uN = at(o.u, P, i, j + 1); kN = 2;
-    if (!fl(P, i - 1, j + 1) && !fl(P, i, j + 1) && P.otype == 2) {
+    if (!fl(P, i - 1, j + 1) && !fl(P, i, j + 1) && SJ && P.otype == 2) {
       dN = 4; DN = jwall_d(B * len, gnode, dyj, P.kz, rnode, jNg, jNr);
     } else if (!fl(P, i - 1, j + 1) && !fl(P, i, j + 1)) {
       dN = 2; DN = B * 0.5 * (gnode + P.sq_obsT) * len * (2.0 * idy);
@@ -823,7 +823,7 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
 // ---------------------------------------------------------------------------
 // (2) v-hat, d^v of a solved v-face (explicit scheme)
 // ---------------------------------------------------------------------------
-template <class S>
+template <bool SJ, class S>
 __device__ void vhat_item(const Params &P, const State o, const Cache cc, const State lo, const Consts C,
                           const Consts lC, const Inter I, const AdjTmp A, int i, int j, S &sk) {
   if (i >= P.nx || !v_solved(P, i, j)) return;
@@ -846,7 +846,7 @@ __device__ void vhat_item(const Params &P, const State o, const Cache cc, const 
   // j*r in rnode); 0 none
   int dW, dE;
   double jWg = 0, jWr = 0, jEg = 0, jEr = 0;
-  const bool so = P.otype == 2;
+  const bool so = SJ && P.otype == 2;
   if (inl) { dW = 1; DW = B * 0.5 * (gnode + gcW) * len * (2.0 * idx); }
   else if (!fl(P, i - 1, j - 1) && !fl(P, i - 1, j) && so) {
     dW = 4; DW = jwall_d(B * len, gnode, dxi, P.kz, rnode, jWg, jWr);
@@ -983,7 +983,9 @@ __global__ __launch_bounds__(AB) void k_adj_rho_faces(const Params P, const Stat
 // inputs and add into shared targets, so one launch runs them side by side
 // (blockIdx.y selects the stage): four times the blocks of one stage, which
 // keeps the CUs busy on grids whose single stage would leave them half idle.
-template <bool TV>
+// SJ: the problem has slip-jump surfaces (their branches are compiled only
+// into these instances, which keeps the others' registers as without them).
+template <bool TV, bool SJ>
 __global__ __launch_bounds__(AB) void k_adj_stage2(const Params P, const State o,
                                                    const State lo, const Consts C,
                                                    const Consts lC, const Inter I,
@@ -995,17 +997,17 @@ __global__ __launch_bounds__(AB) void k_adj_stage2(const Params P, const State o
   if (blockIdx.y == 0) {
     Tiled<4, 1, false> sk{(lds_double *)wl, {lo.T, A.lg, lo.u, lo.v}};
     sk.begin(P, i, j);
-    if (i <= P.nx && j <= P.ny) energy_item(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
+    if (i <= P.nx && j <= P.ny) energy_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
     sk.end(P);
   } else if (blockIdx.y == 1) {
     Tiled<4, 1, false> sk{(lds_double *)wl, {lo.u, lo.v, A.lr, A.lg}};
     sk.begin(P, i, j);
-    if (i <= P.nx && j <= P.ny) uhat_item(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
+    if (i <= P.nx && j <= P.ny) uhat_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
     sk.end(P);
   } else if (blockIdx.y == 2) {
     Tiled<4, 1, false> sk{(lds_double *)wl, {lo.u, lo.v, A.lr, A.lg}};
     sk.begin(P, i, j);
-    if (i <= P.nx && j <= P.ny) vhat_item(P, o, cc, lo, C, lC, I, A, i, j, sk);
+    if (i <= P.nx && j <= P.ny) vhat_item<SJ>(P, o, cc, lo, C, lC, I, A, i, j, sk);
     sk.end(P);
   } else {
     Tiled<1, 2, false> sk{(lds_double *)wl, {A.lr}};
@@ -1518,10 +1520,13 @@ void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, 
   const dim3 g = agrid(P), b(AB);
   hipLaunchKernelGGL(k_adj_front, tgrid(P), b, 0, st, P, o, ln, lo, lC, I, A);
   const dim3 g4(tgrid(P).x, 4);
-  if (scheme & 2)
-    hipLaunchKernelGGL((k_adj_stage2<true>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
-  else
-    hipLaunchKernelGGL((k_adj_stage2<false>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
+  if (scheme & 2) {
+    if (P.sj) hipLaunchKernelGGL((k_adj_stage2<true, true>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
+    else hipLaunchKernelGGL((k_adj_stage2<true, false>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
+  } else {
+    if (P.sj) hipLaunchKernelGGL((k_adj_stage2<false, true>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
+    else hipLaunchKernelGGL((k_adj_stage2<false, false>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
+  }
   hipLaunchKernelGGL(k_adj_cell_props, g, b, 0, st, P, o, lo, A.lr, A.lg);
 }
 
