@@ -158,6 +158,26 @@ def test_full_size_step_from_gpu_state(sts_mod, oracle_lib, wl, name, scheme):
     g.close()
 
 
+@pytest.mark.parametrize("scheme", [W.EXPLICIT | W.TVD, W.IMPLICIT | W.UPWIND])
+def test_large_grid_uniform_stream_is_preserved(sts_mod, scheme):
+    # a 16384 x 16384 channel (268M FV, 30 GB of device workspace, arrays of
+    # 2.2 GB, byte offsets past 2^32 in the workspace) started from the
+    # library's own inlet state, a uniform stream between slip walls: every
+    # equation returns its old value, so every residual is exactly zero (the
+    # oracle's free-stream pin, at a size no oracle run reaches)
+    n = 16384
+    p = W.Problem(nx=n, ny=n, lx=8.0, ly=8.0,
+                  wall_type=(W.WALL_SLIP_ADIABATIC, W.WALL_SLIP_ADIABATIC))
+    print(f"case uniform stream {n}x{n} scheme {scheme}", flush=True)
+    g = sts_mod.Solver(p)
+    for _ in range(2):
+        g.step(p.cfl_dt(), 3, scheme)
+    r = g.residuals()
+    print(f"residuals {r}", flush=True)
+    assert np.all(r == 0.0), r
+    g.close()
+
+
 def test_nonfinite_is_reported(sts_mod):
     p, run = W.workload("channel_120x24")
     g = sts_mod.Solver(p)
