@@ -1204,7 +1204,10 @@ __device__ __forceinline__ void item_consts(const Params &P, const Consts &C,
 // a pass (the plain pass's outputs; the increments of the residual-producing
 // variant are taken against the pass's iterate o, as the window holds the
 // previous solve's T and p).
-template <int NTH, bool CL, bool SJ, bool IM, bool TV, bool RS, bool MX, bool IN, int L3 = 0>
+// S1 = false: the face densities are already in LDS (the first pass of a
+// step, which computed them for its step constants).
+template <int NTH, bool CL, bool SJ, bool IM, bool TV, bool RS, bool MX, bool IN, int L3 = 0,
+          bool S1 = true>
 __device__ void pass_body(Lds &s, const Params &P, const State n,
                           const Resid X, const Inter I, int tile, int x0,
                           int y0, const double c[], double cp, const State o = State{},
@@ -1217,17 +1220,19 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
 
   // stage 1: face densities rho^u on [-1,TX] x [-2,TY], rho^v on
   // [-2,TX] x [-1,TY] (one combined loop)
-  for (int k = t; k < BX * (BY + 1) + (BX + 1) * BY; k += NTH) {
-    if (k < BX * (BY + 1)) {
-      const int fi = k % BX - 1, fj = k / BX - 2;
-      RU_(fi, fj) = rho_xface<CL, TV, MX>(s, P, fi, fj, x0 + fi, y0 + fj);
-    } else {
-      const int q = k - BX * (BY + 1);
-      const int fi = q % (BX + 1) - 2, fj = q / (BX + 1) - 1;
-      RV_(fi, fj) = rho_yface<CL, TV, MX>(s, P, fi, fj, y0 + fj);
+  if constexpr (S1) {
+    for (int k = t; k < BX * (BY + 1) + (BX + 1) * BY; k += NTH) {
+      if (k < BX * (BY + 1)) {
+        const int fi = k % BX - 1, fj = k / BX - 2;
+        RU_(fi, fj) = rho_xface<CL, TV, MX>(s, P, fi, fj, x0 + fi, y0 + fj);
+      } else {
+        const int q = k - BX * (BY + 1);
+        const int fi = q % (BX + 1) - 2, fj = q / (BX + 1) - 1;
+        RV_(fi, fj) = rho_yface<CL, TV, MX>(s, P, fi, fj, y0 + fj);
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
 
   // stage 2: T on [-1,TX-1] x [-1,TY-1]; u-hat, d^u on [-1,TX] x [-1,TY-1];
   // v-hat, d^v on [-1,TX-1] x [-1,TY]
@@ -1596,6 +1601,97 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
 }
 
 // ---------------------------------------------------------------------------
+// The step prologue fused into the step's first pass (FP64, NT threads): the
+// first pass's iterate is the level n-1 state, so its window and face
+// densities are the prologue's.  Every thread computes the step constants of
+// its three items (cell, u-face, v-face at its position, halo included) with
+// the prologue's formulas, stores those of the owned items for the later
+// passes and uses them itself; a position outside the domain takes 0, the
+// value the constant arrays hold there (u-face nx and v-face ny included).
+// ---------------------------------------------------------------------------
+template <int KIND, bool CL, bool EX, bool TV>
+__device__ __forceinline__ double first_const(const Lds &s, const Params &P, int i, int j,
+                                              int gi, int gj, double &cpv) {
+  cpv = 0.0;
+  if (!(gj >= 0 && gj < P.ny && (P.per || (gi >= 0 && gi < P.nx)))) return 0.0;
+  const double dxi = DX_(i), dyj = DY_(j);
+  if (KIND == 0) {
+    double CT = 0.0;
+    if (FL_(i, j)) {
+      const double dV = dxi * dyj;
+      CT = R_(i, j) * T_(i, j) * dV;
+      if (EX) CT += P.dt * t_explicit<CL, TV>(s, P, i, j, gi, gj);
+      cpv = R_(i, j) * dV;
+    }
+    return CT;
+  } else if (KIND == 1) {
+    double Cu = 0.0;
+    if (u_solved(s, P, i, j, gi)) {
+      const double M = (R_(i, j) * dxi + R_(i - 1, j) * DX_(i - 1)) * dyj / 2.0;
+      Cu = M * P.idt * U_(i, j) + P.gx * M;
+      if (EX) Cu += u_explicit<CL, TV>(s, P, i, j, gi, gj);
+    }
+    return Cu;
+  } else {
+    double Cv = 0.0;
+    if (v_solved(s, P, i, j, gj)) {
+      const double M = (R_(i, j) * dyj + R_(i, j - 1) * DY_(j - 1)) * dxi / 2.0;
+      Cv = M * P.idt * V_(i, j) + P.gy * M;
+      if (EX) Cv += v_explicit<CL, TV>(s, P, i, j, gi, gj);
+    }
+    return Cv;
+  }
+}
+
+template <bool CL, bool SJ, bool IM, bool TV>
+__device__ void first_body(Lds &s, const Params &P, const State n, const Consts C, int tile,
+                           int x0, int y0) {
+  const int t = threadIdx.x;
+  for (int k = t; k < BX * (BY + 1) + (BX + 1) * BY; k += NT) {
+    if (k < BX * (BY + 1)) {
+      const int fi = k % BX - 1, fj = k / BX - 2;
+      RU_(fi, fj) = rho_xface<CL, TV>(s, P, fi, fj, x0 + fi, y0 + fj);
+    } else {
+      const int q = k - BX * (BY + 1);
+      const int fi = q % (BX + 1) - 2, fj = q / (BX + 1) - 1;
+      RV_(fi, fj) = rho_yface<CL, TV>(s, P, fi, fj, y0 + fj);
+    }
+  }
+  __syncthreads();
+  // the thread's items: the cell (used on [-1,TX-1] x [-1,TY-1]), the u-face
+  // ([-1,TX] x [-1,TY-1]) and the v-face ([-1,TX-1] x [-1,TY]) at (i, j)
+  const int i = t % BX - 1, j = t / BX - 1, gi = x0 + i, gj = y0 + j;
+  constexpr bool EX = !IM;
+  double c[3] = {0.0, 0.0, 0.0}, cp = 0.0, dummy;
+  if (i <= TX - 1 && j <= TY - 1) c[0] = first_const<0, CL, EX, TV>(s, P, i, j, gi, gj, cp);
+  if (j <= TY - 1) c[1] = first_const<1, CL, EX, TV>(s, P, i, j, gi, gj, dummy);
+  if (i <= TX - 1) c[2] = first_const<2, CL, EX, TV>(s, P, i, j, gi, gj, dummy);
+  if (i >= 0 && i < TX && j >= 0 && j < TY && gi < P.nx && gj < P.ny) {
+    const long k = P.off + (long)gj * P.pitch + gi;
+    C.CT[k] = c[0];
+    C.Cp[k] = cp;
+    C.Cu[k] = c[1];
+    C.Cv[k] = c[2];
+  }
+  pass_body<NT, CL, SJ, IM, TV, false, false, false, 0, false>(
+      s, P, n, Resid{nullptr, nullptr, nullptr, nullptr}, Inter{}, tile, x0, y0, c, cp);
+}
+
+template <bool IM, bool TV, bool SJ>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2 * NT / 256))) void k_pass_first(
+    const Params P, const State o, const State n, const Consts C) {
+  __shared__ Lds s;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
+  load_window<NT>(s, P, o, x0, y0);
+  __syncthreads();
+  if (P.clean[tile])
+    first_body<true, false, IM, TV>(s, P, n, C, tile, x0, y0);
+  else
+    first_body<false, SJ, IM, TV>(s, P, n, C, tile, x0, y0);
+}
+
+// ---------------------------------------------------------------------------
 // continuity residual of the last pass (eq pl24 written as a residual):
 //   R = (rho_new - rho^{n-1}) dV / dt + net outflow of the face mass fluxes,
 // with rho^{n-1} dV = C_p and the fluxes written by the last pass
@@ -1683,6 +1779,21 @@ void launch_prologue(const Params &P, State m, Consts C, int scheme,
   if (ex && tv) hipLaunchKernelGGL((k_prologue<NT, true, true>), g, dim3(NT), 0, st, P, m, C);
   else if (ex) hipLaunchKernelGGL((k_prologue<NTP, true, false>), g, dim3(NTP), 0, st, P, m, C);
   else hipLaunchKernelGGL((k_prologue<NTP, false, false>), g, dim3(NTP), 0, st, P, m, C);
+}
+
+void launch_pass_first(const Params &P, State o, State n, Consts C, int scheme, hipStream_t st) {
+  const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0;
+  dim3 g(ntiles(P));
+#define STS_PF(IM_, TV_)                                                                          \
+  do {                                                                                            \
+    if (P.sj) hipLaunchKernelGGL((k_pass_first<IM_, TV_, true>), g, dim3(NT), 0, st, P, o, n, C);  \
+    else hipLaunchKernelGGL((k_pass_first<IM_, TV_, false>), g, dim3(NT), 0, st, P, o, n, C);      \
+  } while (0)
+  if (im && tv) STS_PF(true, true);
+  else if (im) STS_PF(true, false);
+  else if (tv) STS_PF(false, true);
+  else STS_PF(false, false);
+#undef STS_PF
 }
 
 void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
