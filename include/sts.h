@@ -135,8 +135,8 @@ sts_status sts_create(const sts_grid *grid, const sts_obstacles *obstacles,
 /* Advance one time step of size dt > 0 with n_inner >= 1 Jacobi passes of
    loop 2 (scheme: STS_* bits).  Enqueues on the context's stream and returns
    without waiting.  The residuals of the last pass are reduced on the device
-   and copied to pinned host memory.  With an FP64 scheme and n_inner >= 2
-   the step prologue runs inside the first pass's launch (the same values). */
+   and copied to pinned host memory.  With n_inner >= 2 the step prologue
+   runs inside the first pass's launch (the same values). */
 sts_status sts_step(sts_ctx *ctx, double dt, int n_inner, int scheme);
 
 /* One time step of n_inner passes, each running loop 3 of the CPU
@@ -206,9 +206,9 @@ sts_status sts_timing(sts_ctx *ctx, int enable);
 /* Wait, then return the kernel time summed over the steps recorded since
    timing was enabled or last read: out_ms[0] step prologues, [1] the Jacobi
    passes, [2] residual reductions (with the residual copy), in milliseconds;
-   out_n[0] = steps, out_n[1] = passes counted in [1].  A step of an FP64
-   scheme with n_inner >= 2 runs its prologue inside its first pass: [0]
-   then holds that fused launch and [1] the other n_inner - 1 passes.
+   out_n[0] = steps, out_n[1] = passes counted in [1].  A step with
+   n_inner >= 2 runs its prologue inside its first pass: [0] then holds that
+   fused launch and [1] the other n_inner - 1 passes.
    Clears the accumulation. */
 sts_status sts_read_timing(sts_ctx *ctx, double out_ms[3], long long out_n[2]);
 

@@ -568,9 +568,9 @@ extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
   c->P.dt = dt;
   c->P.idt = 1.0 / dt;
   sts_status s;
-  // the FP64 schemes fold the prologue into the first pass (its iterate is
-  // the level n-1 state); the timing slot of the prologue then holds both
-  const bool fused = !(scheme & STS_MIXED) && n_inner >= 2;
+  // the prologue runs inside the first pass (its iterate is the level n-1
+  // state); the timing slot of the prologue then holds both
+  const bool fused = n_inner >= 2;
   if ((s = record(c, 0)) != STS_OK) return s;
   if (fused) {
     launch_pass_first(c->P, c->st[c->cur], c->st[c->cur ^ 1], c->C, scheme, c->stream);

@@ -105,8 +105,8 @@ void launch_prologue(const Params &P, State m, Consts C, int scheme,
                      hipStream_t st);
 void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
                  const Resid *last, const Inter *inter, hipStream_t st);
-// the step prologue fused into the step's first pass (FP64 schemes; a step
-// of at least two passes): writes the step constants and the first iterate
+// the step prologue fused into the step's first pass (a step of at least two
+// passes): writes the step constants and the first iterate
 void launch_pass_first(const Params &P, State o, State n, Consts C, int scheme, hipStream_t st);
 // one energy-pressure solve of a pass with loop 3 (FP64 schemes): L3 = 1 a
 // solve before the last (T, p into To, po; Ts = NULL for the first, whose T

@@ -1601,7 +1601,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
 }
 
 // ---------------------------------------------------------------------------
-// The step prologue fused into the step's first pass (FP64, NT threads): the
+// The step prologue fused into the step's first pass (NT threads): the
 // first pass's iterate is the level n-1 state, so its window and face
 // densities are the prologue's.  Every thread computes the step constants of
 // its three items (cell, u-face, v-face at its position, halo included) with
@@ -1643,7 +1643,9 @@ __device__ __forceinline__ double first_const(const Lds &s, const Params &P, int
   }
 }
 
-template <bool CL, bool SJ, bool IM, bool TV>
+// MX (mixed form): the constants take the FP64 face densities, as the
+// separate prologue does; the pass then recomputes them with its FP32 limiter.
+template <bool CL, bool SJ, bool IM, bool TV, bool MX>
 __device__ void first_body(Lds &s, const Params &P, const State n, const Consts C, int tile,
                            int x0, int y0) {
   const int t = threadIdx.x;
@@ -1673,22 +1675,23 @@ __device__ void first_body(Lds &s, const Params &P, const State n, const Consts 
     C.Cu[k] = c[1];
     C.Cv[k] = c[2];
   }
-  pass_body<NT, CL, SJ, IM, TV, false, false, false, 0, false>(
+  if constexpr (MX) __syncthreads();  // every read of the FP64 densities is done
+  pass_body<NT, CL, SJ, IM, TV, false, MX, false, 0, MX>(
       s, P, n, Resid{nullptr, nullptr, nullptr, nullptr}, Inter{}, tile, x0, y0, c, cp);
 }
 
-template <bool IM, bool TV, bool SJ>
+template <bool IM, bool TV, bool SJ, bool MX>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2 * NT / 256))) void k_pass_first(
     const Params P, const State o, const State n, const Consts C) {
   __shared__ Lds s;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
-  load_window<NT>(s, P, o, x0, y0);
+  load_window<NT, MX>(s, P, o, x0, y0);
   __syncthreads();
   if (P.clean[tile])
-    first_body<true, false, IM, TV>(s, P, n, C, tile, x0, y0);
+    first_body<true, false, IM, TV, MX>(s, P, n, C, tile, x0, y0);
   else
-    first_body<false, SJ, IM, TV>(s, P, n, C, tile, x0, y0);
+    first_body<false, SJ, IM, TV, MX>(s, P, n, C, tile, x0, y0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1782,17 +1785,23 @@ void launch_prologue(const Params &P, State m, Consts C, int scheme,
 }
 
 void launch_pass_first(const Params &P, State o, State n, Consts C, int scheme, hipStream_t st) {
-  const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0;
+  const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0, mx = (scheme & 4) != 0;
   dim3 g(ntiles(P));
-#define STS_PF(IM_, TV_)                                                                          \
-  do {                                                                                            \
-    if (P.sj) hipLaunchKernelGGL((k_pass_first<IM_, TV_, true>), g, dim3(NT), 0, st, P, o, n, C);  \
-    else hipLaunchKernelGGL((k_pass_first<IM_, TV_, false>), g, dim3(NT), 0, st, P, o, n, C);      \
+#define STS_PF(IM_, TV_, MX_)                                                                          \
+  do {                                                                                                 \
+    if (P.sj) hipLaunchKernelGGL((k_pass_first<IM_, TV_, true, MX_>), g, dim3(NT), 0, st, P, o, n, C);  \
+    else hipLaunchKernelGGL((k_pass_first<IM_, TV_, false, MX_>), g, dim3(NT), 0, st, P, o, n, C);      \
   } while (0)
-  if (im && tv) STS_PF(true, true);
-  else if (im) STS_PF(true, false);
-  else if (tv) STS_PF(false, true);
-  else STS_PF(false, false);
+#define STS_PFM(IM_, TV_)                  \
+  do {                                     \
+    if (mx) STS_PF(IM_, TV_, true);        \
+    else STS_PF(IM_, TV_, false);          \
+  } while (0)
+  if (im && tv) STS_PFM(true, true);
+  else if (im) STS_PFM(true, false);
+  else if (tv) STS_PFM(false, true);
+  else STS_PFM(false, false);
+#undef STS_PFM
 #undef STS_PF
 }
 

@@ -121,3 +121,22 @@ def test_mixed_deterministic(sts_mod):
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
     assert np.array_equal(ra, rb)
+
+
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_mixed_fused_first_pass_equals_separate_prologue(sts_mod, name, scheme):
+    # sts_step runs the prologue inside the first pass; loop 2 with tolerance
+    # 0 launches the prologue on its own (the path of the adjoint's
+    # recompute): the mixed form must give the same bits either way
+    p, run = W.workload("channel_120x24")
+    f0 = W.initial_fields(p, 3)
+    a, b = sts_mod.Solver(p), sts_mod.Solver(p)
+    a.set_fields(*f0)
+    b.set_fields(*f0)
+    for _ in range(4):
+        a.step(run["dt"], 6, scheme | W.MIXED)
+        assert b.step_tol(run["dt"], 6, 0.0, scheme | W.MIXED) == 6
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y), name
+    a.close()
+    b.close()
