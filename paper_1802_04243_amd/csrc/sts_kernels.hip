@@ -1764,6 +1764,21 @@ __global__ __launch_bounds__(FB) void k_finalize(const double *rows, int nrows,
   }
 }
 
+// fold the per-tile rows of a pass (increment maxima, non-finite count) into
+// one row per block, for k_finalize; returns at once when loop 2 has stopped
+__global__ __launch_bounds__(RB) void k_fold_rows(const double *tiles, int ntile, double *rows,
+                                                  const int *stop) {
+  __shared__ double red[RB / 64][NRES];
+  if (stop && *stop) return;
+  double v[NRES] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = blockIdx.x * RB + threadIdx.x; b < ntile; b += gridDim.x * RB) {
+    const double *q = tiles + (long)b * NRES;
+    for (int t = 0; t < 4; t++) v[t] = fmax(v[t], q[t]);
+    v[6] += q[6];
+  }
+  block_partials<RB>(red, v, rows + (long)blockIdx.x * NRES);
+}
+
 __global__ void k_loop2_reset(int *ctl) {
   if (threadIdx.x < 2) ctl[threadIdx.x] = 0;
 }
@@ -1890,8 +1905,19 @@ void launch_loop2_reset(int *ctl, hipStream_t st) {
 void launch_loop2_check(const Params &P, Resid X, double *out, const Loop2 &L,
                         hipStream_t st) {
   // the per-tile rows of the pass hold the increment maxima and the
-  // non-finite count; the continuity sum is not needed for the decision
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, X.partials, ntiles(P), out, L);
+  // non-finite count; the continuity sum is not needed for the decision.
+  // Up to 4 rows per thread the decision block folds them itself (one launch);
+  // more take two levels, one row per block first (measured: 3 % shorter
+  // tolerance steps on 5120x1152, 14,193 tiles; 3 % longer on 4032x200).
+  const int nt = ntiles(P);
+  if (nt <= 4 * FB) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, X.partials, nt, out, L);
+    return;
+  }
+  const int nb = std::min(RES_BLOCKS, (nt + RB - 1) / RB);
+  double *rows = X.partials + (long)nt * NRES;
+  hipLaunchKernelGGL(k_fold_rows, dim3(nb), dim3(RB), 0, st, X.partials, nt, rows, L.ctl);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, st, rows, nb, out, L);
 }
 
 void launch_loop2_final(const Params &P, State even, State odd, Consts C, Resid X, double *out,
