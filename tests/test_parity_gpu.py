@@ -178,6 +178,23 @@ def test_large_grid_uniform_stream_is_preserved(sts_mod, scheme):
     g.close()
 
 
+def test_step_timing_counts(sts_mod):
+    # sts_read_timing: steps and passes; a step of n_inner >= 2 passes runs
+    # its prologue inside the first pass, which the prologue slot then holds
+    p, run = W.workload("channel_120x24")
+    g = sts_mod.Solver(p)
+    g.set_fields(*W.initial_fields(p, 1))
+    g.timing(True)
+    for inner in (6, 6, 1):
+        g.step(run["dt"], inner, W.EXPLICIT | W.TVD)
+    ms, n = g.read_timing()
+    print(f"timing ms {ms}, counts {n}", flush=True)
+    assert list(n) == [3, 5 + 5 + 1]
+    assert all(x > 0 for x in ms)
+    g.timing(False)
+    g.close()
+
+
 def test_nonfinite_is_reported(sts_mod):
     p, run = W.workload("channel_120x24")
     g = sts_mod.Solver(p)
