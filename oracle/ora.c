@@ -6,14 +6,18 @@
  *
  * What it computes (paper sections / equations):
  *   loop 1 (time steps) and loop 2 (inner Jacobi passes) of SIMPLE-TS, GPU
- *   form (Sec. 3.1, figures of the explicit and implicit algorithms);
+ *   form (Sec. 3.1, figures of the explicit and implicit algorithms), with a
+ *   fixed pass count or until the increments fall below a tolerance;
  *   one pass in the order of Appendix A: face densities (pl10, pl11), mass
  *   fluxes (pl8, pl9), temperature (pl30 with pl31 or pl31_1, pl32, pl33,
  *   source pl28/pl29), pseudo velocities (pl20, pl21 with pl14-pl16,
- *   pl15_11), pressure (pl23, pl24), velocities (pl18, pl19).
+ *   pl15_11), pressure (pl23, pl24), velocities (pl18, pl19);
+ *   optionally loop 3 of the CPU algorithm inside each pass (the energy and
+ *   pressure equations solved n3 times with the pass's coefficients);
+ *   velocity-slip / temperature-jump surfaces (pl38, pl39).
  * The u-equation is not printed in the paper (it gives v only); here it is the
  * x<->y mirror image of the printed v-equation.  Boundary rules, constants and
- * the readings of garbled passages are the ones listed in the design notes
+ * the readings of garbled passages are stated where each is implemented
  * (van Leer in the (r+|r|)/(1+|r|) form, face density = upwind + psi*jump,
  * C^{T1..3}_f = gamma*C^{T1}, gamma*C^{T2}, -(gamma-1)).
  *
