@@ -985,8 +985,10 @@ __global__ __launch_bounds__(AB) void k_adj_rho_faces(const Params P, const Stat
 // keeps the CUs busy on grids whose single stage would leave them half idle.
 // SJ: the problem has slip-jump surfaces (their branches are compiled only
 // into these instances, which keeps the others' registers as without them).
+// The others fit 5 waves per SIMD (91 VGPRs; 3.5 % shorter backward on
+// 4096x1024 than at 4); the slip-jump ones would spill there and keep 4.
 template <bool TV, bool SJ>
-__global__ __launch_bounds__(AB) void k_adj_stage2(const Params P, const State o,
+__global__ __launch_bounds__(AB) __attribute__((amdgpu_waves_per_eu(SJ ? 4 : 5))) void k_adj_stage2(const Params P, const State o,
                                                    const State lo, const Consts C,
                                                    const Consts lC, const Inter I,
                                                    const AdjTmp A, double *gtw0, double *gtw1) {
