@@ -14,6 +14,8 @@ times, each with T and p from the previous solve).
 - Within one pass the sub-iterations contract: the change from n3 to n3 + 1
   shrinks geometrically.
 - A uniform stream between walls moving with it is preserved bitwise.
+- Mirror symmetry about the channel's mid-plane is kept (u, p, T even, v odd).
+- Loop 2 run to convergence: two solves per pass take fewer passes than one.
 """
 from __future__ import annotations
 
@@ -123,3 +125,24 @@ def test_loop3_shortens_loop2(oracle_lib, name, scheme):
     assert o.step_tol_l3(run["dt"], 100, 1, 1e-8, scheme) == q.step_tol(run["dt"], 100, 1e-8, scheme)
     for a, b in zip(o.fields(), q.fields()):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("scheme", list(W.SCHEMES.values()))
+def test_loop3_keeps_mirror_symmetry(oracle_lib, scheme):
+    # a channel symmetric about y = H/2 stays symmetric (u, p, T even, v odd)
+    # through steps with three solves per pass: the sub-iterations keep the
+    # index and sign bookkeeping of the plain pass
+    p = W.channel(40, 12, [2.5], wall_u=(0.3, 0.3))
+    rng = np.random.default_rng(2)
+    shapes = ((p.ny, p.nx + 1), (p.ny + 1, p.nx), (p.ny, p.nx), (p.ny, p.nx))
+    u, v, pr, T = [rng.uniform(-0.2, 0.2, s) for s in shapes]
+    pr, T, u = 1.0 + pr, 1.0 + T, 1.0 + u
+    u, pr, T, v = 0.5 * (u + u[::-1]), 0.5 * (pr + pr[::-1]), 0.5 * (T + T[::-1]), 0.5 * (v - v[::-1])
+    o = oracle_lib.Oracle(p)
+    o.set_fields(u, v, pr, T)
+    for _ in range(4):
+        o.step_l3(0.005, 4, 3, scheme)
+    u, v, pr, T = o.fields()
+    for a, sgn in ((u, 1), (pr, 1), (T, 1), (v, -1)):
+        assert np.abs(a - sgn * a[::-1]).max() <= 1e-12 * np.abs(a).max()
+    assert np.abs(v).max() > 1e-6   # the flow is not trivially symmetric
