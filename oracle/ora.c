@@ -21,6 +21,22 @@
  * (van Leer in the (r+|r|)/(1+|r|) form, face density = upwind + psi*jump,
  * C^{T1..3}_f = gamma*C^{T1}, gamma*C^{T2}, -(gamma-1)).
  *
+ * Every formula is written as the paper prints it: conductances and
+ * gradients divide by the printed widths and distances, unsteady terms by
+ * 2 dt or dt, the limiter takes r = a/b; nothing is precomputed or
+ * refactored for speed.
+ *
+ * Pinned against the mathematics, not against another implementation
+ * (tests/test_oracle_pins.py, test_manufactured.py, test_slip_jump_pins.py,
+ * test_loop3_pins.py): closed forms (pl37 constants, compressible Couette and
+ * Poiseuille with heat conduction, the hydrostatic box, slip Couette, jump
+ * conduction), the continuous operators integrated over the control volumes
+ * (manufactured solutions: every interior term at its truncation order, wall,
+ * obstacle, inlet and outlet volumes at first order per face length), the
+ * speed of sound, the convective schemes' orders, invariants (bitwise
+ * free-stream preservation, mirror symmetry, the mass identity, TVD with the
+ * limiter off = upwind, solid rows = a channel wall).
+ *
  * Plain loops, no blocking, no fusion; OpenMP only splits rows of a loop.
  * Build with -ffp-contract=off.
  */
@@ -34,15 +50,6 @@
 struct ora_ctx {
   int nx, ny, per;
   double *dx, *dy;
-  /* geometric factors (computed once from the widths):
-     per cell column i: idx = 1/dx, ihx = 1/(dx/2);
-     per x-face k (between cells k-1 and k): sx = dx_{k-1} + dx_k,
-     wlx = dx_k/sx (weight of cell k-1 at the face), wrx = dx_{k-1}/sx
-     (weight of cell k), icx = 1/(sx/2) (inverse centre distance),
-     isx = 1/sx; the same in y */
-  double *idx, *ihx, *sx, *wlx, *wrx, *icx, *isx;
-  double *idy, *ihy, *sy, *wly, *wry, *icy, *isy;
-  double idt;
   unsigned char *solid; /* [ny][nx] */
   double A, B, C1, C2, C3, gx, gy;
   double *u_in, *T_in, p_in;
@@ -83,8 +90,6 @@ static int cw(const ora_ctx *c, int i) {
   return i;
 }
 static double DX(const ora_ctx *c, int i) { return c->dx[cw(c, i)]; }
-/* x-face factor arrays are stored for faces 0..nx; wrap when periodic */
-static int fwx(const ora_ctx *c, int k) { return c->per ? cw(c, k) : k; }
 static int solid(const ora_ctx *c, int i, int j) {
   return c->solid[IC(c, cw(c, i), j)];
 }
@@ -152,40 +157,45 @@ static double upwind(double f1, double f2, double vel) {
   return vel > 0 ? f1 : f2;
 }
 
+/* Test switch: with the limiter off every TVD correction is zero, which
+   must give the upwind scheme bit for bit (Sec. 3.2 after pl15_2: with
+   upwind approximation the corrections are null). */
+static int limiter_on = 1;
+void ora_set_limiter(int on) { limiter_on = on ? 1 : 0; }
+
 /* van Leer limiter psi(r) (Sec. 3.2 after pl15_2) of r = a/b.  The printed
    denominator (1+r) is read as (1+|r|), the standard van Leer form the paper
    cites: both agree wherever the printed form is defined.  r <= 0 gives 0;
-   r undefined (b == 0) is taken as 0; for r > 0 it is 2a/(a+b). */
+   r undefined (b == 0) is taken as 0; r overflowing to infinity gives the
+   limit 2. */
 double ora_vanleer(double a, double b) {
+  if (!limiter_on) return 0.0;
   if (!((a > 0 && b > 0) || (a < 0 && b < 0))) return 0.0;
-  /* r > 0: (r+|r|)/(1+|r|) = 2r/(1+r) = 2a/(a+b) */
-  return 2.0 * a / (a + b);
+  double r = a / b;
+  if (isinf(r)) return 2.0;
+  return (r + fabs(r)) / (1.0 + fabs(r));
 }
 
-/* TVD correction at a surface between two nodes, non-uniform grid (pl15_2).
-   In terms of the face factors of the face between nodes 2 and 3:
-   s12 = d1+d2, s23 = d2+d3, s34 = d3+d4, w2 = d2/s23, w3 = d3/s23. */
-static double psi_sf(double f1, double f2, double f3, double f4, double s12,
-                     double s23, double s34, double w2, double w3,
-                     double vel) {
-  if (vel > 0) return w2 * ora_vanleer(s23 * (f2 - f1), s12 * (f3 - f2));
-  return -w3 * ora_vanleer(s23 * (f4 - f3), s34 * (f3 - f2));
-}
+/* TVD correction at a surface between two nodes, non-uniform grid (pl15_2) */
 double ora_psi_s(double f1, double f2, double f3, double f4, double d1,
                  double d2, double d3, double d4, double vel) {
-  return psi_sf(f1, f2, f3, f4, d1 + d2, d2 + d3, d3 + d4, d2 / (d2 + d3),
-                d3 / (d2 + d3), vel);
+  if (vel > 0)
+    return d2 / (d2 + d3) *
+           ora_vanleer((d2 + d3) * (f2 - f1), (d1 + d2) * (f3 - f2));
+  return -d3 / (d2 + d3) *
+         ora_vanleer((d2 + d3) * (f4 - f3), (d3 + d4) * (f3 - f2));
 }
-/* psi_s at x-face k of a cell-row stencil k-2 .. k+1, and at y-face k */
+/* psi_s at x-face k of a cell-row stencil k-2 .. k+1 (widths of those
+   cells), and at y-face k */
 static double psi_x(const ora_ctx *c, double f1, double f2, double f3,
                     double f4, int k, double vel) {
-  return psi_sf(f1, f2, f3, f4, c->sx[fwx(c, k - 1)], c->sx[fwx(c, k)],
-                c->sx[fwx(c, k + 1)], c->wrx[fwx(c, k)], c->wlx[fwx(c, k)], vel);
+  return ora_psi_s(f1, f2, f3, f4, DX(c, k - 2), DX(c, k - 1), DX(c, k),
+                   DX(c, k + 1), vel);
 }
 static double psi_y(const ora_ctx *c, double f1, double f2, double f3,
                     double f4, int k, double vel) {
-  return psi_sf(f1, f2, f3, f4, c->sy[k - 1], c->sy[k], c->sy[k + 1],
-                c->wry[k], c->wly[k], vel);
+  return ora_psi_s(f1, f2, f3, f4, c->dy[k - 2], c->dy[k - 1], c->dy[k],
+                   c->dy[k + 1], vel);
 }
 
 /* TVD correction at a control-volume centre (pl15_1) */
@@ -222,8 +232,9 @@ static double gam_harm2(double a, double b) { return 2.0 * a * b / (a + b); }
 
 /* wall temperature of wall w at the x-position of u-face i */
 static double wallT_uface(const ora_ctx *c, int w, int i) {
-  int l = cw(c, i - 1), r = cw(c, i), k = fwx(c, i);
-  return c->wlx[k] * c->wT[w][l] + c->wrx[k] * c->wT[w][r];
+  int l = cw(c, i - 1), r = cw(c, i);
+  double dl = c->dx[l], dr = c->dx[r];
+  return (dr * c->wT[w][l] + dl * c->wT[w][r]) / (dl + dr);
 }
 
 /* Gamma at the corner (x^f_i, y^f_j), bilinear in the four surrounding
@@ -232,13 +243,15 @@ static double wallT_uface(const ora_ctx *c, int w, int i) {
    channel walls only ever multiply wall velocities, which are zero: 0. */
 static double gam_corner(const ora_ctx *c, const double *gam, int i, int j) {
   if (j <= 0 || j >= c->ny) return 0.0;
-  double ws = c->wly[j], wn = c->wry[j];
+  double dys = c->dy[j - 1], dyn = c->dy[j];
+  double ws = dyn / (dys + dyn), wn = dys / (dys + dyn);
   if (!c->per && i == 0)
     return ws * sqrt(c->T_in[j - 1]) + wn * sqrt(c->T_in[j]);
   if (!c->per && i == c->nx)
     return ws * gam[IC(c, c->nx - 1, j - 1)] + wn * gam[IC(c, c->nx - 1, j)];
-  int l = cw(c, i - 1), r = cw(c, i), k = fwx(c, i);
-  double wl = c->wlx[k], wr = c->wrx[k];
+  int l = cw(c, i - 1), r = cw(c, i);
+  double dl = c->dx[l], dr = c->dx[r];
+  double wl = dr / (dl + dr), wr = dl / (dl + dr);
   return ws * (wl * gam[IC(c, l, j - 1)] + wr * gam[IC(c, r, j - 1)]) +
          wn * (wl * gam[IC(c, l, j)] + wr * gam[IC(c, r, j)]);
 }
@@ -460,16 +473,20 @@ static void face_centre_vel(const ora_ctx *c, int i, int j, double *vE,
   } else if (solid(c, i + 1, j)) {
     *vE = (c->otype == 2) ? slip_vel(0.0, vc, c->dx[i], zP) : 0.0;
   } else {
-    int r = cw(c, i + 1), k = fwx(c, i + 1);
-    *vE = c->wlx[k] * vc + c->wrx[k] * (0.5 * (v[IV(c, r, j)] + v[IV(c, r, j + 1)]));
+    int r = cw(c, i + 1);
+    double dxi = c->dx[i], dr = c->dx[r];
+    *vE = dr / (dxi + dr) * vc +
+          dxi / (dxi + dr) * (0.5 * (v[IV(c, r, j)] + v[IV(c, r, j + 1)]));
   }
   if (!c->per && i == 0) {
     *vW = 0.0;
   } else if (solid(c, i - 1, j)) {
     *vW = (c->otype == 2) ? slip_vel(0.0, vc, c->dx[i], zP) : 0.0;
   } else {
-    int l = cw(c, i - 1), k = fwx(c, i);
-    *vW = c->wlx[k] * (0.5 * (v[IV(c, l, j)] + v[IV(c, l, j + 1)])) + c->wrx[k] * vc;
+    int l = cw(c, i - 1);
+    double dxi = c->dx[i], dl = c->dx[l];
+    *vW = dxi / (dl + dxi) * (0.5 * (v[IV(c, l, j)] + v[IV(c, l, j + 1)])) +
+          dl / (dl + dxi) * vc;
   }
   double uc = 0.5 * (Uat(c, u, i, j) + Uat(c, u, i + 1, j));
   if (j == c->ny - 1) {
@@ -479,8 +496,10 @@ static void face_centre_vel(const ora_ctx *c, int i, int j, double *vE,
   } else if (solid(c, i, j + 1)) {
     *uN = (c->otype == 2) ? slip_vel(0.0, uc, c->dy[j], zP) : 0.0;
   } else {
-    *uN = c->wly[j + 1] * uc +
-          c->wry[j + 1] * (0.5 * (Uat(c, u, i, j + 1) + Uat(c, u, i + 1, j + 1)));
+    double dyj = c->dy[j], dn = c->dy[j + 1];
+    *uN = dn / (dyj + dn) * uc +
+          dyj / (dyj + dn) *
+              (0.5 * (Uat(c, u, i, j + 1) + Uat(c, u, i + 1, j + 1)));
   }
   if (j == 0) {
     *uS = (c->wtype[0] == 0)   ? c->wu[0]
@@ -489,8 +508,10 @@ static void face_centre_vel(const ora_ctx *c, int i, int j, double *vE,
   } else if (solid(c, i, j - 1)) {
     *uS = (c->otype == 2) ? slip_vel(0.0, uc, c->dy[j], zP) : 0.0;
   } else {
-    *uS = c->wly[j] * (0.5 * (Uat(c, u, i, j - 1) + Uat(c, u, i + 1, j - 1))) +
-          c->wry[j] * uc;
+    double dyj = c->dy[j], ds = c->dy[j - 1];
+    *uS = dyj / (ds + dyj) *
+              (0.5 * (Uat(c, u, i, j - 1) + Uat(c, u, i + 1, j - 1))) +
+          ds / (ds + dyj) * uc;
   }
 }
 
@@ -509,16 +530,16 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   /* west face x^f_i */
   if (!c->per && i == 0) { /* inlet: T_in on the face, half cell away */
     q.nb[0] = c->T_in[j];
-    D[0] = c->C1 * gam_harm2(gP, sqrt(c->T_in[j])) * dyj * c->ihx[i];
+    D[0] = c->C1 * gam_harm2(gP, sqrt(c->T_in[j])) * dyj / (0.5 * dxi);
   } else {
     int l = cw(c, i - 1);
     q.nb[0] = T[IC(c, l, j)];
     if (c->solid[IC(c, l, j)])
       D[0] = jump ? c->C1 * gP * dyj * iwall(dxi, c->kt, rhoP)
-                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj * c->ihx[i];
+                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj / (0.5 * dxi);
     else
-      D[0] = c->C1 * gam_harm(c->dx[l], gam[IC(c, l, j)], dxi, gP) * dyj *
-             c->icx[fwx(c, i)];
+      D[0] = c->C1 * gam_harm(c->dx[l], gam[IC(c, l, j)], dxi, gP) * dyj /
+             (0.5 * (dxi + c->dx[l]));
   }
   /* east face x^f_{i+1} */
   if (!c->per && i == c->nx - 1) { /* outlet: zero gradient */
@@ -529,16 +550,16 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     q.nb[1] = T[IC(c, r, j)];
     if (c->solid[IC(c, r, j)])
       D[1] = jump ? c->C1 * gP * dyj * iwall(dxi, c->kt, rhoP)
-                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj * c->ihx[i];
+                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dyj / (0.5 * dxi);
     else
-      D[1] = c->C1 * gam_harm(dxi, gP, c->dx[r], gam[IC(c, r, j)]) * dyj *
-             c->icx[fwx(c, i + 1)];
+      D[1] = c->C1 * gam_harm(dxi, gP, c->dx[r], gam[IC(c, r, j)]) * dyj /
+             (0.5 * (dxi + c->dx[r]));
   }
   /* south face y^f_j */
   if (j == 0) {
     if (c->wtype[0] == 0) {
       q.nb[2] = c->wT[0][i];
-      D[2] = c->C1 * gam_harm2(gP, sqrt(c->wT[0][i])) * dxi * c->ihy[j];
+      D[2] = c->C1 * gam_harm2(gP, sqrt(c->wT[0][i])) * dxi / (0.5 * dyj);
     } else if (c->wtype[0] == 2) {
       q.nb[2] = c->wT[0][i];
       D[2] = c->C1 * gP * dxi * iwall(dyj, c->kt, rhoP);
@@ -550,16 +571,16 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     q.nb[2] = T[IC(c, i, j - 1)];
     if (c->solid[IC(c, i, j - 1)])
       D[2] = jump ? c->C1 * gP * dxi * iwall(dyj, c->kt, rhoP)
-                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi * c->ihy[j];
+                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi / (0.5 * dyj);
     else
       D[2] = c->C1 * gam_harm(c->dy[j - 1], gam[IC(c, i, j - 1)], dyj, gP) *
-             dxi * c->icy[j];
+             dxi / (0.5 * (dyj + c->dy[j - 1]));
   }
   /* north face y^f_{j+1} */
   if (j == c->ny - 1) {
     if (c->wtype[1] == 0) {
       q.nb[3] = c->wT[1][i];
-      D[3] = c->C1 * gam_harm2(gP, sqrt(c->wT[1][i])) * dxi * c->ihy[j];
+      D[3] = c->C1 * gam_harm2(gP, sqrt(c->wT[1][i])) * dxi / (0.5 * dyj);
     } else if (c->wtype[1] == 2) {
       q.nb[3] = c->wT[1][i];
       D[3] = c->C1 * gP * dxi * iwall(dyj, c->kt, rhoP);
@@ -571,10 +592,10 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     q.nb[3] = T[IC(c, i, j + 1)];
     if (c->solid[IC(c, i, j + 1)])
       D[3] = jump ? c->C1 * gP * dxi * iwall(dyj, c->kt, rhoP)
-                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi * c->ihy[j];
+                  : c->C1 * gam_harm2(gP, sqrt(c->obsT)) * dxi / (0.5 * dyj);
     else
       D[3] = c->C1 * gam_harm(dyj, gP, c->dy[j + 1], gam[IC(c, i, j + 1)]) *
-             dxi * c->icy[j + 1];
+             dxi / (0.5 * (dyj + c->dy[j + 1]));
   }
   F[0] = c->Fx[IU(c, i, j)];
   F[1] = c->Fx[IU(c, i + 1, j)];
@@ -608,9 +629,9 @@ static tco T_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   /* source S^T_c (pl29), S^T_p = 0 (pl28) */
   double vE, vW, uN, uS;
   face_centre_vel(c, i, j, &vE, &vW, &uN, &uS);
-  double ux = (Uat(c, c->u, i + 1, j) - Uat(c, c->u, i, j)) * c->idx[i];
-  double vy = (c->v[IV(c, i, j + 1)] - c->v[IV(c, i, j)]) * c->idy[j];
-  double vx = (vE - vW) * c->idx[i], uy = (uN - uS) * c->idy[j];
+  double ux = (Uat(c, c->u, i + 1, j) - Uat(c, c->u, i, j)) / dxi;
+  double vy = (c->v[IV(c, i, j + 1)] - c->v[IV(c, i, j)]) / dyj;
+  double vx = (vE - vW) / dxi, uy = (uN - uS) / dyj;
   double div = ux + vy;
   q.src = c->C2 * gP *
               (2.0 * (ux * ux + vy * vy) + (vx + uy) * (vx + uy) -
@@ -642,22 +663,23 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   double vE = (!c->per && i == c->nx - 1) ? vP : Vat(c, v, i + 1, j);
   double M = (rn * dyn + rs * dys) * dxi / 2.0;
   double len = 0.5 * (dys + dyn);
-  double gnode = c->wly[j] * gs + c->wry[j] * gn;
+  /* Gamma at the v-node, linear in y between the two cells */
+  double gnode = (dyn * gs + dys * gn) / (dys + dyn);
   /* a face on an obstacle in x: half-cell shear with the mean of the
      node's and the surface's Gamma (no slip), or with the node's Gamma over
      the distance d/2 + zeta, zeta from the node density (velocity slip) */
   const int slip = (c->otype == 2);
-  const double rnode = c->wly[j] * rs + c->wry[j] * rn;
+  const double rnode = (dyn * rs + dys * rn) / (dys + dyn);
   double DW, DE;
   if (!c->per && i == 0) {
-    DW = c->B * 0.5 * (gnode + gam_corner(c, gam, 0, j)) * len * c->ihx[i];
+    DW = c->B * 0.5 * (gnode + gam_corner(c, gam, 0, j)) * len / (0.5 * dxi);
   } else {
     int l = cw(c, i - 1);
     if (solid(c, l, j - 1) && solid(c, l, j))
       DW = slip ? c->B * gnode * len * iwall(dxi, c->kz, rnode)
-                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihx[i];
+                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len / (0.5 * dxi);
     else
-      DW = c->B * gam_corner(c, gam, i, j) * c->sy[j] * c->isx[fwx(c, i)];
+      DW = c->B * gam_corner(c, gam, i, j) * (dyn + dys) / (dxi + DX(c, i - 1));
   }
   if (!c->per && i == c->nx - 1) {
     DE = 0.0;
@@ -665,11 +687,11 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     int r = cw(c, i + 1);
     if (solid(c, r, j - 1) && solid(c, r, j))
       DE = slip ? c->B * gnode * len * iwall(dxi, c->kz, rnode)
-                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihx[i];
+                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len / (0.5 * dxi);
     else
-      DE = c->B * gam_corner(c, gam, i + 1, j) * c->sy[j] * c->isx[fwx(c, i + 1)];
+      DE = c->B * gam_corner(c, gam, i + 1, j) * (dyn + dys) / (DX(c, i + 1) + dxi);
   }
-  double DS = c->B * gs * dxi * c->idy[j - 1], DN = c->B * gn * dxi * c->idy[j];
+  double DS = c->B * gs * dxi / dys, DN = c->B * gn * dxi / dyn;
   double conv = 0.0;
   if (implicit) {
     double Fw0 = c->Fx[IU(c, i, j)], Fw1 = c->Fx[IU(c, i, j - 1)];
@@ -708,7 +730,7 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     q.a[2] = 4.0 / 3.0 * DS;
     q.a[3] = 4.0 / 3.0 * DN;
   }
-  q.a0 = q.a[0] + q.a[1] + q.a[2] + q.a[3] + conv + M * c->idt;
+  q.a0 = q.a[0] + q.a[1] + q.a[2] + q.a[3] + conv + M / dt;
   double Mm = (c->pm[IC(c, i, j)] / c->Tm[IC(c, i, j)] * dyn +
                c->pm[IC(c, i, j - 1)] / c->Tm[IC(c, i, j - 1)] * dys) *
               dxi / 2.0;
@@ -719,7 +741,7 @@ static mco v_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
              2.0 / 3.0 * gs * (Uat(c, u, i + 1, j - 1) - Uat(c, u, i, j - 1));
   /* b^v (pl14) + v^explicit (pl21): the part fixed for the whole step
      first, then the cross-diffusion of the current iterate */
-  q.b = (Mm * c->idt * c->vm[IV(c, i, j)] + c->gy * Mm +
+  q.b = (Mm / dt * c->vm[IV(c, i, j)] + c->gy * Mm +
          ((scheme & ORA_IMPLICIT) ? 0.0 : c->vexp[IV(c, i, j)])) +
         c->B * X;
   q.nb[0] = vW;
@@ -743,15 +765,16 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
   double uS, uN, DS, DN;
   double M = (rr * dxr + rl * dxl) * dyj / 2.0;
   double len = 0.5 * (dxl + dxr);
-  double gnode = c->wlx[fwx(c, i)] * gl + c->wrx[fwx(c, i)] * gr;
+  /* Gamma at the u-node, linear in x between the two cells */
+  double gnode = (dxr * gl + dxl * gr) / (dxl + dxr);
   /* node density for the slip length of pl38; obstacle faces in y as in
      v_coefs */
   const int slip = (c->otype == 2);
-  const double rnode = c->wlx[fwx(c, i)] * rl + c->wrx[fwx(c, i)] * rr;
+  const double rnode = (dxr * rl + dxl * rr) / (dxl + dxr);
   if (j == 0) {
     if (c->wtype[0] == 0) {
       uS = c->wu[0];
-      DS = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 0, i))) * len * c->ihy[j];
+      DS = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 0, i))) * len / (0.5 * dyj);
     } else if (c->wtype[0] == 2) {
       uS = c->wu[0];
       DS = c->B * gnode * len * iwall(dyj, c->kz, rnode);
@@ -763,14 +786,14 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     uS = u[IU(c, r, j - 1)];
     if (solid(c, l, j - 1) && solid(c, r, j - 1))
       DS = slip ? c->B * gnode * len * iwall(dyj, c->kz, rnode)
-                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihy[j];
+                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len / (0.5 * dyj);
     else
-      DS = c->B * gam_corner(c, gam, i, j) * c->sx[fwx(c, i)] * c->isy[j];
+      DS = c->B * gam_corner(c, gam, i, j) * (dxr + dxl) / (dyj + c->dy[j - 1]);
   }
   if (j == c->ny - 1) {
     if (c->wtype[1] == 0) {
       uN = c->wu[1];
-      DN = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 1, i))) * len * c->ihy[j];
+      DN = c->B * 0.5 * (gnode + sqrt(wallT_uface(c, 1, i))) * len / (0.5 * dyj);
     } else if (c->wtype[1] == 2) {
       uN = c->wu[1];
       DN = c->B * gnode * len * iwall(dyj, c->kz, rnode);
@@ -782,11 +805,11 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     uN = u[IU(c, r, j + 1)];
     if (solid(c, l, j + 1) && solid(c, r, j + 1))
       DN = slip ? c->B * gnode * len * iwall(dyj, c->kz, rnode)
-                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len * c->ihy[j];
+                : c->B * 0.5 * (gnode + sqrt(c->obsT)) * len / (0.5 * dyj);
     else
-      DN = c->B * gam_corner(c, gam, i, j + 1) * c->sx[fwx(c, i)] * c->isy[j + 1];
+      DN = c->B * gam_corner(c, gam, i, j + 1) * (dxr + dxl) / (c->dy[j + 1] + dyj);
   }
-  double DW = c->B * gl * dyj * c->idx[l], DE = c->B * gr * dyj * c->idx[r];
+  double DW = c->B * gl * dyj / dxl, DE = c->B * gr * dyj / dxr;
   double conv = 0.0;
   if (implicit) {
     double Fs0 = c->Fy[IV(c, r, j)], Fs1 = c->Fy[IV(c, l, j)];
@@ -827,7 +850,7 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
     q.a[0] = 4.0 / 3.0 * DW;
     q.a[1] = 4.0 / 3.0 * DE;
   }
-  q.a0 = q.a[2] + q.a[3] + q.a[0] + q.a[1] + conv + M * c->idt;
+  q.a0 = q.a[2] + q.a[3] + q.a[0] + q.a[1] + conv + M / dt;
   double Mm = (c->pm[IC(c, r, j)] / c->Tm[IC(c, r, j)] * dxr +
                c->pm[IC(c, l, j)] / c->Tm[IC(c, l, j)] * dxl) *
               dyj / 2.0;
@@ -836,7 +859,7 @@ static mco u_coefs(const ora_ctx *c, int i, int j, double dt, int scheme) {
              gam_corner(c, gam, i, j) * (v[IV(c, r, j)] - v[IV(c, l, j)]) -
              2.0 / 3.0 * gr * (v[IV(c, r, j + 1)] - v[IV(c, r, j)]) +
              2.0 / 3.0 * gl * (v[IV(c, l, j + 1)] - v[IV(c, l, j)]);
-  q.b = (Mm * c->idt * Uat(c, c->um, i, j) + c->gx * Mm +
+  q.b = (Mm / dt * Uat(c, c->um, i, j) + c->gx * Mm +
          ((scheme & ORA_IMPLICIT) ? 0.0 : c->uexp[IU(c, r, j)])) +
         c->B * X;
   q.nb[0] = uW;
@@ -904,53 +927,6 @@ ora_ctx *ora_create(const ora_setup *s) {
   c->dy = dalloc(ny);
   memcpy(c->dx, s->dx, sizeof(double) * nx);
   memcpy(c->dy, s->dy, sizeof(double) * ny);
-  /* geometric factors; the faces on a non-periodic edge take the edge
-     width twice (they are never used by an interior formula) */
-  c->idx = dalloc(nx);
-  c->ihx = dalloc(nx);
-  c->idy = dalloc(ny);
-  c->ihy = dalloc(ny);
-  c->sx = dalloc(nx + 1);
-  c->wlx = dalloc(nx + 1);
-  c->wrx = dalloc(nx + 1);
-  c->icx = dalloc(nx + 1);
-  c->isx = dalloc(nx + 1);
-  c->sy = dalloc(ny + 1);
-  c->wly = dalloc(ny + 1);
-  c->wry = dalloc(ny + 1);
-  c->icy = dalloc(ny + 1);
-  c->isy = dalloc(ny + 1);
-  for (int i = 0; i < nx; i++) {
-    c->idx[i] = 1.0 / c->dx[i];
-    c->ihx[i] = 1.0 / (0.5 * c->dx[i]);
-  }
-  for (int j = 0; j < ny; j++) {
-    c->idy[j] = 1.0 / c->dy[j];
-    c->ihy[j] = 1.0 / (0.5 * c->dy[j]);
-  }
-  for (int k = 0; k <= nx; k++) {
-    int l = k - 1, r = k;
-    if (c->per) {
-      l = cw(c, l);
-      r = cw(c, r);
-    } else {
-      if (l < 0) l = 0;
-      if (r > nx - 1) r = nx - 1;
-    }
-    c->sx[k] = c->dx[l] + c->dx[r];
-    c->wlx[k] = c->dx[r] / c->sx[k];
-    c->wrx[k] = c->dx[l] / c->sx[k];
-    c->icx[k] = 1.0 / (0.5 * c->sx[k]);
-    c->isx[k] = 1.0 / c->sx[k];
-  }
-  for (int k = 0; k <= ny; k++) {
-    int l = k - 1 < 0 ? 0 : k - 1, r = k > ny - 1 ? ny - 1 : k;
-    c->sy[k] = c->dy[l] + c->dy[r];
-    c->wly[k] = c->dy[r] / c->sy[k];
-    c->wry[k] = c->dy[l] / c->sy[k];
-    c->icy[k] = 1.0 / (0.5 * c->sy[k]);
-    c->isy[k] = 1.0 / c->sy[k];
-  }
   c->solid = (unsigned char *)calloc((size_t)nx * ny, 1);
   for (int k = 0; k < s->n_obst; k++)
     for (int j = s->oj0[k]; j <= s->oj1[k]; j++)
@@ -1026,9 +1002,6 @@ ora_ctx *ora_create(const ora_setup *s) {
 
 void ora_destroy(ora_ctx *c) {
   if (!c) return;
-  double *geo[] = {c->idx, c->ihx, c->idy, c->ihy, c->sx, c->wlx, c->wrx,
-                   c->icx, c->isx, c->sy, c->wly, c->wry, c->icy, c->isy};
-  for (size_t k = 0; k < sizeof(geo) / sizeof(geo[0]); k++) free(geo[k]);
   double *bufs[] = {c->dx,  c->dy,   c->u_in, c->T_in, c->wT[0], c->wT[1],
                     c->u,   c->un,   c->um,   c->v,    c->vn,    c->vm,
                     c->p,   c->pn,   c->pm,   c->T,    c->Tn,    c->Tm,
@@ -1281,7 +1254,7 @@ static void pass(ora_ctx *c, double dt, int scheme, int n3) {
       double GE = c->rhou[ke] * c->un[ke] * dyj;
       double GS = c->rhov[ks] * c->vn[ks] * dxi;
       double GN = c->rhov[kn] * c->vn[kn] * dxi;
-      double R = (c->pn[k] / c->Tn[k] * dV - c->pm[k] / c->Tm[k] * dV) * c->idt +
+      double R = (c->pn[k] / c->Tn[k] * dV - c->pm[k] / c->Tm[k] * dV) / dt +
                  (GE - GW) + (GN - GS);
       rm = dmax(rm, fabs(R));
       sm += R;
@@ -1313,7 +1286,6 @@ static void pass(ora_ctx *c, double dt, int scheme, int n3) {
 }
 
 void ora_step(ora_ctx *c, double dt, int n_inner, int scheme) {
-  c->idt = 1.0 / dt;
   prologue(c, scheme);
   for (int k = 0; k < n_inner; k++) pass(c, dt, scheme, 1);
 }
@@ -1321,7 +1293,6 @@ void ora_step(ora_ctx *c, double dt, int n_inner, int scheme) {
 /* A step whose passes each run loop 3 with n3 >= 1 energy-pressure solves
    (n3 = 1: ora_step). */
 void ora_step_l3(ora_ctx *c, double dt, int n_inner, int n3, int scheme) {
-  c->idt = 1.0 / dt;
   prologue(c, scheme);
   for (int k = 0; k < n_inner; k++) pass(c, dt, scheme, n3);
 }
@@ -1338,7 +1309,6 @@ int ora_step_tol(ora_ctx *c, double dt, int max_inner, double tol, int scheme) {
 
 /* The same with loop 3 in every pass (n3 energy-pressure solves). */
 int ora_step_tol_l3(ora_ctx *c, double dt, int max_inner, int n3, double tol, int scheme) {
-  c->idt = 1.0 / dt;
   prologue(c, scheme);
   int k = 0;
   while (k < max_inner) {
@@ -1353,7 +1323,6 @@ int ora_step_tol_l3(ora_ctx *c, double dt, int max_inner, int n3, double tol, in
 void ora_eq_residuals(ora_ctx *c, double dt, int scheme, double *rT,
                       double *ru, double *rv, double *rp) {
   const int nx = c->nx, ny = c->ny;
-  c->idt = 1.0 / dt;
   prologue(c, scheme);
   cell_props(c, c->p, c->T);
   face_fluxes(c, c->u, c->v, scheme & ORA_TVD);

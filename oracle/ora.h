@@ -81,6 +81,8 @@ void ora_mass(const ora_ctx *c, double out[3]);
 void ora_set_threads(int n);
 int ora_max_threads(void);
 void ora_params(double Ma, double Re, double Pr, double gamma, double out[5]);
+/* Test switch (default on): off forces every TVD correction to zero. */
+void ora_set_limiter(int on);
 /* van Leer limiter psi(r) of r = a/b, division-safe. */
 double ora_vanleer(double a, double b);
 double ora_psi_s(double f1, double f2, double f3, double f4, double d1,

@@ -65,6 +65,7 @@ def lib():
         L.ora_params.argtypes = [C.c_double] * 4 + [_D]
         L.ora_set_threads.argtypes = [C.c_int]
         L.ora_max_threads.restype = C.c_int
+        L.ora_set_limiter.argtypes = [C.c_int]
         L.ora_vanleer.restype = C.c_double
         L.ora_vanleer.argtypes = [C.c_double, C.c_double]
         L.ora_psi_s.restype = C.c_double
@@ -84,6 +85,11 @@ def params(Ma, Re, Pr, gamma):
     out = np.zeros(5)
     lib().ora_params(Ma, Re, Pr, gamma, _ptr(out))
     return out
+
+
+def set_limiter(on: bool) -> None:
+    """Test switch: with the limiter off every TVD correction is zero."""
+    lib().ora_set_limiter(int(bool(on)))
 
 
 def vanleer(a, b):

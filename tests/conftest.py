@@ -30,3 +30,23 @@ def sts_mod():
     from paper_1802_04243_amd import sts
     sts.lib()
     return sts
+
+
+@pytest.fixture(scope="session")
+def oracle_run(oracle_lib):
+    """Oracle of a named workload after its configured run from its seeded
+    state, cached for the session (several GPU tests compare against it)."""
+    from paper_1802_04243_amd import workloads as W
+    cache = {}
+
+    def get(name, scheme):
+        key = (name, scheme)
+        if key not in cache:
+            p, run = W.workload(name)
+            o = oracle_lib.Oracle(p)
+            o.set_fields(*W.initial_fields(p, run["seed"]))
+            for _ in range(run["steps"]):
+                o.step(run["dt"], run["inner"], scheme)
+            cache[key] = o
+        return cache[key]
+    return get

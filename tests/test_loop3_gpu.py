@@ -1,8 +1,9 @@
 """Loop 3 (the CPU algorithm's energy-pressure solves inside each pass) on
 the GPU against the FP64 oracle (through the C ABI).
 
-Expected bitwise equal, as the plain pass; asserted: normwise relative
-difference <= 1e-10 per field and the residuals.  Cases: the small channel
+Asserted: normwise relative difference <= 1e-10 per field and the residuals
+(the two evaluate the equations in different operation orders, so they agree
+to rounding); implicit TVD step by step from shared states.  Cases: the small channel
 in every scheme with 2 and 3 solves per pass; a ragged non-uniform grid with
 a slip-jump and a no-slip wall, two obstacles, heated walls and a body force;
 a periodic slip-jump channel; the 4x4 grid; one step of the bench grid
@@ -26,17 +27,26 @@ SJ = W.WALL_SLIP_JUMP
 
 
 def run_l3(sts_mod, oracle_lib, p, dt, steps, inner, n3, scheme, seed, label):
-    print(f"case loop 3 {label} n3={n3} scheme={scheme} grid={p.nx}x{p.ny} steps={steps}x{inner}",
-          flush=True)
+    # implicit TVD step by step from shared states (the oracle takes the GPU
+    # state before every step): its limiter ties let rounding-level
+    # differences grow over many steps (test_parity_gpu's docstring)
+    resync = scheme == W.IMPLICIT | W.TVD
+    print(f"case loop 3 {label} n3={n3} scheme={scheme} grid={p.nx}x{p.ny} steps={steps}x{inner}"
+          f"{' (step by step from shared states)' if resync else ''}", flush=True)
     g = sts_mod.Solver(p)
     o = oracle_lib.Oracle(p)
     f0 = W.initial_fields(p, seed)
     g.set_fields(*f0)
     o.set_fields(*f0)
-    for _ in range(steps):
+    for s in range(steps):
+        if resync and s:
+            o.set_fields(*g.fields())
         g.step_l3(dt, inner, n3, scheme)
         o.step_l3(dt, inner, n3, scheme)
-    compare(g, o, f"loop 3 {label} n3={n3}")
+        if resync:
+            compare(g, o, f"loop 3 {label} n3={n3} step {s + 1}", quiet=s + 1 < steps)
+    if not resync:
+        compare(g, o, f"loop 3 {label} n3={n3}")
     g.close()
 
 
@@ -93,7 +103,7 @@ def test_loop3_full_size_step_from_gpu_state(sts_mod, oracle_lib):
 @pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
 def test_loop3_with_tolerance_exit(sts_mod, oracle_lib, name, scheme):
     # loop 2 to convergence with two solves per pass: the oracle's pass
-    # counts and bitwise-equal fields
+    # counts and fields within the parity bar
     p, run = W.workload("channel_120x24")
     tol = 1e-4 if scheme == W.IMPLICIT | W.TVD else 1e-8
     print(f"case loop 3 + tolerance exit 120x24/{name} tol {tol:g}", flush=True)

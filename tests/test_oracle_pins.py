@@ -447,3 +447,137 @@ def test_tolerance_exit_takes_the_first_converged_pass(oracle_lib, scheme):
     d = oracle_lib.Oracle(p)
     d.set_fields(*state)
     assert d.step_tol(run["dt"], 7, 0.0, scheme) == 7
+
+
+@pytest.mark.parametrize("time_scheme", [W.EXPLICIT, W.IMPLICIT])
+def test_tvd_with_the_limiter_off_is_upwind_bitwise(oracle_lib, time_scheme):
+    # Sec. 3.2 after pl15_2: with upwind approximation the TVD corrections
+    # psi_c and psi_s are null.  The TVD scheme with the limiter forced to
+    # zero must therefore be the upwind scheme to the last bit (face
+    # densities, convective coefficients and the explicit terms alike), and
+    # with the limiter on it must differ.
+    p, run = W.workload("channel_120x24")
+    f0 = W.initial_fields(p, run["seed"])
+    out = []
+    for scheme, on in ((time_scheme | W.UPWIND, True), (time_scheme | W.TVD, False),
+                       (time_scheme | W.TVD, True)):
+        oracle_lib.set_limiter(on)
+        try:
+            o = oracle_lib.Oracle(p)
+            o.set_fields(*f0)
+            for _ in range(5):
+                o.step(run["dt"], 6, scheme)
+            out.append(o.fields())
+        finally:
+            oracle_lib.set_limiter(True)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    assert max(np.abs(a - b).max() for a, b in zip(out[0], out[2])) > 1e-6
+
+
+def _advected_wave(oracle_lib, nx, scheme, tend=0.25):
+    """A density / temperature wave carried by a uniform stream (u = 1,
+    p = 1, v = 0) in a periodic channel between slip walls at Re = 1e8
+    (conduction and viscosity ~1e-8): the exact solution is the initial
+    profile T0(x - t).  dt = h^2 / 2, so the first-order time error is of the
+    size of a second-order space error.  Returns the mean and the max error
+    of T against the exact cell averages."""
+    ny = 4
+    p = W.Problem(nx=nx, ny=ny, lx=1.0, ly=ny / nx, periodic=True, Re=1e8, Ma=0.5,
+                  wall_type=(W.WALL_SLIP_ADIABATIC, W.WALL_SLIP_ADIABATIC))
+    h = 1.0 / nx
+    x = (np.arange(nx) + 0.5) * h
+    T = np.repeat((1 + 0.1 * np.sin(2 * np.pi * x))[None], ny, 0)
+    o = oracle_lib.Oracle(p)
+    o.set_fields(np.ones((ny, nx + 1)), np.zeros((ny + 1, nx)), np.ones((ny, nx)), T)
+    n = int(round(tend / (0.5 * h * h)))
+    for _ in range(n):
+        o.step(tend / n, 4, scheme)
+    xs = x - tend
+    exact = 1 + 0.1 * (np.cos(2 * np.pi * (xs - h / 2)) - np.cos(2 * np.pi * (xs + h / 2))) / (2 * np.pi * h)
+    err = np.abs(o.fields()[3] - exact[None])
+    return err.mean(), err.max()
+
+
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_spatial_order_of_the_convective_schemes(oracle_lib, name, scheme):
+    # Sec. 3.2, pl15_1 / pl15_2: upwind is first order, TVD (van Leer)
+    # second order in smooth regions.  Mean-error order over nx = 32 -> 128
+    # (measured 0.96 and 2.0); the max error of TVD is lower-order at the
+    # wave's extrema, where the limiter switches to upwind (measured 1.4)
+    e = [_advected_wave(oracle_lib, nx, scheme) for nx in (32, 64, 128)]
+    order = math.log2(e[0][0] / e[2][0]) / 2
+    order_max = math.log2(e[0][1] / e[2][1]) / 2
+    print(name, [f"{a:.2e}/{b:.2e}" for a, b in e], f"order {order:.2f} (max {order_max:.2f})")
+    if scheme & W.TVD:
+        assert 1.8 <= order <= 2.2, (e, order)
+        assert 1.1 <= order_max, (e, order_max)
+    else:
+        assert 0.85 <= order <= 1.15, (e, order)
+
+
+@pytest.mark.parametrize("name,scheme", [("explicit_upwind", W.EXPLICIT | W.UPWIND),
+                                         ("implicit_upwind", W.IMPLICIT | W.UPWIND)])
+def test_solid_rows_are_a_channel_wall(oracle_lib, name, scheme):
+    # An obstacle covering the bottom rows of a periodic channel is a wall:
+    # with the obstacle at the wall's temperature the fluid above it evolves
+    # bitwise as in the channel whose bottom wall sits on the obstacle's top
+    # surface (the obstacle-face branches of the energy, u and v equations,
+    # of the face densities and of the pressure equation against the wall
+    # branches).  Upwind schemes: near a horizontal obstacle surface the TVD
+    # stencils of the velocity equations may take face values inside the
+    # solid (zero), where at a channel wall they stop at the wall.
+    nx, ny, k = 24, 10, 3
+    x = (np.arange(nx) + 0.5) / nx
+    top = dict(wall_u=(0.0, 0.3), gx=0.4, gy=-0.1, Re=30.0, periodic=True, lx=2.0)
+    a = W.Problem(nx=nx, ny=ny, dy=np.full(ny, 1 / 12), wall_T=(np.full(nx, 1.05), 0.95 + 0.05 * x),
+                  **top)
+    b = W.Problem(nx=nx, ny=ny + k, dy=np.full(ny + k, 1 / 12), obstacles=[(0, 0, nx - 1, k - 1)],
+                  obstacle_T=1.05, wall_type=(W.WALL_SLIP_ADIABATIC, W.WALL_NOSLIP_ISOTHERMAL),
+                  wall_T=(np.full(nx, 3.0), 0.95 + 0.05 * x), **top)
+    fa = W.initial_fields(a, 7, amp=1e-2)
+    pad = lambda f, n: np.concatenate([np.ones((n, f.shape[1])), f])
+    fb = (pad(fa[0], k), pad(fa[1], k), pad(fa[2], k), pad(fa[3], k))
+    oa, ob = oracle_lib.Oracle(a), oracle_lib.Oracle(b)
+    oa.set_fields(*fa)
+    ob.set_fields(*fb)
+    dt = 0.2 / 12
+    for _ in range(8):
+        oa.step(dt, 6, scheme)
+        ob.step(dt, 6, scheme)
+    for fa_, fb_ in zip(oa.fields(), ob.fields()):
+        assert np.array_equal(fb_[k:], fa_)
+
+
+def test_hydrostatic_box_between_solid_columns(oracle_lib):
+    # Fluid at rest between two solid columns of a periodic channel under a
+    # body force g along x (eqs pl2, pl5): the steady state is u = v = 0,
+    # T = 1 and A dp/dx = rho g with rho = p, which the u-equation balances
+    # with the trapezoidal mass of its volume, so the discrete profile is
+    # exactly geometric: p_i / p_{i-1} = (1 + g dx / 2A) / (1 - g dx / 2A),
+    # scaled to the fluid's mass (with a fixed number of passes per step the
+    # transient's mass drifts slightly: the pressure equation is the discrete
+    # continuity only at convergence of loop 2).  Pins the
+    # obstacle's vertical faces (normal velocity zero and no pressure flux
+    # through them), the body-force term and the pressure equation next to
+    # the obstacle.
+    nx, ny, g = 18, 8, 0.2
+    dx = 1.0 / 16
+    p = W.Problem(nx=nx, ny=ny, lx=nx * dx, ly=ny * dx, periodic=True,
+                  obstacles=[(0, 0, 1, ny - 1)], Ma=1.0, Re=5.0, gx=g)
+    o = oracle_lib.Oracle(p)
+    o.set_fields(np.zeros((ny, nx + 1)), np.zeros((ny + 1, nx)), np.ones((ny, nx)),
+                 np.ones((ny, nx)))
+    M0 = o.mass()[0]
+    for _ in range(6000):
+        o.step(0.2 * dx, 6, W.IMPLICIT | W.UPWIND)
+    u, v, pr, T = o.fields()
+    A = oracle_lib.params(1.0, 5.0, 0.7, 1.4)[0]
+    q = (1 + g * dx / (2 * A)) / (1 - g * dx / (2 * A))
+    prof = q ** np.arange(nx - 2)
+    M = o.mass()[0]
+    prof *= M / (prof.sum() * dx * ny * dx)
+    assert abs(M - M0) <= 1e-5 * M0
+    assert np.abs(u).max() < 1e-12 and np.abs(v).max() < 1e-12
+    assert np.abs(T[:, 2:] - 1.0).max() < 1e-12
+    assert np.abs(pr[:, 2:] - prof[None]).max() < 1e-12, np.abs(pr[:, 2:] - prof[None]).max()

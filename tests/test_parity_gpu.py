@@ -1,10 +1,20 @@
 """Parity of the HIP library against the FP64 CPU oracle (GPU required).
 
-The FP64 GPU path evaluates every expression in the oracle's order with IEEE
-rounding and no FMA contraction, so the fields are expected to agree to the
-last bit; the bar asserted is the normwise relative difference
-max|gpu - oracle| / max|oracle| <= 1e-10 per field (the FP64 parity bar), and
-the number of bitwise-equal entries is reported.
+The oracle evaluates the equations as the paper prints them (divisions by
+cell widths and by 2 dt, the limiter of r = a/b); the GPU path multiplies by
+precomputed inverse widths and evaluates the limiter in one division, so the
+two agree to rounding, not bitwise.  The bar asserted is the normwise
+relative difference max|gpu - oracle| / max|oracle| <= 1e-10 per field (the
+FP64 parity bar) after the stated step count; the share of bitwise-equal
+entries is reported.
+
+Implicit TVD is discontinuous in the old iterate (its limiter multiplies the
+mass flux in the coefficients and jumps where a downstream difference changes
+sign), so a rounding-level difference at a near-tie moves a pass by O(1e-5)
+and, over hundreds of steps, the two runs drift apart while each step still
+agrees.  Its long runs are therefore checked step by step from shared states
+(the oracle takes the GPU state before every step) and the cells within a few
+ulp of a tie are counted and reported.
 """
 import sys
 
@@ -24,35 +34,74 @@ def normdiff(a, b):
     return np.abs(a - b).max() / (den if den > 0 else 1.0)
 
 
-def compare(gpu, ora, label):
+def compare(gpu, ora, label, quiet=False):
     worst = 0.0
-    for name, a, b in zip("uvpT", gpu.fields(), ora.fields()):
+    fg, fo = gpu.fields(), ora.fields()
+    for name, a, b in zip("uvpT", fg, fo):
         d = normdiff(a, b)
         worst = max(worst, d)
         eq = np.mean(a == b)
-        print(f"{label} {name}: normdiff {d:.3e}, bitwise-equal {100 * eq:.2f}%", flush=True)
+        if not quiet:
+            print(f"{label} {name}: normdiff {d:.3e}, bitwise-equal {100 * eq:.2f}%", flush=True)
         assert np.isfinite(a).all(), (label, name)
         assert d <= TOL, (label, name, d)
     rg, ro = gpu.residuals(), ora.residuals()
-    # maxima are exact operations: equal when the fields are; the sum depends on order
-    assert np.allclose(rg[:5], ro[:5], rtol=1e-8, atol=1e-300), (label, rg, ro)
-    assert abs(rg[5] - ro[5]) <= 1e-9 * max(np.abs(ro[4]), 1e-300) * max(1, gpu.nx * gpu.ny) ** 0.5 + 1e-14
+    # the increments max|d phi| are differences of fields that agree to
+    # ~1e-15 of their scale: compare them on that scale; the continuity
+    # residual on the scale of one face's mass flux; the sum of R depends
+    # on the summation order as well
+    scale = max(np.abs(x).max() for x in fo)
+    dy = ora.prob.widths()[1].max() if hasattr(ora, "prob") else 1.0
+    for k in range(4):
+        assert abs(rg[k] - ro[k]) <= TOL * scale + 1e-8 * abs(ro[k]), (label, k, rg, ro)
+    assert abs(rg[4] - ro[4]) <= TOL * scale * dy + 1e-8 * abs(ro[4]), (label, rg, ro)
+    assert abs(rg[5] - ro[5]) <= (TOL * scale * dy + 1e-9 * abs(ro[4])) * max(1, gpu.nx * gpu.ny) ** 0.5
     return worst
 
 
-def run_pair(sts_mod, oracle_lib, prob, dt, steps, inner, scheme, seed, amp=1e-3, label=""):
-    print(f"case {label} scheme={scheme} grid={prob.nx}x{prob.ny} steps={steps}x{inner}", flush=True)
+def near_ties(prob, fields, ulps=8):
+    """Number of limiter arguments of the cell fields T and rho = p/T, and of
+    u and v along x and y, whose downstream difference phi3 - phi2 is within
+    `ulps` units in the last place of the values (a tie of the van Leer
+    limiter: r undefined or changing sign)."""
+    u, v, p, T = fields
+    out = 0
+    for f in (T, p / T, u, v):
+        for ax in (0, 1):
+            d = np.abs(np.diff(f, axis=ax))
+            lim = ulps * np.spacing(np.maximum(np.abs(f).max(), 1e-300))
+            out += int(np.count_nonzero(d <= lim) - np.count_nonzero(d == 0.0))
+    return out
+
+
+def run_pair(sts_mod, oracle_lib, prob, dt, steps, inner, scheme, seed, amp=1e-3, label="",
+             resync=False):
+    """Run both from the same seeded state.  resync: before every step the
+    oracle takes the GPU's state, and every step is compared."""
+    print(f"case {label} scheme={scheme} grid={prob.nx}x{prob.ny} steps={steps}x{inner}"
+          f"{' (step by step from shared states)' if resync else ''}", flush=True)
     g = sts_mod.Solver(prob)
     o = oracle_lib.Oracle(prob)
     f0 = W.initial_fields(prob, seed, amp)
     g.set_fields(*f0)
     o.set_fields(*f0)
-    for _ in range(steps):
+    worst, ties = 0.0, 0
+    for s in range(steps):
+        if resync and s:
+            st = g.fields()
+            ties = max(ties, near_ties(prob, st))
+            o.set_fields(*st)
         g.step(dt, inner, scheme)
         o.step(dt, inner, scheme)
-    w = compare(g, o, label)
+        if resync:
+            worst = max(worst, compare(g, o, label, quiet=s + 1 < steps))
+    if resync:
+        print(f"{label}: worst step {worst:.3e}, at most {ties} limiter near-ties in a state",
+              flush=True)
+    else:
+        worst = compare(g, o, label)
     g.close()
-    return w
+    return worst
 
 
 # the small case of the workloads: 120x24, one square, 50 steps x 20 inner
@@ -111,11 +160,33 @@ def test_tiny_grid(sts_mod, oracle_lib, scheme):
     run_pair(sts_mod, oracle_lib, p, 0.02, 5, 4, scheme, 23, label="tiny4x4")
 
 
-@pytest.mark.parametrize("scheme", list(W.SCHEMES.values()))
-def test_channel_1280x288_few_steps(sts_mod, oracle_lib, scheme):
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_channel_1280x288_configured_run(sts_mod, oracle_lib, oracle_run, name, scheme):
+    # the configured 200 steps x 10 passes; implicit TVD step by step from
+    # shared states (its limiter ties, module docstring)
     p, run = W.workload("channel_1280x288")
-    run_pair(sts_mod, oracle_lib, p, run["dt"], 3, run["inner"], scheme, run["seed"],
-             label="channel_1280x288")
+    if scheme == W.IMPLICIT | W.TVD:
+        run_pair(sts_mod, oracle_lib, p, run["dt"], run["steps"], run["inner"], scheme,
+                 run["seed"], label=f"channel_1280x288/{name}", resync=True)
+        return
+    print(f"case channel_1280x288/{name} {run['steps']}x{run['inner']}", flush=True)
+    o = oracle_run("channel_1280x288", scheme)
+    g = sts_mod.Solver(p)
+    g.set_fields(*W.initial_fields(p, run["seed"]))
+    for _ in range(run["steps"]):
+        g.step(run["dt"], run["inner"], scheme)
+    compare(g, o, f"channel_1280x288/{name}")
+    g.close()
+
+
+@pytest.mark.parametrize("name,scheme", [("explicit_tvd", W.EXPLICIT | W.TVD),
+                                         ("implicit_upwind", W.IMPLICIT | W.UPWIND)])
+def test_channel_3000x600_configured_run(sts_mod, oracle_lib, name, scheme):
+    # the first throughput grid, the configured 200 steps x 10 passes, in
+    # the launch configuration the benchmark times
+    p, run = W.workload("channel_3000x600")
+    run_pair(sts_mod, oracle_lib, p, run["dt"], run["steps"], run["inner"], scheme, run["seed"],
+             label=f"channel_3000x600/{name}")
 
 
 @pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
@@ -256,7 +327,7 @@ def test_deterministic_and_resumable(sts_mod):
 def test_tolerance_exit_matches_oracle(sts_mod, oracle_lib, name, scheme):
     # loop 2 with its convergence test: the same number of passes in every
     # step and the same fields as the oracle (the decisions are taken on
-    # bitwise-equal residual maxima)
+    # residual maxima that agree to rounding)
     p, run = W.workload("channel_120x24")
     tol = 1e-4 if scheme == W.IMPLICIT | W.TVD else 1e-8
     print(f"case tolerance exit 120x24/{name} tol {tol:g}", flush=True)
@@ -301,7 +372,12 @@ def test_tolerance_exit_stops_at_every_position(sts_mod, oracle_lib):
         r = q.residuals()
         crit.append(max(r[0], r[1], r[3], r[2] / p.p_in))
     print("criterion after 1..7 passes " + " ".join(f"{c:.3e}" for c in crit), flush=True)
-    cases = [(9, c) for c in crit] + [(mi, 0.0) for mi in (1, 2, 3, 5)]
+    # a tolerance a hair above the criterion after m passes (the two
+    # implementations agree to rounding, not bitwise), still below the
+    # criterion after m - 1 passes
+    tols = [c * (1 + 1e-9) for c in crit]
+    assert all(t < c for t, c in zip(tols[1:], crit[:-1])), crit
+    cases = [(9, t) for t in tols] + [(mi, 0.0) for mi in (1, 2, 3, 5)]
     seen = set()
     for max_inner, tol in cases:
         q = oracle_lib.Oracle(p)
@@ -326,7 +402,7 @@ def test_tolerance_exit_stops_at_every_position(sts_mod, oracle_lib):
 def test_tolerance_exit_full_size(sts_mod, oracle_lib):
     # loop 2 to convergence on the bench grid (5120x1152, explicit TVD, the
     # tolerance and pass limit the benchmark uses) from a GPU-advanced state:
-    # the same pass count as the oracle and bitwise-equal fields
+    # the same pass count as the oracle and fields within the parity bar
     p, run = W.workload("channel_5120x1152")
     scheme = W.EXPLICIT | W.TVD
     print("case channel_5120x1152 loop 2 to tol 1e-6: 3 GPU steps, then one on both", flush=True)

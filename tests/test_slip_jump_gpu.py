@@ -1,7 +1,7 @@
 """Velocity-slip / temperature-jump surfaces (eqs pl38, pl39) on the GPU
 against the FP64 CPU oracle (through the C ABI).
 
-The FP64 form is expected bitwise equal, as for the other boundary rules;
+The FP64 form agrees with the oracle to rounding, as for the other boundary rules;
 asserted: normwise relative difference <= 1e-10 per field.  Cases: a small
 channel with slip-jump walls moving with the flow and a slip-jump square
 (all four schemes, and the mixed-precision form within its FP32 tolerance);

@@ -96,7 +96,7 @@ def test_temperature_jump_conduction_converges(oracle_lib):
     f, pex, (Ts0, TsH) = _jump_conduction_exact(Tb, Tt, kn, T0, gamma / (Re * Pr))
     assert Ts0 - Tb > 0.03 and Tt - TsH > 0.03   # a resolved jump at both walls
     errs = []
-    for ny, steps in ((8, 4000), (16, 8000), (32, 16000)):
+    for ny, steps in ((16, 8000), (32, 16000), (64, 40000)):
         p = W.Problem(nx=4, ny=ny, lx=4.0 / ny, ly=1.0, periodic=True, Ma=0.5, Re=Re, Pr=Pr,
                       gamma=gamma, wall_type=(SJ, SJ), kn=kn,
                       wall_T=(np.full(4, Tb), np.full(4, Tt)))
@@ -110,10 +110,13 @@ def test_temperature_jump_conduction_converges(oracle_lib):
         y = (np.arange(ny) + 0.5) / ny
         errs.append(np.abs(T[:, 0] - f(y)).max())
         assert abs(pr[0, 0] - pex) < 1e-3
+    # first order: the node's Gamma and rho stand for the surface's in the
+    # jump conductance Gamma / (d/2 + tau) (measured 0.85 over 16 -> 32 and
+    # 0.91 over 32 -> 64)
     order = math.log2(errs[1] / errs[2])
     assert errs[0] > errs[1] > errs[2], errs
-    assert 0.6 <= order <= 2.5, (errs, order)
-    assert errs[2] <= 3e-4, errs
+    assert 0.8 <= order <= 1.2, (errs, order)
+    assert errs[2] <= 1e-4, errs
 
 
 @pytest.mark.parametrize("scheme", list(W.SCHEMES.values()))
