@@ -236,3 +236,148 @@ def set_threads(n: int) -> None:
 
 def max_threads() -> int:
     return int(lib().ora_max_threads())
+
+
+# ---------------------------------------------------------------------------
+# tangent-linear model: ora.c compiled on dual numbers (tlm.h, ora_tlm.cc)
+# ---------------------------------------------------------------------------
+_TLM_PATH = os.path.join(_HERE, "libora_tlm.so")
+_tlm = None
+
+
+def build_tlm(verbose: bool = False) -> str:
+    """Compile ora_tlm.cc (ora.c on the dual numbers of tlm.h) into
+    oracle/libora_tlm.so."""
+    src = os.path.join(_HERE, "ora_tlm.cc")
+    # -O3 -mavx2: the K tangents of every operation are a short vector loop
+    cmd = ["g++", "-std=c++17", "-O3", "-mavx2", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-I", _HERE, "-o", _TLM_PATH + ".tmp", src]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_TLM_PATH + ".tmp", _TLM_PATH)
+    return _TLM_PATH
+
+
+class _TlmSetup(C.Structure):
+    _fields_ = [f for f in _Setup._fields_] + [("u_in_t", _D), ("wall_T_t", _D * 2)]
+
+
+def tlm_lib():
+    global _tlm
+    if _tlm is None:
+        if not os.path.exists(_TLM_PATH):
+            build_tlm()
+        L = C.CDLL(_TLM_PATH)
+        L.tlm_k.restype = C.c_int
+        L.tlm_create.restype = C.c_void_p
+        L.tlm_create.argtypes = [C.POINTER(_TlmSetup)]
+        L.tlm_destroy.argtypes = [C.c_void_p]
+        L.tlm_set_fields.argtypes = [C.c_void_p, _D * 4, _D * 4]
+        L.tlm_get_fields.argtypes = [C.c_void_p, _D * 4, _D * 4]
+        L.tlm_step.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int]
+        L.tlm_set_threads.argtypes = [C.c_int]
+        _tlm = L
+    return _tlm
+
+
+class Tangent:
+    """The oracle's step with K = tlm_lib().tlm_k() tangent directions carried
+    along (forward mode).  Tangents of the inlet profile and the wall
+    temperatures are fixed at creation ([K, ny], [K, nx] arrays or None);
+    those of the state are given with set_fields ([K, *field shape])."""
+
+    def __init__(self, prob, u_in_t=None, wall_T_t=(None, None)):
+        L = tlm_lib()
+        self.K = int(L.tlm_k())
+        self.prob, self.nx, self.ny = prob, prob.nx, prob.ny
+        dx, dy = prob.widths()
+        u_in, T_in = prob.inlet()
+        wb, wt = prob.walls()
+        ob = np.array(prob.obstacles, dtype=np.int32).reshape(-1, 4)
+        oi0, oj0, oi1, oj1 = [np.ascontiguousarray(ob[:, k]) for k in range(4)]
+        tan = lambda a, n: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(self.K, n)
+        ut = tan(u_in_t, self.ny)
+        wtt = [tan(a, self.nx) for a in wall_T_t]
+        self._keep = [dx, dy, u_in, T_in, wb, wt, oi0, oj0, oi1, oj1, ut] + wtt
+        s = _TlmSetup()
+        s.nx, s.ny = prob.nx, prob.ny
+        s.dx, s.dy = _ptr(dx), _ptr(dy)
+        s.periodic = int(prob.periodic)
+        s.n_obst = len(ob)
+        ip = lambda a: a.ctypes.data_as(_I)
+        s.oi0, s.oj0, s.oi1, s.oj1 = ip(oi0), ip(oj0), ip(oi1), ip(oj1)
+        s.Ma, s.Re, s.Pr, s.gamma = prob.Ma, prob.Re, prob.Pr, prob.gamma
+        s.u_in, s.T_in, s.p_in = _ptr(u_in), _ptr(T_in), prob.p_in
+        s.wall_type[0], s.wall_type[1] = prob.wall_type
+        s.wall_u[0], s.wall_u[1] = prob.wall_u
+        s.wall_T[0], s.wall_T[1] = _ptr(wb), _ptr(wt)
+        s.obstacle_T, s.gx, s.gy = prob.obstacle_T, prob.gx, prob.gy
+        s.obstacle_type, s.kn = prob.obstacle_type, prob.kn
+        s.u_in_t = _ptr(ut) if ut is not None else None
+        s.wall_T_t[0] = _ptr(wtt[0]) if wtt[0] is not None else None
+        s.wall_T_t[1] = _ptr(wtt[1]) if wtt[1] is not None else None
+        h = L.tlm_create(C.byref(s))
+        if not h:
+            raise ValueError("tlm_create rejected the problem")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            tlm_lib().tlm_destroy(self._h)
+            self._h = None
+
+    def shapes(self):
+        nx, ny = self.nx, self.ny
+        return (ny, nx + 1), (ny + 1, nx), (ny, nx), (ny, nx)
+
+    def set_fields(self, vals, tans=(None, None, None, None)):
+        v = [np.ascontiguousarray(a, dtype=np.float64) for a in vals]
+        t = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape((self.K,) + s)
+             for a, s in zip(tans, self.shapes())]
+        for a, s in zip(v, self.shapes()):
+            assert a.shape == s, (a.shape, s)
+        pv = (_D * 4)(*[_ptr(a) for a in v])
+        pt = (_D * 4)(*[(_ptr(a) if a is not None else None) for a in t])
+        tlm_lib().tlm_set_fields(self._h, pv, pt)
+
+    def fields(self):
+        """Values (u, v, p, T) and their tangents ([K, *shape] each)."""
+        v = [np.zeros(s) for s in self.shapes()]
+        t = [np.zeros((self.K,) + s) for s in self.shapes()]
+        tlm_lib().tlm_get_fields(self._h, (_D * 4)(*[_ptr(a) for a in v]),
+                                 (_D * 4)(*[_ptr(a) for a in t]))
+        return tuple(v), tuple(t)
+
+    def step(self, dt, n_inner, scheme):
+        tlm_lib().tlm_step(self._h, float(dt), int(n_inner), int(scheme))
+
+
+def drag_tangent(prob, fields, tangents):
+    """The drag of `drag` and its derivatives along the K tangent directions
+    of a state (tangents: [K, *shape] per field), by the product and chain
+    rules of its terms."""
+    u, _, p, T = fields
+    tu, _, tp, tT = tangents
+    A = 1.0 / (prob.gamma * prob.Ma ** 2)
+    B = 1.0 / prob.Re
+    dx, dy = prob.widths()
+    solid = prob.solid_mask().astype(bool)
+    ny, nx = solid.shape
+    fluid = ~solid
+    east = np.zeros_like(solid)
+    east[:, :-1] = fluid[:, :-1] & solid[:, 1:]
+    west = np.zeros_like(solid)
+    west[:, 1:] = fluid[:, 1:] & solid[:, :-1]
+    walls = np.zeros((ny, nx))
+    walls[1:] += (fluid[1:] & solid[:-1])
+    walls[:-1] += (fluid[:-1] & solid[1:])
+    kp = A * dy[:, None] * (east.astype(float) - west.astype(float))
+    kw = walls * B * dx[None, :] / (0.5 * dy[:, None])
+    G = np.sqrt(T)
+    uc = 0.5 * (u[:, :-1] + u[:, 1:])
+    D = float(np.sum(kp * p) + np.sum(kw * G * uc))
+    tuc = 0.5 * (tu[:, :, :-1] + tu[:, :, 1:])
+    dD = np.sum(kp[None] * tp, axis=(1, 2)) + \
+        np.sum(kw[None] * (0.5 * tT / G[None] * uc[None] + G[None] * tuc), axis=(1, 2))
+    return D, dD
