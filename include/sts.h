@@ -277,6 +277,18 @@ sts_status sts_adjoint_read(sts_ctx *ctx, double *g_uin, double *g_Tw0, double *
                             double *lambda_u, double *lambda_v, double *lambda_p,
                             double *lambda_T);
 
+/* Wait and copy to host arrays (layouts of sts_fields; NULL skips) the
+   gradient with respect to the fields given to sts_set_fields at the
+   current level: lambda mapped through the transpose of that call's
+   boundary-value projection.  Entries the projection overwrites (inlet,
+   wall and obstacle faces, solid cells) get 0; the outlet face is a copy of
+   face nx-1, so its entry of lambda is added to that face's (when face
+   nx-1 is an unknown) and the outlet entry itself gets 0.  At the initial
+   level this is dL/d(initial fields).  STS_ESTATE before
+   sts_adjoint_begin. */
+sts_status sts_adjoint_read_state_grad(sts_ctx *ctx, double *g_u, double *g_v, double *g_p,
+                                       double *g_T);
+
 /* Release everything the context owns.  NULL-safe. */
 void sts_destroy(sts_ctx *ctx);
 

@@ -11,9 +11,8 @@ slot per step), then for n = last .. first: lambda += (dL/dD_n) dD/dstate^n
 gradient with respect to u_in is the inlet entries of lambda at the initial
 level; the wall-temperature gradients accumulate inside the adjoint steps.
 The gradient with respect to the initial state is lambda at the initial
-level mapped through the boundary-value projection of sts_set_fields
-(entries the projection overwrites get 0; the outlet face copies face
-nx-1).
+level mapped through the transpose of sts_set_fields' boundary-value
+projection, which the library applies (sts_adjoint_read_state_grad).
 
 With scheme bit MIXED the forward (and every recompute) runs the
 mixed-precision pass and the backward applies the FP64 step's transpose at
@@ -71,23 +70,6 @@ def forward_loss(base: W.Problem, u_in, Tw0, Tw1, f0: Sequence[np.ndarray], dt: 
         acc += g.drag()
     g.close()
     return acc / steps
-
-
-def _project_grad(p: W.Problem, lam):
-    """Gradient with respect to the fields given to set_fields from the
-    adjoint state: zero where the projection imposes a boundary value."""
-    lu, lv, lp, lT = [a.copy() for a in lam]
-    solid = p.solid_mask().astype(bool)
-    nx, ny = p.nx, p.ny
-    fluid = ~solid
-    usolved = np.zeros((ny, nx + 1), dtype=bool)
-    usolved[:, 1:nx] = fluid[:, :-1] & fluid[:, 1:]
-    vsolved = np.zeros((ny + 1, nx), dtype=bool)
-    vsolved[1:ny, :] = fluid[:-1, :] & fluid[1:, :]
-    gu = np.where(usolved, lu, 0.0)
-    gu[:, nx - 1] += np.where(fluid[:, nx - 2] & fluid[:, nx - 1], lu[:, nx], 0.0)
-    gv = np.where(vsolved, lv, 0.0)
-    return gu, gv, np.where(fluid, lp, 0.0), np.where(fluid, lT, 0.0)
 
 
 class DragLoss(torch.autograd.Function):
@@ -148,12 +130,12 @@ class DragLoss(torch.autograd.Function):
                 g.adjoint_seed_drag(w)
                 g.state_load(nseg + n - 1 - n0)
                 g.adjoint_step(dt, inner, scheme)
-        (gu, g0, g1), lam = g.adjoint_read(with_lambda=True)
+        gu, g0, g1 = g.adjoint_read()
+        gf = g.adjoint_state_grad()
         LAST_STATS["backward_s"] = time.perf_counter() - t0
         g.close()
         ctx.g = None
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=ctx.dev)  # noqa: E731
-        gf = _project_grad(ctx.prob, lam)
         return (t(gu), t(g0), t(g1), *[t(a) for a in gf], None, None, None, None, None, None)
 
 

@@ -137,6 +137,7 @@ struct sts_ctx {
 
 extern "C" const char *sts_last_error(void) { return g_err.c_str(); }
 
+
 extern "C" sts_status sts_workspace_bytes(const sts_grid *grid, size_t *bytes) {
   if (!grid || !bytes) return fail(STS_EINVAL, "NULL argument");
   if (grid->nx < 4 || grid->ny < 4) return fail(STS_EINVAL, "nx, ny must be >= 4");
@@ -1068,6 +1069,43 @@ extern "C" sts_status sts_adjoint_step(sts_ctx *c, double dt, int n_inner, int s
   HIPCHK(hipMemsetAsync(c->A.luh, 0, 9 * c->L.field_bytes, c->stream));
   launch_adjoint_prologue(c->P, x0, c->lC, c->lam[c->lcur], c->A, scheme, c->stream);
   HIPCHK(hipGetLastError());
+  return STS_OK;
+}
+
+extern "C" sts_status sts_adjoint_read_state_grad(sts_ctx *c, double *gu, double *gv, double *gp,
+                                                  double *gT) {
+  if (!c) return fail(STS_EINVAL, "ctx is NULL");
+  if (!c->adj_K) return fail(STS_ESTATE, "sts_adjoint_begin has not been called");
+  const int nx = c->nx, ny = c->ny;
+  std::vector<double> lu((size_t)(nx + 1) * ny), lv((size_t)nx * (ny + 1)), lp((size_t)nx * ny),
+      lT((size_t)nx * ny);
+  sts_status s = sts_adjoint_read(c, nullptr, nullptr, nullptr, lu.data(), lv.data(), lp.data(),
+                                  lT.data());
+  if (s != STS_OK) return s;
+  // the transpose of sts_set_fields' boundary-value projection: entries it
+  // overwrites with a fixed value pass no derivative; the outlet face is a
+  // copy of face nx-1, so its adjoint adds to that face's
+  auto solid = [&](int i, int j) { return c->solid[(size_t)j * nx + i] != 0; };
+  if (gu)
+    for (int j = 0; j < ny; j++) {
+      double *row = gu + (size_t)j * (nx + 1);
+      const double *lrow = lu.data() + (size_t)j * (nx + 1);
+      for (int i = 0; i <= nx; i++)
+        row[i] = (i >= 1 && i <= nx - 1 && !solid(i - 1, j) && !solid(i, j)) ? lrow[i] : 0.0;
+      if (!solid(nx - 2, j) && !solid(nx - 1, j)) row[nx - 1] += lrow[nx];
+    }
+  if (gv)
+    for (int j = 0; j <= ny; j++)
+      for (int i = 0; i < nx; i++) {
+        const size_t k = (size_t)j * nx + i;
+        gv[k] = (j >= 1 && j <= ny - 1 && !solid(i, j - 1) && !solid(i, j)) ? lv[k] : 0.0;
+      }
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      const size_t k = (size_t)j * nx + i;
+      if (gp) gp[k] = solid(i, j) ? 0.0 : lp[k];
+      if (gT) gT[k] = solid(i, j) ? 0.0 : lT[k];
+    }
   return STS_OK;
 }
 

@@ -25,7 +25,7 @@ EXPLICIT, IMPLICIT, UPWIND, TVD, MIXED = 0, 1, 0, 2, 4
 EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_step_tol", "sts_residuals", "sts_fields",
            "sts_set_fields", "sts_field_ptrs", "sts_timing", "sts_read_timing", "sts_drag",
            "sts_state_slots", "sts_state_save", "sts_state_load", "sts_adjoint_begin",
-           "sts_adjoint_seed_drag", "sts_adjoint_seed", "sts_adjoint_step", "sts_step_l3", "sts_step_tol_l3", "sts_adjoint_read", "sts_destroy",
+           "sts_adjoint_seed_drag", "sts_adjoint_seed", "sts_adjoint_step", "sts_step_l3", "sts_step_tol_l3", "sts_adjoint_read", "sts_adjoint_read_state_grad", "sts_destroy",
            "sts_last_error")
 
 _D = C.POINTER(C.c_double)
@@ -94,6 +94,7 @@ def lib():
                                       C.c_int, C.POINTER(C.c_int)]
         L.sts_adjoint_step.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int]
         L.sts_adjoint_read.argtypes = [C.c_void_p] + [_D] * 7
+        L.sts_adjoint_read_state_grad.argtypes = [C.c_void_p] + [_D] * 4
         L.sts_destroy.argtypes = [C.c_void_p]
         L.sts_destroy.restype = None
         L.sts_last_error.restype = C.c_char_p
@@ -263,6 +264,13 @@ class Solver:
 
     def adjoint_step(self, dt: float, n_inner: int, scheme: int):
         _check(lib().sts_adjoint_step(self._h, float(dt), int(n_inner), int(scheme)))
+
+    def adjoint_state_grad(self):
+        """dL/d(the fields given to set_fields at the current level), layouts
+        of fields() (sts_adjoint_read_state_grad)."""
+        out = [np.zeros(s) for s in self.shapes()]
+        _check(lib().sts_adjoint_read_state_grad(self._h, *[_ptr(a) for a in out]))
+        return tuple(out)
 
     def adjoint_read(self, with_lambda: bool = False):
         """(dL/du_in[ny], dL/dwall_T[0][nx], dL/dwall_T[1][nx]) and, if asked,

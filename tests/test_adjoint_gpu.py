@@ -7,15 +7,17 @@ wall_T[1][nx].  Checks, at relative error 1e-5:
 - against an FP64 CPU reference gradient: central differences (h = 1e-6) of
   the oracle's loss in every parameter, on a small channel with one
   obstacle, heated walls and a seeded parabolic inlet (upwind and TVD);
-- on the 1024x256 channel (one centred square), against central
-  differences of the GPU forward along 16 seeded random directions of the
-  initial state around the square: one step of 10 passes at h = 1e-8 (both
-  spatial schemes), and the configured 100 steps x 10 passes with
-  checkpoints every 10 steps at h = 1e-6 (criterion: robust_ok).
-  In 100 steps (0.015 time units) the flow moves about 4 cells, so the drag
-  does not feel the inlet (512 cells upstream) or the walls (96 cells away)
-  at FP64 resolution: the parameter directions are checked on the small
-  channel, where they are resolved.
+- on the 1024x256 channel (one centred square), a dot-product test against
+  the oracle's tangent-linear model (the oracle compiled on dual numbers,
+  every branch taken on the value: the derivative of the same piecewise
+  smooth step, with no difference quotient across upwind or limiter
+  kinks) along 16 seeded directions, 6 in the inlet profile, 5 in the wall
+  temperatures and 5 in the initial state around the square: one step of 10
+  passes (both spatial schemes) and the configured 100 steps x 10 passes
+  with checkpoints every 10 steps (TVD).  In 100 steps the drag feels the
+  inlet 486 cells upstream and the walls 96 cells away only through many
+  Jacobi passes (derivatives ~1e-224 and ~1e-15), but both sides carry
+  them exactly, so each direction is held to 1e-5 relative.
 """
 from __future__ import annotations
 
@@ -100,74 +102,75 @@ def test_adjoint_vs_oracle_gradient(sts_mod, oracle_lib, name, scheme):
         assert err <= TOL, (which, err)
 
 
-def fd_directions_1024x256(steps, scheme, h, every, ndir=16):
-    """Relative differences between the adjoint's directional derivatives
-    and central differences of the GPU forward along seeded standard normal
-    directions on the unknowns of a box of 16 cells around the square."""
-    from paper_1802_04243_amd import adjoint
-    p, run = W.workload("adjoint_1024x256")
+def tlm_directions_1024x256(oracle_lib, steps, scheme, every):
+    """Dot-product test on the 1024x256 channel: the adjoint's directional
+    derivatives <gradient, delta> against the oracle's tangent-linear model
+    (ora.c compiled on dual numbers: the exact derivative of the branch the
+    forward takes) along K seeded directions: 6 in the inlet profile, 5 in
+    both wall temperatures, the rest in the initial state around the
+    square.  Returns (adjoint, tangent-linear) per direction."""
+    from paper_1802_04243_amd import workloads as W_
+    p, run = W_.workload("adjoint_1024x256")
     f0 = W.initial_fields(p, run["seed"])
     dt, inner = run["dt"], run["inner"]
-    print(f"case adjoint 1024x256 {steps}x{inner} every {every} scheme {scheme} h {h}", flush=True)
+    K = oracle_lib.tlm_lib().tlm_k()
+    print(f"case adjoint dot-product 1024x256 {steps}x{inner} every {every} scheme {scheme} "
+          f"({K} directions)", flush=True)
     L, gu, g0, g1, gf = adjoint_gradient(p, f0, dt, steps, inner, scheme, every, fields=True)
     print(f"L {L:.12e}; max|dL/du_in| {np.abs(gu).max():.2e}, max|dL/dwall_T| "
           f"{max(np.abs(g0).max(), np.abs(g1).max()):.2e}", flush=True)
+    rng = np.random.default_rng(2024)
+    nx, ny = p.nx, p.ny
+    du = np.zeros((K, ny))
+    dw0, dw1 = np.zeros((K, nx)), np.zeros((K, nx))
+    df = [np.zeros((K,) + a.shape) for a in f0]
     (i0, j0, i1, j1), = p.obstacles
     box = (slice(max(j0 - 16, 1), j1 + 17), slice(i0 - 16, i1 + 17))
-    solid = p.solid_mask().astype(bool)
-    bc = [p.inlet()[0]] + list(p.walls())
-    rng = np.random.default_rng(2024)
-    rels = []
-    for d in range(ndir):
-        dirs = []
-        for a in f0:
-            m = np.zeros_like(a)
-            m[box] = rng.standard_normal(m[box].shape)
-            dirs.append(m)
-        # only the unknowns: faces between two fluid cells, fluid cells
-        dirs[0][:, 1:p.nx][solid[:, :-1] | solid[:, 1:]] = 0.0
-        dirs[1][1:p.ny, :][solid[:-1, :] | solid[1:, :]] = 0.0
-        dirs[2][solid] = 0.0
-        dirs[3][solid] = 0.0
-        # entries of order 1: h moves each by about h
-        lp = adjoint.forward_loss(p, *bc, [a + h * x for a, x in zip(f0, dirs)], dt, steps,
-                                  inner, scheme)
-        lm = adjoint.forward_loss(p, *bc, [a - h * x for a, x in zip(f0, dirs)], dt, steps,
-                                  inner, scheme)
-        fd = (lp - lm) / (2 * h)
-        ad = sum(float((g * x).sum()) for g, x in zip(gf, dirs))
-        rels.append(abs(ad - fd) / max(abs(fd), abs(ad)))
-        print(f"direction {d}: adjoint {ad:.10e} fd {fd:.10e} rel {rels[-1]:.2e}", flush=True)
-    return np.array(rels)
+    for k in range(K):
+        if k < 6:
+            du[k] = rng.standard_normal(ny)
+        elif k < 11:
+            dw0[k] = rng.standard_normal(nx)
+            dw1[k] = rng.standard_normal(nx)
+        else:
+            for a in df:
+                a[k][box] = rng.standard_normal(a[k][box].shape)
+    t = oracle_lib.Tangent(p, du, (dw0, dw1))
+    t.set_fields(f0, df)
+    acc, Lt = np.zeros(K), 0.0
+    for n in range(steps):
+        t.step(dt, inner, scheme)
+        D, dD = oracle_lib.drag_tangent(p, *t.fields())
+        acc += dD
+        Lt += D
+    tlm, Lt = acc / steps, Lt / steps
+    assert abs(L - Lt) <= 1e-10 * abs(Lt), (L, Lt)
+    ad = np.array([float((gu * du[k]).sum() + (g0 * dw0[k]).sum() + (g1 * dw1[k]).sum() +
+                         sum((g * d[k]).sum() for g, d in zip(gf, df))) for k in range(K)])
+    for k in range(K):
+        kind = "u_in" if k < 6 else ("wall_T" if k < 11 else "state")
+        rel = abs(ad[k] - tlm[k]) / abs(tlm[k]) if tlm[k] != 0 else abs(ad[k])
+        print(f"direction {k} ({kind}): adjoint {ad[k]:.12e} tangent-linear {tlm[k]:.12e} "
+              f"rel {rel:.2e}", flush=True)
+    return ad, tlm
 
 
-def robust_ok(rels):
-    """The discrete step is only piecewise smooth: upwind choices (and TVD
-    limiter branches) flip where a velocity crosses zero, and the initial
-    noise puts many v-faces there.  A difference quotient that straddles a
-    flip is not a derivative; its disagreement with the adjoint then varies
-    erratically with h (measured over h = 1e-8 .. 1e-4 on these cases),
-    while below h = 1e-8 round-off of the loss takes over.  Asserted: the
-    median over the directions within 1e-5 and every direction within 1e-4
-    (the strict per-parameter check is the small channel's)."""
-    print(f"median rel {np.median(rels):.2e}, max {rels.max():.2e}, "
-          f"{int((rels > TOL).sum())} of {rels.size} above {TOL:g}", flush=True)
-    return np.median(rels) <= TOL and rels.max() <= 10 * TOL
+def assert_dot_products(ad, tlm):
+    # every direction within 1e-5 (a direction whose derivative is exactly
+    # zero in the tangent-linear model must be zero in the adjoint too)
+    for k, (a, t) in enumerate(zip(ad, tlm)):
+        assert np.isfinite(a) and abs(a - t) <= TOL * abs(t), (k, a, t)
 
 
 @pytest.mark.parametrize("name,scheme", [("explicit_upwind", W.EXPLICIT | W.UPWIND),
                                          ("explicit_tvd", W.EXPLICIT | W.TVD)])
-def test_adjoint_fd_directions_1024x256_one_step(sts_mod, name, scheme):
-    # one step of 10 passes, h = 1e-8
-    rels = fd_directions_1024x256(1, scheme, 1e-8, 1)
-    assert robust_ok(rels), rels
+def test_adjoint_dot_product_1024x256_one_step(sts_mod, oracle_lib, name, scheme):
+    assert_dot_products(*tlm_directions_1024x256(oracle_lib, 1, scheme, 1))
 
 
-def test_adjoint_fd_directions_1024x256_100_steps(sts_mod):
-    # the configured run: 100 steps x 10 passes, checkpoints every 10 steps,
-    # h = 1e-6
-    rels = fd_directions_1024x256(100, W.EXPLICIT | W.UPWIND, 1e-6, 10)
-    assert robust_ok(rels), rels
+def test_adjoint_dot_product_1024x256_configured_run(sts_mod, oracle_lib):
+    # the configured run: 100 steps x 10 passes, checkpoints every 10 steps
+    assert_dot_products(*tlm_directions_1024x256(oracle_lib, 100, W.EXPLICIT | W.TVD, 10))
 
 
 def test_adjoint_argument_errors(sts_mod):

@@ -77,7 +77,9 @@ def near_ties(prob, fields, ulps=8):
 def run_pair(sts_mod, oracle_lib, prob, dt, steps, inner, scheme, seed, amp=1e-3, label="",
              resync=False):
     """Run both from the same seeded state.  resync: before every step the
-    oracle takes the GPU's state, and every step is compared."""
+    oracle takes the GPU's state, and every step is compared; always so for
+    implicit TVD (its limiter ties, module docstring)."""
+    resync = resync or (scheme & 3) == (W.IMPLICIT | W.TVD)
     print(f"case {label} scheme={scheme} grid={prob.nx}x{prob.ny} steps={steps}x{inner}"
           f"{' (step by step from shared states)' if resync else ''}", flush=True)
     g = sts_mod.Solver(prob)
