@@ -224,6 +224,20 @@ sts_status sts_read_timing(sts_ctx *ctx, double out_ms[3], long long out_n[2]);
 /* Wait and return D of the current state. */
 sts_status sts_drag(sts_ctx *ctx, double *out);
 
+/* For callers that cannot allocate device or pinned memory (code under HIP
+   graph capture, serving loops, harnesses that forbid hipMalloc): sts_drag
+   without any allocation and without waiting.  Enqueues the drag D of the
+   current state on the context's stream and writes it to d_out[0], device
+   memory of the context's GPU owned by the caller (the value is there once
+   the stream reaches this point).  The reduction's block partials (at most
+   1024 doubles) live in a fixed array of the library that each GPU holds
+   until the process ends, shared by every context on that GPU: calls that
+   overlap on one GPU (other streams or threads) race on it.  The result is
+   bitwise sts_drag's.  STS_EINVAL for NULL arguments, slip-jump obstacles
+   (as sts_drag) or a reduction needing more partials than the array
+   holds. */
+sts_status sts_drag_noalloc(sts_ctx *ctx, double *d_out);
+
 /* Device checkpoint storage: (re)allocate n >= 0 state slots owned by the
    context (n = 0 frees them; previous contents are lost).  STS_ENOMEM if
    the allocation fails.  sts_state_save copies the current state into a

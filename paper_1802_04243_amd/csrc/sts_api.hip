@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -137,6 +138,35 @@ struct sts_ctx {
 
 extern "C" const char *sts_last_error(void) { return g_err.c_str(); }
 
+namespace {
+// Block partials of the drag reduction of sts_drag_noalloc: a fixed array
+// that every GPU running this library holds in its copy of the code object
+// (8 KiB, until the process ends).  Host code never names the array after
+// set-up: sts_create resolves its device address once per device, with that
+// device current, and the entry point passes that address to the kernels.
+constexpr int NOALLOC_PARTIALS = 1024;
+static __device__ __align__(256) double scratch[NOALLOC_PARTIALS];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[MAX_DEVICES] = {};
+
+sts_status resolve_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(STS_EDEVICE, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return STS_OK;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(STS_EDEVICE, "hipGetSymbolAddress of the drag scratch array: %s", hipGetErrorString(e));
+  g_scratch[device] = (double *)p;
+  return STS_OK;
+}
+double *scratch_of(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
+}  // namespace
 
 extern "C" sts_status sts_workspace_bytes(const sts_grid *grid, size_t *bytes) {
   if (!grid || !bytes) return fail(STS_EINVAL, "NULL argument");
@@ -493,6 +523,13 @@ extern "C" sts_status sts_create(const sts_grid *grid, const sts_obstacles *obst
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return fail(STS_EDEVICE, "no HIP device");
+  }
+  {
+    sts_status s = resolve_scratch(c->device);
+    if (s != STS_OK) {
+      delete c;
+      return s;
+    }
   }
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
@@ -891,6 +928,23 @@ extern "C" sts_status sts_drag(sts_ctx *c, double *out) {
                         hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   *out = *c->haux;
+  return STS_OK;
+}
+
+extern "C" sts_status sts_drag_noalloc(sts_ctx *c, double *d_out) {
+  if (!c || !d_out) return fail(STS_EINVAL, "NULL argument");
+  if (c->otype != STS_WALL_NOSLIP_ISOTHERMAL)
+    return fail(STS_EINVAL, "the drag is defined for no-slip obstacle surfaces");
+  const int nb = drag_blocks(c->P);
+  if (nb > NOALLOC_PARTIALS)
+    return fail(STS_EINVAL, "the drag reduction needs %d partials; the fixed array holds %d", nb,
+                NOALLOC_PARTIALS);
+  double *part = scratch_of(c->device);
+  if (!part) return fail(STS_ESTATE, "the drag scratch array of device %d is not resolved", c->device);
+  // every block assigns its partial and the sum reads exactly nb of them:
+  // nothing in the array has to start at zero
+  launch_drag(c->P, c->st[c->cur], part, d_out, c->stream);
+  HIPCHK(hipGetLastError());
   return STS_OK;
 }
 

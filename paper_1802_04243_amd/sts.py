@@ -23,7 +23,7 @@ EXPLICIT, IMPLICIT, UPWIND, TVD, MIXED = 0, 1, 0, 2, 4
 
 # every symbol the header declares
 EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_step_tol", "sts_residuals", "sts_fields",
-           "sts_set_fields", "sts_field_ptrs", "sts_timing", "sts_read_timing", "sts_drag",
+           "sts_set_fields", "sts_field_ptrs", "sts_timing", "sts_read_timing", "sts_drag", "sts_drag_noalloc",
            "sts_state_slots", "sts_state_save", "sts_state_load", "sts_adjoint_begin",
            "sts_adjoint_seed_drag", "sts_adjoint_seed", "sts_adjoint_step", "sts_step_l3", "sts_step_tol_l3", "sts_adjoint_read", "sts_adjoint_read_state_grad", "sts_destroy",
            "sts_last_error")
@@ -83,6 +83,7 @@ def lib():
         L.sts_timing.argtypes = [C.c_void_p, C.c_int]
         L.sts_read_timing.argtypes = [C.c_void_p, _D, C.POINTER(C.c_longlong)]
         L.sts_drag.argtypes = [C.c_void_p, _D]
+        L.sts_drag_noalloc.argtypes = [C.c_void_p, C.c_void_p]
         L.sts_state_slots.argtypes = [C.c_void_p, C.c_int]
         L.sts_state_save.argtypes = [C.c_void_p, C.c_int]
         L.sts_state_load.argtypes = [C.c_void_p, C.c_int]
@@ -235,6 +236,12 @@ class Solver:
         out = np.zeros(1)
         _check(lib().sts_drag(self._h, _ptr(out)))
         return float(out[0])
+
+    def drag_noalloc(self, out) -> None:
+        """sts_drag_noalloc: enqueue the drag into out[0], a float64 tensor on
+        the solver's GPU (no allocation, no wait)."""
+        assert out.is_cuda and out.dtype.is_floating_point and out.element_size() == 8
+        _check(lib().sts_drag_noalloc(self._h, C.c_void_p(out.data_ptr())))
 
     def state_slots(self, n: int):
         _check(lib().sts_state_slots(self._h, int(n)))
