@@ -103,9 +103,12 @@ typedef struct {
    form of any variant: the T, u and v coefficients are assembled and the
    Jacobi corrections formed in FP32, applied to the FP64 state through an
    FP64 defect of each equation; face densities, the pressure equation, the
-   velocity update, the per-step constants and the residuals stay FP64.  Its
-   results differ from the FP64 form at the level of FP32 rounding of the
-   coefficients (not bitwise). */
+   velocity update, the per-step constants and the residuals stay FP64.  The
+   FP64 defect keeps the state and its increments in FP64 but is formed from
+   the FP32-rounded coefficients, so loop 2 converges to the solution of the
+   FP32-perturbed operator: results differ from the FP64 form at the level of
+   FP32 rounding of the coefficients (about 1e-7 relative), which the defect
+   does not remove. */
 enum {
   STS_EXPLICIT = 0,
   STS_IMPLICIT = 1,
