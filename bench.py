@@ -373,6 +373,8 @@ def main():
                     help="comma list of further grids timed with every FP64 scheme ('' = none)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint timing and print its JSON (profiling)")
+    ap.add_argument("--combined-only", action="store_true",
+                    help="run only the combined run (4096x1024) and print its JSON (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration)")
     a = ap.parse_args()
@@ -381,6 +383,9 @@ def main():
         return
     if a.adjoint_only:
         print(json.dumps(run_adjoint()), flush=True)
+        return
+    if a.combined_only:
+        print(json.dumps(run_combined()), flush=True)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "

@@ -12,9 +12,10 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sts_api.hip", "sts_kernels.h
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: keep hipcc from emitting packed FP32 instructions.
-# -ffp-contract=off: no a*b+c fusion, so every FP64 operation is the single
-# IEEE-rounded operation the source states.
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+# -ffp-contract=on: a*b+c within one expression becomes one fused
+# multiply-add (one rounding); across expressions nothing is fused, so a
+# function inlined into several kernels rounds the same way in each.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 

@@ -27,13 +27,29 @@ namespace {
 // ---------------------------------------------------------------------------
 // elementary functions (Sec. 3.2)
 // ---------------------------------------------------------------------------
+// a / b for the finite, normal, non-zero divisors of the equations: the
+// hardware reciprocal refined by one Newton step, the quotient corrected by
+// its residual (b = 0, infinities and subnormals are not handled; the
+// divisors here are sums of positive coefficients, widths, T and limiter
+// denominators whose terms share a sign)
+__device__ __forceinline__ double ddiv(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
+__device__ __forceinline__ double drcp(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+  return __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+}
 // van Leer limiter psi(r) = (r+|r|)/(1+|r|) of r = a/b; 0 for r <= 0 and
 // when r is undefined (b == 0).
 __device__ __forceinline__ double vanleer(double a, double b) {
   // branch-free: the quotient is formed in every lane and discarded where
   // r <= 0 (2r/(1+r) = 2a/(a+b) for r = a/b > 0)
   const bool pos = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);
-  const double q = 2.0 * a / (a + b);
+  const double q = ddiv(2.0 * a, a + b);
   return pos ? q : 0.0;
 }
 // max(a, b) as a > b ? a : b (the sign of a zero result is that of b)
@@ -68,11 +84,11 @@ __device__ __forceinline__ double upw(double f1, double f2, double vel) {
 // harmonic mean of Gamma between two nodes (eq pl33)
 __device__ __forceinline__ double hmean(double dl, double gl, double dr,
                                         double gr) {
-  return (dl + dr) * gl * gr / (dl * gr + dr * gl);
+  return ddiv((dl + dr) * gl * gr, dl * gr + dr * gl);
 }
 // harmonic mean of a node value and a boundary value over a half cell
 __device__ __forceinline__ double hmean2(double a, double b) {
-  return 2.0 * a * b / (a + b);
+  return ddiv(2.0 * a * b, a + b);
 }
 __device__ __forceinline__ int clampi(int v, int lo, int hi) {
   return v < lo ? lo : (v > hi ? hi : v);
@@ -226,7 +242,7 @@ __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
       const int a = k % LW, b = k / LW;
       s.p[b][a] = SUB ? sp[m] : pp[m];
       s.T[b][a] = SUB ? st[m] : tt[m];
-      s.r[b][a] = pp[m] / tt[m];
+      s.r[b][a] = ddiv(pp[m], tt[m]);
       s.g[b][a] = MX ? (double)__builtin_amdgcn_sqrtf((float)tt[m]) : sqrt(tt[m]);
       s.fl[b][a] = ff[m];
       s.u[b][a] = uu[m];
@@ -507,7 +523,7 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
                    2.0 / 3.0 * dv * dv) *
           dV +
       P.C3 * P_(i, j) * dv * dV;
-  return (P.dt * (aW * nW + aE * nE + aS * nS + aN * nN + Sc) + CT) / a0;
+  return ddiv(P.dt * (aW * nW + aE * nE + aS * nS + aN * nN + Sc) + CT, a0);
 }
 
 // ---------------------------------------------------------------------------
@@ -604,8 +620,9 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
                    2.0 / 3.0 * gr * (V_(i, j + 1) - V_(i, j)) +
                    2.0 / 3.0 * gl * (V_(i - 1, j + 1) - V_(i - 1, j));
   const double b = Cu + P.B * X;
-  uh = (aS * uS + aN * uN + aW * uW + aE * uE + b) / a0;
-  du = P.A * dyj / a0;
+  const double ia0 = drcp(a0);
+  uh = (aS * uS + aN * uN + aW * uW + aE * uE + b) * ia0;
+  du = P.A * dyj * ia0;
 }
 
 // ---------------------------------------------------------------------------
@@ -680,8 +697,9 @@ __device__ void v_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
                    2.0 / 3.0 * gn * (U_(i + 1, j) - U_(i, j)) +
                    2.0 / 3.0 * gs * (U_(i + 1, j - 1) - U_(i, j - 1));
   const double b = Cv + P.B * X;
-  vh = (aW * vW + aE * vE + aS * vS + aN * vN + b) / a0;
-  dv = P.A * dxi / a0;
+  const double ia0 = drcp(a0);
+  vh = (aW * vW + aE * vE + aS * vS + aN * vN + b) * ia0;
+  dv = P.A * dxi * ia0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1265,10 +1283,10 @@ __device__ void pass_body(Lds &s, const Params &P, const State n,
       const double aS = RV_(i, j) * DV_(i, j) * dxi, aN = RV_(i, j + 1) * DV_(i, j + 1) * dxi;
       const double bW = RU_(i, j) * UH_(i, j) * dyj, bE = RU_(i + 1, j) * UH_(i + 1, j) * dyj;
       const double bS = RV_(i, j) * VH_(i, j) * dxi, bN = RV_(i, j + 1) * VH_(i, j + 1) * dxi;
-      const double a0 = dV / tnew + (aW + aE + aS + aN) * P.dt;
+      const double a0 = ddiv(dV, tnew) + (aW + aE + aS + aN) * P.dt;
       const double bp = cp - (bE - bW + bN - bS) * P.dt;
       pnew = ((aW * P_(i - 1, j) + aE * P_(i + 1, j) + aS * P_(i, j - 1) +
-               aN * P_(i, j + 1)) * P.dt + bp) / a0;
+               aN * P_(i, j + 1)) * P.dt + bp) * drcp(a0);
     }
     PN_(i, j) = pnew;
     if constexpr (L3 == 1) {

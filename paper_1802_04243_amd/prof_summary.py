@@ -3,6 +3,8 @@
 Usage (after the rocprofv3 runs listed in the summary files):
   python -m paper_1802_04243_amd.prof_summary <kt_dir> <fetch_dir> <write_dir> \
       <copy_fetch_dir> <copy_write_dir> <out_dir>
+  python -m paper_1802_04243_amd.prof_summary sq <sq_dir> [<sq_dir> ...]
+  python -m paper_1802_04243_amd.prof_summary trace <kt_dir>
 
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch; each is scaled by
 what the same counter reads for a plain 1 GiB device copy (bench.py
@@ -86,5 +88,46 @@ def main(kt, fetch, write, cfetch, cwrite, outdir):
     return lines, fscale, wscale
 
 
+def sq(dirs):
+    """Mean per dispatch of every SQ counter of every k_* kernel over the
+    counter runs in dirs, as a markdown table (one column per kernel)."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                k = short(r["Kernel_Name"])
+                if k.startswith("k_"):
+                    vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    kernels = sorted(vals)
+    names = sorted({c for k in kernels for c in vals[k]})
+    lines = ["| counter | " + " | ".join(kernels) + " |", "|---|" + "---|" * len(kernels)]
+    for c in names:
+        row = [f"{sum(vals[k][c]) / len(vals[k][c]):,.0f}" if vals[k][c] else "" for k in kernels]
+        lines.append(f"| {c} | " + " | ".join(row) + " |")
+    lines.append("| dispatches | " + " | ".join(
+        str(max(len(v) for v in vals[k].values()) // max(1, len(dirs))) for k in kernels) + " |")
+    print("\n".join(lines))
+    return vals
+
+
+def trace(kt):
+    """Kernel-trace statistics as a markdown table with each kernel's share
+    of the summed kernel time."""
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(kt, "*kernel_stats.csv"))[0])))
+    total = sum(float(r["TotalDurationNs"]) for r in stats)
+    lines = ["| kernel | calls | avg us | total ms | share |", "|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{100 * float(r['TotalDurationNs']) / total:.1f} % |")
+    print("\n".join(lines))
+    return stats
+
+
 if __name__ == "__main__":
-    main(*sys.argv[1:7])
+    if sys.argv[1] == "sq":
+        sq(sys.argv[2:])
+    elif sys.argv[1] == "trace":
+        trace(sys.argv[2])
+    else:
+        main(*sys.argv[1:7])

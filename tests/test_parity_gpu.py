@@ -236,8 +236,11 @@ def test_large_grid_uniform_stream_is_preserved(sts_mod, scheme):
     # a 16384 x 16384 channel (268M FV, 30 GB of device workspace, arrays of
     # 2.2 GB, byte offsets past 2^32 in the workspace) started from the
     # library's own inlet state, a uniform stream between slip walls: every
-    # equation returns its old value, so every residual is exactly zero (the
-    # oracle's free-stream pin, at a size no oracle run reaches)
+    # equation returns its old value up to the rounding of the fused
+    # multiply-adds (measured: all increments zero but max|dv| 1.3e-19), so
+    # every residual is zero to 1e-15 where an indexing error at this size
+    # would leave values of order one (the oracle's free-stream pin, at a
+    # size no oracle run reaches)
     n = 16384
     p = W.Problem(nx=n, ny=n, lx=8.0, ly=8.0,
                   wall_type=(W.WALL_SLIP_ADIABATIC, W.WALL_SLIP_ADIABATIC))
@@ -247,7 +250,7 @@ def test_large_grid_uniform_stream_is_preserved(sts_mod, scheme):
         g.step(p.cfl_dt(), 3, scheme)
     r = g.residuals()
     print(f"residuals {r}", flush=True)
-    assert np.all(r == 0.0), r
+    assert np.all(np.abs(r) <= 1e-15), r
     g.close()
 
 
