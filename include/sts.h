@@ -148,10 +148,11 @@ sts_status sts_step(sts_ctx *ctx, double dt, int n_inner, int scheme);
    Gamma, u-hat, v-hat and d of the pass's iterate fixed, each solve taking T
    and p (the Jacobi neighbour values, the pressure work, the cell's T in the
    pressure equation) from the previous one; then the velocities.  n3 = 1 is
-   sts_step (the GPU algorithm's pass).  FP64 schemes only.  Allocates four
-   field arrays on first use with n3 > 1 (STS_ENOMEM if that fails).
-   STS_EINVAL for dt <= 0, n_inner < 1, n3 outside [1, 64], unknown scheme
-   bits or STS_MIXED with n3 > 1 (state unchanged). */
+   sts_step (the GPU algorithm's pass).  Every scheme, STS_MIXED included
+   (each solve then assembles the T, u and v coefficients in FP32 as
+   sts_step does).  Allocates four field arrays on first use with n3 > 1
+   (STS_ENOMEM if that fails).  STS_EINVAL for dt <= 0, n_inner < 1, n3
+   outside [1, 64] or unknown scheme bits (state unchanged). */
 sts_status sts_step_l3(sts_ctx *ctx, double dt, int n_inner, int n3, int scheme);
 
 /* One time step whose loop 2 runs until convergence (Sec. 3.1: the inner
@@ -173,7 +174,7 @@ sts_status sts_step_tol(sts_ctx *ctx, double dt, int max_inner, double tol, int 
 
 /* sts_step_tol with loop 3 (n3 energy-pressure solves, as sts_step_l3) in
    every pass; n3 = 1 is sts_step_tol.  STS_EINVAL as sts_step_tol, and for
-   n3 outside [1, 64] or STS_MIXED with n3 > 1; STS_ENOMEM as sts_step_l3. */
+   n3 outside [1, 64]; STS_ENOMEM as sts_step_l3. */
 sts_status sts_step_tol_l3(sts_ctx *ctx, double dt, int max_inner, int n3, double tol,
                            int scheme, int *n_inner);
 
@@ -183,6 +184,17 @@ sts_status sts_step_tol_l3(sts_ctx *ctx, double dt, int max_inner, int n3, doubl
    rho^u u_new dy and rho^v v_new dx.  Returns STS_ENONFINITE if the last
    step produced a non-finite value. */
 sts_status sts_residuals(sts_ctx *ctx, double out[6]);
+
+/* Per-pass residuals of the last sts_step_tol or sts_step_tol_l3 call
+   (Sec. 5: the maximal residuals are read after every inner iteration of
+   loop 2).  Waits for the stream, then copies min(max_rows, *rows) rows of
+   {max|du|, max|dv|, max|dp|, max|dT|} of passes 1, 2, ... over the unknowns
+   into out[max_rows][4] (host, caller-owned; NULL allowed when max_rows is
+   0) and sets *rows to the passes recorded: the passes that call ran, at
+   most 4096 (later passes are run but not recorded), and 0 after any other
+   kind of step or before the first.  STS_EINVAL for NULL ctx or rows,
+   max_rows < 0, or NULL out with max_rows > 0. */
+sts_status sts_residual_history(sts_ctx *ctx, double *out, int max_rows, int *rows);
 
 /* Wait for the stream and copy the current state to host arrays (layout
    above; caller-owned; NULL skips a field). */

@@ -58,7 +58,7 @@ Layout make_layout(int nx, int ny) {
   return L;
 }
 struct Sizes {
-  size_t state, consts, mask, small, partials, res, total;
+  size_t state, consts, mask, small, partials, res, hist, total;
 };
 Sizes make_sizes(int nx, int ny, const Layout &L) {
   Sizes S;
@@ -73,7 +73,8 @@ Sizes make_sizes(int nx, int ny, const Layout &L) {
             align_up(tiles, 256);
   S.partials = align_up(sizeof(double) * NRES * (tiles + RES_BLOCKS), 256);
   S.res = 256;  // NRES doubles, then the loop-2 control block at RES_CTL
-  S.total = S.state + S.consts + S.mask + S.small + S.partials + S.res;
+  S.hist = align_up(sizeof(double) * 4 * HIST_CAP, 256);  // per-pass residuals of loop 2
+  S.total = S.state + S.consts + S.mask + S.small + S.partials + S.res + S.hist;
   return S;
 }
 
@@ -95,6 +96,8 @@ struct sts_ctx {
   Resid X;
   double *dres;   // NRES residuals; at RES_CTL the loop-2 control block
   double *hres;   // pinned: NRES residuals; at RES_CTL host copies of it
+  double *dhist;  // [HIST_CAP][4] per-pass residuals of the last tolerance step
+  int hist_rows = 0;
   hipEvent_t l2ev[2] = {nullptr, nullptr};
   bool stepped;
   int last_scheme;
@@ -137,6 +140,11 @@ struct sts_ctx {
 };
 
 extern "C" const char *sts_last_error(void) { return g_err.c_str(); }
+
+sts_status sts::report_error(sts_status s, const char *msg) {
+  g_err = msg;
+  return s;
+}
 
 namespace {
 // Block partials of the drag reduction of sts_drag_noalloc: a fixed array
@@ -319,6 +327,7 @@ sts_status build(sts_ctx *c, const sts_bc *bc) {
   char *small = q; q += c->S.small;
   c->X.partials = (double *)q; q += c->S.partials;
   c->dres = (double *)q; q += c->S.res;
+  c->dhist = (double *)q; q += c->S.hist;
 
   // host-side boundary data
   std::vector<double> hs;
@@ -635,6 +644,7 @@ extern "C" sts_status sts_step(sts_ctx *c, double dt, int n_inner, int scheme) {
     c->t_passes += fused ? n_inner - 1 : n_inner;
   }
   c->stepped = true;
+  c->hist_rows = 0;
   c->last_scheme = scheme;
   return STS_OK;
 }
@@ -696,8 +706,6 @@ sts_status step_tol(sts_ctx *c, double dt, int max_inner, int n3, double tol, in
   if (!(tol >= 0) || !isfinite(tol)) return fail(STS_EINVAL, "tol must be >= 0 and finite");
   if (scheme & ~STS_SCHEME_MASK) return fail(STS_EINVAL, "unknown scheme bits 0x%x", scheme);
   if (n3 < 1 || n3 > 64) return fail(STS_EINVAL, "n3 must be in [1, 64]");
-  if (n3 > 1 && (scheme & STS_MIXED))
-    return fail(STS_EINVAL, "loop 3 is of the FP64 step (scheme 0x%x)", scheme);
   if (n3 > 1) {
     const sts_status s = ensure_l3(c);
     if (s != STS_OK) return s;
@@ -711,9 +719,10 @@ sts_status step_tol(sts_ctx *c, double dt, int max_inner, int n3, double tol, in
   HIPCHK(hipGetLastError());
   Resid X = c->X;
   X.stop = ctl;
-  Loop2 L{ctl, tol, c->p_in, 0};
+  Loop2 L{ctl, tol, c->p_in, 0, c->dhist};
   const int cur0 = c->cur;
   c->stepped = true;
+  c->hist_rows = 0;
   c->last_scheme = scheme;
   int slot = 0, waiting = -1;
   for (int k = 0; k < max_inner;) {
@@ -745,6 +754,7 @@ sts_status step_tol(sts_ctx *c, double dt, int max_inner, int n3, double tol, in
   const int k = hctl[5];
   if (k < 1 || k > max_inner) return fail(STS_EDEVICE, "loop 2 control block reads %d passes", k);
   c->cur = cur0 ^ (k & 1);
+  c->hist_rows = std::min(k, HIST_CAP);
   *n_inner = k;
   return STS_OK;
 }
@@ -774,7 +784,6 @@ extern "C" sts_status sts_step_l3(sts_ctx *c, double dt, int n_inner, int n3, in
   if (n3 < 1 || n3 > 64) return fail(STS_EINVAL, "n3 must be in [1, 64]");
   if (scheme & ~STS_SCHEME_MASK) return fail(STS_EINVAL, "unknown scheme bits 0x%x", scheme);
   if (n3 == 1) return sts_step(c, dt, n_inner, scheme);
-  if (scheme & STS_MIXED) return fail(STS_EINVAL, "loop 3 is of the FP64 step (scheme 0x%x)", scheme);
   sts_status s;
   if ((s = ensure_l3(c)) != STS_OK) return s;
   c->P.dt = dt;
@@ -791,7 +800,18 @@ extern "C" sts_status sts_step_l3(sts_ctx *c, double dt, int n_inner, int n3, in
   HIPCHK(hipMemcpyAsync(c->hres, c->dres, NRES * sizeof(double), hipMemcpyDeviceToHost,
                         c->stream));
   c->stepped = true;
+  c->hist_rows = 0;
   c->last_scheme = scheme;
+  return STS_OK;
+}
+
+extern "C" sts_status sts_residual_history(sts_ctx *c, double *out, int max_rows, int *rows) {
+  if (!c || !rows) return fail(STS_EINVAL, "NULL argument");
+  if (max_rows < 0 || (max_rows > 0 && !out)) return fail(STS_EINVAL, "bad output buffer");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const int n = std::min(max_rows, c->hist_rows);
+  if (n > 0) HIPCHK(hipMemcpy(out, c->dhist, sizeof(double) * 4 * n, hipMemcpyDeviceToHost));
+  *rows = c->hist_rows;
   return STS_OK;
 }
 

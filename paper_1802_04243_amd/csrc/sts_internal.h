@@ -5,7 +5,13 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/sts.h"
+
 namespace sts {
+// set the thread's last-error message of the C ABI (sts_last_error) and
+// return s
+sts_status report_error(sts_status s, const char *msg);
+
 
 // Tiling of the Jacobi pass: a block of BX x BY threads computes T, p,
 // u-hat, v-hat on the owned TX x TY cells plus a one-cell halo, and writes
@@ -78,11 +84,15 @@ struct Resid {
 // Device-side convergence control of loop 2: ctl[0] = stop flag, ctl[1] =
 // passes run.  The reduction after pass k writes ctl[1] = k and sets the flag
 // when max(max|du|, max|dv|, max|dT|, max|dp| / p_in) <= tol or some value is
-// non-finite (some pass's per-tile non-finite count is not zero).
+// non-finite (some pass's per-tile non-finite count is not zero).  hist: the
+// residual history, row k - 1 = max|du|, max|dv|, max|dp|, max|dT| of pass
+// k for k <= HIST_CAP (NULL: not recorded).
+constexpr int HIST_CAP = 4096;
 struct Loop2 {
   int *ctl;
   double tol, p_in;
   int k;
+  double *hist = nullptr;
 };
 
 // Intermediates of one pass (face densities, u-hat, d^u, v-hat, d^v, new p,

@@ -1393,11 +1393,12 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
     pass_body<NTH, false, SJ, IM, TV, RS, MX, IN>(s, P, n, X, I, tile, x0, y0, c, cp);
 }
 
-// One energy-pressure solve of a pass with loop 3 (FP64): L3 = 1 a solve
-// before the last (T, p to To, po), 2 the last (the pass's outputs in n);
-// SUB: the window's T and p from the previous solve (Ts, ps), rho, Gamma
-// and everything else from the pass's iterate o.
-template <int NTH, bool IM, bool TV, bool RS, bool SJ, int L3, bool SUB>
+// One energy-pressure solve of a pass with loop 3: L3 = 1 a solve before
+// the last (T, p to To, po), 2 the last (the pass's outputs in n); SUB: the
+// window's T and p from the previous solve (Ts, ps), rho, Gamma and
+// everything else from the pass's iterate o; MX: the mixed-precision form of
+// the T, u, v updates, as in k_pass.
+template <int NTH, bool IM, bool TV, bool RS, bool SJ, int L3, bool SUB, bool MX>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 256))) void k_pass3(
     const Params P, const State o, const State n, const Consts C, const Resid X,
     const double *Ts, const double *ps, double *To, double *po) {
@@ -1407,14 +1408,14 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2 * NTH / 2
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
   double c[Items<NTH>::rounds], cp;
   item_consts<NTH>(P, C, x0, y0, c, cp);
-  load_window<NTH, false, SUB>(s, P, o, x0, y0, Ts, ps);
+  load_window<NTH, MX, SUB>(s, P, o, x0, y0, Ts, ps);
   __syncthreads();
   if (P.clean[tile])
-    pass_body<NTH, true, false, IM, TV, RS, false, false, L3>(s, P, n, X, Inter{}, tile, x0, y0, c,
-                                                              cp, o, To, po);
+    pass_body<NTH, true, false, IM, TV, RS, MX, false, L3>(s, P, n, X, Inter{}, tile, x0, y0, c,
+                                                           cp, o, To, po);
   else
-    pass_body<NTH, false, SJ, IM, TV, RS, false, false, L3>(s, P, n, X, Inter{}, tile, x0, y0, c,
-                                                            cp, o, To, po);
+    pass_body<NTH, false, SJ, IM, TV, RS, MX, false, L3>(s, P, n, X, Inter{}, tile, x0, y0, c,
+                                                         cp, o, To, po);
 }
 
 // ---------------------------------------------------------------------------
@@ -1777,6 +1778,8 @@ __global__ __launch_bounds__(FB) void k_finalize(const double *rows, int nrows,
   block_partials<FB>(red, v, out);
   if (L.ctl && threadIdx.x == 0) {
     const double crit = fmax(fmax(out[0], out[1]), fmax(out[3], out[2] / L.p_in));
+    if (L.hist && L.k <= HIST_CAP)
+      for (int q = 0; q < 4; q++) L.hist[(long)(L.k - 1) * 4 + q] = out[q];
     L.ctl[1] = L.k;
     if (out[6] != 0.0 || crit <= L.tol) L.ctl[0] = 1;
   }
@@ -1879,30 +1882,38 @@ void launch_pass(const Params &P, State o, State n, Consts C, int scheme,
 void launch_pass3(const Params &P, State o, State n, Consts C, int scheme, const Resid *last,
                   int L3, const double *Ts, const double *ps, double *To, double *po,
                   hipStream_t st) {
-  const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0;
+  const bool im = (scheme & 1) != 0, tv = (scheme & 2) != 0, mx = (scheme & 4) != 0;
   dim3 g(ntiles(P));
   const Resid X = last ? *last : Resid{nullptr, nullptr, nullptr, nullptr};
-#define STS_P3(IM_, TV_, SJ_)                                                                   \
+  // threads per block: the FP64 form as k_pass3 always had it (NT for the
+  // implicit schemes), the mixed form as k_pass (NT where its registers need it)
+#define STS_P3(IM_, TV_, SJ_, MX_)                                                              \
   do {                                                                                          \
-    constexpr int nth = IM_ ? NT : NTP;                                                         \
+    constexpr int nth = (MX_ ? TV_ : IM_) ? NT : NTP;                                           \
     if (L3 == 1 && !Ts)                                                                         \
-      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, false, SJ_, 1, false>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
+      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, false, SJ_, 1, false, MX_>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
     else if (L3 == 1)                                                                           \
-      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, false, SJ_, 1, true>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
+      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, false, SJ_, 1, true, MX_>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
     else if (last)                                                                              \
-      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, true, SJ_, 2, true>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
+      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, true, SJ_, 2, true, MX_>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
     else                                                                                        \
-      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, false, SJ_, 2, true>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
+      hipLaunchKernelGGL((k_pass3<nth, IM_, TV_, false, SJ_, 2, true, MX_>), g, dim3(nth), 0, st, P, o, n, C, X, Ts, ps, To, po); \
   } while (0)
-#define STS_P3S(IM_, TV_)                 \
-  do {                                    \
-    if (P.sj) STS_P3(IM_, TV_, true);     \
-    else STS_P3(IM_, TV_, false);         \
+#define STS_P3S(IM_, TV_, MX_)                \
+  do {                                        \
+    if (P.sj) STS_P3(IM_, TV_, true, MX_);    \
+    else STS_P3(IM_, TV_, false, MX_);        \
   } while (0)
-  if (im && tv) STS_P3S(true, true);
-  else if (im) STS_P3S(true, false);
-  else if (tv) STS_P3S(false, true);
-  else STS_P3S(false, false);
+#define STS_P3M(IM_, TV_)                     \
+  do {                                        \
+    if (mx) STS_P3S(IM_, TV_, true);          \
+    else STS_P3S(IM_, TV_, false);            \
+  } while (0)
+  if (im && tv) STS_P3M(true, true);
+  else if (im) STS_P3M(true, false);
+  else if (tv) STS_P3M(false, true);
+  else STS_P3M(false, false);
+#undef STS_P3M
 #undef STS_P3S
 #undef STS_P3
 }

@@ -22,7 +22,8 @@ STS_OK, STS_EINVAL, STS_ENOMEM, STS_EDEVICE, STS_ENONFINITE, STS_ESTATE = 0, -1,
 EXPLICIT, IMPLICIT, UPWIND, TVD, MIXED = 0, 1, 0, 2, 4
 
 # every symbol the header declares
-EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_step_tol", "sts_residuals", "sts_fields",
+EXPORTS = ("sts_workspace_bytes", "sts_create", "sts_step", "sts_step_tol", "sts_residuals",
+           "sts_residual_history", "sts_fields",
            "sts_set_fields", "sts_field_ptrs", "sts_timing", "sts_read_timing", "sts_drag", "sts_drag_noalloc",
            "sts_state_slots", "sts_state_save", "sts_state_load", "sts_adjoint_begin",
            "sts_adjoint_seed_drag", "sts_adjoint_seed", "sts_adjoint_step", "sts_step_l3", "sts_step_tol_l3", "sts_adjoint_read", "sts_adjoint_read_state_grad", "sts_destroy",
@@ -76,6 +77,7 @@ def lib():
         L.sts_step_tol.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_int,
                                    C.POINTER(C.c_int)]
         L.sts_residuals.argtypes = [C.c_void_p, _D]
+        L.sts_residual_history.argtypes = [C.c_void_p, _D, C.c_int, C.POINTER(C.c_int)]
         L.sts_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
         L.sts_set_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
         L.sts_field_ptrs.argtypes = [C.c_void_p] + [C.POINTER(C.c_void_p)] * 4 + \
@@ -198,6 +200,16 @@ class Solver:
     def residuals(self) -> np.ndarray:
         out = np.zeros(6)
         _check(lib().sts_residuals(self._h, _ptr(out)))
+        return out
+
+    def residual_history(self) -> np.ndarray:
+        """Per-pass max|du|, max|dv|, max|dp|, max|dT| of the last tolerance
+        step, shape (passes, 4)."""
+        rows = C.c_int(0)
+        _check(lib().sts_residual_history(self._h, None, 0, C.byref(rows)))
+        out = np.zeros((rows.value, 4))
+        if rows.value:
+            _check(lib().sts_residual_history(self._h, _ptr(out), rows.value, C.byref(rows)))
         return out
 
     def fields(self) -> Tuple[np.ndarray, ...]:

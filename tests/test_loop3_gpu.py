@@ -10,7 +10,9 @@ a periodic slip-jump channel; the 4x4 grid; one step of the bench grid
 (5120x1152, explicit TVD, 2 solves) from a GPU-advanced state; loop 2 run
 to convergence with two solves per pass (sts_step_tol_l3: the oracle's pass
 counts, every scheme, and the bench grid).  Plus: one solve is sts_step /
-sts_step_tol, and the argument checks.
+sts_step_tol, and the argument checks.  The mixed-precision form with loop 3
+against the FP64 oracle's loop 3 within the mixed form's tolerances
+(test_mixed_gpu), and with one solve per pass bitwise the mixed sts_step.
 """
 from __future__ import annotations
 
@@ -161,7 +163,7 @@ def test_loop3_one_solve_is_the_step_and_argument_checks(sts_mod):
     assert np.array_equal(a.residuals(), b.residuals())
     for args in ((run["dt"], 6, 0, W.EXPLICIT), (run["dt"], 6, 65, W.EXPLICIT),
                  (run["dt"], 0, 2, W.EXPLICIT), (0.0, 6, 2, W.EXPLICIT),
-                 (run["dt"], 6, 2, W.EXPLICIT | W.MIXED)):
+                 (run["dt"], 6, 2, W.EXPLICIT | 8)):
         with pytest.raises(sts_mod.StsError) as e:
             a.step_l3(*args)
         assert e.value.code == sts_mod.STS_EINVAL, args
@@ -176,3 +178,97 @@ def test_loop3_one_solve_is_the_step_and_argument_checks(sts_mod):
         assert np.array_equal(x, y)
     a.close()
     b.close()
+
+
+def _mixed_l3_errors(sts_mod, oracle_lib, scheme, n3, resync):
+    from test_mixed_gpu import normdiff
+    p, run = W.workload("channel_120x24")
+    f0 = W.initial_fields(p, 1)
+    g, o = sts_mod.Solver(p), oracle_lib.Oracle(p)
+    g.set_fields(*f0)
+    o.set_fields(*f0)
+    worst = [0.0] * 4
+    for s in range(15):
+        if resync and s:
+            o.set_fields(*g.fields())
+        g.step_l3(run["dt"], 6, n3, scheme | W.MIXED)
+        o.step_l3(run["dt"], 6, n3, scheme)
+        if resync or s == 14:
+            errs = [normdiff(a, b) for a, b in zip(g.fields(), o.fields())]
+            worst = [max(a, b) for a, b in zip(worst, errs)]
+    g.close()
+    return worst
+
+
+@pytest.mark.parametrize("n3", [2, 3])
+@pytest.mark.parametrize("name,scheme", list(W.SCHEMES.items()))
+def test_loop3_mixed_vs_oracle_120x24(sts_mod, oracle_lib, name, scheme, n3):
+    # each solve of the mixed form assembles T, u, v in FP32 like its pass:
+    # the loop-3 step stays within the mixed form's FP32-rounding tolerance
+    # of the FP64 oracle's loop-3 step.  Implicit TVD is compared step by
+    # step from shared states and against the mixed form's own error with
+    # one solve per pass (the plain mixed step) on the same case: its
+    # coefficients can turn negative where the limiter exceeds one, and the
+    # Jacobi passes of such a step amplify any perturbation of the
+    # coefficients (FP64 rounding by about 1e4, see the parity tests), so the
+    # form's FP32 rounding shows at the 1e-4 level there, with or without
+    # loop 3.
+    from test_mixed_gpu import TOL
+    resync = scheme == W.IMPLICIT | W.TVD
+    print(f"case loop 3 mixed 120x24/{name} n3={n3} 15x6"
+          f"{' (step by step from shared states)' if resync else ''}", flush=True)
+    errs = _mixed_l3_errors(sts_mod, oracle_lib, scheme, n3, resync)
+    print(f"loop 3 mixed {name} n3={n3}: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) > 0.0  # the mixed form ran
+    if not resync:
+        assert max(errs) <= TOL[scheme], errs
+        return
+    one = _mixed_l3_errors(sts_mod, oracle_lib, scheme, 1, resync)
+    print(f"mixed {name}, one solve per pass: " + " ".join(f"{e:.2e}" for e in one), flush=True)
+    assert max(errs) <= max(TOL[scheme], 10.0 * max(one)) and max(errs) <= 1e-3, (errs, one)
+
+
+def test_loop3_mixed_one_solve_is_the_mixed_step(sts_mod):
+    p, run = W.workload("channel_120x24")
+    f0 = W.initial_fields(p, 5)
+    for scheme in W.SCHEMES.values():
+        a, b = sts_mod.Solver(p), sts_mod.Solver(p)
+        a.set_fields(*f0)
+        b.set_fields(*f0)
+        for _ in range(3):
+            a.step_l3(run["dt"], 6, 1, scheme | W.MIXED)
+            b.step(run["dt"], 6, scheme | W.MIXED)
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+        a.set_fields(*f0)
+        b.set_fields(*f0)
+        assert (a.step_tol_l3(run["dt"], 40, 1, 1e-8, scheme | W.MIXED)
+                == b.step_tol(run["dt"], 40, 1e-8, scheme | W.MIXED))
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+        a.close()
+        b.close()
+
+
+def test_loop3_mixed_with_tolerance_exit(sts_mod, oracle_lib):
+    # loop 2 run to convergence with two mixed solves per pass reaches the
+    # FP64 oracle's solution of the step within the mixed tolerance.  The
+    # tolerance is 1e-6 (the bench's): the mixed form's coefficients are the
+    # FP32 roundings of functions of the iterate, so its increments level off
+    # near FP32 resolution instead of falling to FP64 ones
+    from test_mixed_gpu import TOL, normdiff
+    p, run = W.workload("channel_120x24")
+    f0 = W.initial_fields(p, 2)
+    scheme = W.EXPLICIT | W.TVD
+    g, o = sts_mod.Solver(p), oracle_lib.Oracle(p)
+    g.set_fields(*f0)
+    o.set_fields(*f0)
+    for _ in range(5):
+        ng = g.step_tol_l3(run["dt"], 60, 2, 1e-6, scheme | W.MIXED)
+        no = o.step_tol_l3(run["dt"], 60, 2, 1e-6, scheme)
+        print(f"passes: mixed {ng}, oracle {no}", flush=True)
+        assert 1 < ng < 60 and 1 < no < 60, (ng, no)
+    errs = [normdiff(a, b) for a, b in zip(g.fields(), o.fields())]
+    print("loop 3 mixed + tolerance exit: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) <= TOL[scheme], errs
+    g.close()

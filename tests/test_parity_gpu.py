@@ -459,3 +459,51 @@ def test_tolerance_exit_zero_tol_is_fixed_count(sts_mod):
         assert e.value.code == sts_mod.STS_EINVAL
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("name,scheme", [("explicit_tvd", W.EXPLICIT | W.TVD),
+                                         ("implicit_upwind", W.IMPLICIT | W.UPWIND)])
+def test_residual_history_of_a_tolerance_step(sts_mod, oracle_lib, name, scheme):
+    # the per-pass residuals of loop 2 (Sec. 5 reads them after every pass):
+    # row k of the history is the oracle's max|du|, max|dv|, max|dp|, max|dT|
+    # after pass k + 1 of the same step (the oracle re-run from the step's
+    # start state for k + 1 passes; tolerance 0 never stops it early)
+    p, run = W.workload("channel_120x24")
+    print(f"case residual history 120x24/{name}", flush=True)
+    f0 = W.initial_fields(p, run["seed"])
+    g = sts_mod.Solver(p)
+    g.set_fields(*f0)
+    n = g.step_tol(run["dt"], 60, 1e-9, scheme)
+    h = g.residual_history()
+    assert h.shape == (n, 4) and 2 < n < 60, (h.shape, n)
+    assert np.allclose(h[-1], g.residuals()[:4], rtol=1e-12, atol=0.0)
+    o = oracle_lib.Oracle(p)
+    for k in range(n):
+        o.set_fields(*f0)
+        assert o.step_tol(run["dt"], k + 1, 0.0, scheme) == k + 1
+        ro = o.residuals()[:4]
+        assert np.allclose(h[k], ro, rtol=1e-6, atol=1e-13), (k, h[k], ro)
+    # the increments fall pass after pass once the first passes are done
+    crit = np.maximum(np.maximum(h[:, 0], h[:, 1]), np.maximum(h[:, 3], h[:, 2] / p.p_in))
+    assert crit[-1] <= 1e-9 < crit[-2]
+    # a fixed-count step clears the history
+    g.step(run["dt"], 3, scheme)
+    assert g.residual_history().shape == (0, 4)
+    g.close()
+
+
+def test_residual_history_keeps_the_first_4096_passes(sts_mod):
+    p, run = W.workload("channel_120x24")
+    g = sts_mod.Solver(p)
+    g.set_fields(*W.initial_fields(p, run["seed"]))
+    n = g.step_tol(run["dt"], 4200, 0.0, W.EXPLICIT | W.UPWIND)
+    h = g.residual_history()
+    print(f"passes {n}, history rows {h.shape[0]}", flush=True)
+    assert h.shape == (min(n, 4096), 4)
+    assert np.all(np.isfinite(h)) and h[0].max() > h[-1].max()
+    from paper_1802_04243_amd import sts as S
+    rows = S.C.c_int(0)
+    assert S.lib().sts_residual_history(g._h, None, -1, S.C.byref(rows)) == sts_mod.STS_EINVAL
+    assert S.lib().sts_residual_history(g._h, None, 3, S.C.byref(rows)) == sts_mod.STS_EINVAL
+    assert S.lib().sts_residual_history(g._h, None, 0, None) == sts_mod.STS_EINVAL
+    g.close()
