@@ -271,6 +271,49 @@ def run_other_grid(name: str, steps: int, warmup: int):
     return out
 
 
+# algorithmic bytes of one 3-D pass per FV: read u, v, w, p, T (40) and the
+# five per-step constants C_u, C_v, C_w, C_T, C_p (40), write u, v, w, p, T (40)
+BYTES_PER_FV_PASS_3D = 120
+
+
+def run_three_d(name: str = "duct_512x128x128", steps: int = 5, warmup: int = 2):
+    """FP64 throughput of the 3-D step in every scheme: whole steps timed with
+    HIP events on the stream the library enqueues on."""
+    import torch
+    from paper_1802_04243_amd import sts3
+    from paper_1802_04243_amd import workloads3 as W3
+    b, run = W3.workload3(name)
+    f0 = W3.initial_fields3(b, run["seed"])
+    out = {"workload": name, "grid": "x".join(str(k) for k in b.n), "n_fv": b.n_fv,
+           "steps": steps, "n_inner": run["inner"], "dt": run["dt"],
+           "bytes_per_fv_pass_algorithmic": BYTES_PER_FV_PASS_3D}
+    for nm, sch in W.SCHEMES.items():
+        g = sts3.Solver3(b)
+        g.set_fields(*f0)
+        for _ in range(warmup):
+            g.step(run["dt"], run["inner"], sch)
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(steps):
+            g.step(run["dt"], run["inner"], sch)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        r = g.residuals()
+        g.close()
+        pass_ms = ms / run["inner"]
+        gbs = BYTES_PER_FV_PASS_3D * b.n_fv / (pass_ms * 1e-3) / 1e9
+        out[nm] = {"mfv_iters_s": round(b.n_fv * run["inner"] / (ms * 1e-3) / 1e6, 2),
+                   "ms_per_step": round(ms, 4), "ms_per_pass_incl_prologue": round(pass_ms, 5),
+                   "gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                   "max_residuals": [float(f"{x:.3e}") for x in r[:5]]}
+        print(f"# 3-D {name} {nm}: {out[nm]['mfv_iters_s']:.1f} MFV-iters/s, step {ms:.3f} ms",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def field_errors(fm, fd):
     """max |a - b| / max |b| and rms(a - b) / rms(b) per field (u, v, p, T)."""
     mx, l2 = {}, {}
@@ -375,6 +418,8 @@ def main():
                     help="run only the adjoint timing and print its JSON (profiling)")
     ap.add_argument("--combined-only", action="store_true",
                     help="run only the combined run (4096x1024) and print its JSON (profiling)")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D step")
+    ap.add_argument("--three-d-only", action="store_true", help="run only the 3-D step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration)")
     a = ap.parse_args()
@@ -386,6 +431,9 @@ def main():
         return
     if a.combined_only:
         print(json.dumps(run_combined()), flush=True)
+        return
+    if a.three_d_only:
+        print(json.dumps(run_three_d()), flush=True)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
@@ -446,6 +494,7 @@ def main():
         print("# loop 3: " + ", ".join(f"{k} {v['ms_per_step']:.3f} ms/step" for k, v in loop3.items()
                                       if isinstance(v, dict)), file=sys.stderr, flush=True)
     others = {g: run_other_grid(g, a.steps, a.warmup) for g in a.other_grids.split(",") if g}
+    three_d = None if a.no_3d else run_three_d()
     h = sorted(head_runs, key=lambda r: r["mfv_iters_s"])[1]   # the median run
     traffic = measured_traffic(HEADLINE)
     copy_gbs = copy_ceiling()
@@ -498,6 +547,7 @@ def main():
         "loop3": loop3,
         "adjoint": adj,
         "combined": comb,
+        "three_d": three_d,
     }
     if rank == 0:
         print(json.dumps(out), flush=True)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsts.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sts_api.hip", "sts_kernels.hip", "sts_adjoint.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sts_api.hip", "sts_kernels.hip", "sts_adjoint.hip", "sts3.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: keep hipcc from emitting packed FP32 instructions.

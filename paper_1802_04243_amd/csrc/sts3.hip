@@ -1,0 +1,1120 @@
+// Three-dimensional SIMPLE-TS step: kernels and the C ABI of include/sts3.h.
+//
+// One thread per unknown.  A pass is a chain of streaming stencil kernels,
+// each reading its neighbours through the L1/L2 caches (no LDS tiles):
+//   cell properties rho = p/T, Gamma = sqrt(T)       (k3_cell)
+//   face densities of the three directions (pl10-pl11 read per direction)
+//                                                   (k3_rf<a>)
+//   energy equation (pl30-pl33, pl28, pl29)          (k3_energy)
+//   pseudo velocities and d of each component (pl14-pl16, pl18-pl21 read
+//   for any component a)                             (k3_mom<a>)
+//   pressure equation (pl23, pl24), six neighbours   (k3_pressure)
+//   velocity update (pl18, pl19)                     (k3_velocity<a>)
+// The step prologue stores the per-step constants (the level n-1 parts of
+// b^u, b^v, b^w, b^T, b^p and, for the explicit schemes, the explicit
+// convective terms pl15_11 / pl31_1).  The last pass of a step reduces the
+// increments and the continuity residual in fixed-order block partials.
+//
+// Every field array has the shape (nz+1) x (ny+1) x pitch doubles (x
+// fastest, pitch a multiple of 32), so that one index serves cells and the
+// faces of every direction.  Indices outside the domain wrap in a periodic
+// direction and are clamped otherwise (such values are loaded but never
+// used by an equation).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/sts3.h"
+#include "sts_internal.h"
+
+namespace sts3 {
+namespace {
+
+constexpr int BX = 64, BY = 4, NTB = BX * BY;  // 256 threads per block
+constexpr int NR = 8;                           // residual partials per block
+
+struct P3 {
+  int n[3];
+  int per[3];
+  int io;  // inlet / outlet in x
+  int wt[3][2];
+  double wv[3][2][3];
+  double wT[3][2], sqwT[3][2];
+  double A, B, C1, C2, C3, g[3];
+  double u_in, T_in, p_in, rho_in, sqT_in;
+  double dt;
+  long sy, sz;
+  const double *d[3];
+};
+
+struct Fld {
+  double *q[5];  // u, v, w, p, T
+};
+
+struct Work {
+  double *rho, *gam;
+  double *rf[3];            // face densities
+  double *qh[3], *dq[3];    // pseudo velocities and d
+  double *cq[3], *cT, *cp;  // per-step constants
+};
+
+// ---------------------------------------------------------------------------
+// indexing
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cidx(const P3 &P, int e, int i) {
+  const int n = P.n[e];
+  if (P.per[e]) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+}
+__device__ __forceinline__ int fidx(const P3 &P, int e, int i) {
+  const int n = P.n[e];
+  if (P.per[e]) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return i < 0 ? 0 : (i > n ? n : i);
+}
+__device__ __forceinline__ long lin(const P3 &P, int i, int j, int k) {
+  return (long)k * P.sz + (long)j * P.sy + i;
+}
+// value of a cell array at x (+ s along e)
+__device__ __forceinline__ double cv(const P3 &P, const double *a, const int x[3], int e = 0,
+                                     int s = 0) {
+  int y[3] = {x[0], x[1], x[2]};
+  y[e] += s;
+  return a[lin(P, cidx(P, 0, y[0]), cidx(P, 1, y[1]), cidx(P, 2, y[2]))];
+}
+// value of a face array of direction f at x (+ s along e)
+__device__ __forceinline__ double fv(const P3 &P, const double *a, int f, const int x[3],
+                                     int e = 0, int s = 0) {
+  int y[3] = {x[0], x[1], x[2]};
+  y[e] += s;
+  const int i = f == 0 ? fidx(P, 0, y[0]) : cidx(P, 0, y[0]);
+  const int j = f == 1 ? fidx(P, 1, y[1]) : cidx(P, 1, y[1]);
+  const int k = f == 2 ? fidx(P, 2, y[2]) : cidx(P, 2, y[2]);
+  return a[lin(P, i, j, k)];
+}
+__device__ __forceinline__ double W(const P3 &P, int e, int i) { return P.d[e][cidx(P, e, i)]; }
+__device__ __forceinline__ bool has_cell(const P3 &P, int e, int i) {
+  return P.per[e] || (i >= 0 && i < P.n[e]);
+}
+__device__ __forceinline__ bool has_face(const P3 &P, int e, int i) {
+  return P.per[e] || (i >= 0 && i <= P.n[e]);
+}
+// side s (0 low, 1 high) of cell index xe along e: 0 interior, 1 wall,
+// 2 inlet, 3 outlet
+__device__ __forceinline__ int side(const P3 &P, int e, int xe, int s) {
+  if (P.per[e]) return 0;
+  if (s == 0 && xe == 0) return (e == 0 && P.io) ? 2 : 1;
+  if (s == 1 && xe == P.n[e] - 1) return (e == 0 && P.io) ? 3 : 1;
+  return 0;
+}
+__device__ __forceinline__ bool solved(const P3 &P, int a, int fa) {
+  return P.per[a] ? fa < P.n[a] : (fa > 0 && fa < P.n[a]);
+}
+// area of the e-faces of cell x
+__device__ __forceinline__ double area(const P3 &P, int e, const int x[3]) {
+  const int b = e == 0 ? 1 : 0, t = e == 2 ? 1 : 2;
+  return W(P, b, x[b]) * W(P, t, x[t]);
+}
+
+// ---------------------------------------------------------------------------
+// elementary functions (Sec. 3.2)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double upw(double f1, double f2, double vel) {
+  return vel > 0.0 ? f1 : f2;
+}
+// van Leer psi(r) = (r + |r|) / (1 + |r|) of r = a/b, written as 2a / (a + b)
+// where a and b have one sign (0 otherwise)
+__device__ __forceinline__ double vanleer(double a, double b) {
+  const bool same = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);
+  return same ? 2.0 * a / (a + b) : 0.0;
+}
+__device__ __forceinline__ double psi_s(double f1, double f2, double f3, double f4, double d1,
+                                        double d2, double d3, double d4, double vel) {
+  if (vel > 0.0) return d2 / (d2 + d3) * vanleer((d2 + d3) * (f2 - f1), (d1 + d2) * (f3 - f2));
+  return -d3 / (d2 + d3) * vanleer((d2 + d3) * (f4 - f3), (d3 + d4) * (f3 - f2));
+}
+__device__ __forceinline__ double psi_c(double f1, double f2, double f3, double f4, double d1,
+                                        double d2, double d3, double vel) {
+  if (vel > 0.0) return 0.5 * vanleer(d2 * (f2 - f1), d1 * (f3 - f2));
+  return -0.5 * vanleer(d2 * (f4 - f3), d3 * (f3 - f2));
+}
+__device__ __forceinline__ double hmean(double dl, double gl, double dr, double gr) {
+  return (dl + dr) * gl * gr / (dl * gr + dr * gl);
+}
+__device__ __forceinline__ double hmean2(double a, double b) { return 2.0 * a * b / (a + b); }
+
+// thread -> point of an index space of extent (X, Y, Z)
+__device__ __forceinline__ bool point(int X, int Y, int Z, int x[3]) {
+  x[0] = blockIdx.x * BX + threadIdx.x;
+  x[1] = blockIdx.y * BY + threadIdx.y;
+  x[2] = blockIdx.z;
+  return x[0] < X && x[1] < Y && x[2] < Z;
+}
+
+// ---------------------------------------------------------------------------
+// cell properties and face densities
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NTB) void k3_cell(P3 P, Fld S, Work Wk) {
+  int x[3];
+  if (!point(P.n[0], P.n[1], P.n[2], x)) return;
+  const long m = lin(P, x[0], x[1], x[2]);
+  const double p = S.q[3][m], T = S.q[4][m];
+  Wk.rho[m] = p / T;
+  Wk.gam[m] = sqrt(T);
+}
+
+template <int A, bool TV>
+__global__ __launch_bounds__(NTB) void k3_rf(P3 P, Fld S, Work Wk) {
+  int f[3];
+  if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
+  const long m = lin(P, f[0], f[1], f[2]);
+  const double vel = S.q[A][m];
+  const int fa = f[A];
+  double r;
+  if (!P.per[A] && fa == 0) {
+    const double rr = cv(P, Wk.rho, f);
+    r = (A == 0 && P.io) ? upw(P.rho_in, rr, vel) : rr;
+  } else if (!P.per[A] && fa == P.n[A]) {
+    r = cv(P, Wk.rho, f, A, -1);
+  } else {
+    const double rl = cv(P, Wk.rho, f, A, -1), rr = cv(P, Wk.rho, f);
+    r = upw(rl, rr, vel);
+    if (TV && has_cell(P, A, fa - 2) && has_cell(P, A, fa + 1))
+      r += psi_s(cv(P, Wk.rho, f, A, -2), rl, rr, cv(P, Wk.rho, f, A, 1), W(P, A, fa - 2),
+                 W(P, A, fa - 1), W(P, A, fa), W(P, A, fa + 1), vel) *
+           (rr - rl);
+  }
+  Wk.rf[A][m] = r;
+}
+
+// mass flux through the e-face of cell x on side s (0 low, 1 high)
+__device__ __forceinline__ double flux(const P3 &P, const Fld &S, const Work &Wk, int e,
+                                       const int x[3], int s) {
+  int y[3] = {x[0], x[1], x[2]};
+  y[e] += s;
+  return fv(P, Wk.rf[e], e, y) * fv(P, S.q[e], e, y) * area(P, e, x);
+}
+
+// ---------------------------------------------------------------------------
+// energy equation
+// ---------------------------------------------------------------------------
+// T of the neighbour of cell x across side s of direction e, as the
+// convective terms take it (inlet T_in, wall and outlet the cell's own)
+__device__ __forceinline__ double T_nb(const P3 &P, const double *T, int e, const int x[3],
+                                       int s, double TP) {
+  const int k = side(P, e, x[e], s);
+  if (k == 2) return P.T_in;
+  if (k) return TP;
+  return cv(P, T, x, e, s ? 1 : -1);
+}
+
+// explicit convective term of T (pl31_1) at level n-1 (S, rho, rf of n-1)
+template <bool TV>
+__device__ double T_explicit(const P3 &P, const Fld &S, const Work &Wk, const int x[3]) {
+  const double *T = S.q[4];
+  const double TP = cv(P, T, x);
+  double sum = 0.0;
+#pragma unroll
+  for (int e = 0; e < 3; e++) {
+    const double TL = T_nb(P, T, e, x, 0, TP), TH = T_nb(P, T, e, x, 1, TP);
+    int yh[3] = {x[0], x[1], x[2]};
+    yh[e] += 1;
+    const double vl = fv(P, S.q[e], e, x), vh = fv(P, S.q[e], e, yh);
+    const double Fl = flux(P, S, Wk, e, x, 0), Fh = flux(P, S, Wk, e, x, 1);
+    double pl = 0.0, ph = 0.0;
+    if (TV) {
+      const int xe = x[e];
+      if (has_cell(P, e, xe - 1) && has_cell(P, e, xe + 2))
+        ph = psi_s(cv(P, T, x, e, -1), TP, TH, cv(P, T, x, e, 2), W(P, e, xe - 1), W(P, e, xe),
+                   W(P, e, xe + 1), W(P, e, xe + 2), vh);
+      if (has_cell(P, e, xe - 2) && has_cell(P, e, xe + 1))
+        pl = psi_s(cv(P, T, x, e, -2), TL, TP, TH, W(P, e, xe - 2), W(P, e, xe - 1), W(P, e, xe),
+                   W(P, e, xe + 1), vl);
+    }
+    sum += -Fh * (upw(TP, TH, vh) + (TH - TP) * ph) + Fl * (upw(TL, TP, vl) + (TP - TL) * pl);
+  }
+  return sum;
+}
+
+// cell-centre value of component e in cell x (+ s along f)
+__device__ __forceinline__ double qcell(const P3 &P, const Fld &S, int e, const int x[3], int f,
+                                        int s) {
+  int y[3] = {x[0], x[1], x[2]};
+  y[f] += s;
+  int z[3] = {y[0], y[1], y[2]};
+  z[e] += 1;
+  return 0.5 * (fv(P, S.q[e], e, y) + fv(P, S.q[e], e, z));
+}
+// component e at the centre of the f-face on side s of cell x: bilinear in
+// the nearest nodes; the wall's velocity (no slip) or the cell's (slip) on a
+// wall, 0 (tangential) at the inlet, the cell's at the outlet
+__device__ double qface(const P3 &P, const Fld &S, int e, int f, const int x[3], int s) {
+  const double qc = qcell(P, S, e, x, f, 0);
+  const int k = side(P, f, x[f], s);
+  if (k == 1) return P.wt[f][s] == STS3_NOSLIP ? P.wv[f][s][e] : qc;
+  if (k == 2) return 0.0;
+  if (k == 3) return qc;
+  const double dx = W(P, f, x[f]), dy = W(P, f, x[f] + (s ? 1 : -1));
+  return (dy * qc + dx * qcell(P, S, e, x, f, s ? 1 : -1)) / (dx + dy);
+}
+
+template <bool IM, bool TV>
+__global__ __launch_bounds__(NTB) void k3_energy(P3 P, Fld S, Work Wk, double *Tout) {
+  int x[3];
+  if (!point(P.n[0], P.n[1], P.n[2], x)) return;
+  const double *T = S.q[4];
+  const double TP = cv(P, T, x), gP = cv(P, Wk.gam, x), rP = cv(P, Wk.rho, x);
+  const double dV = W(P, 0, x[0]) * W(P, 1, x[1]) * W(P, 2, x[2]);
+  double sa = 0.0, sn = 0.0, sF = 0.0;
+#pragma unroll
+  for (int e = 0; e < 3; e++) {
+    const double ar = area(P, e, x), de = W(P, e, x[e]);
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+      const int k = side(P, e, x[e], s);
+      double D, nb;
+      if (k == 1) {
+        if (P.wt[e][s] == STS3_NOSLIP) {
+          nb = P.wT[e][s];
+          D = P.C1 * hmean2(gP, P.sqwT[e][s]) * ar / (0.5 * de);
+        } else {
+          nb = TP;
+          D = 0.0;
+        }
+      } else if (k == 2) {
+        nb = P.T_in;
+        D = P.C1 * hmean2(gP, P.sqT_in) * ar / (0.5 * de);
+      } else if (k == 3) {
+        nb = TP;
+        D = 0.0;
+      } else {
+        const int sg = s ? 1 : -1;
+        const double dn = W(P, e, x[e] + sg), gn = cv(P, Wk.gam, x, e, sg);
+        nb = cv(P, T, x, e, sg);
+        D = P.C1 * (s ? hmean(de, gP, dn, gn) : hmean(dn, gn, de, gP)) * ar / (0.5 * (de + dn));
+      }
+      double a = D;
+      if (IM) {
+        const double Fv = flux(P, S, Wk, e, x, s);
+        double psi = 0.0;
+        if (TV) {
+          int yf[3] = {x[0], x[1], x[2]};
+          yf[e] += s;
+          const double vel = fv(P, S.q[e], e, yf);
+          const int xe = x[e];
+          if (s == 0 && has_cell(P, e, xe - 2) && has_cell(P, e, xe + 1))
+            psi = psi_s(cv(P, T, x, e, -2), cv(P, T, x, e, -1), TP, cv(P, T, x, e, 1),
+                        W(P, e, xe - 2), W(P, e, xe - 1), de, W(P, e, xe + 1), vel);
+          if (s == 1 && has_cell(P, e, xe - 1) && has_cell(P, e, xe + 2))
+            psi = psi_s(cv(P, T, x, e, -1), TP, cv(P, T, x, e, 1), cv(P, T, x, e, 2),
+                        W(P, e, xe - 1), de, W(P, e, xe + 1), W(P, e, xe + 2), vel);
+        }
+        a = (s ? fmax(0.0, -Fv) : fmax(0.0, Fv)) - Fv * psi + D;
+        sF += s ? Fv : -Fv;
+      }
+      sa += a;
+      sn += a * nb;
+    }
+  }
+  const double a0 = P.dt * (sa + sF) + rP * dV;
+  // dissipation (strain rates from the face values) and pressure work
+  double dd[3], div = 0.0;
+#pragma unroll
+  for (int e = 0; e < 3; e++) {
+    dd[e] = (fv(P, S.q[e], e, x, e, 1) - fv(P, S.q[e], e, x)) / W(P, e, x[e]);
+    div += dd[e];
+  }
+  double phi = 2.0 * (dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+#pragma unroll
+  for (int e = 0; e < 3; e++)
+#pragma unroll
+    for (int f = e + 1; f < 3; f++) {
+      const double sef = (qface(P, S, e, f, x, 1) - qface(P, S, e, f, x, 0)) / W(P, f, x[f]) +
+                         (qface(P, S, f, e, x, 1) - qface(P, S, f, e, x, 0)) / W(P, e, x[e]);
+      phi += sef * sef;
+    }
+  phi -= 2.0 / 3.0 * div * div;
+  const double src = P.C2 * gP * phi * dV + P.C3 * cv(P, S.q[3], x) * div * dV;
+  const long m = lin(P, x[0], x[1], x[2]);
+  Tout[m] = (P.dt * (sn + src) + Wk.cT[m]) / a0;
+}
+
+// ---------------------------------------------------------------------------
+// momentum of component A
+// ---------------------------------------------------------------------------
+// Gamma on the edge of the A-momentum volume at face f towards side s of
+// direction b (the edge runs along the third direction): bilinear in the
+// four cells around it; 0 on a wall (it multiplies wall-normal velocities
+// only), sqrt(T_in) at the inlet, the last cells along A at the outlet
+template <int A>
+__device__ double gam_edge(const P3 &P, const Work &Wk, int b, const int f[3], int s) {
+  const int bf = f[b] + s;
+  if (!P.per[b] && (bf == 0 || bf == P.n[b])) {
+    if (b == 0 && P.io) {
+      if (bf == 0) return P.sqT_in;
+      int l[3] = {f[0], f[1], f[2]};
+      l[A] -= 1;
+      l[b] = P.n[b] - 1;
+      int r[3] = {f[0], f[1], f[2]};
+      r[b] = P.n[b] - 1;
+      const double dl = W(P, A, f[A] - 1), dr = W(P, A, f[A]);
+      return (dr * cv(P, Wk.gam, l) + dl * cv(P, Wk.gam, r)) / (dl + dr);
+    }
+    return 0.0;
+  }
+  const double dal = W(P, A, f[A] - 1), dar = W(P, A, f[A]);
+  const double dbl = W(P, b, bf - 1), dbr = W(P, b, bf);
+  double g = 0.0;
+#pragma unroll
+  for (int ia = 0; ia < 2; ia++)
+#pragma unroll
+    for (int ib = 0; ib < 2; ib++) {
+      int y[3] = {f[0], f[1], f[2]};
+      y[A] = f[A] - 1 + ia;
+      y[b] = bf - 1 + ib;
+      const double wa = ia ? dal / (dal + dar) : dar / (dal + dar);
+      const double wb = ib ? dbl / (dbl + dbr) : dbr / (dbl + dbr);
+      g += wa * wb * cv(P, Wk.gam, y);
+    }
+  return g;
+}
+
+// neighbour of component A at face f across side s (-1, +1) of direction b
+template <int A>
+__device__ __forceinline__ double q_nb(const P3 &P, const double *q, int b, const int f[3],
+                                       int s, double qP) {
+  if (b == A) return fv(P, q, A, f, A, s);
+  const int k = side(P, b, f[b], s > 0);
+  if (k == 1) return P.wt[b][s > 0] == STS3_NOSLIP ? P.wv[b][s > 0][A] : qP;
+  if (k == 2) return 0.0;
+  if (k == 3) return qP;
+  return fv(P, q, A, f, b, s);
+}
+
+// explicit convective term of component A (pl15_11) at level n-1
+template <int A, bool TV>
+__device__ double q_explicit(const P3 &P, const Fld &S, const Work &Wk, const int f[3]) {
+  const double *q = S.q[A];
+  const double qP = fv(P, q, A, f);
+  int l[3] = {f[0], f[1], f[2]};
+  l[A] -= 1;
+  double sum = 0.0;
+#pragma unroll
+  for (int b = 0; b < 3; b++) {
+    const double qL = q_nb<A>(P, q, b, f, -1, qP), qH = q_nb<A>(P, q, b, f, 1, qP);
+    if (b == A) {
+      const double Ap = area(P, A, f);
+      const double ubH = 0.5 * (qP + qH), ubL = 0.5 * (qL + qP);
+      const double FbH = cv(P, Wk.rho, f) * ubH * Ap, FbL = cv(P, Wk.rho, l) * ubL * Ap;
+      double pH = 0.0, pL = 0.0;
+      if (TV) {
+        const int fa = f[A];
+        if (has_face(P, A, fa - 1) && has_face(P, A, fa + 2))
+          pH = psi_c(qL, qP, qH, fv(P, q, A, f, A, 2), W(P, A, fa - 1), W(P, A, fa),
+                     W(P, A, fa + 1), ubH);
+        if (has_face(P, A, fa - 2) && has_face(P, A, fa + 1))
+          pL = psi_c(fv(P, q, A, f, A, -2), qL, qP, qH, W(P, A, fa - 2), W(P, A, fa - 1),
+                     W(P, A, fa), ubL);
+      }
+      sum += -FbH * (upw(qP, qH, ubH) + (qH - qP) * pH) + FbL * (upw(qL, qP, ubL) + (qP - qL) * pL);
+    } else {
+      const int fb = f[b];
+      double pl = 0.0, ph = 0.0;
+      const bool okh = TV && has_cell(P, b, fb - 1) && has_cell(P, b, fb + 2);
+      const bool okl = TV && has_cell(P, b, fb - 2) && has_cell(P, b, fb + 1);
+      const double q1h = okh ? fv(P, q, A, f, b, -1) : 0.0, q4h = okh ? fv(P, q, A, f, b, 2) : 0.0;
+      const double q1l = okl ? fv(P, q, A, f, b, -2) : 0.0, q4l = okl ? fv(P, q, A, f, b, 1) : 0.0;
+#pragma unroll
+      for (int sd = 0; sd < 2; sd++) {
+        const int *cx = sd ? f : l;
+        int bh[3] = {cx[0], cx[1], cx[2]};
+        bh[b] += 1;
+        const double vl = fv(P, S.q[b], b, cx), vh = fv(P, S.q[b], b, bh);
+        const double Fl = flux(P, S, Wk, b, cx, 0), Fh = flux(P, S, Wk, b, cx, 1);
+        if (okh)
+          ph = psi_s(q1h, qP, qH, q4h, W(P, b, fb - 1), W(P, b, fb), W(P, b, fb + 1),
+                     W(P, b, fb + 2), vh);
+        if (okl)
+          pl = psi_s(q1l, qL, qP, q4l, W(P, b, fb - 2), W(P, b, fb - 1), W(P, b, fb),
+                     W(P, b, fb + 1), vl);
+        sum += 0.5 * (-Fh * (upw(qP, qH, vh) + (qH - qP) * ph) +
+                      Fl * (upw(qL, qP, vl) + (qP - qL) * pl));
+      }
+    }
+  }
+  return sum;
+}
+
+template <int A, bool IM, bool TV>
+__global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
+  int f[3];
+  if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
+  const long m = lin(P, f[0], f[1], f[2]);
+  const double *q = S.q[A];
+  const double qP = q[m];
+  if (!solved(P, A, f[A])) {
+    Wk.qh[A][m] = qP;
+    Wk.dq[A][m] = 0.0;
+    return;
+  }
+  int l[3] = {f[0], f[1], f[2]};
+  l[A] -= 1;
+  const double dal = W(P, A, f[A] - 1), dar = W(P, A, f[A]);
+  const double rl = cv(P, Wk.rho, l), rr = cv(P, Wk.rho, f);
+  const double gl = cv(P, Wk.gam, l), gr = cv(P, Wk.gam, f);
+  const double Ap = area(P, A, f), len = 0.5 * (dal + dar);
+  const double M = (rr * dar + rl * dal) * Ap / 2.0;
+  const double gnode = (dar * gl + dal * gr) / (dal + dar);
+  double sa = 0.0, sn = 0.0, conv = 0.0, X = 0.0;
+#pragma unroll
+  for (int b = 0; b < 3; b++) {
+    const double qL = q_nb<A>(P, q, b, f, -1, qP), qH = q_nb<A>(P, q, b, f, 1, qP);
+    double aL, aH;
+    if (b == A) {
+      const double DL = P.B * gl * Ap / dal, DH = P.B * gr * Ap / dar;
+      double cl = 0.0, ch = 0.0;
+      if (IM) {
+        const double ubL = 0.5 * (qL + qP), ubH = 0.5 * (qP + qH);
+        const double FbL = rl * ubL * Ap, FbH = rr * ubH * Ap;
+        double pL = 0.0, pH = 0.0;
+        if (TV) {
+          const int fa = f[A];
+          if (has_face(P, A, fa - 2) && has_face(P, A, fa + 1))
+            pL = psi_c(fv(P, q, A, f, A, -2), qL, qP, qH, W(P, A, fa - 2), dal, dar, ubL);
+          if (has_face(P, A, fa - 1) && has_face(P, A, fa + 2))
+            pH = psi_c(qL, qP, qH, fv(P, q, A, f, A, 2), dal, dar, W(P, A, fa + 1), ubH);
+        }
+        cl = fmax(0.0, FbL) - FbL * pL;
+        ch = fmax(0.0, -FbH) - FbH * pH;
+        conv += FbH - FbL;
+      }
+      aL = cl + 4.0 / 3.0 * DL;
+      aH = ch + 4.0 / 3.0 * DH;
+    } else {
+      const int t = 3 - A - b;
+      const double d3 = W(P, t, f[t]), db = W(P, b, f[b]);
+      double D[2];
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        const int k = side(P, b, f[b], s);
+        if (k == 1)
+          D[s] = P.wt[b][s] == STS3_NOSLIP
+                     ? P.B * 0.5 * (gnode + P.sqwT[b][s]) * len * d3 / (0.5 * db)
+                     : 0.0;
+        else if (k == 2)
+          D[s] = P.B * 0.5 * (gnode + gam_edge<A>(P, Wk, b, f, 0)) * len * d3 / (0.5 * db);
+        else if (k == 3)
+          D[s] = 0.0;
+        else
+          D[s] = P.B * gam_edge<A>(P, Wk, b, f, s) * (dal + dar) * 0.5 * d3 /
+                 (0.5 * (db + W(P, b, f[b] + (s ? 1 : -1))));
+      }
+      double cl = 0.0, ch = 0.0;
+      if (IM) {
+        const int fb = f[b];
+        const bool okl = TV && has_cell(P, b, fb - 2) && has_cell(P, b, fb + 1);
+        const bool okh = TV && has_cell(P, b, fb - 1) && has_cell(P, b, fb + 2);
+#pragma unroll
+        for (int sd = 0; sd < 2; sd++) {
+          const int *cx = sd ? f : l;
+          int bh[3] = {cx[0], cx[1], cx[2]};
+          bh[b] += 1;
+          const double vl = fv(P, S.q[b], b, cx), vh = fv(P, S.q[b], b, bh);
+          const double Fl = flux(P, S, Wk, b, cx, 0), Fh = flux(P, S, Wk, b, cx, 1);
+          double pl = 0.0, ph = 0.0;
+          if (okl)
+            pl = psi_s(fv(P, q, A, f, b, -2), qL, qP, fv(P, q, A, f, b, 1), W(P, b, fb - 2),
+                       W(P, b, fb - 1), db, W(P, b, fb + 1), vl);
+          if (okh)
+            ph = psi_s(fv(P, q, A, f, b, -1), qP, qH, fv(P, q, A, f, b, 2), W(P, b, fb - 1), db,
+                       W(P, b, fb + 1), W(P, b, fb + 2), vh);
+          cl += 0.5 * (fmax(0.0, Fl) - Fl * pl);
+          ch += 0.5 * (fmax(0.0, -Fh) - Fh * ph);
+          conv += 0.5 * (Fh - Fl);
+        }
+      }
+      aL = cl + D[0];
+      aH = ch + D[1];
+      // cross-diffusion for the tangential direction b
+      int rh[3] = {f[0], f[1], f[2]}, lh[3] = {l[0], l[1], l[2]};
+      rh[b] += 1;
+      lh[b] += 1;
+      const double *qb = S.q[b];
+      const double b_rl = fv(P, qb, b, f), b_rh = fv(P, qb, b, rh);
+      const double b_ll = fv(P, qb, b, l), b_lh = fv(P, qb, b, lh);
+      X += (gam_edge<A>(P, Wk, b, f, 1) * (b_rh - b_lh) - gam_edge<A>(P, Wk, b, f, 0) * (b_rl - b_ll)) *
+               d3 -
+           2.0 / 3.0 * (gr * (b_rh - b_rl) - gl * (b_lh - b_ll)) * d3;
+    }
+    sa += aL + aH;
+    sn += aL * qL + aH * qH;
+  }
+  const double a0 = sa + conv + M / P.dt;
+  const double b = Wk.cq[A][m] + P.B * X;
+  Wk.qh[A][m] = (sn + b) / a0;
+  Wk.dq[A][m] = P.A * Ap / a0;
+}
+
+// ---------------------------------------------------------------------------
+// pressure and velocities
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NTB) void k3_pressure(P3 P, Fld S, Work Wk, const double *Tn,
+                                                   double *pout) {
+  int x[3];
+  if (!point(P.n[0], P.n[1], P.n[2], x)) return;
+  const long m = lin(P, x[0], x[1], x[2]);
+  const double pP = S.q[3][m];
+  const double dV = W(P, 0, x[0]) * W(P, 1, x[1]) * W(P, 2, x[2]);
+  double sa = 0.0, sap = 0.0, sb = 0.0;
+#pragma unroll
+  for (int e = 0; e < 3; e++) {
+    int xh[3] = {x[0], x[1], x[2]};
+    xh[e] += 1;
+    const double ar = area(P, e, x);
+    const double rL = fv(P, Wk.rf[e], e, x), rH = fv(P, Wk.rf[e], e, xh);
+    const double aL = rL * fv(P, Wk.dq[e], e, x) * ar, aH = rH * fv(P, Wk.dq[e], e, xh) * ar;
+    const double bL = rL * fv(P, Wk.qh[e], e, x) * ar, bH = rH * fv(P, Wk.qh[e], e, xh) * ar;
+    const double pL = side(P, e, x[e], 0) ? pP : cv(P, S.q[3], x, e, -1);
+    const double pH = side(P, e, x[e], 1) ? pP : cv(P, S.q[3], x, e, 1);
+    sa += aL + aH;
+    sap += aL * pL + aH * pH;
+    sb += bH - bL;
+  }
+  const double a0 = dV / Tn[m] + sa * P.dt;
+  pout[m] = (sap * P.dt + (Wk.cp[m] - sb * P.dt)) / a0;
+}
+
+template <int A>
+__device__ __forceinline__ double q_update(const P3 &P, const Work &Wk, const double *pn,
+                                           const int f[3]) {
+  return fv(P, Wk.qh[A], A, f) - fv(P, Wk.dq[A], A, f) * (cv(P, pn, f) - cv(P, pn, f, A, -1));
+}
+
+template <int A>
+__global__ __launch_bounds__(NTB) void k3_velocity(P3 P, Fld S, Work Wk, const double *pn,
+                                                   double *qout) {
+  int f[3];
+  if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
+  const long m = lin(P, f[0], f[1], f[2]);
+  const int fa = f[A];
+  double qn;
+  if (solved(P, A, fa)) {
+    qn = q_update<A>(P, Wk, pn, f);
+  } else if (P.per[A]) {  // the last face repeats face 0
+    int g[3] = {f[0], f[1], f[2]};
+    g[A] = 0;
+    qn = q_update<A>(P, Wk, pn, g);
+  } else if (A == 0 && P.io && fa == P.n[0]) {  // outlet: zero gradient
+    int g[3] = {f[0], f[1], f[2]};
+    g[A] = fa - 1;
+    qn = q_update<A>(P, Wk, pn, g);
+  } else {
+    qn = S.q[A][m];  // inlet u_in, wall faces 0
+  }
+  qout[m] = qn;
+}
+
+// ---------------------------------------------------------------------------
+// per-step constants (prologue), from the state S as level n-1, with rho and
+// the face densities of S in Wk
+// ---------------------------------------------------------------------------
+template <bool EX, bool TV>
+__global__ __launch_bounds__(NTB) void k3_const_cell(P3 P, Fld S, Work Wk) {
+  int x[3];
+  if (!point(P.n[0], P.n[1], P.n[2], x)) return;
+  const long m = lin(P, x[0], x[1], x[2]);
+  const double dV = W(P, 0, x[0]) * W(P, 1, x[1]) * W(P, 2, x[2]);
+  const double r = Wk.rho[m];
+  Wk.cp[m] = r * dV;
+  Wk.cT[m] = r * S.q[4][m] * dV + (EX ? P.dt * T_explicit<TV>(P, S, Wk, x) : 0.0);
+}
+
+template <int A, bool EX, bool TV>
+__global__ __launch_bounds__(NTB) void k3_const_face(P3 P, Fld S, Work Wk) {
+  int f[3];
+  if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
+  const long m = lin(P, f[0], f[1], f[2]);
+  if (!solved(P, A, f[A])) {
+    Wk.cq[A][m] = 0.0;
+    return;
+  }
+  int l[3] = {f[0], f[1], f[2]};
+  l[A] -= 1;
+  const double dal = W(P, A, f[A] - 1), dar = W(P, A, f[A]);
+  const double Mm = (cv(P, Wk.rho, f) * dar + cv(P, Wk.rho, l) * dal) * area(P, A, f) / 2.0;
+  Wk.cq[A][m] = Mm / P.dt * S.q[A][m] + P.g[A] * Mm + (EX ? q_explicit<A, TV>(P, S, Wk, f) : 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// residuals of the last pass: increments of the unknowns, continuity
+// residual; block partials in a fixed order, then one block folds them
+// ---------------------------------------------------------------------------
+__device__ void block_reduce(double v[NR], double *out) {
+  __shared__ double red[NTB / 64][NR];
+  const int t = threadIdx.y * BX + threadIdx.x, lane = t & 63, wv = t >> 6;
+#pragma unroll
+  for (int q = 0; q < NR; q++) {
+    double a = v[q];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double b = __shfl_down(a, o, 64);
+      a = (q == 6 || q == 7) ? a + b : fmax(a, b);
+    }
+    if (lane == 0) red[wv][q] = a;
+  }
+  __syncthreads();
+  if (t < NR) {
+    double a = red[0][t];
+    for (int w = 1; w < NTB / 64; w++) a = (t == 6 || t == 7) ? a + red[w][t] : fmax(a, red[w][t]);
+    out[t] = a;
+  }
+}
+
+// partial slot of a block (blocks of the cell kernel first, then those of
+// the three face kernels)
+__device__ __forceinline__ long block_slot(int base) {
+  return base + ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+}
+
+__global__ __launch_bounds__(NTB) void k3_resid_cell(P3 P, Fld O, Fld N, Work Wk,
+                                                     double *part) {
+  int x[3];
+  double v[NR] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (point(P.n[0], P.n[1], P.n[2], x)) {
+    const long m = lin(P, x[0], x[1], x[2]);
+    const double dV = W(P, 0, x[0]) * W(P, 1, x[1]) * W(P, 2, x[2]);
+    const double pn = N.q[3][m], Tn = N.q[4][m];
+    v[3] = fabs(pn - O.q[3][m]);
+    v[4] = fabs(Tn - O.q[4][m]);
+    double R = (pn / Tn * dV - Wk.cp[m]) / P.dt;
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+      int xh[3] = {x[0], x[1], x[2]};
+      xh[e] += 1;
+      const double ar = area(P, e, x);
+      R += fv(P, Wk.rf[e], e, xh) * fv(P, N.q[e], e, xh) * ar -
+           fv(P, Wk.rf[e], e, x) * fv(P, N.q[e], e, x) * ar;
+    }
+    v[5] = fabs(R);
+    v[6] = R;
+    v[7] = (double)(!isfinite(pn)) + (double)(!isfinite(Tn));
+  }
+  block_reduce(v, part + block_slot(0) * NR);
+}
+
+template <int A>
+__global__ __launch_bounds__(NTB) void k3_resid_face(P3 P, Fld O, Fld N, double *part, int base) {
+  int f[3];
+  double v[NR] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) {
+    const long m = lin(P, f[0], f[1], f[2]);
+    const double qn = N.q[A][m];
+    if (solved(P, A, f[A])) v[A] = fabs(qn - O.q[A][m]);
+    v[7] = (double)(!isfinite(qn));
+  }
+  block_reduce(v, part + block_slot(base) * NR);
+}
+
+__global__ __launch_bounds__(NTB) void k3_resid_final(const double *part, int nblocks,
+                                                      double *out) {
+  double v[NR] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int t = threadIdx.y * BX + threadIdx.x;
+  for (int b = t; b < nblocks; b += NTB)
+#pragma unroll
+    for (int q = 0; q < NR; q++)
+      v[q] = (q == 6 || q == 7) ? v[q] + part[(long)b * NR + q] : fmax(v[q], part[(long)b * NR + q]);
+  block_reduce(v, out);
+}
+
+}  // namespace
+}  // namespace sts3
+
+// ===========================================================================
+// host side
+// ===========================================================================
+using namespace sts3;
+
+struct sts3_ctx {
+  P3 P;
+  int n[3];
+  long pitch, sy, sz;
+  size_t field_bytes;
+  hipStream_t stream;
+  bool own_stream;
+  int device;
+  std::vector<void *> allocs;
+  Fld st[2];
+  int cur;
+  Work Wk;
+  double *d_d[3];
+  double *part, *dres;
+  double *hres;  // pinned
+  int nblk_cell, nblk_face[3], nblocks;
+  bool stepped;
+  std::vector<double> wid[3];
+  int bc[3];
+  double u_in;
+};
+
+namespace {
+sts_status fail3(sts_status s, const char *msg) { return sts::report_error(s, msg); }
+
+#define HIP3(call)                                                         \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess) {                                                \
+      std::string m_ = std::string(#call) + " failed: " + hipGetErrorString(e_); \
+      return fail3(STS_EDEVICE, m_.c_str());                               \
+    }                                                                      \
+  } while (0)
+
+dim3 grid_of(const sts3_ctx *c, int X, int Y, int Z) {
+  (void)c;
+  return dim3((X + BX - 1) / BX, (Y + BY - 1) / BY, Z);
+}
+dim3 grid_face(const sts3_ctx *c, int a) {
+  return grid_of(c, c->n[0] + (a == 0), c->n[1] + (a == 1), c->n[2] + (a == 2));
+}
+
+void launch_rf(sts3_ctx *c, const Fld &S, bool tv) {
+  const dim3 b(BX, BY);
+  if (tv) {
+    hipLaunchKernelGGL((k3_rf<0, true>), grid_face(c, 0), b, 0, c->stream, c->P, S, c->Wk);
+    hipLaunchKernelGGL((k3_rf<1, true>), grid_face(c, 1), b, 0, c->stream, c->P, S, c->Wk);
+    hipLaunchKernelGGL((k3_rf<2, true>), grid_face(c, 2), b, 0, c->stream, c->P, S, c->Wk);
+  } else {
+    hipLaunchKernelGGL((k3_rf<0, false>), grid_face(c, 0), b, 0, c->stream, c->P, S, c->Wk);
+    hipLaunchKernelGGL((k3_rf<1, false>), grid_face(c, 1), b, 0, c->stream, c->P, S, c->Wk);
+    hipLaunchKernelGGL((k3_rf<2, false>), grid_face(c, 2), b, 0, c->stream, c->P, S, c->Wk);
+  }
+}
+
+template <bool EX, bool TV>
+void launch_prologue3(sts3_ctx *c, const Fld &S) {
+  const dim3 b(BX, BY), gc = grid_of(c, c->n[0], c->n[1], c->n[2]);
+  hipLaunchKernelGGL(k3_cell, gc, b, 0, c->stream, c->P, S, c->Wk);
+  if (EX) launch_rf(c, S, TV);
+  hipLaunchKernelGGL((k3_const_cell<EX, TV>), gc, b, 0, c->stream, c->P, S, c->Wk);
+  hipLaunchKernelGGL((k3_const_face<0, EX, TV>), grid_face(c, 0), b, 0, c->stream, c->P, S, c->Wk);
+  hipLaunchKernelGGL((k3_const_face<1, EX, TV>), grid_face(c, 1), b, 0, c->stream, c->P, S, c->Wk);
+  hipLaunchKernelGGL((k3_const_face<2, EX, TV>), grid_face(c, 2), b, 0, c->stream, c->P, S, c->Wk);
+}
+
+template <bool IM, bool TV>
+void launch_pass3d(sts3_ctx *c, const Fld &O, const Fld &N, bool last) {
+  const dim3 b(BX, BY), gc = grid_of(c, c->n[0], c->n[1], c->n[2]);
+  hipLaunchKernelGGL(k3_cell, gc, b, 0, c->stream, c->P, O, c->Wk);
+  launch_rf(c, O, TV);
+  hipLaunchKernelGGL((k3_energy<IM, TV>), gc, b, 0, c->stream, c->P, O, c->Wk, N.q[4]);
+  hipLaunchKernelGGL((k3_mom<0, IM, TV>), grid_face(c, 0), b, 0, c->stream, c->P, O, c->Wk);
+  hipLaunchKernelGGL((k3_mom<1, IM, TV>), grid_face(c, 1), b, 0, c->stream, c->P, O, c->Wk);
+  hipLaunchKernelGGL((k3_mom<2, IM, TV>), grid_face(c, 2), b, 0, c->stream, c->P, O, c->Wk);
+  hipLaunchKernelGGL(k3_pressure, gc, b, 0, c->stream, c->P, O, c->Wk, N.q[4], N.q[3]);
+  hipLaunchKernelGGL((k3_velocity<0>), grid_face(c, 0), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[0]);
+  hipLaunchKernelGGL((k3_velocity<1>), grid_face(c, 1), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[1]);
+  hipLaunchKernelGGL((k3_velocity<2>), grid_face(c, 2), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[2]);
+  if (last) {
+    hipLaunchKernelGGL(k3_resid_cell, gc, b, 0, c->stream, c->P, O, N, c->Wk, c->part);
+    int base = c->nblk_cell;
+    hipLaunchKernelGGL((k3_resid_face<0>), grid_face(c, 0), b, 0, c->stream, c->P, O, N, c->part, base);
+    base += c->nblk_face[0];
+    hipLaunchKernelGGL((k3_resid_face<1>), grid_face(c, 1), b, 0, c->stream, c->P, O, N, c->part, base);
+    base += c->nblk_face[1];
+    hipLaunchKernelGGL((k3_resid_face<2>), grid_face(c, 2), b, 0, c->stream, c->P, O, N, c->part, base);
+    hipLaunchKernelGGL(k3_resid_final, dim3(1), b, 0, c->stream, c->part, c->nblocks, c->dres);
+  }
+}
+
+int nblk(const dim3 &g) { return (int)(g.x * g.y * g.z); }
+
+// host-side boundary values of a dense state (the oracle's rules)
+void impose(const sts3_ctx *c, std::vector<double> *q) {
+  const int *n = c->n;
+  for (int a = 0; a < 3; a++) {
+    const int D0 = n[0] + (a == 0), D1 = n[1] + (a == 1), D2 = n[2] + (a == 2);
+    for (int k = 0; k < D2; k++)
+      for (int j = 0; j < D1; j++)
+        for (int i = 0; i < D0; i++) {
+          const int f[3] = {i, j, k};
+          const size_t m = ((size_t)k * D1 + j) * D0 + i;
+          if (c->bc[a] == STS3_PERIODIC) {
+            if (f[a] == n[a]) {
+              int g[3] = {i, j, k};
+              g[a] = 0;
+              q[a][m] = q[a][((size_t)g[2] * D1 + g[1]) * D0 + g[0]];
+            }
+          } else if (a == 0 && c->bc[0] == STS3_INLET_OUTLET) {
+            if (i == 0) q[a][m] = c->u_in;
+            if (i == n[0]) q[a][m] = q[a][m - 1];
+          } else if (f[a] == 0 || f[a] == n[a]) {
+            q[a][m] = 0.0;
+          }
+        }
+  }
+}
+
+size_t field_elems(const int n[3], long *pitch) {
+  const long p = (long)((n[0] + 1 + 31) / 32) * 32;
+  if (pitch) *pitch = p;
+  return (size_t)p * (n[1] + 1) * (n[2] + 1);
+}
+constexpr int NFIELDS = 26;  // 2 states x 5, rho, gam, rf x3, qh x3, dq x3, cq x3, cT, cp
+}  // namespace
+
+extern "C" sts_status sts3_device_bytes(const int n[3], size_t *bytes) {
+  if (!n || !bytes) return fail3(STS_EINVAL, "NULL argument");
+  for (int e = 0; e < 3; e++)
+    if (n[e] < 4) return fail3(STS_EINVAL, "every direction needs >= 4 cells");
+  const size_t fe = field_elems(n, nullptr);
+  *bytes = NFIELDS * fe * sizeof(double);
+  return STS_OK;
+}
+
+extern "C" void sts3_destroy(sts3_ctx *c) {
+  if (!c) return;
+  if (c->device >= 0) (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->allocs) (void)hipFree(p);
+  if (c->hres) (void)hipHostFree(c->hres);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ctx **out) {
+  if (!s || !out) return fail3(STS_EINVAL, "NULL argument");
+  for (int e = 0; e < 3; e++) {
+    if (s->n[e] < 4) return fail3(STS_EINVAL, "every direction needs >= 4 cells");
+    if (!s->d[e]) return fail3(STS_EINVAL, "cell widths missing");
+    for (int i = 0; i < s->n[e]; i++)
+      if (!(s->d[e][i] > 0) || !isfinite(s->d[e][i]))
+        return fail3(STS_EINVAL, "cell widths must be positive and finite");
+    const int bc = s->bc[e];
+    if (e == 0 && bc != STS3_PERIODIC && bc != STS3_INLET_OUTLET)
+      return fail3(STS_EINVAL, "x is inlet/outlet or periodic");
+    if (e > 0 && bc != STS3_PERIODIC && bc != STS3_WALLS)
+      return fail3(STS_EINVAL, "y and z are walls or periodic");
+    for (int w = 0; w < 2; w++) {
+      if (s->wall_type[e][w] != STS3_NOSLIP && s->wall_type[e][w] != STS3_SLIP)
+        return fail3(STS_EINVAL, "unknown wall type");
+      if (bc == STS3_WALLS && s->wall_type[e][w] == STS3_NOSLIP && !(s->wall_T[e][w] > 0))
+        return fail3(STS_EINVAL, "wall temperatures must be > 0");
+    }
+  }
+  if (!(s->Ma > 0) || !(s->Re > 0) || !(s->Pr > 0) || !(s->gamma > 1))
+    return fail3(STS_EINVAL, "Ma, Re, Pr must be > 0 and gamma > 1");
+  if (!(s->T_in > 0) || !(s->p_in > 0) || !isfinite(s->u_in))
+    return fail3(STS_EINVAL, "T_in, p_in must be > 0 and u_in finite");
+  size_t bytes = 0;
+  sts_status st = sts3_device_bytes(s->n, &bytes);
+  if (st != STS_OK) return st;
+
+  sts3_ctx *c = new sts3_ctx();
+  c->device = -1;
+  c->hres = nullptr;
+  c->stream = nullptr;
+  c->own_stream = false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    delete c;
+    return fail3(STS_EDEVICE, "no HIP device");
+  }
+  c->device = dev;
+  for (int e = 0; e < 3; e++) {
+    c->n[e] = s->n[e];
+    c->bc[e] = s->bc[e];
+    c->wid[e].assign(s->d[e], s->d[e] + s->n[e]);
+  }
+  c->u_in = s->u_in;
+  const size_t fe = field_elems(c->n, &c->pitch);
+  c->sy = c->pitch;
+  c->sz = c->pitch * (c->n[1] + 1);
+  c->field_bytes = fe * sizeof(double);
+  auto alloc = [&](size_t b, void **p) -> bool {
+    if (hipMalloc(p, b) != hipSuccess) return false;
+    c->allocs.push_back(*p);
+    return true;
+  };
+  std::vector<double *> fields(NFIELDS);
+  for (int k = 0; k < NFIELDS; k++)
+    if (!alloc(c->field_bytes, (void **)&fields[k])) {
+      sts3_destroy(c);
+      return fail3(STS_ENOMEM, "device allocation failed");
+    }
+  int k = 0;
+  for (int b = 0; b < 2; b++)
+    for (int f = 0; f < 5; f++) c->st[b].q[f] = fields[k++];
+  c->Wk.rho = fields[k++];
+  c->Wk.gam = fields[k++];
+  for (int a = 0; a < 3; a++) c->Wk.rf[a] = fields[k++];
+  for (int a = 0; a < 3; a++) c->Wk.qh[a] = fields[k++];
+  for (int a = 0; a < 3; a++) c->Wk.dq[a] = fields[k++];
+  for (int a = 0; a < 3; a++) c->Wk.cq[a] = fields[k++];
+  c->Wk.cT = fields[k++];
+  c->Wk.cp = fields[k++];
+  for (int e = 0; e < 3; e++)
+    if (!alloc(sizeof(double) * c->n[e], (void **)&c->d_d[e])) {
+      sts3_destroy(c);
+      return fail3(STS_ENOMEM, "device allocation failed");
+    }
+  c->nblk_cell = nblk(grid_of(c, c->n[0], c->n[1], c->n[2]));
+  c->nblocks = c->nblk_cell;
+  for (int a = 0; a < 3; a++) {
+    c->nblk_face[a] = nblk(grid_face(c, a));
+    c->nblocks += c->nblk_face[a];
+  }
+  if (!alloc(sizeof(double) * NR * (size_t)c->nblocks, (void **)&c->part) ||
+      !alloc(256, (void **)&c->dres) || hipHostMalloc((void **)&c->hres, 256) != hipSuccess) {
+    c->hres = nullptr;
+    sts3_destroy(c);
+    return fail3(STS_ENOMEM, "allocation failed");
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      c->stream = nullptr;
+      sts3_destroy(c);
+      return fail3(STS_EDEVICE, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  // parameters (eqs pl2-pl6 coefficients as in the 2-D library)
+  P3 &P = c->P;
+  memset(&P, 0, sizeof P);
+  for (int e = 0; e < 3; e++) {
+    P.n[e] = c->n[e];
+    P.per[e] = s->bc[e] == STS3_PERIODIC;
+    P.g[e] = s->g[e];
+    P.d[e] = c->d_d[e];
+    for (int w = 0; w < 2; w++) {
+      P.wt[e][w] = s->wall_type[e][w];
+      P.wT[e][w] = s->wall_T[e][w];
+      P.sqwT[e][w] = s->wall_T[e][w] > 0 ? sqrt(s->wall_T[e][w]) : 0.0;
+      for (int v = 0; v < 3; v++) P.wv[e][w][v] = s->wall_vel[e][w][v];
+    }
+  }
+  P.io = s->bc[0] == STS3_INLET_OUTLET;
+  const double g = s->gamma;
+  P.A = 1.0 / (g * s->Ma * s->Ma);
+  P.B = 1.0 / s->Re;
+  P.C1 = g / (s->Re * s->Pr);
+  P.C2 = g * (g - 1.0) * s->Ma * s->Ma / s->Re;
+  P.C3 = -(g - 1.0);
+  P.u_in = s->u_in;
+  P.T_in = s->T_in;
+  P.p_in = s->p_in;
+  P.rho_in = s->p_in / s->T_in;
+  P.sqT_in = sqrt(s->T_in);
+  P.sy = c->sy;
+  P.sz = c->sz;
+  for (int e = 0; e < 3; e++)
+    HIP3(hipMemcpyAsync(c->d_d[e], c->wid[e].data(), sizeof(double) * c->n[e],
+                        hipMemcpyHostToDevice, c->stream));
+  // clear every array (frame entries stay finite), then the initial state
+  for (int k2 = 0; k2 < NFIELDS; k2++) HIP3(hipMemsetAsync(fields[k2], 0, c->field_bytes, c->stream));
+  c->cur = 0;
+  c->stepped = false;
+  std::vector<double> q[5];
+  for (int f = 0; f < 5; f++) {
+    const size_t len = (size_t)(c->n[0] + (f == 0)) * (c->n[1] + (f == 1)) * (c->n[2] + (f == 2));
+    q[f].assign(len, f == 0 ? (P.io ? s->u_in : 0.0) : (f == 3 ? s->p_in : (f == 4 ? s->T_in : 0.0)));
+  }
+  const double *qp[5] = {q[0].data(), q[1].data(), q[2].data(), q[3].data(), q[4].data()};
+  st = sts3_set_fields(c, qp);
+  if (st != STS_OK) {
+    sts3_destroy(c);
+    return st;
+  }
+  *out = c;
+  return STS_OK;
+}
+
+extern "C" sts_status sts3_set_fields(sts3_ctx *c, const double *const q[5]) {
+  if (!c || !q) return fail3(STS_EINVAL, "NULL argument");
+  HIP3(hipSetDevice(c->device));
+  HIP3(hipStreamSynchronize(c->stream));
+  std::vector<double> dense[5];
+  const int *n = c->n;
+  for (int f = 0; f < 5; f++) {
+    const size_t len = (size_t)(n[0] + (f == 0)) * (n[1] + (f == 1)) * (n[2] + (f == 2));
+    dense[f].resize(len);
+    if (q[f]) {
+      memcpy(dense[f].data(), q[f], len * sizeof(double));
+    } else {
+      // keep the current field
+      const int D0 = n[0] + (f == 0), D1 = n[1] + (f == 1), D2 = n[2] + (f == 2);
+      for (int k = 0; k < D2; k++)
+        HIP3(hipMemcpy2D(dense[f].data() + (size_t)k * D1 * D0, D0 * 8,
+                         c->st[c->cur].q[f] + (size_t)k * c->sz, c->pitch * 8, D0 * 8, D1,
+                         hipMemcpyDeviceToHost));
+    }
+  }
+  impose(c, dense);
+  for (int f = 0; f < 5; f++) {
+    const int D0 = n[0] + (f == 0), D1 = n[1] + (f == 1), D2 = n[2] + (f == 2);
+    for (int k = 0; k < D2; k++)
+      HIP3(hipMemcpy2D(c->st[c->cur].q[f] + (size_t)k * c->sz, c->pitch * 8,
+                       dense[f].data() + (size_t)k * D1 * D0, D0 * 8, D0 * 8, D1,
+                       hipMemcpyHostToDevice));
+  }
+  // the other state buffer holds the same boundary entries (faces that the
+  // passes do not write keep them)
+  for (int f = 0; f < 5; f++)
+    HIP3(hipMemcpy(c->st[c->cur ^ 1].q[f], c->st[c->cur].q[f], c->field_bytes,
+                   hipMemcpyDeviceToDevice));
+  c->stepped = false;
+  return STS_OK;
+}
+
+extern "C" sts_status sts3_fields(sts3_ctx *c, double *const q[5]) {
+  if (!c || !q) return fail3(STS_EINVAL, "NULL argument");
+  HIP3(hipSetDevice(c->device));
+  HIP3(hipStreamSynchronize(c->stream));
+  const int *n = c->n;
+  for (int f = 0; f < 5; f++) {
+    if (!q[f]) continue;
+    const int D0 = n[0] + (f == 0), D1 = n[1] + (f == 1), D2 = n[2] + (f == 2);
+    for (int k = 0; k < D2; k++)
+      HIP3(hipMemcpy2D(q[f] + (size_t)k * D1 * D0, D0 * 8, c->st[c->cur].q[f] + (size_t)k * c->sz,
+                       c->pitch * 8, D0 * 8, D1, hipMemcpyDeviceToHost));
+  }
+  return STS_OK;
+}
+
+extern "C" sts_status sts3_step(sts3_ctx *c, double dt, int n_inner, int scheme) {
+  if (!c) return fail3(STS_EINVAL, "ctx is NULL");
+  if (!(dt > 0) || !isfinite(dt)) return fail3(STS_EINVAL, "dt must be > 0");
+  if (n_inner < 1) return fail3(STS_EINVAL, "n_inner must be >= 1");
+  if (scheme & ~(STS_IMPLICIT | STS_TVD)) return fail3(STS_EINVAL, "unknown scheme bits");
+  HIP3(hipSetDevice(c->device));
+  c->P.dt = dt;
+  const bool im = scheme & STS_IMPLICIT, tv = scheme & STS_TVD;
+  const Fld S0 = c->st[c->cur];
+  if (im) launch_prologue3<false, false>(c, S0);
+  else if (tv) launch_prologue3<true, true>(c, S0);
+  else launch_prologue3<true, false>(c, S0);
+  for (int k = 0; k < n_inner; k++) {
+    const Fld O = c->st[c->cur], N = c->st[c->cur ^ 1];
+    const bool last = k == n_inner - 1;
+    if (im && tv) launch_pass3d<true, true>(c, O, N, last);
+    else if (im) launch_pass3d<true, false>(c, O, N, last);
+    else if (tv) launch_pass3d<false, true>(c, O, N, last);
+    else launch_pass3d<false, false>(c, O, N, last);
+    c->cur ^= 1;
+  }
+  HIP3(hipGetLastError());
+  HIP3(hipMemcpyAsync(c->hres, c->dres, NR * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  c->stepped = true;
+  return STS_OK;
+}
+
+extern "C" sts_status sts3_residuals(sts3_ctx *c, double out[7]) {
+  if (!c || !out) return fail3(STS_EINVAL, "NULL argument");
+  HIP3(hipSetDevice(c->device));
+  HIP3(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 7; k++) out[k] = c->stepped ? c->hres[k] : 0.0;
+  if (c->stepped && c->hres[7] != 0.0) return fail3(STS_ENONFINITE, "the last step produced non-finite values");
+  return STS_OK;
+}

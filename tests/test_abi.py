@@ -81,3 +81,54 @@ def test_workspace_bytes_scale_with_the_grid():
     # 14 FP64 arrays per cell (two states, four step constants, two face
     # mass fluxes) plus framing: about 112 B per finite volume
     assert 112 * 256 * 256 < sizes[2] < 1.3 * 112 * 256 * 256 + 4e5
+
+
+def declared_functions3():
+    text = open(os.path.join(ROOT, "include", "sts3.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sts3_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_3d_header_matches_binding_and_library():
+    from paper_1802_04243_amd import sts3
+    assert declared_functions3() == sorted(sts3.EXPORTS3)
+    L = C.CDLL(sts.LIB_PATH)
+    for name in declared_functions3():
+        assert hasattr(L, name), name
+
+
+def _box3(**kw):
+    from paper_1802_04243_amd import workloads3 as W3
+    n = kw.pop("n", (8, 6, 5))
+    d = kw.pop("d", tuple(np.full(k, 0.1) for k in n))
+    return W3.Box3(d=d, **kw)
+
+
+@pytest.mark.parametrize("kw", [dict(n=(3, 6, 5)), dict(n=(8, 6, 3)),
+                                dict(d=(np.full(8, 0.1), np.full(6, -0.1), np.full(5, 0.1))),
+                                dict(bc=(0, 0, 0)), dict(bc=(1, 2, 0)), dict(Ma=0.0),
+                                dict(Re=-1.0), dict(gamma=1.0), dict(p_in=0.0), dict(T_in=0.0),
+                                dict(wall_type=((0, 0), (3, 0), (0, 0))),
+                                dict(wall_T=((1, 1), (0.0, 1), (1, 1)))])
+def test_3d_create_rejects_invalid_setups(kw):
+    from paper_1802_04243_amd import sts3
+    box = _box3(**kw)
+    h = C.c_void_p()
+    rc = sts3.lib3().sts3_create(C.byref(sts3.setup_of(box)), None, C.byref(h))
+    assert rc == sts.STS_EINVAL
+    assert h.value is None
+    assert sts.lib().sts_last_error().decode()
+
+
+def test_3d_null_arguments_and_device_bytes():
+    from paper_1802_04243_amd import sts3
+    L = sts3.lib3()
+    assert L.sts3_step(None, 0.1, 1, 0) == sts.STS_EINVAL
+    assert L.sts3_residuals(None, None) == sts.STS_EINVAL
+    assert L.sts3_create(None, None, None) == sts.STS_EINVAL
+    L.sts3_destroy(None)
+    b = C.c_size_t()
+    assert L.sts3_device_bytes((C.c_int * 3)(64, 32, 32), C.byref(b)) == sts.STS_OK
+    # 26 FP64 arrays of (nz+1) (ny+1) pitch doubles, pitch = 96 for nx = 64
+    assert b.value == 26 * 8 * 96 * 33 * 33
+    assert L.sts3_device_bytes((C.c_int * 3)(64, 3, 32), C.byref(b)) == sts.STS_EINVAL
