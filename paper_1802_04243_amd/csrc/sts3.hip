@@ -15,11 +15,13 @@
 // convective terms pl15_11 / pl31_1).  The last pass of a step reduces the
 // increments and the continuity residual in fixed-order block partials.
 //
-// Every field array has the shape (nz+1) x (ny+1) x pitch doubles (x
-// fastest, pitch a multiple of 32), so that one index serves cells and the
-// faces of every direction.  Indices outside the domain wrap in a periodic
-// direction and are clamped otherwise (such values are loaded but never
-// used by an equation).
+// Every field array holds (nz+1+2G) x (ny+1+2G) rows of a pitch of at least
+// nx+1+2G doubles (x fastest): one index serves cells and the faces of every
+// direction, and G = 2 ghost layers around the domain let every neighbour of
+// a stencil be loaded at a constant offset.  In a periodic direction each
+// kernel that writes an array also writes the periodic images of the entries
+// within G of either end (face n is the image of face 0); elsewhere the
+// ghost entries hold finite values that no equation uses.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -36,6 +38,7 @@ namespace {
 
 constexpr int BX = 64, BY = 4, NTB = BX * BY;  // 256 threads per block
 constexpr int NR = 8;                           // residual partials per block
+constexpr int G = 2;                            // ghost layers
 
 struct P3 {
   int n[3];
@@ -46,9 +49,14 @@ struct P3 {
   double wT[3][2], sqwT[3][2];
   double A, B, C1, C2, C3, g[3];
   double u_in, T_in, p_in, rho_in, sqT_in;
-  double dt;
-  long sy, sz;
-  const double *d[3];
+  double dt, idt;
+  long sy, sz, off;  // strides; index of (0, 0, 0)
+  // per direction, index 0 = the first cell or face (G ghost entries before):
+  // widths d, their inverses id; at face i (between cells i-1 and i) the
+  // weights of cells i-1 and i in the linear interpolation to the face,
+  // wlo = d_i / (d_{i-1} + d_i) and whi = d_{i-1} / (d_{i-1} + d_i), and the
+  // inverse centre distance ic = 2 / (d_{i-1} + d_i)
+  const double *d[3], *id[3], *wlo[3], *whi[3], *ic[3];
 };
 
 struct Fld {
@@ -65,37 +73,49 @@ struct Work {
 // ---------------------------------------------------------------------------
 // indexing
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int cidx(const P3 &P, int e, int i) {
-  const int n = P.n[e];
-  if (P.per[e]) return i < 0 ? i + n : (i >= n ? i - n : i);
-  return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
-}
-__device__ __forceinline__ int fidx(const P3 &P, int e, int i) {
-  const int n = P.n[e];
-  if (P.per[e]) return i < 0 ? i + n : (i >= n ? i - n : i);
-  return i < 0 ? 0 : (i > n ? n : i);
-}
 __device__ __forceinline__ long lin(const P3 &P, int i, int j, int k) {
-  return (long)k * P.sz + (long)j * P.sy + i;
+  return P.off + (long)k * P.sz + (long)j * P.sy + i;
 }
-// value of a cell array at x (+ s along e)
+__device__ __forceinline__ long stride(const P3 &P, int e) {
+  return e == 0 ? 1 : (e == 1 ? P.sy : P.sz);
+}
+// value of an array at x (+ s along e); x may lie up to G outside the domain
 __device__ __forceinline__ double cv(const P3 &P, const double *a, const int x[3], int e = 0,
                                      int s = 0) {
-  int y[3] = {x[0], x[1], x[2]};
-  y[e] += s;
-  return a[lin(P, cidx(P, 0, y[0]), cidx(P, 1, y[1]), cidx(P, 2, y[2]))];
+  return a[lin(P, x[0], x[1], x[2]) + s * stride(P, e)];
 }
-// value of a face array of direction f at x (+ s along e)
 __device__ __forceinline__ double fv(const P3 &P, const double *a, int f, const int x[3],
                                      int e = 0, int s = 0) {
-  int y[3] = {x[0], x[1], x[2]};
-  y[e] += s;
-  const int i = f == 0 ? fidx(P, 0, y[0]) : cidx(P, 0, y[0]);
-  const int j = f == 1 ? fidx(P, 1, y[1]) : cidx(P, 1, y[1]);
-  const int k = f == 2 ? fidx(P, 2, y[2]) : cidx(P, 2, y[2]);
-  return a[lin(P, i, j, k)];
+  (void)f;
+  return cv(P, a, x, e, s);
 }
-__device__ __forceinline__ double W(const P3 &P, int e, int i) { return P.d[e][cidx(P, e, i)]; }
+__device__ __forceinline__ double W(const P3 &P, int e, int i) { return P.d[e][i]; }
+__device__ __forceinline__ double IW(const P3 &P, int e, int i) { return P.id[e][i]; }
+__device__ __forceinline__ double WLO(const P3 &P, int e, int i) { return P.wlo[e][i]; }
+__device__ __forceinline__ double WHI(const P3 &P, int e, int i) { return P.whi[e][i]; }
+__device__ __forceinline__ double IC(const P3 &P, int e, int i) { return P.ic[e][i]; }
+// store v at x and, in periodic directions, at the images of x within the
+// ghost layers (F: the face direction of a face array, -1 for a cell array)
+template <int F>
+__device__ void put(const P3 &P, double *a, const int x[3], double v) {
+  const long m = lin(P, x[0], x[1], x[2]);
+  a[m] = v;
+  int o[3][3], no[3];
+#pragma unroll
+  for (int e = 0; e < 3; e++) {
+    no[e] = 1;
+    o[e][0] = 0;
+    if (P.per[e]) {
+      if (x[e] <= (F == e ? G : G - 1)) o[e][no[e]++] = P.n[e];
+      if (x[e] >= P.n[e] - G) o[e][no[e]++] = -P.n[e];
+    }
+  }
+  if (no[0] + no[1] + no[2] == 3) return;
+  for (int a0 = 0; a0 < no[0]; a0++)
+    for (int a1 = 0; a1 < no[1]; a1++)
+      for (int a2 = 0; a2 < no[2]; a2++)
+        if (a0 | a1 | a2) a[m + o[0][a0] + (long)o[1][a1] * P.sy + (long)o[2][a2] * P.sz] = v;
+}
 __device__ __forceinline__ bool has_cell(const P3 &P, int e, int i) {
   return P.per[e] || (i >= 0 && i < P.n[e]);
 }
@@ -125,16 +145,33 @@ __device__ __forceinline__ double area(const P3 &P, int e, const int x[3]) {
 __device__ __forceinline__ double upw(double f1, double f2, double vel) {
   return vel > 0.0 ? f1 : f2;
 }
+// a / b as a reciprocal refined by Newton steps and a residual correction
+// (within one ulp of the IEEE quotient), and 1 / b
+__device__ __forceinline__ double ddiv(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
+__device__ __forceinline__ double drcp(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+  return __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+}
 // van Leer psi(r) = (r + |r|) / (1 + |r|) of r = a/b, written as 2a / (a + b)
 // where a and b have one sign (0 otherwise)
 __device__ __forceinline__ double vanleer(double a, double b) {
   const bool same = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);
-  return same ? 2.0 * a / (a + b) : 0.0;
+  const double q = ddiv(2.0 * a, a + b);
+  return same ? q : 0.0;
 }
-__device__ __forceinline__ double psi_s(double f1, double f2, double f3, double f4, double d1,
-                                        double d2, double d3, double d4, double vel) {
-  if (vel > 0.0) return d2 / (d2 + d3) * vanleer((d2 + d3) * (f2 - f1), (d1 + d2) * (f3 - f2));
-  return -d3 / (d2 + d3) * vanleer((d2 + d3) * (f4 - f3), (d3 + d4) * (f3 - f2));
+// psi_s of the face i along e between nodes 2 and 3 (cells i-1 and i), with
+// the stencil widths d1..d4 and the face's weights d2/(d2+d3), d3/(d2+d3)
+__device__ __forceinline__ double psi_s(const P3 &P, int e, int i, double f1, double f2, double f3,
+                                        double f4, double vel) {
+  const double d1 = W(P, e, i - 2), d2 = W(P, e, i - 1), d3 = W(P, e, i), d4 = W(P, e, i + 1);
+  if (vel > 0.0) return WHI(P, e, i) * vanleer((d2 + d3) * (f2 - f1), (d1 + d2) * (f3 - f2));
+  return -WLO(P, e, i) * vanleer((d2 + d3) * (f4 - f3), (d3 + d4) * (f3 - f2));
 }
 __device__ __forceinline__ double psi_c(double f1, double f2, double f3, double f4, double d1,
                                         double d2, double d3, double vel) {
@@ -142,9 +179,9 @@ __device__ __forceinline__ double psi_c(double f1, double f2, double f3, double 
   return -0.5 * vanleer(d2 * (f4 - f3), d3 * (f3 - f2));
 }
 __device__ __forceinline__ double hmean(double dl, double gl, double dr, double gr) {
-  return (dl + dr) * gl * gr / (dl * gr + dr * gl);
+  return ddiv((dl + dr) * gl * gr, dl * gr + dr * gl);
 }
-__device__ __forceinline__ double hmean2(double a, double b) { return 2.0 * a * b / (a + b); }
+__device__ __forceinline__ double hmean2(double a, double b) { return ddiv(2.0 * a * b, a + b); }
 
 // thread -> point of an index space of extent (X, Y, Z)
 __device__ __forceinline__ bool point(int X, int Y, int Z, int x[3]) {
@@ -162,17 +199,18 @@ __global__ __launch_bounds__(NTB) void k3_cell(P3 P, Fld S, Work Wk) {
   if (!point(P.n[0], P.n[1], P.n[2], x)) return;
   const long m = lin(P, x[0], x[1], x[2]);
   const double p = S.q[3][m], T = S.q[4][m];
-  Wk.rho[m] = p / T;
-  Wk.gam[m] = sqrt(T);
+  put<-1>(P, Wk.rho, x, ddiv(p, T));
+  put<-1>(P, Wk.gam, x, sqrt(T));
 }
 
 template <int A, bool TV>
 __global__ __launch_bounds__(NTB) void k3_rf(P3 P, Fld S, Work Wk) {
   int f[3];
   if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
+  const int fa = f[A];
+  if (P.per[A] && fa == P.n[A]) return;  // the image of face 0
   const long m = lin(P, f[0], f[1], f[2]);
   const double vel = S.q[A][m];
-  const int fa = f[A];
   double r;
   if (!P.per[A] && fa == 0) {
     const double rr = cv(P, Wk.rho, f);
@@ -183,11 +221,10 @@ __global__ __launch_bounds__(NTB) void k3_rf(P3 P, Fld S, Work Wk) {
     const double rl = cv(P, Wk.rho, f, A, -1), rr = cv(P, Wk.rho, f);
     r = upw(rl, rr, vel);
     if (TV && has_cell(P, A, fa - 2) && has_cell(P, A, fa + 1))
-      r += psi_s(cv(P, Wk.rho, f, A, -2), rl, rr, cv(P, Wk.rho, f, A, 1), W(P, A, fa - 2),
-                 W(P, A, fa - 1), W(P, A, fa), W(P, A, fa + 1), vel) *
+      r += psi_s(P, A, fa, cv(P, Wk.rho, f, A, -2), rl, rr, cv(P, Wk.rho, f, A, 1), vel) *
            (rr - rl);
   }
-  Wk.rf[A][m] = r;
+  put<A>(P, Wk.rf[A], f, r);
 }
 
 // mass flux through the e-face of cell x on side s (0 low, 1 high)
@@ -228,11 +265,9 @@ __device__ double T_explicit(const P3 &P, const Fld &S, const Work &Wk, const in
     if (TV) {
       const int xe = x[e];
       if (has_cell(P, e, xe - 1) && has_cell(P, e, xe + 2))
-        ph = psi_s(cv(P, T, x, e, -1), TP, TH, cv(P, T, x, e, 2), W(P, e, xe - 1), W(P, e, xe),
-                   W(P, e, xe + 1), W(P, e, xe + 2), vh);
+        ph = psi_s(P, e, xe + 1, cv(P, T, x, e, -1), TP, TH, cv(P, T, x, e, 2), vh);
       if (has_cell(P, e, xe - 2) && has_cell(P, e, xe + 1))
-        pl = psi_s(cv(P, T, x, e, -2), TL, TP, TH, W(P, e, xe - 2), W(P, e, xe - 1), W(P, e, xe),
-                   W(P, e, xe + 1), vl);
+        pl = psi_s(P, e, xe, cv(P, T, x, e, -2), TL, TP, TH, vl);
     }
     sum += -Fh * (upw(TP, TH, vh) + (TH - TP) * ph) + Fl * (upw(TL, TP, vl) + (TP - TL) * pl);
   }
@@ -257,8 +292,9 @@ __device__ double qface(const P3 &P, const Fld &S, int e, int f, const int x[3],
   if (k == 1) return P.wt[f][s] == STS3_NOSLIP ? P.wv[f][s][e] : qc;
   if (k == 2) return 0.0;
   if (k == 3) return qc;
-  const double dx = W(P, f, x[f]), dy = W(P, f, x[f] + (s ? 1 : -1));
-  return (dy * qc + dx * qcell(P, S, e, x, f, s ? 1 : -1)) / (dx + dy);
+  const double qn = qcell(P, S, e, x, f, s ? 1 : -1);
+  return s ? WLO(P, f, x[f] + 1) * qc + WHI(P, f, x[f] + 1) * qn
+           : WHI(P, f, x[f]) * qc + WLO(P, f, x[f]) * qn;
 }
 
 template <bool IM, bool TV>
@@ -279,14 +315,14 @@ __global__ __launch_bounds__(NTB) void k3_energy(P3 P, Fld S, Work Wk, double *T
       if (k == 1) {
         if (P.wt[e][s] == STS3_NOSLIP) {
           nb = P.wT[e][s];
-          D = P.C1 * hmean2(gP, P.sqwT[e][s]) * ar / (0.5 * de);
+          D = P.C1 * hmean2(gP, P.sqwT[e][s]) * ar * 2.0 * IW(P, e, x[e]);
         } else {
           nb = TP;
           D = 0.0;
         }
       } else if (k == 2) {
         nb = P.T_in;
-        D = P.C1 * hmean2(gP, P.sqT_in) * ar / (0.5 * de);
+        D = P.C1 * hmean2(gP, P.sqT_in) * ar * 2.0 * IW(P, e, x[e]);
       } else if (k == 3) {
         nb = TP;
         D = 0.0;
@@ -294,7 +330,7 @@ __global__ __launch_bounds__(NTB) void k3_energy(P3 P, Fld S, Work Wk, double *T
         const int sg = s ? 1 : -1;
         const double dn = W(P, e, x[e] + sg), gn = cv(P, Wk.gam, x, e, sg);
         nb = cv(P, T, x, e, sg);
-        D = P.C1 * (s ? hmean(de, gP, dn, gn) : hmean(dn, gn, de, gP)) * ar / (0.5 * (de + dn));
+        D = P.C1 * (s ? hmean(de, gP, dn, gn) : hmean(dn, gn, de, gP)) * ar * IC(P, e, x[e] + s);
       }
       double a = D;
       if (IM) {
@@ -306,11 +342,10 @@ __global__ __launch_bounds__(NTB) void k3_energy(P3 P, Fld S, Work Wk, double *T
           const double vel = fv(P, S.q[e], e, yf);
           const int xe = x[e];
           if (s == 0 && has_cell(P, e, xe - 2) && has_cell(P, e, xe + 1))
-            psi = psi_s(cv(P, T, x, e, -2), cv(P, T, x, e, -1), TP, cv(P, T, x, e, 1),
-                        W(P, e, xe - 2), W(P, e, xe - 1), de, W(P, e, xe + 1), vel);
+            psi = psi_s(P, e, xe, cv(P, T, x, e, -2), cv(P, T, x, e, -1), TP, cv(P, T, x, e, 1), vel);
           if (s == 1 && has_cell(P, e, xe - 1) && has_cell(P, e, xe + 2))
-            psi = psi_s(cv(P, T, x, e, -1), TP, cv(P, T, x, e, 1), cv(P, T, x, e, 2),
-                        W(P, e, xe - 1), de, W(P, e, xe + 1), W(P, e, xe + 2), vel);
+            psi = psi_s(P, e, xe + 1, cv(P, T, x, e, -1), TP, cv(P, T, x, e, 1), cv(P, T, x, e, 2),
+                        vel);
         }
         a = (s ? fmax(0.0, -Fv) : fmax(0.0, Fv)) - Fv * psi + D;
         sF += s ? Fv : -Fv;
@@ -324,7 +359,7 @@ __global__ __launch_bounds__(NTB) void k3_energy(P3 P, Fld S, Work Wk, double *T
   double dd[3], div = 0.0;
 #pragma unroll
   for (int e = 0; e < 3; e++) {
-    dd[e] = (fv(P, S.q[e], e, x, e, 1) - fv(P, S.q[e], e, x)) / W(P, e, x[e]);
+    dd[e] = (fv(P, S.q[e], e, x, e, 1) - fv(P, S.q[e], e, x)) * IW(P, e, x[e]);
     div += dd[e];
   }
   double phi = 2.0 * (dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
@@ -332,14 +367,14 @@ __global__ __launch_bounds__(NTB) void k3_energy(P3 P, Fld S, Work Wk, double *T
   for (int e = 0; e < 3; e++)
 #pragma unroll
     for (int f = e + 1; f < 3; f++) {
-      const double sef = (qface(P, S, e, f, x, 1) - qface(P, S, e, f, x, 0)) / W(P, f, x[f]) +
-                         (qface(P, S, f, e, x, 1) - qface(P, S, f, e, x, 0)) / W(P, e, x[e]);
+      const double sef = (qface(P, S, e, f, x, 1) - qface(P, S, e, f, x, 0)) * IW(P, f, x[f]) +
+                         (qface(P, S, f, e, x, 1) - qface(P, S, f, e, x, 0)) * IW(P, e, x[e]);
       phi += sef * sef;
     }
   phi -= 2.0 / 3.0 * div * div;
   const double src = P.C2 * gP * phi * dV + P.C3 * cv(P, S.q[3], x) * div * dV;
   const long m = lin(P, x[0], x[1], x[2]);
-  Tout[m] = (P.dt * (sn + src) + Wk.cT[m]) / a0;
+  put<-1>(P, Tout, x, ddiv(P.dt * (sn + src) + Wk.cT[m], a0));
 }
 
 // ---------------------------------------------------------------------------
@@ -360,13 +395,10 @@ __device__ double gam_edge(const P3 &P, const Work &Wk, int b, const int f[3], i
       l[b] = P.n[b] - 1;
       int r[3] = {f[0], f[1], f[2]};
       r[b] = P.n[b] - 1;
-      const double dl = W(P, A, f[A] - 1), dr = W(P, A, f[A]);
-      return (dr * cv(P, Wk.gam, l) + dl * cv(P, Wk.gam, r)) / (dl + dr);
+      return WLO(P, A, f[A]) * cv(P, Wk.gam, l) + WHI(P, A, f[A]) * cv(P, Wk.gam, r);
     }
     return 0.0;
   }
-  const double dal = W(P, A, f[A] - 1), dar = W(P, A, f[A]);
-  const double dbl = W(P, b, bf - 1), dbr = W(P, b, bf);
   double g = 0.0;
 #pragma unroll
   for (int ia = 0; ia < 2; ia++)
@@ -375,8 +407,8 @@ __device__ double gam_edge(const P3 &P, const Work &Wk, int b, const int f[3], i
       int y[3] = {f[0], f[1], f[2]};
       y[A] = f[A] - 1 + ia;
       y[b] = bf - 1 + ib;
-      const double wa = ia ? dal / (dal + dar) : dar / (dal + dar);
-      const double wb = ib ? dbl / (dbl + dbr) : dbr / (dbl + dbr);
+      const double wa = ia ? WHI(P, A, f[A]) : WLO(P, A, f[A]);
+      const double wb = ib ? WHI(P, b, bf) : WLO(P, b, bf);
       g += wa * wb * cv(P, Wk.gam, y);
     }
   return g;
@@ -435,11 +467,9 @@ __device__ double q_explicit(const P3 &P, const Fld &S, const Work &Wk, const in
         const double vl = fv(P, S.q[b], b, cx), vh = fv(P, S.q[b], b, bh);
         const double Fl = flux(P, S, Wk, b, cx, 0), Fh = flux(P, S, Wk, b, cx, 1);
         if (okh)
-          ph = psi_s(q1h, qP, qH, q4h, W(P, b, fb - 1), W(P, b, fb), W(P, b, fb + 1),
-                     W(P, b, fb + 2), vh);
+          ph = psi_s(P, b, fb + 1, q1h, qP, qH, q4h, vh);
         if (okl)
-          pl = psi_s(q1l, qL, qP, q4l, W(P, b, fb - 2), W(P, b, fb - 1), W(P, b, fb),
-                     W(P, b, fb + 1), vl);
+          pl = psi_s(P, b, fb, q1l, qL, qP, q4l, vl);
         sum += 0.5 * (-Fh * (upw(qP, qH, vh) + (qH - qP) * ph) +
                       Fl * (upw(qL, qP, vl) + (qP - qL) * pl));
       }
@@ -452,12 +482,13 @@ template <int A, bool IM, bool TV>
 __global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
   int f[3];
   if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
+  if (P.per[A] && f[A] == P.n[A]) return;  // the image of face 0
   const long m = lin(P, f[0], f[1], f[2]);
   const double *q = S.q[A];
   const double qP = q[m];
   if (!solved(P, A, f[A])) {
-    Wk.qh[A][m] = qP;
-    Wk.dq[A][m] = 0.0;
+    put<A>(P, Wk.qh[A], f, qP);
+    put<A>(P, Wk.dq[A], f, 0.0);
     return;
   }
   int l[3] = {f[0], f[1], f[2]};
@@ -467,14 +498,14 @@ __global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
   const double gl = cv(P, Wk.gam, l), gr = cv(P, Wk.gam, f);
   const double Ap = area(P, A, f), len = 0.5 * (dal + dar);
   const double M = (rr * dar + rl * dal) * Ap / 2.0;
-  const double gnode = (dar * gl + dal * gr) / (dal + dar);
+  const double gnode = WLO(P, A, f[A]) * gl + WHI(P, A, f[A]) * gr;
   double sa = 0.0, sn = 0.0, conv = 0.0, X = 0.0;
 #pragma unroll
   for (int b = 0; b < 3; b++) {
     const double qL = q_nb<A>(P, q, b, f, -1, qP), qH = q_nb<A>(P, q, b, f, 1, qP);
     double aL, aH;
     if (b == A) {
-      const double DL = P.B * gl * Ap / dal, DH = P.B * gr * Ap / dar;
+      const double DL = P.B * gl * Ap * IW(P, A, f[A] - 1), DH = P.B * gr * Ap * IW(P, A, f[A]);
       double cl = 0.0, ch = 0.0;
       if (IM) {
         const double ubL = 0.5 * (qL + qP), ubH = 0.5 * (qP + qH);
@@ -495,22 +526,21 @@ __global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
       aH = ch + 4.0 / 3.0 * DH;
     } else {
       const int t = 3 - A - b;
-      const double d3 = W(P, t, f[t]), db = W(P, b, f[b]);
+      const double d3 = W(P, t, f[t]);
       double D[2];
 #pragma unroll
       for (int s = 0; s < 2; s++) {
         const int k = side(P, b, f[b], s);
         if (k == 1)
           D[s] = P.wt[b][s] == STS3_NOSLIP
-                     ? P.B * 0.5 * (gnode + P.sqwT[b][s]) * len * d3 / (0.5 * db)
+                     ? P.B * (gnode + P.sqwT[b][s]) * len * d3 * IW(P, b, f[b])
                      : 0.0;
         else if (k == 2)
-          D[s] = P.B * 0.5 * (gnode + gam_edge<A>(P, Wk, b, f, 0)) * len * d3 / (0.5 * db);
+          D[s] = P.B * (gnode + gam_edge<A>(P, Wk, b, f, 0)) * len * d3 * IW(P, b, f[b]);
         else if (k == 3)
           D[s] = 0.0;
         else
-          D[s] = P.B * gam_edge<A>(P, Wk, b, f, s) * (dal + dar) * 0.5 * d3 /
-                 (0.5 * (db + W(P, b, f[b] + (s ? 1 : -1))));
+          D[s] = P.B * gam_edge<A>(P, Wk, b, f, s) * len * d3 * IC(P, b, f[b] + s);
       }
       double cl = 0.0, ch = 0.0;
       if (IM) {
@@ -526,11 +556,9 @@ __global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
           const double Fl = flux(P, S, Wk, b, cx, 0), Fh = flux(P, S, Wk, b, cx, 1);
           double pl = 0.0, ph = 0.0;
           if (okl)
-            pl = psi_s(fv(P, q, A, f, b, -2), qL, qP, fv(P, q, A, f, b, 1), W(P, b, fb - 2),
-                       W(P, b, fb - 1), db, W(P, b, fb + 1), vl);
+            pl = psi_s(P, b, fb, fv(P, q, A, f, b, -2), qL, qP, fv(P, q, A, f, b, 1), vl);
           if (okh)
-            ph = psi_s(fv(P, q, A, f, b, -1), qP, qH, fv(P, q, A, f, b, 2), W(P, b, fb - 1), db,
-                       W(P, b, fb + 1), W(P, b, fb + 2), vh);
+            ph = psi_s(P, b, fb + 1, fv(P, q, A, f, b, -1), qP, qH, fv(P, q, A, f, b, 2), vh);
           cl += 0.5 * (fmax(0.0, Fl) - Fl * pl);
           ch += 0.5 * (fmax(0.0, -Fh) - Fh * ph);
           conv += 0.5 * (Fh - Fl);
@@ -552,10 +580,11 @@ __global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
     sa += aL + aH;
     sn += aL * qL + aH * qH;
   }
-  const double a0 = sa + conv + M / P.dt;
+  const double a0 = sa + conv + M * P.idt;
   const double b = Wk.cq[A][m] + P.B * X;
-  Wk.qh[A][m] = (sn + b) / a0;
-  Wk.dq[A][m] = P.A * Ap / a0;
+  const double ia0 = drcp(a0);
+  put<A>(P, Wk.qh[A], f, (sn + b) * ia0);
+  put<A>(P, Wk.dq[A], f, P.A * Ap * ia0);
 }
 
 // ---------------------------------------------------------------------------
@@ -583,8 +612,8 @@ __global__ __launch_bounds__(NTB) void k3_pressure(P3 P, Fld S, Work Wk, const d
     sap += aL * pL + aH * pH;
     sb += bH - bL;
   }
-  const double a0 = dV / Tn[m] + sa * P.dt;
-  pout[m] = (sap * P.dt + (Wk.cp[m] - sb * P.dt)) / a0;
+  const double a0 = ddiv(dV, Tn[m]) + sa * P.dt;
+  put<-1>(P, pout, x, ddiv(sap * P.dt + (Wk.cp[m] - sb * P.dt), a0));
 }
 
 template <int A>
@@ -598,15 +627,12 @@ __global__ __launch_bounds__(NTB) void k3_velocity(P3 P, Fld S, Work Wk, const d
                                                    double *qout) {
   int f[3];
   if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
-  const long m = lin(P, f[0], f[1], f[2]);
   const int fa = f[A];
+  if (P.per[A] && fa == P.n[A]) return;  // the image of face 0
+  const long m = lin(P, f[0], f[1], f[2]);
   double qn;
   if (solved(P, A, fa)) {
     qn = q_update<A>(P, Wk, pn, f);
-  } else if (P.per[A]) {  // the last face repeats face 0
-    int g[3] = {f[0], f[1], f[2]};
-    g[A] = 0;
-    qn = q_update<A>(P, Wk, pn, g);
   } else if (A == 0 && P.io && fa == P.n[0]) {  // outlet: zero gradient
     int g[3] = {f[0], f[1], f[2]};
     g[A] = fa - 1;
@@ -614,7 +640,7 @@ __global__ __launch_bounds__(NTB) void k3_velocity(P3 P, Fld S, Work Wk, const d
   } else {
     qn = S.q[A][m];  // inlet u_in, wall faces 0
   }
-  qout[m] = qn;
+  put<A>(P, qout, f, qn);
 }
 
 // ---------------------------------------------------------------------------
@@ -645,7 +671,7 @@ __global__ __launch_bounds__(NTB) void k3_const_face(P3 P, Fld S, Work Wk) {
   l[A] -= 1;
   const double dal = W(P, A, f[A] - 1), dar = W(P, A, f[A]);
   const double Mm = (cv(P, Wk.rho, f) * dar + cv(P, Wk.rho, l) * dal) * area(P, A, f) / 2.0;
-  Wk.cq[A][m] = Mm / P.dt * S.q[A][m] + P.g[A] * Mm + (EX ? q_explicit<A, TV>(P, S, Wk, f) : 0.0);
+  Wk.cq[A][m] = Mm * P.idt * S.q[A][m] + P.g[A] * Mm + (EX ? q_explicit<A, TV>(P, S, Wk, f) : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -717,16 +743,20 @@ __global__ __launch_bounds__(NTB) void k3_resid_face(P3 P, Fld O, Fld N, double 
   block_reduce(v, part + block_slot(base) * NR);
 }
 
-__global__ __launch_bounds__(NTB) void k3_resid_final(const double *part, int nblocks,
-                                                      double *out) {
+// fold rows [blockIdx.x * chunk, (blockIdx.x + 1) * chunk) of nrows into
+// row blockIdx.x of out (fixed order)
+__global__ __launch_bounds__(NTB) void k3_resid_fold(const double *part, int nrows, int chunk,
+                                                     double *out) {
   double v[NR] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int t = threadIdx.y * BX + threadIdx.x;
-  for (int b = t; b < nblocks; b += NTB)
+  const int b0 = blockIdx.x * chunk, b1 = min(nrows, b0 + chunk);
+  for (int b = b0 + t; b < b1; b += NTB)
 #pragma unroll
     for (int q = 0; q < NR; q++)
       v[q] = (q == 6 || q == 7) ? v[q] + part[(long)b * NR + q] : fmax(v[q], part[(long)b * NR + q]);
-  block_reduce(v, out);
+  block_reduce(v, out + (long)blockIdx.x * NR);
 }
+constexpr int FOLD_BLOCKS = 512;
 
 }  // namespace
 }  // namespace sts3
@@ -739,7 +769,7 @@ using namespace sts3;
 struct sts3_ctx {
   P3 P;
   int n[3];
-  long pitch, sy, sz;
+  long pitch, sy, sz, off;
   size_t field_bytes;
   hipStream_t stream;
   bool own_stream;
@@ -748,7 +778,7 @@ struct sts3_ctx {
   Fld st[2];
   int cur;
   Work Wk;
-  double *d_d[3];
+  double *d_d[3];  // per direction: widths, inverses, wlo, whi, ic (G ghosts each end)
   double *part, *dres;
   double *hres;  // pinned
   int nblk_cell, nblk_face[3], nblocks;
@@ -823,7 +853,12 @@ void launch_pass3d(sts3_ctx *c, const Fld &O, const Fld &N, bool last) {
     hipLaunchKernelGGL((k3_resid_face<1>), grid_face(c, 1), b, 0, c->stream, c->P, O, N, c->part, base);
     base += c->nblk_face[1];
     hipLaunchKernelGGL((k3_resid_face<2>), grid_face(c, 2), b, 0, c->stream, c->P, O, N, c->part, base);
-    hipLaunchKernelGGL(k3_resid_final, dim3(1), b, 0, c->stream, c->part, c->nblocks, c->dres);
+    const int chunk = (c->nblocks + FOLD_BLOCKS - 1) / FOLD_BLOCKS;
+    double *rows = c->part + (long)c->nblocks * NR;
+    hipLaunchKernelGGL(k3_resid_fold, dim3(FOLD_BLOCKS), b, 0, c->stream, c->part, c->nblocks,
+                       chunk, rows);
+    hipLaunchKernelGGL(k3_resid_fold, dim3(1), b, 0, c->stream, rows, FOLD_BLOCKS, FOLD_BLOCKS,
+                       c->dres);
   }
 }
 
@@ -856,9 +891,52 @@ void impose(const sts3_ctx *c, std::vector<double> *q) {
 }
 
 size_t field_elems(const int n[3], long *pitch) {
-  const long p = (long)((n[0] + 1 + 31) / 32) * 32;
+  const long p = (long)((n[0] + 1 + 2 * G + 31) / 32) * 32;
   if (pitch) *pitch = p;
-  return (size_t)p * (n[1] + 1) * (n[2] + 1);
+  return (size_t)p * (n[1] + 1 + 2 * G) * (n[2] + 1 + 2 * G);
+}
+
+// dense host array of field f (x fastest, extents n + (f == e)) <-> the
+// padded device layout; the ghost entries get the periodic images, or
+// `ghost` (finite, unused) in a direction that is not periodic
+void to_padded(const sts3_ctx *c, int f, const std::vector<double> &dense,
+               std::vector<double> &pad, double ghost) {
+  const int *n = c->n;
+  const int D[3] = {n[0] + (f == 0), n[1] + (f == 1), n[2] + (f == 2)};
+  const long E[3] = {c->pitch, n[1] + 1 + 2 * G, n[2] + 1 + 2 * G};
+  pad.assign(c->field_bytes / sizeof(double), ghost);
+  auto at = [&](int i, int j, int k) -> double & {
+    return pad[(size_t)(k + G) * c->sz + (size_t)(j + G) * c->sy + (size_t)(i + G)];
+  };
+  for (int k = 0; k < D[2]; k++)
+    for (int j = 0; j < D[1]; j++)
+      for (int i = 0; i < D[0]; i++) at(i, j, k) = dense[((size_t)k * D[1] + j) * D[0] + i];
+  for (int e = 0; e < 3; e++) {
+    if (c->bc[e] != STS3_PERIODIC) continue;
+    const int ne = n[e], top = (f == e) ? ne + 1 : ne;  // first index above the domain
+    const int lo[3] = {-G, -G, -G};
+    const int hi[3] = {(int)E[0] - G, (int)E[1] - G, (int)E[2] - G};
+    int x[3];
+    for (x[2] = lo[2]; x[2] < hi[2]; x[2]++)
+      for (x[1] = lo[1]; x[1] < hi[1]; x[1]++)
+        for (x[0] = lo[0]; x[0] < hi[0]; x[0]++) {
+          const int xe = x[e];
+          if (xe >= 0 && xe < top) continue;
+          if (xe >= top + G) continue;
+          int y[3] = {x[0], x[1], x[2]};
+          y[e] = xe < 0 ? xe + ne : xe - ne;
+          at(x[0], x[1], x[2]) = at(y[0], y[1], y[2]);
+        }
+  }
+}
+void from_padded(const sts3_ctx *c, int f, const std::vector<double> &pad, double *dense) {
+  const int *n = c->n;
+  const int D[3] = {n[0] + (f == 0), n[1] + (f == 1), n[2] + (f == 2)};
+  for (int k = 0; k < D[2]; k++)
+    for (int j = 0; j < D[1]; j++)
+      for (int i = 0; i < D[0]; i++)
+        dense[((size_t)k * D[1] + j) * D[0] + i] =
+            pad[(size_t)(k + G) * c->sz + (size_t)(j + G) * c->sy + (size_t)(i + G)];
 }
 constexpr int NFIELDS = 26;  // 2 states x 5, rho, gam, rf x3, qh x3, dq x3, cq x3, cT, cp
 }  // namespace
@@ -929,7 +1007,8 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
   c->u_in = s->u_in;
   const size_t fe = field_elems(c->n, &c->pitch);
   c->sy = c->pitch;
-  c->sz = c->pitch * (c->n[1] + 1);
+  c->sz = c->pitch * (c->n[1] + 1 + 2 * G);
+  c->off = (long)G * c->sz + (long)G * c->sy + G;
   c->field_bytes = fe * sizeof(double);
   auto alloc = [&](size_t b, void **p) -> bool {
     if (hipMalloc(p, b) != hipSuccess) return false;
@@ -954,7 +1033,7 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
   c->Wk.cT = fields[k++];
   c->Wk.cp = fields[k++];
   for (int e = 0; e < 3; e++)
-    if (!alloc(sizeof(double) * c->n[e], (void **)&c->d_d[e])) {
+    if (!alloc(sizeof(double) * 5 * (c->n[e] + 2 * G), (void **)&c->d_d[e])) {
       sts3_destroy(c);
       return fail3(STS_ENOMEM, "device allocation failed");
     }
@@ -964,7 +1043,7 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
     c->nblk_face[a] = nblk(grid_face(c, a));
     c->nblocks += c->nblk_face[a];
   }
-  if (!alloc(sizeof(double) * NR * (size_t)c->nblocks, (void **)&c->part) ||
+  if (!alloc(sizeof(double) * NR * ((size_t)c->nblocks + FOLD_BLOCKS), (void **)&c->part) ||
       !alloc(256, (void **)&c->dres) || hipHostMalloc((void **)&c->hres, 256) != hipSuccess) {
     c->hres = nullptr;
     sts3_destroy(c);
@@ -987,7 +1066,12 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
     P.n[e] = c->n[e];
     P.per[e] = s->bc[e] == STS3_PERIODIC;
     P.g[e] = s->g[e];
-    P.d[e] = c->d_d[e];
+    const int ne = c->n[e] + 2 * G;
+    P.d[e] = c->d_d[e] + G;
+    P.id[e] = c->d_d[e] + ne + G;
+    P.wlo[e] = c->d_d[e] + 2 * ne + G;
+    P.whi[e] = c->d_d[e] + 3 * ne + G;
+    P.ic[e] = c->d_d[e] + 4 * ne + G;
     for (int w = 0; w < 2; w++) {
       P.wt[e][w] = s->wall_type[e][w];
       P.wT[e][w] = s->wall_T[e][w];
@@ -1009,9 +1093,22 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
   P.sqT_in = sqrt(s->T_in);
   P.sy = c->sy;
   P.sz = c->sz;
-  for (int e = 0; e < 3; e++)
-    HIP3(hipMemcpyAsync(c->d_d[e], c->wid[e].data(), sizeof(double) * c->n[e],
-                        hipMemcpyHostToDevice, c->stream));
+  P.off = c->off;
+  // widths with G ghosts at each end: periodic images, or the end cell's
+  for (int e = 0; e < 3; e++) {
+    const int ne = c->n[e];
+    auto width = [&](int i) {
+      const int w = P.per[e] ? ((i % ne) + ne) % ne : std::min(std::max(i, 0), ne - 1);
+      return c->wid[e][w];
+    };
+    std::vector<double> g;
+    for (int i = -G; i < ne + G; i++) g.push_back(width(i));
+    for (int i = -G; i < ne + G; i++) g.push_back(1.0 / width(i));
+    for (int i = -G; i < ne + G; i++) g.push_back(width(i) / (width(i - 1) + width(i)));
+    for (int i = -G; i < ne + G; i++) g.push_back(width(i - 1) / (width(i - 1) + width(i)));
+    for (int i = -G; i < ne + G; i++) g.push_back(2.0 / (width(i - 1) + width(i)));
+    HIP3(hipMemcpy(c->d_d[e], g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice));
+  }
   // clear every array (frame entries stay finite), then the initial state
   for (int k2 = 0; k2 < NFIELDS; k2++) HIP3(hipMemsetAsync(fields[k2], 0, c->field_bytes, c->stream));
   c->cur = 0;
@@ -1035,35 +1132,26 @@ extern "C" sts_status sts3_set_fields(sts3_ctx *c, const double *const q[5]) {
   if (!c || !q) return fail3(STS_EINVAL, "NULL argument");
   HIP3(hipSetDevice(c->device));
   HIP3(hipStreamSynchronize(c->stream));
-  std::vector<double> dense[5];
+  std::vector<double> dense[5], pad;
   const int *n = c->n;
   for (int f = 0; f < 5; f++) {
     const size_t len = (size_t)(n[0] + (f == 0)) * (n[1] + (f == 1)) * (n[2] + (f == 2));
     dense[f].resize(len);
     if (q[f]) {
       memcpy(dense[f].data(), q[f], len * sizeof(double));
-    } else {
-      // keep the current field
-      const int D0 = n[0] + (f == 0), D1 = n[1] + (f == 1), D2 = n[2] + (f == 2);
-      for (int k = 0; k < D2; k++)
-        HIP3(hipMemcpy2D(dense[f].data() + (size_t)k * D1 * D0, D0 * 8,
-                         c->st[c->cur].q[f] + (size_t)k * c->sz, c->pitch * 8, D0 * 8, D1,
-                         hipMemcpyDeviceToHost));
+    } else {  // keep the current field
+      pad.resize(c->field_bytes / sizeof(double));
+      HIP3(hipMemcpy(pad.data(), c->st[c->cur].q[f], c->field_bytes, hipMemcpyDeviceToHost));
+      from_padded(c, f, pad, dense[f].data());
     }
   }
   impose(c, dense);
   for (int f = 0; f < 5; f++) {
-    const int D0 = n[0] + (f == 0), D1 = n[1] + (f == 1), D2 = n[2] + (f == 2);
-    for (int k = 0; k < D2; k++)
-      HIP3(hipMemcpy2D(c->st[c->cur].q[f] + (size_t)k * c->sz, c->pitch * 8,
-                       dense[f].data() + (size_t)k * D1 * D0, D0 * 8, D0 * 8, D1,
-                       hipMemcpyHostToDevice));
+    to_padded(c, f, dense[f], pad, f >= 3 ? 1.0 : 0.0);
+    // both state buffers: faces that the passes do not write keep these values
+    for (int b = 0; b < 2; b++)
+      HIP3(hipMemcpy(c->st[b].q[f], pad.data(), c->field_bytes, hipMemcpyHostToDevice));
   }
-  // the other state buffer holds the same boundary entries (faces that the
-  // passes do not write keep them)
-  for (int f = 0; f < 5; f++)
-    HIP3(hipMemcpy(c->st[c->cur ^ 1].q[f], c->st[c->cur].q[f], c->field_bytes,
-                   hipMemcpyDeviceToDevice));
   c->stepped = false;
   return STS_OK;
 }
@@ -1072,13 +1160,11 @@ extern "C" sts_status sts3_fields(sts3_ctx *c, double *const q[5]) {
   if (!c || !q) return fail3(STS_EINVAL, "NULL argument");
   HIP3(hipSetDevice(c->device));
   HIP3(hipStreamSynchronize(c->stream));
-  const int *n = c->n;
+  std::vector<double> pad(c->field_bytes / sizeof(double));
   for (int f = 0; f < 5; f++) {
     if (!q[f]) continue;
-    const int D0 = n[0] + (f == 0), D1 = n[1] + (f == 1), D2 = n[2] + (f == 2);
-    for (int k = 0; k < D2; k++)
-      HIP3(hipMemcpy2D(q[f] + (size_t)k * D1 * D0, D0 * 8, c->st[c->cur].q[f] + (size_t)k * c->sz,
-                       c->pitch * 8, D0 * 8, D1, hipMemcpyDeviceToHost));
+    HIP3(hipMemcpy(pad.data(), c->st[c->cur].q[f], c->field_bytes, hipMemcpyDeviceToHost));
+    from_padded(c, f, pad, q[f]);
   }
   return STS_OK;
 }
@@ -1090,6 +1176,7 @@ extern "C" sts_status sts3_step(sts3_ctx *c, double dt, int n_inner, int scheme)
   if (scheme & ~(STS_IMPLICIT | STS_TVD)) return fail3(STS_EINVAL, "unknown scheme bits");
   HIP3(hipSetDevice(c->device));
   c->P.dt = dt;
+  c->P.idt = 1.0 / dt;
   const bool im = scheme & STS_IMPLICIT, tv = scheme & STS_TVD;
   const Fld S0 = c->st[c->cur];
   if (im) launch_prologue3<false, false>(c, S0);

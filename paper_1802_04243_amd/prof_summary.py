@@ -17,6 +17,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -42,7 +43,8 @@ def kernel_hash() -> str:
 
 
 def short(name: str) -> str:
-    return name.replace("sts::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+    name = re.sub(r"\b\w+::\(anonymous namespace\)::", "", name).replace("void ", "")
+    return name.split("(")[0]
 
 
 def counters(d: str):

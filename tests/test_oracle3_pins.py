@@ -29,8 +29,12 @@ from test_oracle_pins import _couette_exact
 
 @pytest.fixture(scope="module", autouse=True)
 def _one_thread():
+    # these grids are small: one thread; the OpenMP setting is per process
+    # (both oracles share it), so it is restored for the modules that follow
+    prev = O.max_threads()
     O3.set_threads(1)
     yield
+    O3.set_threads(prev)
 
 
 def _ones(box):

@@ -37,7 +37,6 @@ def sts3_mod():
 @pytest.fixture(scope="module")
 def ora3():
     from oracle import oracle3
-    oracle3.set_threads(16)
     return oracle3
 
 
