@@ -226,11 +226,15 @@ def _drag_grad(p, f0, run, scheme):
     return float(L.detach()), grads, dict(adjoint.LAST_STATS)
 
 
-def run_combined(name: str = "combined_4096x1024", scheme: int = W.EXPLICIT | W.TVD):
+def run_combined(name: str = "combined_4096x1024", scheme: int = W.EXPLICIT | W.TVD,
+                 steps: int = 0):
     """Mixed-precision forward with the FP64 adjoint under sqrt(N)
     checkpoints, and the gradient of the same loss through the FP64 forward
-    and adjoint as the reference."""
+    and adjoint as the reference.  steps > 0 shortens the run (for counter
+    collection; the configured run is the default)."""
     p, run = W.workload(name)
+    if steps > 0:
+        run["steps"] = steps
     f0 = W.initial_fields(p, run["seed"])
     Lm, gm, sm = _drag_grad(p, f0, run, scheme | W.MIXED)
     Lf, gf, sf = _drag_grad(p, f0, run, scheme)
@@ -419,6 +423,8 @@ def main():
     ap.add_argument("--combined-only", action="store_true",
                     help="run only the combined run (4096x1024) and print its JSON (profiling)")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D step")
+    ap.add_argument("--combined-steps", type=int, default=0,
+                    help="with --combined-only: steps of a shortened run (counter collection)")
     ap.add_argument("--three-d-only", action="store_true", help="run only the 3-D step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration)")
@@ -430,7 +436,7 @@ def main():
         print(json.dumps(run_adjoint()), flush=True)
         return
     if a.combined_only:
-        print(json.dumps(run_combined()), flush=True)
+        print(json.dumps(run_combined(steps=a.combined_steps)), flush=True)
         return
     if a.three_d_only:
         print(json.dumps(run_three_d()), flush=True)
