@@ -56,7 +56,7 @@ typedef struct {
 
 /* Create a solver (arrays copied).  hip_stream: a hipStream_t to order all
    work on, or NULL for a stream owned by the context.  The library allocates
-   its device memory (26 field arrays of (nz+1)(ny+1) rows of a padded x
+   its device memory (29 field arrays of (nz+5)(ny+5) rows of a padded x
    pitch).  Initial state: u = u_in (inlet/outlet in x) or 0, v = w = 0,
    p = p_in, T = T_in, with the boundary values imposed.  STS_EINVAL for an
    invalid setup (x WALLS, y or z INLET_OUTLET, n < 4, non-positive widths or

@@ -68,6 +68,7 @@ struct Work {
   double *rf[3];            // face densities
   double *qh[3], *dq[3];    // pseudo velocities and d
   double *cq[3], *cT, *cp;  // per-step constants
+  double *ge[3];            // Gamma on the cell edges along each direction
 };
 
 // ---------------------------------------------------------------------------
@@ -95,8 +96,9 @@ __device__ __forceinline__ double WLO(const P3 &P, int e, int i) { return P.wlo[
 __device__ __forceinline__ double WHI(const P3 &P, int e, int i) { return P.whi[e][i]; }
 __device__ __forceinline__ double IC(const P3 &P, int e, int i) { return P.ic[e][i]; }
 // store v at x and, in periodic directions, at the images of x within the
-// ghost layers (F: the face direction of a face array, -1 for a cell array)
-template <int F>
+// ghost layers (FM: bit e set where the array's index along e is a face
+// index, 0 for a cell array)
+template <int FM>
 __device__ void put(const P3 &P, double *a, const int x[3], double v) {
   const long m = lin(P, x[0], x[1], x[2]);
   a[m] = v;
@@ -106,7 +108,7 @@ __device__ void put(const P3 &P, double *a, const int x[3], double v) {
     no[e] = 1;
     o[e][0] = 0;
     if (P.per[e]) {
-      if (x[e] <= (F == e ? G : G - 1)) o[e][no[e]++] = P.n[e];
+      if (x[e] <= (((FM >> e) & 1) ? G : G - 1)) o[e][no[e]++] = P.n[e];
       if (x[e] >= P.n[e] - G) o[e][no[e]++] = -P.n[e];
     }
   }
@@ -183,7 +185,11 @@ __device__ __forceinline__ double hmean(double dl, double gl, double dr, double 
 }
 __device__ __forceinline__ double hmean2(double a, double b) { return ddiv(2.0 * a * b, a + b); }
 
-// thread -> point of an index space of extent (X, Y, Z)
+// thread -> point of an index space of extent (X, Y, Z): one block per
+// BX x BY tile of an x-y plane, blockIdx.z the plane.  (Dealing each XCD a
+// contiguous slab of planes, as the 2-D pass deals tile bands, was measured
+// and made no kernel faster: these kernels are bound by their per-thread
+// load chains, not by L2 misses.)
 __device__ __forceinline__ bool point(int X, int Y, int Z, int x[3]) {
   x[0] = blockIdx.x * BX + threadIdx.x;
   x[1] = blockIdx.y * BY + threadIdx.y;
@@ -199,8 +205,8 @@ __global__ __launch_bounds__(NTB) void k3_cell(P3 P, Fld S, Work Wk) {
   if (!point(P.n[0], P.n[1], P.n[2], x)) return;
   const long m = lin(P, x[0], x[1], x[2]);
   const double p = S.q[3][m], T = S.q[4][m];
-  put<-1>(P, Wk.rho, x, ddiv(p, T));
-  put<-1>(P, Wk.gam, x, sqrt(T));
+  put<0>(P, Wk.rho, x, ddiv(p, T));
+  put<0>(P, Wk.gam, x, sqrt(T));
 }
 
 template <int A, bool TV>
@@ -224,7 +230,7 @@ __global__ __launch_bounds__(NTB) void k3_rf(P3 P, Fld S, Work Wk) {
       r += psi_s(P, A, fa, cv(P, Wk.rho, f, A, -2), rl, rr, cv(P, Wk.rho, f, A, 1), vel) *
            (rr - rl);
   }
-  put<A>(P, Wk.rf[A], f, r);
+  put<1 << A>(P, Wk.rf[A], f, r);
 }
 
 // mass flux through the e-face of cell x on side s (0 low, 1 high)
@@ -374,7 +380,7 @@ __global__ __launch_bounds__(NTB) void k3_energy(P3 P, Fld S, Work Wk, double *T
   phi -= 2.0 / 3.0 * div * div;
   const double src = P.C2 * gP * phi * dV + P.C3 * cv(P, S.q[3], x) * div * dV;
   const long m = lin(P, x[0], x[1], x[2]);
-  put<-1>(P, Tout, x, ddiv(P.dt * (sn + src) + Wk.cT[m], a0));
+  put<0>(P, Tout, x, ddiv(P.dt * (sn + src) + Wk.cT[m], a0));
 }
 
 // ---------------------------------------------------------------------------
@@ -385,33 +391,52 @@ __global__ __launch_bounds__(NTB) void k3_energy(P3 P, Fld S, Work Wk, double *T
 // four cells around it; 0 on a wall (it multiplies wall-normal velocities
 // only), sqrt(T_in) at the inlet, the last cells along A at the outlet
 template <int A>
-__device__ double gam_edge(const P3 &P, const Work &Wk, int b, const int f[3], int s) {
-  const int bf = f[b] + s;
-  if (!P.per[b] && (bf == 0 || bf == P.n[b])) {
-    if (b == 0 && P.io) {
-      if (bf == 0) return P.sqT_in;
-      int l[3] = {f[0], f[1], f[2]};
-      l[A] -= 1;
-      l[b] = P.n[b] - 1;
-      int r[3] = {f[0], f[1], f[2]};
-      r[b] = P.n[b] - 1;
-      return WLO(P, A, f[A]) * cv(P, Wk.gam, l) + WHI(P, A, f[A]) * cv(P, Wk.gam, r);
-    }
-    return 0.0;
-  }
+__device__ __forceinline__ double gam_edge(const P3 &P, const Work &Wk, int b, const int f[3],
+                                           int s) {
+  return cv(P, Wk.ge[3 - A - b], f, b, s);
+}
+
+// Gamma on the edges along direction C (k3_edge): at the a-face and b-face
+// positions of the edge ({a, b} the two other directions) and cell index
+// along C; bilinear in the four cells around it.  An edge on one boundary:
+// 0 on a wall (it multiplies wall-normal velocities only), sqrt(T_in) at the
+// inlet, at the outlet the last cells interpolated along the other
+// direction; an edge on two boundaries is never used (0).
+template <int C>
+__global__ __launch_bounds__(NTB) void k3_edge(P3 P, Work Wk) {
+  constexpr int a = C == 0 ? 1 : 0, b = C == 2 ? 1 : 2;
+  int x[3];
+  if (!point(P.n[0] + (C != 0), P.n[1] + (C != 1), P.n[2] + (C != 2), x)) return;
+  if ((P.per[a] && x[a] == P.n[a]) || (P.per[b] && x[b] == P.n[b])) return;  // images
+  const bool ba = !P.per[a] && (x[a] == 0 || x[a] == P.n[a]);
+  const bool bb = !P.per[b] && (x[b] == 0 || x[b] == P.n[b]);
   double g = 0.0;
-#pragma unroll
-  for (int ia = 0; ia < 2; ia++)
-#pragma unroll
-    for (int ib = 0; ib < 2; ib++) {
-      int y[3] = {f[0], f[1], f[2]};
-      y[A] = f[A] - 1 + ia;
-      y[b] = bf - 1 + ib;
-      const double wa = ia ? WHI(P, A, f[A]) : WLO(P, A, f[A]);
-      const double wb = ib ? WHI(P, b, bf) : WLO(P, b, bf);
-      g += wa * wb * cv(P, Wk.gam, y);
+  if (ba != bb) {
+    const int d = ba ? a : b, o = ba ? b : a;
+    if (d == 0 && P.io) {
+      if (x[d] == 0) {
+        g = P.sqT_in;
+      } else {
+        int l[3] = {x[0], x[1], x[2]}, r[3] = {x[0], x[1], x[2]};
+        l[d] = r[d] = P.n[d] - 1;
+        l[o] -= 1;
+        g = WLO(P, o, x[o]) * cv(P, Wk.gam, l) + WHI(P, o, x[o]) * cv(P, Wk.gam, r);
+      }
     }
-  return g;
+  } else if (!ba) {
+#pragma unroll
+    for (int ia = 0; ia < 2; ia++)
+#pragma unroll
+      for (int ib = 0; ib < 2; ib++) {
+        int y[3] = {x[0], x[1], x[2]};
+        y[a] = x[a] - 1 + ia;
+        y[b] = x[b] - 1 + ib;
+        const double wa = ia ? WHI(P, a, x[a]) : WLO(P, a, x[a]);
+        const double wb = ib ? WHI(P, b, x[b]) : WLO(P, b, x[b]);
+        g += wa * wb * cv(P, Wk.gam, y);
+      }
+  }
+  put<(1 << a) | (1 << b)>(P, Wk.ge[C], x, g);
 }
 
 // neighbour of component A at face f across side s (-1, +1) of direction b
@@ -487,8 +512,8 @@ __global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
   const double *q = S.q[A];
   const double qP = q[m];
   if (!solved(P, A, f[A])) {
-    put<A>(P, Wk.qh[A], f, qP);
-    put<A>(P, Wk.dq[A], f, 0.0);
+    put<1 << A>(P, Wk.qh[A], f, qP);
+    put<1 << A>(P, Wk.dq[A], f, 0.0);
     return;
   }
   int l[3] = {f[0], f[1], f[2]};
@@ -583,8 +608,8 @@ __global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
   const double a0 = sa + conv + M * P.idt;
   const double b = Wk.cq[A][m] + P.B * X;
   const double ia0 = drcp(a0);
-  put<A>(P, Wk.qh[A], f, (sn + b) * ia0);
-  put<A>(P, Wk.dq[A], f, P.A * Ap * ia0);
+  put<1 << A>(P, Wk.qh[A], f, (sn + b) * ia0);
+  put<1 << A>(P, Wk.dq[A], f, P.A * Ap * ia0);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,7 +638,7 @@ __global__ __launch_bounds__(NTB) void k3_pressure(P3 P, Fld S, Work Wk, const d
     sb += bH - bL;
   }
   const double a0 = ddiv(dV, Tn[m]) + sa * P.dt;
-  put<-1>(P, pout, x, ddiv(sap * P.dt + (Wk.cp[m] - sb * P.dt), a0));
+  put<0>(P, pout, x, ddiv(sap * P.dt + (Wk.cp[m] - sb * P.dt), a0));
 }
 
 template <int A>
@@ -640,7 +665,7 @@ __global__ __launch_bounds__(NTB) void k3_velocity(P3 P, Fld S, Work Wk, const d
   } else {
     qn = S.q[A][m];  // inlet u_in, wall faces 0
   }
-  put<A>(P, qout, f, qn);
+  put<1 << A>(P, qout, f, qn);
 }
 
 // ---------------------------------------------------------------------------
@@ -837,6 +862,12 @@ void launch_pass3d(sts3_ctx *c, const Fld &O, const Fld &N, bool last) {
   const dim3 b(BX, BY), gc = grid_of(c, c->n[0], c->n[1], c->n[2]);
   hipLaunchKernelGGL(k3_cell, gc, b, 0, c->stream, c->P, O, c->Wk);
   launch_rf(c, O, TV);
+  hipLaunchKernelGGL((k3_edge<0>), grid_of(c, c->n[0], c->n[1] + 1, c->n[2] + 1), b, 0, c->stream,
+                     c->P, c->Wk);
+  hipLaunchKernelGGL((k3_edge<1>), grid_of(c, c->n[0] + 1, c->n[1], c->n[2] + 1), b, 0, c->stream,
+                     c->P, c->Wk);
+  hipLaunchKernelGGL((k3_edge<2>), grid_of(c, c->n[0] + 1, c->n[1] + 1, c->n[2]), b, 0, c->stream,
+                     c->P, c->Wk);
   hipLaunchKernelGGL((k3_energy<IM, TV>), gc, b, 0, c->stream, c->P, O, c->Wk, N.q[4]);
   hipLaunchKernelGGL((k3_mom<0, IM, TV>), grid_face(c, 0), b, 0, c->stream, c->P, O, c->Wk);
   hipLaunchKernelGGL((k3_mom<1, IM, TV>), grid_face(c, 1), b, 0, c->stream, c->P, O, c->Wk);
@@ -938,7 +969,7 @@ void from_padded(const sts3_ctx *c, int f, const std::vector<double> &pad, doubl
         dense[((size_t)k * D[1] + j) * D[0] + i] =
             pad[(size_t)(k + G) * c->sz + (size_t)(j + G) * c->sy + (size_t)(i + G)];
 }
-constexpr int NFIELDS = 26;  // 2 states x 5, rho, gam, rf x3, qh x3, dq x3, cq x3, cT, cp
+constexpr int NFIELDS = 29;  // 2 states x 5, rho, gam, rf x3, qh x3, dq x3, cq x3, cT, cp, ge x3
 }  // namespace
 
 extern "C" sts_status sts3_device_bytes(const int n[3], size_t *bytes) {
@@ -1032,6 +1063,7 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
   for (int a = 0; a < 3; a++) c->Wk.cq[a] = fields[k++];
   c->Wk.cT = fields[k++];
   c->Wk.cp = fields[k++];
+  for (int a = 0; a < 3; a++) c->Wk.ge[a] = fields[k++];
   for (int e = 0; e < 3; e++)
     if (!alloc(sizeof(double) * 5 * (c->n[e] + 2 * G), (void **)&c->d_d[e])) {
       sts3_destroy(c);

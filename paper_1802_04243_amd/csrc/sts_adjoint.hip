@@ -213,6 +213,13 @@ __device__ __forceinline__ bool elem(const Params &P, int &i, int &j) {
 // directly.  Like the plain scatter, the result is exact up to the order of
 // the sums.
 constexpr int TW = 32, TH = 8;
+// tile of block b of n: blocks are dealt round-robin to the 8 XCDs (b mod
+// 8); each XCD gets one contiguous band of tiles, so that the halo rows a
+// tile shares with its neighbours are read through the same L2
+__device__ __forceinline__ int tile_of_block(int b, int n) {
+  const int k = b & 7, m = b >> 3, q = n >> 3, r = n & 7;
+  return k * q + (k < r ? k : r) + m;
+}
 static_assert(TW * TH == AB, "one element per thread");
 typedef __attribute__((address_space(3))) double lds_double;
 template <int NA, int R, bool EXCL = true>
@@ -223,8 +230,9 @@ struct Tiled {
   int x0, y0;        // tile origin
   __device__ void begin(const Params &P, int &i, int &j) {
     const int ntx = (P.nx + 1 + TW - 1) / TW;
-    x0 = (int)(blockIdx.x % ntx) * TW;
-    y0 = (int)(blockIdx.x / ntx) * TH;
+    const int tile = tile_of_block(blockIdx.x, gridDim.x);
+    x0 = (tile % ntx) * TW;
+    y0 = (tile / ntx) * TH;
     i = x0 + (int)threadIdx.x % TW;
     j = y0 + (int)threadIdx.x / TW;
     for (int e = threadIdx.x; e < NA * WN; e += AB) w[e] = 0.0;
@@ -315,7 +323,8 @@ __global__ __launch_bounds__(AB) void k_adj_front(const Params P, const State o,
                                                   const AdjTmp A) {
   __shared__ double sq0[CH * CW], sq1[CH * CW];
   const int ntx = (P.nx + 1 + TW - 1) / TW;
-  const int x0 = (int)(blockIdx.x % ntx) * TW, y0 = (int)(blockIdx.x / ntx) * TH;
+  const int tile = tile_of_block(blockIdx.x, gridDim.x);
+  const int x0 = (tile % ntx) * TW, y0 = (tile / ntx) * TH;
   for (int c = threadIdx.x; c < CW * CH; c += AB) {
     const int ci = x0 - 1 + c % CW, cj = y0 - 1 + c / CW;
     double lN = 0.0, la0 = 0.0;

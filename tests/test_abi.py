@@ -129,7 +129,7 @@ def test_3d_null_arguments_and_device_bytes():
     L.sts3_destroy(None)
     b = C.c_size_t()
     assert L.sts3_device_bytes((C.c_int * 3)(64, 32, 32), C.byref(b)) == sts.STS_OK
-    # 26 FP64 arrays of (nz+1+4) (ny+1+4) rows of a pitch of 96 doubles for
+    # 29 FP64 arrays of (nz+1+4) (ny+1+4) rows of a pitch of 96 doubles for
     # nx = 64 (two ghost layers at each end of every direction)
-    assert b.value == 26 * 8 * 96 * 37 * 37
+    assert b.value == 29 * 8 * 96 * 37 * 37
     assert L.sts3_device_bytes((C.c_int * 3)(64, 3, 32), C.byref(b)) == sts.STS_EINVAL
