@@ -40,8 +40,8 @@ __device__ __forceinline__ bool fl(const Params &P, int i, int j) {
 }
 // geometry: q = 0 width, 1 inverse width, 2 face sum, 3 its inverse,
 // 4/5 weight of the low/high cell at the face
-__device__ __forceinline__ double gx(const Params &P, int q, int i) { return P.gx_[q][i + XPAD]; }
-__device__ __forceinline__ double gy(const Params &P, int q, int j) { return P.gy_[q][j + XPAD]; }
+__device__ __forceinline__ double gx(const Params &P, int q, int i) { return P.gx6[6 * (i + XPAD) + q]; }
+__device__ __forceinline__ double gy(const Params &P, int q, int j) { return P.gy6[6 * (j + XPAD) + q]; }
 __device__ __forceinline__ double rho(const Params &P, const State &o, int i, int j) {
   return at(o.p, P, i, j) / at(o.T, P, i, j);
 }
@@ -162,7 +162,7 @@ template <class Src>
 __device__ double gamc(const Params &P, const Src &o, int i, int j) {
   if (j <= 0 || j >= P.ny) return 0.0;
   const double ws = gy(P, 4, j), wn = gy(P, 5, j);
-  if (i == 0) return ws * P.sq_T_in[j - 1] + wn * P.sq_T_in[j];
+  if (i == 0) return ws * P.inl[4 * (j - 1) + 2] + wn * P.inl[4 * (j) + 2];
   if (i == P.nx) return ws * gam(P, o, i - 1, j - 1) + wn * gam(P, o, i - 1, j);
   const double wl = gx(P, 4, i), wr = gx(P, 5, i);
   return ws * (wl * gam(P, o, i - 1, j - 1) + wr * gam(P, o, i, j - 1)) +
@@ -184,9 +184,11 @@ __device__ void gamc_adj(S &sk, int slot, const Params &P, int i, int j, double 
   sk.add(slot, P, i, j, l * wn * wr);
 }
 // d sqrt(Tw at u-face i) / d Tw of the two neighbouring columns
-__device__ void sqtwu_adj(const Params &P, const double *sqtwu, double *gtw, int i, double l) {
+// w: 0 bottom wall, 1 top wall (sqrt of its temperature at u-face i in
+// P.wu[2 i + w])
+__device__ void sqtwu_adj(const Params &P, int w, double *gtw, int i, double l) {
   const int L = i - 1 < 0 ? 0 : i - 1, R = i > P.nx - 1 ? P.nx - 1 : i;
-  const double d = l / (2.0 * sqtwu[i]);
+  const double d = l / (2.0 * P.wu[2 * i + w]);
   unsafeAtomicAdd(gtw + L, d * gx(P, 4, i));
   unsafeAtomicAdd(gtw + R, d * gx(P, 5, i));
 }
@@ -464,9 +466,9 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   double dWr = 0, dEr = 0, dSr = 0, dNr = 0;
   double x;
   if (i == 0) {
-    nW = P.T_in[j];
+    nW = P.inl[4 * (j) + 1];
     const double K = P.C1 * dyj * (2.0 * idx);
-    DW = K * hmean2_d(gP, P.sq_T_in[j], dWP, x);
+    DW = K * hmean2_d(gP, P.inl[4 * (j) + 2], dWP, x);
     dWP *= K;
   } else {
     nW = at(o.T, P, i - 1, j);
@@ -503,13 +505,13 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   }
   if (j == 0) {
     if (P.wtype0 == 0) {
-      nS = P.Tw0[i];
+      nS = P.wl[4 * (i)];
       const double K = P.C1 * dxi * (2.0 * idy);
-      DS = K * hmean2_d(gP, P.sq_Tw0[i], dSP, dSw);
+      DS = K * hmean2_d(gP, P.wl[4 * (i) + 2], dSP, dSw);
       dSP *= K;
       dSw *= K;
     } else if (SJ && P.wtype0 == 2) {
-      nS = P.Tw0[i];
+      nS = P.wl[4 * (i)];
       DS = jwall_d(P.C1 * dxi, gP, dyj, P.kt, rP, dSP, dSr);
     } else {
       nS = TP;
@@ -532,13 +534,13 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   }
   if (j == P.ny - 1) {
     if (P.wtype1 == 0) {
-      nN = P.Tw1[i];
+      nN = P.wl[4 * (i) + 1];
       const double K = P.C1 * dxi * (2.0 * idy);
-      DN = K * hmean2_d(gP, P.sq_Tw1[i], dNP, dNw);
+      DN = K * hmean2_d(gP, P.wl[4 * (i) + 3], dNP, dNw);
       dNP *= K;
       dNw *= K;
     } else if (SJ && P.wtype1 == 2) {
-      nN = P.Tw1[i];
+      nN = P.wl[4 * (i) + 1];
       DN = jwall_d(P.C1 * dxi, gP, dyj, P.kt, rP, dNP, dNr);
     } else {
       nN = TP;
@@ -580,7 +582,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   }
   if (j == 0) {
     if (P.wtype0 == 0) {
-      unsafeAtomicAdd(gtw0 + i, lnum * dt * DS + lDS * dSw / (2.0 * P.sq_Tw0[i]));
+      unsafeAtomicAdd(gtw0 + i, lnum * dt * DS + lDS * dSw / (2.0 * P.wl[4 * (i) + 2]));
     } else if (SJ && P.wtype0 == 2) {
       unsafeAtomicAdd(gtw0 + i, lnum * dt * DS);
     } else {
@@ -592,7 +594,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   }
   if (j == P.ny - 1) {
     if (P.wtype1 == 0) {
-      unsafeAtomicAdd(gtw1 + i, lnum * dt * DN + lDN * dNw / (2.0 * P.sq_Tw1[i]));
+      unsafeAtomicAdd(gtw1 + i, lnum * dt * DN + lDN * dNw / (2.0 * P.wl[4 * (i) + 3]));
     } else if (SJ && P.wtype1 == 2) {
       unsafeAtomicAdd(gtw1 + i, lnum * dt * DN);
     } else {
@@ -730,7 +732,7 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
   if (j == 0) {
     if (P.wtype0 == 0) {
       uS = P.wu0; kS = 0; dS = 1;
-      DS = B * 0.5 * (gnode + P.sq_Twu0[i]) * len * (2.0 * idy);
+      DS = B * 0.5 * (gnode + P.wu[2 * (i)]) * len * (2.0 * idy);
     } else if (SJ && P.wtype0 == 2) {
       uS = P.wu0; kS = 0; dS = 4;
       DS = jwall_d(B * len, gnode, dyj, P.kz, rnode, jSg, jSr);
@@ -748,7 +750,7 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
   if (j == P.ny - 1) {
     if (P.wtype1 == 0) {
       uN = P.wu1; kN = 0; dN = 1;
-      DN = B * 0.5 * (gnode + P.sq_Twu1[i]) * len * (2.0 * idy);
+      DN = B * 0.5 * (gnode + P.wu[2 * (i) + 1]) * len * (2.0 * idy);
     } else if (SJ && P.wtype1 == 2) {
       uN = P.wu1; kN = 0; dN = 4;
       DN = jwall_d(B * len, gnode, dyj, P.kz, rnode, jNg, jNr);
@@ -796,14 +798,14 @@ __device__ void uhat_item(const Params &P, const State o, const Cache cc, const 
   if (dS == 1) {
     const double q = laS * B * 0.5 * len * (2.0 * idy);
     lgn += q;
-    sqtwu_adj(P, P.sq_Twu0, gtw0, i, q);
+    sqtwu_adj(P, 0, gtw0, i, q);
   } else if (dS == 2) lgn += laS * B * 0.5 * len * (2.0 * idy);
   else if (dS == 3) lgcS += laS * B * gx(P, 2, i) * gy(P, 3, j);
   else if (dS == 4) { lgn += laS * jSg; lrn += laS * jSr; }
   if (dN == 1) {
     const double q = laN * B * 0.5 * len * (2.0 * idy);
     lgn += q;
-    sqtwu_adj(P, P.sq_Twu1, gtw1, i, q);
+    sqtwu_adj(P, 1, gtw1, i, q);
   } else if (dN == 2) lgn += laN * B * 0.5 * len * (2.0 * idy);
   else if (dN == 3) lgcN += laN * B * gx(P, 2, i) * gy(P, 3, j + 1);
   else if (dN == 4) { lgn += laN * jNg; lrn += laN * jNr; }
@@ -1067,7 +1069,7 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
     const double lt = lCT * dt;  // adjoint of T^exp
     if (lt != 0.0) {
       const bool inl = i == 0, outl = i == P.nx - 1, bot = j == 0, top = j == P.ny - 1;
-      const double TW = inl ? P.T_in[j] : at(m.T, P, i - 1, j);
+      const double TW = inl ? P.inl[4 * (j) + 1] : at(m.T, P, i - 1, j);
       const double TE = outl ? TP : at(m.T, P, i + 1, j);
       const double TS = bot ? TP : at(m.T, P, i, j - 1);
       const double TN = top ? TP : at(m.T, P, i, j + 1);
@@ -1402,7 +1404,7 @@ __global__ __launch_bounds__(AB) void k_face_densities(const Params P, const Sta
   if (j < P.ny) {
     const double uf = at(m.u, P, i, j);
     double r;
-    if (i == 0) r = uf > 0.0 ? P.rho_in[j] : rho(P, m, 0, j);
+    if (i == 0) r = uf > 0.0 ? P.inl[4 * (j) + 3] : rho(P, m, 0, j);
     else if (i == P.nx) r = rho(P, m, P.nx - 1, j);
     else {
       const double rl = rho(P, m, i - 1, j), rr = rho(P, m, i, j);

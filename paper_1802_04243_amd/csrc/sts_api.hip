@@ -376,21 +376,38 @@ sts_status build(sts_ctx *c, const sts_bc *bc) {
     sqTwu0[i] = sqrt(wl * c->Tw[0][l] + wr * c->Tw[0][r]);
     sqTwu1[i] = sqrt(wl * c->Tw[1][l] + wr * c->Tw[1][r]);
   }
-  size_t o_gx[6], o_gy[6];
-  for (int q = 0; q < 6; q++) o_gx[q] = put(gxv[q]);
-  for (int q = 0; q < 6; q++) o_gy[q] = put(gyv[q]);
-  size_t o_uin = put(c->u_in), o_tin = put(c->T_in),
-         o_sqtin = put(sqTin), o_rhoin = put(rhoin), o_tw0 = put(c->Tw[0]), o_tw1 = put(c->Tw[1]),
-         o_sqtw0 = put(sqTw0), o_sqtw1 = put(sqTw1), o_sqtwu0 = put(sqTwu0), o_sqtwu1 = put(sqTwu1);
+  auto interleave = [](const std::vector<double> *g) {
+    std::vector<double> a(6 * g[0].size());
+    for (size_t i = 0; i < g[0].size(); i++)
+      for (int q = 0; q < 6; q++) a[6 * i + q] = g[q][i];
+    return a;
+  };
+  const size_t o_gx = put(interleave(gxv)), o_gy = put(interleave(gyv));
+  std::vector<double> inl(4 * (size_t)ny), wl(4 * (size_t)nx), wu(2 * (size_t)(nx + 1));
+  for (int j = 0; j < ny; j++) {
+    inl[4 * j] = c->u_in[j];
+    inl[4 * j + 1] = c->T_in[j];
+    inl[4 * j + 2] = sqTin[j];
+    inl[4 * j + 3] = rhoin[j];
+  }
+  for (int i = 0; i < nx; i++) {
+    wl[4 * i] = c->Tw[0][i];
+    wl[4 * i + 1] = c->Tw[1][i];
+    wl[4 * i + 2] = sqTw0[i];
+    wl[4 * i + 3] = sqTw1[i];
+  }
+  for (int i = 0; i <= nx; i++) {
+    wu[2 * i] = sqTwu0[i];
+    wu[2 * i + 1] = sqTwu1[i];
+  }
+  const size_t o_inl = put(inl), o_wl = put(wl), o_wu = put(wu);
   HIPCHK(hipMemcpyAsync(small, hs.data(), hs.size() * 8, hipMemcpyHostToDevice, c->stream));
   const double *sd = (const double *)small;
-  for (int q = 0; q < 6; q++) {
-    P.gx_[q] = sd + o_gx[q];
-    P.gy_[q] = sd + o_gy[q];
-  }
-  P.u_in = sd + o_uin; P.T_in = sd + o_tin; P.sq_T_in = sd + o_sqtin; P.rho_in = sd + o_rhoin;
-  P.Tw0 = sd + o_tw0; P.Tw1 = sd + o_tw1; P.sq_Tw0 = sd + o_sqtw0; P.sq_Tw1 = sd + o_sqtw1;
-  P.sq_Twu0 = sd + o_sqtwu0; P.sq_Twu1 = sd + o_sqtwu1;
+  P.gx6 = sd + o_gx;
+  P.gy6 = sd + o_gy;
+  P.inl = sd + o_inl;
+  P.wl = sd + o_wl;
+  P.wu = sd + o_wu;
   unsigned char *clean_dev = (unsigned char *)(small + align_up(hs.size() * 8, 256));
 
   // fluid mask with frame

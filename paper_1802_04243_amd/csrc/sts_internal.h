@@ -51,14 +51,19 @@ struct Params {
   // slip / jump length times rho of the slip-jump surfaces (eqs pl38, pl39):
   // zeta = kz / rho, tau = kt / rho
   double kz, kt;
-  // geometry per column i (index i + XPAD, wrapped or clamped outside the
-  // domain): [0] dx_i, [1] 1/dx_i; per x-face i (between cells i-1 and i):
-  // [2] s = dx_{i-1} + dx_i, [3] 1/s, [4] dx_i/s (weight of cell i-1),
-  // [5] dx_{i-1}/s (weight of cell i).  The same in y.
-  const double *gx_[6], *gy_[6];
-  const double *u_in, *T_in, *sq_T_in, *rho_in;  // [ny]
-  const double *Tw0, *Tw1, *sq_Tw0, *sq_Tw1;     // [nx] per cell column
-  const double *sq_Twu0, *sq_Twu1;               // [nx+1] at u-face x
+  // geometry per column i, six values interleaved at gx6[6 (i + XPAD) + q]
+  // (wrapped or clamped outside the domain): [0] dx_i, [1] 1/dx_i; per
+  // x-face i (between cells i-1 and i): [2] s = dx_{i-1} + dx_i, [3] 1/s,
+  // [4] dx_i/s (weight of cell i-1), [5] dx_{i-1}/s (weight of cell i).
+  // The same in y.  One pointer per direction keeps the kernels' scalar
+  // registers free (six pointers each spilled them into vector lanes).
+  const double *gx6, *gy6;
+  // boundary data, interleaved like the geometry: per row j of the inlet
+  // inl[4 j + q], q = u_in, T_in, sqrt(T_in), rho_in = p_in / T_in; per cell
+  // column i of the walls wl[4 i + q], q = bottom T, top T, their square
+  // roots; per u-face i wu[2 i + q], q = sqrt of the bottom, top wall T at
+  // the face's x
+  const double *inl, *wl, *wu;
   const unsigned char *fl;   // 1 = fluid cell, frame = 0; cell layout
   const unsigned char *clean; // [tiles] 1 = no boundary rule in the window
 };

@@ -229,11 +229,11 @@ __device__ void load_window(Lds &s, const Params &P, const State o, int x0,
   if (gcol) {
     c0 = win_ci(P, x0, t);
     c1 = win_ui(P, x0, t);
-    for (int q = 0; q < 6; q++) gq[q] = P.gx_[q][c0 + XPAD];
+    for (int q = 0; q < 6; q++) gq[q] = P.gx6[6 * (c0 + XPAD) + q];
   } else if (grow) {
     c0 = win_cj(P, y0, t - LW);
     c1 = win_vj(P, y0, t - LW);
-    for (int q = 0; q < 6; q++) gq[q] = P.gy_[q][c0 + XPAD];
+    for (int q = 0; q < 6; q++) gq[q] = P.gy6[6 * (c0 + XPAD) + q];
   }
 #pragma unroll
   for (int m = 0; m < WPT; m++) {
@@ -326,7 +326,7 @@ __device__ double rho_xface(const Lds &s, const Params &P, int i, int j,
                             int gi, int gj) {
   const double uf = U_(i, j);
   if (!CL && !P.per) {
-    if (gi == 0) return uf > 0.0 ? P.rho_in[clampi(gj, 0, P.ny - 1)] : R_(i, j);
+    if (gi == 0) return uf > 0.0 ? P.inl[4 * (clampi(gj, 0, P.ny - 1)) + 3] : R_(i, j);
     if (gi == P.nx) return R_(i - 1, j);
   }
   const double rl = R_(i - 1, j), rr = R_(i, j);
@@ -363,7 +363,7 @@ __device__ double gam_c(const Lds &s, const Params &P, int i, int j, int gi,
   if (!CL && (gj <= 0 || gj >= P.ny)) return 0.0;
   const double ws = WLY_(j), wn = WRY_(j);
   if (!CL && !P.per) {
-    if (gi == 0) return ws * P.sq_T_in[gj - 1] + wn * P.sq_T_in[gj];
+    if (gi == 0) return ws * P.inl[4 * (gj - 1) + 2] + wn * P.inl[4 * (gj) + 2];
     if (gi == P.nx) return ws * G_(i - 1, j - 1) + wn * G_(i - 1, j);
   }
   const double wl = WLX_(i), wr = WRX_(i);
@@ -396,8 +396,8 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   const double gP = G_(i, j), TP = T_(i, j);
   double nW, nE, nS, nN, DW, DE, DS, DN;
   if (!CL && !P.per && gi == 0) {  // inlet: T_in on the face
-    nW = P.T_in[gj];
-    DW = P.C1 * hmean2(gP, P.sq_T_in[gj]) * dyj * (2.0 * IDX_(i));
+    nW = P.inl[4 * (gj) + 1];
+    DW = P.C1 * hmean2(gP, P.inl[4 * (gj) + 2]) * dyj * (2.0 * IDX_(i));
   } else {
     nW = T_(i - 1, j);
     if (!CL && !FL_(i - 1, j))
@@ -419,10 +419,10 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   }
   if (!CL && gj == 0) {
     if (P.wtype0 == 0) {
-      nS = P.Tw0[wall_c(s, P, i)];
-      DS = P.C1 * hmean2(gP, P.sq_Tw0[wall_c(s, P, i)]) * dxi * (2.0 * IDY_(j));
+      nS = P.wl[4 * (wall_c(s, P, i))];
+      DS = P.C1 * hmean2(gP, P.wl[4 * (wall_c(s, P, i)) + 2]) * dxi * (2.0 * IDY_(j));
     } else if ((SJ && P.wtype0 == 2)) {
-      nS = P.Tw0[wall_c(s, P, i)];
+      nS = P.wl[4 * (wall_c(s, P, i))];
       DS = P.C1 * gP * dxi * iwall(dyj, P.kt, R_(i, j));
     } else {
       nS = TP;
@@ -438,10 +438,10 @@ __device__ double t_update(const Lds &s, const Params &P, int i, int j,
   }
   if (!CL && gj == P.ny - 1) {
     if (P.wtype1 == 0) {
-      nN = P.Tw1[wall_c(s, P, i)];
-      DN = P.C1 * hmean2(gP, P.sq_Tw1[wall_c(s, P, i)]) * dxi * (2.0 * IDY_(j));
+      nN = P.wl[4 * (wall_c(s, P, i)) + 1];
+      DN = P.C1 * hmean2(gP, P.wl[4 * (wall_c(s, P, i)) + 3]) * dxi * (2.0 * IDY_(j));
     } else if ((SJ && P.wtype1 == 2)) {
-      nN = P.Tw1[wall_c(s, P, i)];
+      nN = P.wl[4 * (wall_c(s, P, i)) + 1];
       DN = P.C1 * gP * dxi * iwall(dyj, P.kt, R_(i, j));
     } else {
       nN = TP;
@@ -542,7 +542,7 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   if (!CL && gj == 0) {
     if (P.wtype0 == 0) {
       uS = P.wu0;
-      DS = P.B * 0.5 * (gnode + P.sq_Twu0[wall_u(s, P, i)]) * len * (2.0 * IDY_(j));
+      DS = P.B * 0.5 * (gnode + P.wu[2 * (wall_u(s, P, i))]) * len * (2.0 * IDY_(j));
     } else if ((SJ && P.wtype0 == 2)) {
       uS = P.wu0;
       DS = P.B * gnode * len * iwall(dyj, P.kz, WLX_(i) * rl + WRX_(i) * rr);
@@ -561,7 +561,7 @@ __device__ void u_pseudo(const Lds &s, const Params &P, int i, int j, int gi,
   if (!CL && gj == P.ny - 1) {
     if (P.wtype1 == 0) {
       uN = P.wu1;
-      DN = P.B * 0.5 * (gnode + P.sq_Twu1[wall_u(s, P, i)]) * len * (2.0 * IDY_(j));
+      DN = P.B * 0.5 * (gnode + P.wu[2 * (wall_u(s, P, i)) + 1]) * len * (2.0 * IDY_(j));
     } else if ((SJ && P.wtype1 == 2)) {
       uN = P.wu1;
       DN = P.B * gnode * len * iwall(dyj, P.kz, WLX_(i) * rl + WRX_(i) * rr);
@@ -729,7 +729,7 @@ __device__ float gam_c_f(const Lds &s, const Params &P, int i, int j, int gi,
   if (!CL && (gj <= 0 || gj >= P.ny)) return 0.0f;
   const float ws = F_(WLY_(j)), wn = F_(WRY_(j));
   if (!CL && !P.per) {
-    if (gi == 0) return ws * F_(P.sq_T_in[gj - 1]) + wn * F_(P.sq_T_in[gj]);
+    if (gi == 0) return ws * F_(P.inl[4 * (gj - 1) + 2]) + wn * F_(P.inl[4 * (gj) + 2]);
     if (gi == P.nx) return ws * F_(G_(i - 1, j - 1)) + wn * F_(G_(i - 1, j));
   }
   const float wl = F_(WLX_(i)), wr = F_(WRX_(i));
@@ -747,8 +747,8 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
   double nW, nE, nS, nN;
   float DW, DE, DS, DN;
   if (!CL && !P.per && gi == 0) {
-    nW = P.T_in[gj];
-    DW = C1 * hmean2_f(gP, F_(P.sq_T_in[gj])) * dyj * (2.0f * F_(IDX_(i)));
+    nW = P.inl[4 * (gj) + 1];
+    DW = C1 * hmean2_f(gP, F_(P.inl[4 * (gj) + 2])) * dyj * (2.0f * F_(IDX_(i)));
   } else {
     nW = T_(i - 1, j);
     if (!CL && !FL_(i - 1, j))
@@ -770,10 +770,10 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
   }
   if (!CL && gj == 0) {
     if (P.wtype0 == 0) {
-      nS = P.Tw0[wall_c(s, P, i)];
-      DS = C1 * hmean2_f(gP, F_(P.sq_Tw0[wall_c(s, P, i)])) * dxi * (2.0f * F_(IDY_(j)));
+      nS = P.wl[4 * (wall_c(s, P, i))];
+      DS = C1 * hmean2_f(gP, F_(P.wl[4 * (wall_c(s, P, i)) + 2])) * dxi * (2.0f * F_(IDY_(j)));
     } else if ((SJ && P.wtype0 == 2)) {
-      nS = P.Tw0[wall_c(s, P, i)];
+      nS = P.wl[4 * (wall_c(s, P, i))];
       DS = C1 * gP * dxi * iwall_f(dyj, F_(P.kt), F_(R_(i, j)));
     } else {
       nS = TP;
@@ -789,10 +789,10 @@ __device__ double t_update_mx(const Lds &s, const Params &P, int i, int j,
   }
   if (!CL && gj == P.ny - 1) {
     if (P.wtype1 == 0) {
-      nN = P.Tw1[wall_c(s, P, i)];
-      DN = C1 * hmean2_f(gP, F_(P.sq_Tw1[wall_c(s, P, i)])) * dxi * (2.0f * F_(IDY_(j)));
+      nN = P.wl[4 * (wall_c(s, P, i)) + 1];
+      DN = C1 * hmean2_f(gP, F_(P.wl[4 * (wall_c(s, P, i)) + 3])) * dxi * (2.0f * F_(IDY_(j)));
     } else if ((SJ && P.wtype1 == 2)) {
-      nN = P.Tw1[wall_c(s, P, i)];
+      nN = P.wl[4 * (wall_c(s, P, i)) + 1];
       DN = C1 * gP * dxi * iwall_f(dyj, F_(P.kt), F_(R_(i, j)));
     } else {
       nN = TP;
@@ -893,7 +893,7 @@ __device__ void u_pseudo_mx(const Lds &s, const Params &P, int i, int j,
   if (!CL && gj == 0) {
     if (P.wtype0 == 0) {
       uS = P.wu0;
-      DS = B * 0.5f * (gnode + F_(P.sq_Twu0[wall_u(s, P, i)])) * len * (2.0f * F_(IDY_(j)));
+      DS = B * 0.5f * (gnode + F_(P.wu[2 * (wall_u(s, P, i))])) * len * (2.0f * F_(IDY_(j)));
     } else if ((SJ && P.wtype0 == 2)) {
       uS = P.wu0;
       DS = B * gnode * len * iwall_f(dyj, F_(P.kz), F_(WLX_(i) * R_(i - 1, j) + WRX_(i) * R_(i, j)));
@@ -913,7 +913,7 @@ __device__ void u_pseudo_mx(const Lds &s, const Params &P, int i, int j,
   if (!CL && gj == P.ny - 1) {
     if (P.wtype1 == 0) {
       uN = P.wu1;
-      DN = B * 0.5f * (gnode + F_(P.sq_Twu1[wall_u(s, P, i)])) * len * (2.0f * F_(IDY_(j)));
+      DN = B * 0.5f * (gnode + F_(P.wu[2 * (wall_u(s, P, i)) + 1])) * len * (2.0f * F_(IDY_(j)));
     } else if ((SJ && P.wtype1 == 2)) {
       uN = P.wu1;
       DN = B * gnode * len * iwall_f(dyj, F_(P.kz), F_(WLX_(i) * R_(i - 1, j) + WRX_(i) * R_(i, j)));
@@ -1430,7 +1430,7 @@ template <bool CL, bool TV>
 __device__ double t_explicit(const Lds &s, const Params &P, int i, int j,
                              int gi, int gj) {
   const double TP = T_(i, j);
-  const double TW = (!CL && !P.per && gi == 0) ? P.T_in[gj] : T_(i - 1, j);
+  const double TW = (!CL && !P.per && gi == 0) ? P.inl[4 * (gj) + 1] : T_(i - 1, j);
   const double TE = (!CL && !P.per && gi == P.nx - 1) ? TP : T_(i + 1, j);
   const double TS = (!CL && gj == 0) ? TP : T_(i, j - 1);
   const double TN = (!CL && gj == P.ny - 1) ? TP : T_(i, j + 1);
@@ -1747,7 +1747,7 @@ __global__ __launch_bounds__(RB) void k_continuity(const Params P,
     if (i >= P.nx) continue;
     const long k = P.off + (long)j * P.pitch + i;
     if (!P.fl[k]) continue;
-    const double dV = P.gx_[0][i + XPAD] * P.gy_[0][j + XPAD];
+    const double dV = P.gx6[6 * (i + XPAD)] * P.gy6[6 * (j + XPAD)];
     const double GW = X.gu[k], GE = X.gu[k + 1];
     const double GS = X.gv[k], GN = X.gv[k + P.pitch];
     const double R = (n.p[k] / n.T[k] * dV - C.Cp[k]) * P.idt + (GE - GW) + (GN - GS);
