@@ -991,14 +991,18 @@ __global__ __launch_bounds__(AB) void k_adj_rho_faces(const Params P, const Stat
 
 
 // The energy, u-hat, v-hat and face-density stages read disjoint adjoint
-// inputs and add into shared targets, so one launch runs them side by side
-// (blockIdx.y selects the stage): four times the blocks of one stage, which
-// keeps the CUs busy on grids whose single stage would leave them half idle.
+// inputs and add into shared targets.  One stage of them (ST = 0 energy, 1
+// u-hat, 2 v-hat, 3 face densities; ST < 0: blockIdx.y selects it).  On
+// small grids one launch runs the four side by side (four times the blocks of
+// one stage, which keeps the CUs busy where a single stage would leave them
+// half idle); on large grids each stage runs as a launch of its own, whose
+// kernel holds only that stage's arrays (the side-by-side kernel needs more
+// scalar registers than the CU gives and spills them into vector lanes).
 // SJ: the problem has slip-jump surfaces (their branches are compiled only
 // into these instances, which keeps the others' registers as without them).
 // The others fit 5 waves per SIMD (91 VGPRs; 3.5 % shorter backward on
 // 4096x1024 than at 4); the slip-jump ones would spill there and keep 4.
-template <bool TV, bool SJ>
+template <int ST, bool TV, bool SJ>
 __global__ __launch_bounds__(AB) __attribute__((amdgpu_waves_per_eu(SJ ? 4 : 5))) void k_adj_stage2(const Params P, const State o,
                                                    const State lo, const Consts C,
                                                    const Consts lC, const Inter I,
@@ -1006,18 +1010,19 @@ __global__ __launch_bounds__(AB) __attribute__((amdgpu_waves_per_eu(SJ ? 4 : 5))
   __shared__ double wl[4 * Tiled<4, 1, false>::WN];
   static_assert(Tiled<1, 2, false>::WN <= 4 * Tiled<4, 1, false>::WN, "LDS");
   const Cache cc{A.cr, A.cg};
+  const int st = ST < 0 ? (int)blockIdx.y : ST;
   int i, j;
-  if (blockIdx.y == 0) {
+  if (st == 0) {
     Tiled<4, 1, false> sk{(lds_double *)wl, {lo.T, A.lg, lo.u, lo.v}};
     sk.begin(P, i, j);
     if (i <= P.nx && j <= P.ny) energy_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
     sk.end(P);
-  } else if (blockIdx.y == 1) {
+  } else if (st == 1) {
     Tiled<4, 1, false> sk{(lds_double *)wl, {lo.u, lo.v, A.lr, A.lg}};
     sk.begin(P, i, j);
     if (i <= P.nx && j <= P.ny) uhat_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
     sk.end(P);
-  } else if (blockIdx.y == 2) {
+  } else if (st == 2) {
     Tiled<4, 1, false> sk{(lds_double *)wl, {lo.u, lo.v, A.lr, A.lg}};
     sk.begin(P, i, j);
     if (i <= P.nx && j <= P.ny) vhat_item<SJ>(P, o, cc, lo, C, lC, I, A, i, j, sk);
@@ -1532,14 +1537,31 @@ void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, 
                          hipStream_t st) {
   const dim3 g = agrid(P), b(AB);
   hipLaunchKernelGGL(k_adj_front, tgrid(P), b, 0, st, P, o, ln, lo, lC, I, A);
-  const dim3 g4(tgrid(P).x, 4);
+  // side by side below 4 blocks per SIMD of one stage's tiles, stage by stage above
+  const bool split = tgrid(P).x >= 4096;
+  const dim3 g4(tgrid(P).x, 4), g1(tgrid(P).x);
+#define STS_ST(ST_, TV_, SJ_) \
+  hipLaunchKernelGGL((k_adj_stage2<ST_, TV_, SJ_>), ST_ < 0 ? g4 : g1, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1)
+#define STS_STAGES(TV_, SJ_)      \
+  do {                            \
+    if (split) {                  \
+      STS_ST(0, TV_, SJ_);        \
+      STS_ST(1, TV_, SJ_);        \
+      STS_ST(2, TV_, SJ_);        \
+      STS_ST(3, TV_, SJ_);        \
+    } else {                      \
+      STS_ST(-1, TV_, SJ_);       \
+    }                             \
+  } while (0)
   if (scheme & 2) {
-    if (P.sj) hipLaunchKernelGGL((k_adj_stage2<true, true>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
-    else hipLaunchKernelGGL((k_adj_stage2<true, false>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
+    if (P.sj) STS_STAGES(true, true);
+    else STS_STAGES(true, false);
   } else {
-    if (P.sj) hipLaunchKernelGGL((k_adj_stage2<false, true>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
-    else hipLaunchKernelGGL((k_adj_stage2<false, false>), g4, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
+    if (P.sj) STS_STAGES(false, true);
+    else STS_STAGES(false, false);
   }
+#undef STS_STAGES
+#undef STS_ST
   hipLaunchKernelGGL(k_adj_cell_props, g, b, 0, st, P, o, lo, A.lr, A.lg);
 }
 

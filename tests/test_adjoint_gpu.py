@@ -103,18 +103,22 @@ def test_adjoint_vs_oracle_gradient(sts_mod, oracle_lib, name, scheme):
 
 
 def tlm_directions_1024x256(oracle_lib, steps, scheme, every):
-    """Dot-product test on the 1024x256 channel: the adjoint's directional
+    from paper_1802_04243_amd import workloads as W_
+    p, run = W_.workload("adjoint_1024x256")
+    return tlm_directions(oracle_lib, p, run, steps, scheme, every)
+
+
+def tlm_directions(oracle_lib, p, run, steps, scheme, every):
+    """Dot-product test on a channel with one square: the adjoint's directional
     derivatives <gradient, delta> against the oracle's tangent-linear model
     (ora.c compiled on dual numbers: the exact derivative of the branch the
     forward takes) along K seeded directions: 6 in the inlet profile, 5 in
     both wall temperatures, the rest in the initial state around the
     square.  Returns (adjoint, tangent-linear) per direction."""
-    from paper_1802_04243_amd import workloads as W_
-    p, run = W_.workload("adjoint_1024x256")
     f0 = W.initial_fields(p, run["seed"])
     dt, inner = run["dt"], run["inner"]
     K = oracle_lib.tlm_lib().tlm_k()
-    print(f"case adjoint dot-product 1024x256 {steps}x{inner} every {every} scheme {scheme} "
+    print(f"case adjoint dot-product {p.nx}x{p.ny} {steps}x{inner} every {every} scheme {scheme} "
           f"({K} directions)", flush=True)
     L, gu, g0, g1, gf = adjoint_gradient(p, f0, dt, steps, inner, scheme, every, fields=True)
     print(f"L {L:.12e}; max|dL/du_in| {np.abs(gu).max():.2e}, max|dL/dwall_T| "
@@ -171,6 +175,16 @@ def test_adjoint_dot_product_1024x256_one_step(sts_mod, oracle_lib, name, scheme
 def test_adjoint_dot_product_1024x256_configured_run(sts_mod, oracle_lib):
     # the configured run: 100 steps x 10 passes, checkpoints every 10 steps
     assert_dot_products(*tlm_directions_1024x256(oracle_lib, 100, W.EXPLICIT | W.TVD, 10))
+
+
+def test_adjoint_dot_product_2048x512_one_step(sts_mod, oracle_lib):
+    # 65 x 65 = 4225 tiles of 32 x 8: the grid size from which the four
+    # scatter stages of the reverse pass run as separate launches
+    from paper_1802_04243_amd import workloads as W_
+    from fractions import Fraction
+    p = W_.channel(2048, 512, [Fraction(5, 2)], u_in=W_.parabolic_inlet(512, 4))
+    run = dict(inner=10, seed=4, dt=p.cfl_dt())
+    assert_dot_products(*tlm_directions(oracle_lib, p, run, 1, W.EXPLICIT | W.TVD, 1))
 
 
 def test_adjoint_argument_errors(sts_mod):
