@@ -2,16 +2,17 @@
 //
 // One thread per unknown.  A pass is a chain of streaming stencil kernels,
 // each reading its neighbours through the L1/L2 caches (no LDS tiles):
-//   cell properties rho = p/T, Gamma = sqrt(T)       (k3_cell)
-//   face densities of the three directions (pl10-pl11 read per direction)
-//                                                   (k3_rf<a>)
-//   energy equation (pl30-pl33, pl28, pl29)          (k3_energy)
-//   pseudo velocities and d of each component (pl14-pl16, pl18-pl21 read
-//   for any component a)                             (k3_mom<a>)
-//   pressure equation (pl23, pl24), six neighbours   (k3_pressure)
-//   velocity update (pl18, pl19)                     (k3_velocity<a>)
-// The step prologue stores the per-step constants (the level n-1 parts of
-// b^u, b^v, b^w, b^T, b^p and, for the explicit schemes, the explicit
+//   Gamma on the cell edges along each direction      (k3_edge<c>)
+//   energy equation (pl30-pl33, pl28, pl29), and the pseudo velocities and
+//   d of each component (pl14-pl16, pl18-pl21 read for any component a),
+//   all from the old iterate                          (k3_eqs)
+//   pressure equation (pl23, pl24), six neighbours, and rho = p/T,
+//   Gamma = sqrt(T) of the new iterate               (k3_pressure)
+//   velocity update (pl18, pl19) and the new iterate's face densities
+//   (pl10-pl11 read per direction)                   (k3_velocity<a>)
+// The step prologue computes rho, Gamma and the face densities of the state
+// (k3_cell, k3_rf<a>) and stores the per-step constants (the level n-1 parts
+// of b^u, b^v, b^w, b^T, b^p and, for the explicit schemes, the explicit
 // convective terms pl15_11 / pl31_1).  The last pass of a step reduces the
 // increments and the continuity residual in fixed-order block partials.
 //
@@ -55,9 +56,12 @@ struct P3 {
   // widths d, their inverses id; at face i (between cells i-1 and i) the
   // weights of cells i-1 and i in the linear interpolation to the face,
   // wlo = d_i / (d_{i-1} + d_i) and whi = d_{i-1} / (d_{i-1} + d_i), and the
-  // inverse centre distance ic = 2 / (d_{i-1} + d_i)
-  const double *d[3], *id[3], *wlo[3], *whi[3], *ic[3];
+  // inverse centre distance ic = 2 / (d_{i-1} + d_i); interleaved, five
+  // values per index (one pointer per direction keeps the kernels' uniform
+  // values within the scalar register file)
+  const double *geo[3];
 };
+constexpr int NGEO = 5;  // d, 1/d, wlo, whi, ic
 
 struct Fld {
   double *q[5];  // u, v, w, p, T
@@ -90,11 +94,11 @@ __device__ __forceinline__ double fv(const P3 &P, const double *a, int f, const 
   (void)f;
   return cv(P, a, x, e, s);
 }
-__device__ __forceinline__ double W(const P3 &P, int e, int i) { return P.d[e][i]; }
-__device__ __forceinline__ double IW(const P3 &P, int e, int i) { return P.id[e][i]; }
-__device__ __forceinline__ double WLO(const P3 &P, int e, int i) { return P.wlo[e][i]; }
-__device__ __forceinline__ double WHI(const P3 &P, int e, int i) { return P.whi[e][i]; }
-__device__ __forceinline__ double IC(const P3 &P, int e, int i) { return P.ic[e][i]; }
+__device__ __forceinline__ double W(const P3 &P, int e, int i) { return P.geo[e][NGEO * i]; }
+__device__ __forceinline__ double IW(const P3 &P, int e, int i) { return P.geo[e][NGEO * i + 1]; }
+__device__ __forceinline__ double WLO(const P3 &P, int e, int i) { return P.geo[e][NGEO * i + 2]; }
+__device__ __forceinline__ double WHI(const P3 &P, int e, int i) { return P.geo[e][NGEO * i + 3]; }
+__device__ __forceinline__ double IC(const P3 &P, int e, int i) { return P.geo[e][NGEO * i + 4]; }
 // store v at x and, in periodic directions, at the images of x within the
 // ghost layers (FM: bit e set where the array's index along e is a face
 // index, 0 for a cell array)
@@ -190,9 +194,14 @@ __device__ __forceinline__ double hmean2(double a, double b) { return ddiv(2.0 *
 // contiguous slab of planes, as the 2-D pass deals tile bands, was measured
 // and made no kernel faster: these kernels are bound by their per-thread
 // load chains, not by L2 misses.)
+// A wave covers one row of its tile (BX = 64 lanes), so y and z are uniform
+// across it: taken from the first lane, they live in scalar registers, and
+// the widths, weights and boundary tests along y and z become scalar loads
+// and scalar branches.
+static_assert(BX == 64, "one tile row per wave");
 __device__ __forceinline__ bool point(int X, int Y, int Z, int x[3]) {
   x[0] = blockIdx.x * BX + threadIdx.x;
-  x[1] = blockIdx.y * BY + threadIdx.y;
+  x[1] = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * BY + threadIdx.y));
   x[2] = blockIdx.z;
   return x[0] < X && x[1] < Y && x[2] < Z;
 }
@@ -209,14 +218,10 @@ __global__ __launch_bounds__(NTB) void k3_cell(P3 P, Fld S, Work Wk) {
   put<0>(P, Wk.gam, x, sqrt(T));
 }
 
+// face density of the A-face f with velocity vel there, from rho in Wk
 template <int A, bool TV>
-__global__ __launch_bounds__(NTB) void k3_rf(P3 P, Fld S, Work Wk) {
-  int f[3];
-  if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
+__device__ __forceinline__ double rf_at(const P3 &P, const Work &Wk, const int f[3], double vel) {
   const int fa = f[A];
-  if (P.per[A] && fa == P.n[A]) return;  // the image of face 0
-  const long m = lin(P, f[0], f[1], f[2]);
-  const double vel = S.q[A][m];
   double r;
   if (!P.per[A] && fa == 0) {
     const double rr = cv(P, Wk.rho, f);
@@ -230,7 +235,15 @@ __global__ __launch_bounds__(NTB) void k3_rf(P3 P, Fld S, Work Wk) {
       r += psi_s(P, A, fa, cv(P, Wk.rho, f, A, -2), rl, rr, cv(P, Wk.rho, f, A, 1), vel) *
            (rr - rl);
   }
-  put<1 << A>(P, Wk.rf[A], f, r);
+  return r;
+}
+
+template <int A, bool TV>
+__global__ __launch_bounds__(NTB) void k3_rf(P3 P, Fld S, Work Wk) {
+  int f[3];
+  if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
+  if (P.per[A] && f[A] == P.n[A]) return;  // the image of face 0
+  put<1 << A>(P, Wk.rf[A], f, rf_at<A, TV>(P, Wk, f, S.q[A][lin(P, f[0], f[1], f[2])]));
 }
 
 // mass flux through the e-face of cell x on side s (0 low, 1 high)
@@ -303,10 +316,10 @@ __device__ double qface(const P3 &P, const Fld &S, int e, int f, const int x[3],
            : WHI(P, f, x[f]) * qc + WLO(P, f, x[f]) * qn;
 }
 
+// new T of cell x (pl28-pl33)
 template <bool IM, bool TV>
-__global__ __launch_bounds__(NTB) void k3_energy(P3 P, Fld S, Work Wk, double *Tout) {
-  int x[3];
-  if (!point(P.n[0], P.n[1], P.n[2], x)) return;
+__device__ __forceinline__ void energy_at(const P3 &P, const Fld &S, const Work &Wk,
+                                          double *Tout, const int x[3]) {
   const double *T = S.q[4];
   const double TP = cv(P, T, x), gP = cv(P, Wk.gam, x), rP = cv(P, Wk.rho, x);
   const double dV = W(P, 0, x[0]) * W(P, 1, x[1]) * W(P, 2, x[2]);
@@ -503,10 +516,9 @@ __device__ double q_explicit(const P3 &P, const Fld &S, const Work &Wk, const in
   return sum;
 }
 
+// pseudo velocity and d of component A at its face f (pl14-pl16, pl18-pl21)
 template <int A, bool IM, bool TV>
-__global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
-  int f[3];
-  if (!point(P.n[0] + (A == 0), P.n[1] + (A == 1), P.n[2] + (A == 2), f)) return;
+__device__ __forceinline__ void mom_at(const P3 &P, const Fld &S, const Work &Wk, const int f[3]) {
   if (P.per[A] && f[A] == P.n[A]) return;  // the image of face 0
   const long m = lin(P, f[0], f[1], f[2]);
   const double *q = S.q[A];
@@ -612,6 +624,27 @@ __global__ __launch_bounds__(NTB) void k3_mom(P3 P, Fld S, Work Wk) {
   put<1 << A>(P, Wk.dq[A], f, P.A * Ap * ia0);
 }
 
+// Equations that read only the old iterate, several in one launch (M: bit 0
+// energy, bit 1 + a momentum of component a): the thread at index x takes
+// the cell x and the low face of that cell in each direction (the threads
+// one past the last cell along a direction take that direction's last faces
+// only).  Their inputs overlap (velocities, face densities, rho, Gamma and
+// the edge Gamma around x), so a block's neighbour loads are served by the
+// caches of one launch instead of being fetched again by each.  (A grid
+// banded by x per XCD halved the launch's L2 misses but not its time: the
+// launch holds more uniform values than the scalar registers take, and its
+// spill traffic through vector lanes grew with that layout.)
+template <bool IM, bool TV, int M>
+__global__ __launch_bounds__(NTB) void k3_eqs(P3 P, Fld S, Work Wk, double *Tout) {
+  int x[3];
+  if (!point(P.n[0] + 1, P.n[1] + 1, P.n[2] + 1, x)) return;
+  const bool i0 = x[0] < P.n[0], i1 = x[1] < P.n[1], i2 = x[2] < P.n[2];
+  if ((M & 1) && i0 && i1 && i2) energy_at<IM, TV>(P, S, Wk, Tout, x);
+  if ((M & 2) && i1 && i2) mom_at<0, IM, TV>(P, S, Wk, x);
+  if ((M & 4) && i0 && i2) mom_at<1, IM, TV>(P, S, Wk, x);
+  if ((M & 8) && i0 && i1) mom_at<2, IM, TV>(P, S, Wk, x);
+}
+
 // ---------------------------------------------------------------------------
 // pressure and velocities
 // ---------------------------------------------------------------------------
@@ -637,8 +670,14 @@ __global__ __launch_bounds__(NTB) void k3_pressure(P3 P, Fld S, Work Wk, const d
     sap += aL * pL + aH * pH;
     sb += bH - bL;
   }
-  const double a0 = ddiv(dV, Tn[m]) + sa * P.dt;
-  put<0>(P, pout, x, ddiv(sap * P.dt + (Wk.cp[m] - sb * P.dt), a0));
+  const double Tm = Tn[m];
+  const double a0 = ddiv(dV, Tm) + sa * P.dt;
+  const double pm = ddiv(sap * P.dt + (Wk.cp[m] - sb * P.dt), a0);
+  put<0>(P, pout, x, pm);
+  // rho and Gamma of the new iterate, which the next pass reads (nothing
+  // later in this pass reads those of the old one)
+  put<0>(P, Wk.rho, x, ddiv(pm, Tm));
+  put<0>(P, Wk.gam, x, sqrt(Tm));
 }
 
 template <int A>
@@ -647,7 +686,11 @@ __device__ __forceinline__ double q_update(const P3 &P, const Work &Wk, const do
   return fv(P, Wk.qh[A], A, f) - fv(P, Wk.dq[A], A, f) * (cv(P, pn, f) - cv(P, pn, f, A, -1));
 }
 
-template <int A>
+// new velocity of component A (pl18, pl19); RF: also the face density of the
+// new iterate at the face (the next pass's, from the rho the pressure kernel
+// stored), which replaces the old one (read by nothing later in this pass
+// but the residuals of the last pass, which launches without RF)
+template <int A, bool RF, bool TV>
 __global__ __launch_bounds__(NTB) void k3_velocity(P3 P, Fld S, Work Wk, const double *pn,
                                                    double *qout) {
   int f[3];
@@ -666,6 +709,7 @@ __global__ __launch_bounds__(NTB) void k3_velocity(P3 P, Fld S, Work Wk, const d
     qn = S.q[A][m];  // inlet u_in, wall faces 0
   }
   put<1 << A>(P, qout, f, qn);
+  if (RF) put<1 << A>(P, Wk.rf[A], f, rf_at<A, TV>(P, Wk, f, qn));
 }
 
 // ---------------------------------------------------------------------------
@@ -803,7 +847,7 @@ struct sts3_ctx {
   Fld st[2];
   int cur;
   Work Wk;
-  double *d_d[3];  // per direction: widths, inverses, wlo, whi, ic (G ghosts each end)
+  double *d_d[3];  // per direction: NGEO values per index (G ghosts each end)
   double *part, *dres;
   double *hres;  // pinned
   int nblk_cell, nblk_face[3], nblocks;
@@ -846,36 +890,44 @@ void launch_rf(sts3_ctx *c, const Fld &S, bool tv) {
   }
 }
 
+// Per-step constants from S, and rho, Gamma and the face densities of S,
+// which the first pass reads as those of its old iterate (EX, TV: explicit
+// convective terms of that scheme; tvd: TVD face densities).
 template <bool EX, bool TV>
-void launch_prologue3(sts3_ctx *c, const Fld &S) {
+void launch_prologue3(sts3_ctx *c, const Fld &S, bool tvd) {
   const dim3 b(BX, BY), gc = grid_of(c, c->n[0], c->n[1], c->n[2]);
   hipLaunchKernelGGL(k3_cell, gc, b, 0, c->stream, c->P, S, c->Wk);
-  if (EX) launch_rf(c, S, TV);
+  launch_rf(c, S, tvd);
   hipLaunchKernelGGL((k3_const_cell<EX, TV>), gc, b, 0, c->stream, c->P, S, c->Wk);
   hipLaunchKernelGGL((k3_const_face<0, EX, TV>), grid_face(c, 0), b, 0, c->stream, c->P, S, c->Wk);
   hipLaunchKernelGGL((k3_const_face<1, EX, TV>), grid_face(c, 1), b, 0, c->stream, c->P, S, c->Wk);
   hipLaunchKernelGGL((k3_const_face<2, EX, TV>), grid_face(c, 2), b, 0, c->stream, c->P, S, c->Wk);
 }
 
+// One pass from O to N.  rho, Gamma and the face densities of O are in Wk on
+// entry (from the prologue, or the previous pass's pressure and velocity
+// kernels); a pass other than the last leaves those of N there.
 template <bool IM, bool TV>
 void launch_pass3d(sts3_ctx *c, const Fld &O, const Fld &N, bool last) {
   const dim3 b(BX, BY), gc = grid_of(c, c->n[0], c->n[1], c->n[2]);
-  hipLaunchKernelGGL(k3_cell, gc, b, 0, c->stream, c->P, O, c->Wk);
-  launch_rf(c, O, TV);
   hipLaunchKernelGGL((k3_edge<0>), grid_of(c, c->n[0], c->n[1] + 1, c->n[2] + 1), b, 0, c->stream,
                      c->P, c->Wk);
   hipLaunchKernelGGL((k3_edge<1>), grid_of(c, c->n[0] + 1, c->n[1], c->n[2] + 1), b, 0, c->stream,
                      c->P, c->Wk);
   hipLaunchKernelGGL((k3_edge<2>), grid_of(c, c->n[0] + 1, c->n[1] + 1, c->n[2]), b, 0, c->stream,
                      c->P, c->Wk);
-  hipLaunchKernelGGL((k3_energy<IM, TV>), gc, b, 0, c->stream, c->P, O, c->Wk, N.q[4]);
-  hipLaunchKernelGGL((k3_mom<0, IM, TV>), grid_face(c, 0), b, 0, c->stream, c->P, O, c->Wk);
-  hipLaunchKernelGGL((k3_mom<1, IM, TV>), grid_face(c, 1), b, 0, c->stream, c->P, O, c->Wk);
-  hipLaunchKernelGGL((k3_mom<2, IM, TV>), grid_face(c, 2), b, 0, c->stream, c->P, O, c->Wk);
+  const dim3 ge = grid_of(c, c->n[0] + 1, c->n[1] + 1, c->n[2] + 1);
+  hipLaunchKernelGGL((k3_eqs<IM, TV, 15>), ge, b, 0, c->stream, c->P, O, c->Wk, N.q[4]);
   hipLaunchKernelGGL(k3_pressure, gc, b, 0, c->stream, c->P, O, c->Wk, N.q[4], N.q[3]);
-  hipLaunchKernelGGL((k3_velocity<0>), grid_face(c, 0), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[0]);
-  hipLaunchKernelGGL((k3_velocity<1>), grid_face(c, 1), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[1]);
-  hipLaunchKernelGGL((k3_velocity<2>), grid_face(c, 2), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[2]);
+  if (last) {
+    hipLaunchKernelGGL((k3_velocity<0, false, TV>), grid_face(c, 0), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[0]);
+    hipLaunchKernelGGL((k3_velocity<1, false, TV>), grid_face(c, 1), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[1]);
+    hipLaunchKernelGGL((k3_velocity<2, false, TV>), grid_face(c, 2), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[2]);
+  } else {
+    hipLaunchKernelGGL((k3_velocity<0, true, TV>), grid_face(c, 0), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[0]);
+    hipLaunchKernelGGL((k3_velocity<1, true, TV>), grid_face(c, 1), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[1]);
+    hipLaunchKernelGGL((k3_velocity<2, true, TV>), grid_face(c, 2), b, 0, c->stream, c->P, O, c->Wk, N.q[3], N.q[2]);
+  }
   if (last) {
     hipLaunchKernelGGL(k3_resid_cell, gc, b, 0, c->stream, c->P, O, N, c->Wk, c->part);
     int base = c->nblk_cell;
@@ -1065,7 +1117,7 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
   c->Wk.cp = fields[k++];
   for (int a = 0; a < 3; a++) c->Wk.ge[a] = fields[k++];
   for (int e = 0; e < 3; e++)
-    if (!alloc(sizeof(double) * 5 * (c->n[e] + 2 * G), (void **)&c->d_d[e])) {
+    if (!alloc(sizeof(double) * NGEO * (c->n[e] + 2 * G), (void **)&c->d_d[e])) {
       sts3_destroy(c);
       return fail3(STS_ENOMEM, "device allocation failed");
     }
@@ -1098,12 +1150,7 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
     P.n[e] = c->n[e];
     P.per[e] = s->bc[e] == STS3_PERIODIC;
     P.g[e] = s->g[e];
-    const int ne = c->n[e] + 2 * G;
-    P.d[e] = c->d_d[e] + G;
-    P.id[e] = c->d_d[e] + ne + G;
-    P.wlo[e] = c->d_d[e] + 2 * ne + G;
-    P.whi[e] = c->d_d[e] + 3 * ne + G;
-    P.ic[e] = c->d_d[e] + 4 * ne + G;
+    P.geo[e] = c->d_d[e] + NGEO * G;
     for (int w = 0; w < 2; w++) {
       P.wt[e][w] = s->wall_type[e][w];
       P.wT[e][w] = s->wall_T[e][w];
@@ -1134,11 +1181,14 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
       return c->wid[e][w];
     };
     std::vector<double> g;
-    for (int i = -G; i < ne + G; i++) g.push_back(width(i));
-    for (int i = -G; i < ne + G; i++) g.push_back(1.0 / width(i));
-    for (int i = -G; i < ne + G; i++) g.push_back(width(i) / (width(i - 1) + width(i)));
-    for (int i = -G; i < ne + G; i++) g.push_back(width(i - 1) / (width(i - 1) + width(i)));
-    for (int i = -G; i < ne + G; i++) g.push_back(2.0 / (width(i - 1) + width(i)));
+    for (int i = -G; i < ne + G; i++) {
+      const double dl = width(i - 1), d = width(i);
+      g.push_back(d);
+      g.push_back(1.0 / d);
+      g.push_back(d / (dl + d));
+      g.push_back(dl / (dl + d));
+      g.push_back(2.0 / (dl + d));
+    }
     HIP3(hipMemcpy(c->d_d[e], g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice));
   }
   // clear every array (frame entries stay finite), then the initial state
@@ -1211,9 +1261,9 @@ extern "C" sts_status sts3_step(sts3_ctx *c, double dt, int n_inner, int scheme)
   c->P.idt = 1.0 / dt;
   const bool im = scheme & STS_IMPLICIT, tv = scheme & STS_TVD;
   const Fld S0 = c->st[c->cur];
-  if (im) launch_prologue3<false, false>(c, S0);
-  else if (tv) launch_prologue3<true, true>(c, S0);
-  else launch_prologue3<true, false>(c, S0);
+  if (im) launch_prologue3<false, false>(c, S0, tv);
+  else if (tv) launch_prologue3<true, true>(c, S0, true);
+  else launch_prologue3<true, false>(c, S0, false);
   for (int k = 0; k < n_inner; k++) {
     const Fld O = c->st[c->cur], N = c->st[c->cur ^ 1];
     const bool last = k == n_inner - 1;
