@@ -197,11 +197,12 @@ def run_adjoint(name: str = "adjoint_1024x256"):
     p, run = W.workload(name)
     f0 = W.initial_fields(p, run["seed"])
     wb, wt = p.walls()
-    args = [torch.tensor(a, dtype=torch.float64, requires_grad=True)
-            for a in (p.inlet()[0], wb, wt)]
-    L = adjoint.drag_loss(p, *args, f0, run["dt"], run["steps"], run["inner"], W.EXPLICIT,
-                          run["every"])
-    L.backward()
+    for _ in range(2):  # the first run warms the library, its kernels and allocations up
+        args = [torch.tensor(a, dtype=torch.float64, requires_grad=True)
+                for a in (p.inlet()[0], wb, wt)]
+        L = adjoint.drag_loss(p, *args, f0, run["dt"], run["steps"], run["inner"], W.EXPLICIT,
+                              run["every"])
+        L.backward()
     st = dict(adjoint.LAST_STATS)
     return {"workload": name, "steps": run["steps"], "n_inner": run["inner"],
             "checkpoint_every": run["every"], "scheme": "explicit_upwind",

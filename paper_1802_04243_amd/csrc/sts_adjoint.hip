@@ -1055,13 +1055,10 @@ __global__ __launch_bounds__(AB) void k_adj_cell_props(const Params P, const Sta
 // u^exp, C_v likewise (explicit convective terms with the face densities of
 // the level n-1 fields, ru0 / rv0)
 // ---------------------------------------------------------------------------
-template <bool TV>
-__global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State m,
-                                                     const Consts lC, const State lm,
-                                                     const double *ru0, const double *rv0,
-                                                     double *lru, double *lrv, double *lr) {
-  int i, j;
-  if (!elem(P, i, j)) return;
+template <bool TV, class SK>
+__device__ __forceinline__ void prologue_item(const Params &P, const State &m, const Consts &lC,
+                                              const double *ru0, const double *rv0, int i, int j,
+                                              SK &sk) {
   const double dt = P.dt;
   // ---- cell constants
   if (i < P.nx && j < P.ny && fl(P, i, j)) {
@@ -1069,7 +1066,7 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
     const double lCT = lC.CT[k], lCp = lC.Cp[k];
     const double dxi = gx(P, 0, i), dyj = gy(P, 0, j), dV = dxi * dyj;
     const double TP = m.T[k], rP = rho(P, m, i, j);
-    aadd(lr, P, i, j, lCT * TP * dV + lCp * dV);
+    sk.add(3, P, i, j, lCT * TP * dV + lCp * dV);
     double lTP = lCT * rP * dV;
     const double lt = lCT * dt;  // adjoint of T^exp
     if (lt != 0.0) {
@@ -1102,14 +1099,14 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
       const double phS = upw(TS, TP, vS) + (TP - TS) * pS;
       const double lFE = -lt * phE, lFW = lt * phW, lFN = -lt * phN, lFS = lt * phS;
       const double lpE = -lt * FE, lpW = lt * FW, lpN = -lt * FN, lpS = lt * FS;
-      unsafeAtomicAdd(lru + k, lFW * uW * dyj);
-      unsafeAtomicAdd(lru + k + 1, lFE * uE * dyj);
-      unsafeAtomicAdd(lrv + k, lFS * vS * dxi);
-      unsafeAtomicAdd(lrv + k + P.pitch, lFN * vN * dxi);
-      aadd(lm.u, P, i, j, lFW * rW * dyj);
-      aadd(lm.u, P, i + 1, j, lFE * rE * dyj);
-      aadd(lm.v, P, i, j, lFS * rS * dxi);
-      aadd(lm.v, P, i, j + 1, lFN * rN * dxi);
+      sk.add(4, P, i, j, lFW * uW * dyj);
+      sk.add(4, P, i + 1, j, lFE * uE * dyj);
+      sk.add(5, P, i, j, lFS * vS * dxi);
+      sk.add(5, P, i, j + 1, lFN * vN * dxi);
+      sk.add(0, P, i, j, lFW * rW * dyj);
+      sk.add(0, P, i + 1, j, lFE * rE * dyj);
+      sk.add(1, P, i, j, lFS * rS * dxi);
+      sk.add(1, P, i, j + 1, lFN * rN * dxi);
       // face values: d phi / d (nodes)
       double lTW = 0, lTE = 0, lTS = 0, lTN = 0;
       // phiE = upw(TP, TE) + (TE - TP) psiE(T_{i-1}, TP, TE, T_{i+2})
@@ -1118,17 +1115,17 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
       lTP -= lpE * pE;
       if (tE) {
         const double q = lpE * (TE - TP);
-        aadd(lm.T, P, i - 1, j, q * gE[0]);
+        sk.add(2, P, i - 1, j, q * gE[0]);
         lTP += q * gE[1];
         lTE += q * gE[2];
-        aadd(lm.T, P, i + 2, j, q * gE[3]);
+        sk.add(2, P, i + 2, j, q * gE[3]);
       }
       if (uW > 0.0) lTW += lpW; else lTP += lpW;
       lTP += lpW * pW;
       lTW -= lpW * pW;
       if (tW) {
         const double q = lpW * (TP - TW);
-        aadd(lm.T, P, i - 2, j, q * gW[0]);
+        sk.add(2, P, i - 2, j, q * gW[0]);
         lTW += q * gW[1];
         lTP += q * gW[2];
         lTE += q * gW[3];
@@ -1138,28 +1135,28 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
       lTP -= lpN * pN;
       if (tN) {
         const double q = lpN * (TN - TP);
-        aadd(lm.T, P, i, j - 1, q * gN[0]);
+        sk.add(2, P, i, j - 1, q * gN[0]);
         lTP += q * gN[1];
         lTN += q * gN[2];
-        aadd(lm.T, P, i, j + 2, q * gN[3]);
+        sk.add(2, P, i, j + 2, q * gN[3]);
       }
       if (vS > 0.0) lTS += lpS; else lTP += lpS;
       lTP += lpS * pS;
       lTS -= lpS * pS;
       if (tS) {
         const double q = lpS * (TP - TS);
-        aadd(lm.T, P, i, j - 2, q * gS[0]);
+        sk.add(2, P, i, j - 2, q * gS[0]);
         lTS += q * gS[1];
         lTP += q * gS[2];
         lTN += q * gS[3];
       }
       // neighbour values that are boundary rules
-      if (!inl) aadd(lm.T, P, i - 1, j, lTW);
-      if (outl) lTP += lTE; else aadd(lm.T, P, i + 1, j, lTE);
-      if (bot) lTP += lTS; else aadd(lm.T, P, i, j - 1, lTS);
-      if (top) lTP += lTN; else aadd(lm.T, P, i, j + 1, lTN);
+      if (!inl) sk.add(2, P, i - 1, j, lTW);
+      if (outl) lTP += lTE; else sk.add(2, P, i + 1, j, lTE);
+      if (bot) lTP += lTS; else sk.add(2, P, i, j - 1, lTS);
+      if (top) lTP += lTN; else sk.add(2, P, i, j + 1, lTN);
     }
-    aadd(lm.T, P, i, j, lTP);
+    sk.add(2, P, i, j, lTP);
   }
   // ---- u-face constant
   if (j < P.ny && u_solved(P, i, j)) {
@@ -1170,9 +1167,9 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
       const double uP = m.u[k];
       const double M = (rho(P, m, i, j) * dxr + rho(P, m, i - 1, j) * dxl) * dyj / 2.0;
       const double lM = l * (P.idt * uP + P.gx);
-      aadd(lm.u, P, i, j, l * M * P.idt);
-      aadd(lr, P, i, j, lM * dxr * dyj / 2.0);
-      aadd(lr, P, i - 1, j, lM * dxl * dyj / 2.0);
+      sk.add(0, P, i, j, l * M * P.idt);
+      sk.add(3, P, i, j, lM * dxr * dyj / 2.0);
+      sk.add(3, P, i - 1, j, lM * dxl * dyj / 2.0);
       // u^exp
       const bool bot = j == 0, top = j == P.ny - 1;
       const double uW = at(m.u, P, i - 1, j), uE = at(m.u, P, i + 1, j);
@@ -1218,16 +1215,16 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
       const double lpn0 = -0.5 * l * Fn0, lpn1 = -0.5 * l * Fn1;
       const double lps0 = 0.5 * l * Fs0, lps1 = 0.5 * l * Fs1;
       const double lpe = -l * FbE, lpw = l * FbW;
-      unsafeAtomicAdd(lrv + k - 1 + P.pitch, lFn0 * vn0 * dxl);
-      unsafeAtomicAdd(lrv + k + P.pitch, lFn1 * vn1 * dxr);
-      unsafeAtomicAdd(lrv + k - 1, lFs0 * vs0 * dxl);
-      unsafeAtomicAdd(lrv + k, lFs1 * vs1 * dxr);
-      aadd(lm.v, P, i - 1, j + 1, lFn0 * rn0 * dxl);
-      aadd(lm.v, P, i, j + 1, lFn1 * rn1 * dxr);
-      aadd(lm.v, P, i - 1, j, lFs0 * rs0 * dxl);
-      aadd(lm.v, P, i, j, lFs1 * rs1 * dxr);
-      aadd(lr, P, i, j, lFbE * ubE * dyj);
-      aadd(lr, P, i - 1, j, lFbW * ubW * dyj);
+      sk.add(5, P, i - 1, j + 1, lFn0 * vn0 * dxl);
+      sk.add(5, P, i, j + 1, lFn1 * vn1 * dxr);
+      sk.add(5, P, i - 1, j, lFs0 * vs0 * dxl);
+      sk.add(5, P, i, j, lFs1 * vs1 * dxr);
+      sk.add(1, P, i - 1, j + 1, lFn0 * rn0 * dxl);
+      sk.add(1, P, i, j + 1, lFn1 * rn1 * dxr);
+      sk.add(1, P, i - 1, j, lFs0 * rs0 * dxl);
+      sk.add(1, P, i, j, lFs1 * rs1 * dxr);
+      sk.add(3, P, i, j, lFbE * ubE * dyj);
+      sk.add(3, P, i - 1, j, lFbW * ubW * dyj);
       const double lubE = lFbE * rE * dyj, lubW = lFbW * rW * dyj;
       double luP = 0.5 * (lubE + lubW), luW = 0.5 * lubW, luE = 0.5 * lubE, luS = 0, luN = 0;
       // face values
@@ -1247,37 +1244,37 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
       luW -= lpw * pw;
       if (tn) {
         const double q0 = lpn0 * (uN - uP), q1 = lpn1 * (uN - uP);
-        aadd(lm.u, P, i, j - 1, q0 * gn0[0] + q1 * gn1[0]);
+        sk.add(0, P, i, j - 1, q0 * gn0[0] + q1 * gn1[0]);
         luP += q0 * gn0[1] + q1 * gn1[1];
         luN += q0 * gn0[2] + q1 * gn1[2];
-        aadd(lm.u, P, i, j + 2, q0 * gn0[3] + q1 * gn1[3]);
+        sk.add(0, P, i, j + 2, q0 * gn0[3] + q1 * gn1[3]);
       }
       if (ts) {
         const double q0 = lps0 * (uP - uS), q1 = lps1 * (uP - uS);
-        aadd(lm.u, P, i, j - 2, q0 * gs0[0] + q1 * gs1[0]);
+        sk.add(0, P, i, j - 2, q0 * gs0[0] + q1 * gs1[0]);
         luS += q0 * gs0[1] + q1 * gs1[1];
         luP += q0 * gs0[2] + q1 * gs1[2];
-        aadd(lm.u, P, i, j + 1, q0 * gs0[3] + q1 * gs1[3]);
+        sk.add(0, P, i, j + 1, q0 * gs0[3] + q1 * gs1[3]);
       }
       if (te) {
         const double q = lpe * (uE - uP);
         luW += q * ge[0];
         luP += q * ge[1];
         luE += q * ge[2];
-        aadd(lm.u, P, i + 2, j, q * ge[3]);
+        sk.add(0, P, i + 2, j, q * ge[3]);
       }
       if (tw) {
         const double q = lpw * (uP - uW);
-        aadd(lm.u, P, i - 2, j, q * gw[0]);
+        sk.add(0, P, i - 2, j, q * gw[0]);
         luW += q * gw[1];
         luP += q * gw[2];
         luE += q * gw[3];
       }
-      if (bot) luP += luS; else aadd(lm.u, P, i, j - 1, luS);
-      if (top) luP += luN; else aadd(lm.u, P, i, j + 1, luN);
-      aadd(lm.u, P, i - 1, j, luW);
-      aadd(lm.u, P, i + 1, j, luE);
-      aadd(lm.u, P, i, j, luP);
+      if (bot) luP += luS; else sk.add(0, P, i, j - 1, luS);
+      if (top) luP += luN; else sk.add(0, P, i, j + 1, luN);
+      sk.add(0, P, i - 1, j, luW);
+      sk.add(0, P, i + 1, j, luE);
+      sk.add(0, P, i, j, luP);
     }
   }
   // ---- v-face constant
@@ -1289,9 +1286,9 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
       const double vP = m.v[k];
       const double M = (rho(P, m, i, j) * dyn + rho(P, m, i, j - 1) * dys) * dxi / 2.0;
       const double lM = l * (P.idt * vP + P.gy);
-      aadd(lm.v, P, i, j, l * M * P.idt);
-      aadd(lr, P, i, j, lM * dyn * dxi / 2.0);
-      aadd(lr, P, i, j - 1, lM * dys * dxi / 2.0);
+      sk.add(1, P, i, j, l * M * P.idt);
+      sk.add(3, P, i, j, lM * dyn * dxi / 2.0);
+      sk.add(3, P, i, j - 1, lM * dys * dxi / 2.0);
       const bool inl = i == 0, outl = i == P.nx - 1;
       const double vW = inl ? 0.0 : at(m.v, P, i - 1, j);
       const double vE = outl ? vP : at(m.v, P, i + 1, j);
@@ -1336,16 +1333,16 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
       const double lpe0 = -0.5 * l * Fe0, lpe1 = -0.5 * l * Fe1;
       const double lpw0 = 0.5 * l * Fw0, lpw1 = 0.5 * l * Fw1;
       const double lpn = -l * FbN, lps = l * FbS;
-      unsafeAtomicAdd(lru + k + 1 - P.pitch, lFe0 * ue0 * dys);
-      unsafeAtomicAdd(lru + k + 1, lFe1 * ue1 * dyn);
-      unsafeAtomicAdd(lru + k - P.pitch, lFw0 * uw0 * dys);
-      unsafeAtomicAdd(lru + k, lFw1 * uw1 * dyn);
-      aadd(lm.u, P, i + 1, j - 1, lFe0 * re0 * dys);
-      aadd(lm.u, P, i + 1, j, lFe1 * re1 * dyn);
-      aadd(lm.u, P, i, j - 1, lFw0 * rw0 * dys);
-      aadd(lm.u, P, i, j, lFw1 * rw1 * dyn);
-      aadd(lr, P, i, j, lFbN * vbN * dxi);
-      aadd(lr, P, i, j - 1, lFbS * vbS * dxi);
+      sk.add(4, P, i + 1, j - 1, lFe0 * ue0 * dys);
+      sk.add(4, P, i + 1, j, lFe1 * ue1 * dyn);
+      sk.add(4, P, i, j - 1, lFw0 * uw0 * dys);
+      sk.add(4, P, i, j, lFw1 * uw1 * dyn);
+      sk.add(0, P, i + 1, j - 1, lFe0 * re0 * dys);
+      sk.add(0, P, i + 1, j, lFe1 * re1 * dyn);
+      sk.add(0, P, i, j - 1, lFw0 * rw0 * dys);
+      sk.add(0, P, i, j, lFw1 * rw1 * dyn);
+      sk.add(3, P, i, j, lFbN * vbN * dxi);
+      sk.add(3, P, i, j - 1, lFbS * vbS * dxi);
       const double lvbN = lFbN * rN * dxi, lvbS = lFbS * rS * dxi;
       double lvP = 0.5 * (lvbN + lvbS), lvN = 0.5 * lvbN, lvS = 0.5 * lvbS, lvW = 0, lvE = 0;
       if (ue0 > 0.0) lvP += lpe0; else lvE += lpe0;
@@ -1364,39 +1361,55 @@ __global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State
       lvS -= lps * ps;
       if (te) {
         const double q0 = lpe0 * (vE - vP), q1 = lpe1 * (vE - vP);
-        aadd(lm.v, P, i - 1, j, q0 * ge0[0] + q1 * ge1[0]);
+        sk.add(1, P, i - 1, j, q0 * ge0[0] + q1 * ge1[0]);
         lvP += q0 * ge0[1] + q1 * ge1[1];
         lvE += q0 * ge0[2] + q1 * ge1[2];
-        aadd(lm.v, P, i + 2, j, q0 * ge0[3] + q1 * ge1[3]);
+        sk.add(1, P, i + 2, j, q0 * ge0[3] + q1 * ge1[3]);
       }
       if (tw) {
         const double q0 = lpw0 * (vP - vW), q1 = lpw1 * (vP - vW);
-        aadd(lm.v, P, i - 2, j, q0 * gw0[0] + q1 * gw1[0]);
+        sk.add(1, P, i - 2, j, q0 * gw0[0] + q1 * gw1[0]);
         lvW += q0 * gw0[1] + q1 * gw1[1];
         lvP += q0 * gw0[2] + q1 * gw1[2];
-        aadd(lm.v, P, i + 1, j, q0 * gw0[3] + q1 * gw1[3]);
+        sk.add(1, P, i + 1, j, q0 * gw0[3] + q1 * gw1[3]);
       }
       if (tn) {
         const double q = lpn * (vN - vP);
         lvS += q * gn[0];
         lvP += q * gn[1];
         lvN += q * gn[2];
-        aadd(lm.v, P, i, j + 2, q * gn[3]);
+        sk.add(1, P, i, j + 2, q * gn[3]);
       }
       if (ts) {
         const double q = lps * (vP - vS);
-        aadd(lm.v, P, i, j - 2, q * gs[0]);
+        sk.add(1, P, i, j - 2, q * gs[0]);
         lvS += q * gs[1];
         lvP += q * gs[2];
         lvN += q * gs[3];
       }
-      if (!inl) aadd(lm.v, P, i - 1, j, lvW);
-      if (outl) lvP += lvE; else aadd(lm.v, P, i + 1, j, lvE);
-      aadd(lm.v, P, i, j - 1, lvS);
-      aadd(lm.v, P, i, j + 1, lvN);
-      aadd(lm.v, P, i, j, lvP);
+      if (!inl) sk.add(1, P, i - 1, j, lvW);
+      if (outl) lvP += lvE; else sk.add(1, P, i + 1, j, lvE);
+      sk.add(1, P, i, j - 1, lvS);
+      sk.add(1, P, i, j + 1, lvN);
+      sk.add(1, P, i, j, lvP);
     }
   }
+}
+
+// Reverse of the prologue.  Its scatters are summed per tile in LDS first
+// (slots: lambda of u, v, T of level n-1, of rho, of the u- and v-face
+// densities), then added to the arrays once per touched window entry.
+template <bool TV>
+__global__ __launch_bounds__(AB) void k_adj_prologue(const Params P, const State m,
+                                                     const Consts lC, const State lm,
+                                                     const double *ru0, const double *rv0,
+                                                     double *lru, double *lrv, double *lr) {
+  __shared__ double wl[6 * Tiled<6, 2, false>::WN];
+  Tiled<6, 2, false> sk{(lds_double *)wl, {lm.u, lm.v, lm.T, lr, lru, lrv}};
+  int i, j;
+  sk.begin(P, i, j);
+  if (i <= P.nx && j <= P.ny) prologue_item<TV>(P, m, lC, ru0, rv0, i, j, sk);
+  sk.end(P);
 }
 
 // face densities of a state (as in the forward pass), for the prologue
@@ -1574,11 +1587,11 @@ void launch_adjoint_prologue(const Params &P, State m, Consts lC, State lm, AdjT
   if (tv) hipLaunchKernelGGL((k_face_densities<true>), g, b, 0, st, P, m, A.luh, A.lvh);
   else hipLaunchKernelGGL((k_face_densities<false>), g, b, 0, st, P, m, A.luh, A.lvh);
   if (tv)
-    hipLaunchKernelGGL((k_adj_prologue<true>), g, b, 0, st, P, m, lC, lm, A.luh, A.lvh, A.lru,
-                       A.lrv, A.lr);
+    hipLaunchKernelGGL((k_adj_prologue<true>), tgrid(P), b, 0, st, P, m, lC, lm, A.luh, A.lvh,
+                       A.lru, A.lrv, A.lr);
   else
-    hipLaunchKernelGGL((k_adj_prologue<false>), g, b, 0, st, P, m, lC, lm, A.luh, A.lvh, A.lru,
-                       A.lrv, A.lr);
+    hipLaunchKernelGGL((k_adj_prologue<false>), tgrid(P), b, 0, st, P, m, lC, lm, A.luh, A.lvh,
+                       A.lru, A.lrv, A.lr);
   hipLaunchKernelGGL(k_cell_cache, cgrid(P), b, 0, st, P, m, A.cr, A.cg);
   if (tv)
     hipLaunchKernelGGL((k_adj_rho_faces<true>), tgrid(P), b, 0, st, P, m, Cache{A.cr, A.cg},
