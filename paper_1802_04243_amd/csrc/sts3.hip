@@ -869,6 +869,17 @@ sts_status fail3(sts_status s, const char *msg) { return sts::report_error(s, ms
     }                                                                      \
   } while (0)
 
+// as HIP3, for sts3_create after the context exists: releases it first
+#define HIP3_CREATE(call)                                                  \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess) {                                                \
+      std::string m_ = std::string(#call) + " failed: " + hipGetErrorString(e_); \
+      sts3_destroy(c);                                                     \
+      return fail3(STS_EDEVICE, m_.c_str());                               \
+    }                                                                      \
+  } while (0)
+
 dim3 grid_of(const sts3_ctx *c, int X, int Y, int Z) {
   (void)c;
   return dim3((X + BX - 1) / BX, (Y + BY - 1) / BY, Z);
@@ -1189,10 +1200,11 @@ extern "C" sts_status sts3_create(const sts3_setup *s, void *hip_stream, sts3_ct
       g.push_back(dl / (dl + d));
       g.push_back(2.0 / (dl + d));
     }
-    HIP3(hipMemcpy(c->d_d[e], g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice));
+    HIP3_CREATE(hipMemcpy(c->d_d[e], g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice));
   }
   // clear every array (frame entries stay finite), then the initial state
-  for (int k2 = 0; k2 < NFIELDS; k2++) HIP3(hipMemsetAsync(fields[k2], 0, c->field_bytes, c->stream));
+  for (int k2 = 0; k2 < NFIELDS; k2++)
+    HIP3_CREATE(hipMemsetAsync(fields[k2], 0, c->field_bytes, c->stream));
   c->cur = 0;
   c->stepped = false;
   std::vector<double> q[5];
