@@ -990,49 +990,47 @@ __global__ __launch_bounds__(AB) void k_adj_rho_faces(const Params P, const Stat
 }
 
 
+// Slot adapter: an item's slot s goes to slot S<s> of a window shared by
+// several items.
+template <class T, int S0, int S1 = 0, int S2 = 0, int S3 = 0>
+struct Slots {
+  T &t;
+  __device__ __forceinline__ void add(int s, const Params &P, int i, int j, double x) {
+    t.add(s == 0 ? S0 : (s == 1 ? S1 : (s == 2 ? S2 : S3)), P, i, j, x);
+  }
+};
+
 // The energy, u-hat, v-hat and face-density stages read disjoint adjoint
-// inputs and add into shared targets.  One stage of them (ST = 0 energy, 1
-// u-hat, 2 v-hat, 3 face densities; ST < 0: blockIdx.y selects it).  On
-// small grids one launch runs the four side by side (four times the blocks of
-// one stage, which keeps the CUs busy where a single stage would leave them
-// half idle); on large grids each stage runs as a launch of its own, whose
-// kernel holds only that stage's arrays (the side-by-side kernel needs more
-// scalar registers than the CU gives and spills them into vector lanes).
+// inputs and add into shared targets.  A block runs the four stages of its
+// tile one after the other into one window of the five target arrays and
+// flushes it once: the global atomic adds of the flush take most of these
+// stages' time, and one flush for the four halves them (against four
+// windows, whether the stages run as four launches or side by side in one).
 // SJ: the problem has slip-jump surfaces (their branches are compiled only
 // into these instances, which keeps the others' registers as without them).
 // The others fit 5 waves per SIMD (91 VGPRs; 3.5 % shorter backward on
 // 4096x1024 than at 4); the slip-jump ones would spill there and keep 4.
-template <int ST, bool TV, bool SJ>
+template <bool TV, bool SJ>
 __global__ __launch_bounds__(AB) __attribute__((amdgpu_waves_per_eu(SJ ? 4 : 5))) void k_adj_stage2(const Params P, const State o,
                                                    const State lo, const Consts C,
                                                    const Consts lC, const Inter I,
                                                    const AdjTmp A, double *gtw0, double *gtw1) {
-  __shared__ double wl[4 * Tiled<4, 1, false>::WN];
-  static_assert(Tiled<1, 2, false>::WN <= 4 * Tiled<4, 1, false>::WN, "LDS");
+  using W = Tiled<5, 2, false>;
+  __shared__ double wl[5 * W::WN];
   const Cache cc{A.cr, A.cg};
-  const int st = ST < 0 ? (int)blockIdx.y : ST;
+  W sk{(lds_double *)wl, {lo.T, lo.u, lo.v, A.lr, A.lg}};
   int i, j;
-  if (st == 0) {
-    Tiled<4, 1, false> sk{(lds_double *)wl, {lo.T, A.lg, lo.u, lo.v}};
-    sk.begin(P, i, j);
-    if (i <= P.nx && j <= P.ny) energy_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
-    sk.end(P);
-  } else if (st == 1) {
-    Tiled<4, 1, false> sk{(lds_double *)wl, {lo.u, lo.v, A.lr, A.lg}};
-    sk.begin(P, i, j);
-    if (i <= P.nx && j <= P.ny) uhat_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sk);
-    sk.end(P);
-  } else if (st == 2) {
-    Tiled<4, 1, false> sk{(lds_double *)wl, {lo.u, lo.v, A.lr, A.lg}};
-    sk.begin(P, i, j);
-    if (i <= P.nx && j <= P.ny) vhat_item<SJ>(P, o, cc, lo, C, lC, I, A, i, j, sk);
-    sk.end(P);
-  } else {
-    Tiled<1, 2, false> sk{(lds_double *)wl, {A.lr}};
-    sk.begin(P, i, j);
-    if (i <= P.nx && j <= P.ny) rho_faces_item<TV>(P, o, cc, A.lru, A.lrv, i, j, sk);
-    sk.end(P);
+  sk.begin(P, i, j);
+  if (i <= P.nx && j <= P.ny) {
+    Slots<W, 0, 4, 1, 2> se{sk};  // energy: T, Gamma, u, v
+    energy_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, se);
+    Slots<W, 1, 2, 3, 4> sq{sk};  // u-hat, v-hat: u, v, rho, Gamma
+    uhat_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sq);
+    vhat_item<SJ>(P, o, cc, lo, C, lC, I, A, i, j, sq);
+    Slots<W, 3> sr{sk};  // face densities: rho
+    rho_faces_item<TV>(P, o, cc, A.lru, A.lrv, i, j, sr);
   }
+  sk.end(P);
 }
 
 // ---------------------------------------------------------------------------
@@ -1549,32 +1547,15 @@ void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, 
                          Consts lC, AdjTmp A, double *gtw0, double *gtw1, int scheme,
                          hipStream_t st) {
   const dim3 g = agrid(P), b(AB);
-  hipLaunchKernelGGL(k_adj_front, tgrid(P), b, 0, st, P, o, ln, lo, lC, I, A);
-  // side by side below 4 blocks per SIMD of one stage's tiles, stage by stage above
-  const bool split = tgrid(P).x >= 4096;
-  const dim3 g4(tgrid(P).x, 4), g1(tgrid(P).x);
-#define STS_ST(ST_, TV_, SJ_) \
-  hipLaunchKernelGGL((k_adj_stage2<ST_, TV_, SJ_>), ST_ < 0 ? g4 : g1, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1)
-#define STS_STAGES(TV_, SJ_)      \
-  do {                            \
-    if (split) {                  \
-      STS_ST(0, TV_, SJ_);        \
-      STS_ST(1, TV_, SJ_);        \
-      STS_ST(2, TV_, SJ_);        \
-      STS_ST(3, TV_, SJ_);        \
-    } else {                      \
-      STS_ST(-1, TV_, SJ_);       \
-    }                             \
-  } while (0)
+  const dim3 gt = tgrid(P);
+  hipLaunchKernelGGL(k_adj_front, gt, b, 0, st, P, o, ln, lo, lC, I, A);
   if (scheme & 2) {
-    if (P.sj) STS_STAGES(true, true);
-    else STS_STAGES(true, false);
+    if (P.sj) hipLaunchKernelGGL((k_adj_stage2<true, true>), gt, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
+    else hipLaunchKernelGGL((k_adj_stage2<true, false>), gt, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
   } else {
-    if (P.sj) STS_STAGES(false, true);
-    else STS_STAGES(false, false);
+    if (P.sj) hipLaunchKernelGGL((k_adj_stage2<false, true>), gt, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
+    else hipLaunchKernelGGL((k_adj_stage2<false, false>), gt, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
   }
-#undef STS_STAGES
-#undef STS_ST
   hipLaunchKernelGGL(k_adj_cell_props, g, b, 0, st, P, o, lo, A.lr, A.lg);
 }
 
