@@ -348,11 +348,10 @@ __global__ __launch_bounds__(AB) void k_adj_front(const Params P, const State o,
   // cell (i, j)
   const bool cell = i < P.nx && j < P.ny, fluid = cell && fl(P, i, j);
   double lTn = 0.0;
-  if (fluid) {
-    double lN, la0, tn, dV;
-    press_adj(P, I, i, j, k, lam_pnew(P, ln, I, i, j, k), lN, la0, tn, dV);
-    lTn = ln.T[k] + la0 * (-dV / (tn * tn));
-    lC.Cp[k] += lN;
+  if (fluid) {  // lN, la0 of this cell from phase 1
+    const double tn = I.tn[k], dV = gx(P, 0, i) * gy(P, 0, j);
+    lTn = ln.T[k] + sq1[c] * (-dV / (tn * tn));
+    lC.Cp[k] += sq0[c];
   }
   A.ltn[k] = lTn;
   double lpo = cell && !fluid ? ln.p[k] : 0.0;  // old pressure
