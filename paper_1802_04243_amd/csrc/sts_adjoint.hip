@@ -368,8 +368,6 @@ __global__ __launch_bounds__(AB) void k_adj_front(const Params P, const State o,
   }
   lo.p[k] = lpo;
   lo.T[k] = cell && !fluid ? ln.T[k] : 0.0;
-  A.lr[k] = 0.0;
-  A.lg[k] = 0.0;
 
   // u-face (i, j): velocity update, then the west face of cell (i, j) and
   // the east face of cell (i-1, j) in the pressure equation; an unsolved
@@ -565,7 +563,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   // T = (dt (sum D n + Sc) + C_T) / a0
   const double lnum = l / a0, la0 = -l * tn / a0;
   lC.CT[k] += lnum;
-  unsafeAtomicAdd(A.lr + k, la0 * dV);  // u-hat, v-hat, rho faces add to A.lr too
+  sk.add(4, P, i, j, la0 * dV);  // rho_P (u-hat, v-hat and the face densities add to it too)
   const double lDW = lnum * dt * nW + la0 * dt, lDE = lnum * dt * nE + la0 * dt;
   const double lDS = lnum * dt * nS + la0 * dt, lDN = lnum * dt * nN + la0 * dt;
   double lgP = lDW * dWP + lDE * dEP + lDS * dSP + lDN * dNP;
@@ -651,7 +649,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   const double S1 = 2.0 * (ux * ux + vy * vy) + (vx + uy) * (vx + uy) - 2.0 / 3.0 * dv * dv;
   const double pP = at(o.p, P, i, j);
   lgP += lSc * P.C2 * S1 * dV;
-  lo.p[k] += lSc * P.C3 * dv * dV;  // this cell only
+  sk.add(5, P, i, j, lSc * P.C3 * dv * dV);  // p_P
   const double lS1 = lSc * P.C2 * gP * dV;
   const double ldv = lSc * P.C3 * pP * dV - lS1 * (4.0 / 3.0) * dv;
   const double lux = lS1 * 4.0 * ux + ldv, lvy = lS1 * 4.0 * vy + ldv;
@@ -699,7 +697,7 @@ __device__ void energy_item(const Params &P, const State o, const Cache cc, cons
   sk.add(3, P, i, j, lV0);
   sk.add(3, P, i, j + 1, lV1);
   sk.add(1, P, i, j, lgP);
-  if (lrw != 0.0) unsafeAtomicAdd(A.lr + k, lrw);
+  if (lrw != 0.0) sk.add(4, P, i, j, lrw);
 }
 
 // ---------------------------------------------------------------------------
@@ -991,20 +989,27 @@ __global__ __launch_bounds__(AB) void k_adj_rho_faces(const Params P, const Stat
 
 // Slot adapter: an item's slot s goes to slot S<s> of a window shared by
 // several items.
-template <class T, int S0, int S1 = 0, int S2 = 0, int S3 = 0>
+template <class T, int S0, int S1 = 0, int S2 = 0, int S3 = 0, int S4 = 0, int S5 = 0>
 struct Slots {
   T &t;
   __device__ __forceinline__ void add(int s, const Params &P, int i, int j, double x) {
-    t.add(s == 0 ? S0 : (s == 1 ? S1 : (s == 2 ? S2 : S3)), P, i, j, x);
+    t.add(s == 0 ? S0 : (s == 1 ? S1 : (s == 2 ? S2 : (s == 3 ? S3 : (s == 4 ? S4 : S5)))), P, i,
+          j, x);
   }
 };
 
 // The energy, u-hat, v-hat and face-density stages read disjoint adjoint
 // inputs and add into shared targets.  A block runs the four stages of its
-// tile one after the other into one window of the five target arrays and
+// tile one after the other into one window of the six target arrays and
 // flushes it once: the global atomic adds of the flush take most of these
 // stages' time, and one flush for the four halves them (against four
 // windows, whether the stages run as four launches or side by side in one).
+// The flush also takes the rho and Gamma adjoints of each domain cell back
+// to p and T (rho = p/T, Gamma = sqrt(T) of the iterate), so they reach
+// global memory only as parts of the p and T adjoints (the frame's stand for
+// boundary values and are dropped).  Every scatter of these stages lies
+// within two elements of its item, inside the window, and reaches global
+// memory only through the flush's atomic adds.
 // SJ: the problem has slip-jump surfaces (their branches are compiled only
 // into these instances, which keeps the others' registers as without them).
 // The others fit 5 waves per SIMD (91 VGPRs; 3.5 % shorter backward on
@@ -1014,14 +1019,14 @@ __global__ __launch_bounds__(AB) __attribute__((amdgpu_waves_per_eu(SJ ? 4 : 5))
                                                    const State lo, const Consts C,
                                                    const Consts lC, const Inter I,
                                                    const AdjTmp A, double *gtw0, double *gtw1) {
-  using W = Tiled<5, 2, false>;
-  __shared__ double wl[5 * W::WN];
+  using W = Tiled<6, 2, false>;
+  __shared__ double wl[6 * W::WN];
   const Cache cc{A.cr, A.cg};
-  W sk{(lds_double *)wl, {lo.T, lo.u, lo.v, A.lr, A.lg}};
+  W sk{(lds_double *)wl, {lo.T, lo.u, lo.v, A.lr, A.lg, lo.p}};
   int i, j;
   sk.begin(P, i, j);
   if (i <= P.nx && j <= P.ny) {
-    Slots<W, 0, 4, 1, 2> se{sk};  // energy: T, Gamma, u, v
+    Slots<W, 0, 4, 1, 2, 3, 5> se{sk};  // energy: T, Gamma, u, v, rho, p
     energy_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, se);
     Slots<W, 1, 2, 3, 4> sq{sk};  // u-hat, v-hat: u, v, rho, Gamma
     uhat_item<SJ>(P, o, cc, lo, C, lC, I, A, gtw0, gtw1, i, j, sq);
@@ -1029,7 +1034,23 @@ __global__ __launch_bounds__(AB) __attribute__((amdgpu_waves_per_eu(SJ ? 4 : 5))
     Slots<W, 3> sr{sk};  // face densities: rho
     rho_faces_item<TV>(P, o, cc, A.lru, A.lrv, i, j, sr);
   }
-  sk.end(P);
+  __syncthreads();
+  for (int r = threadIdx.x; r < W::WN; r += AB) {
+    const double du = wl[W::WN + r], dv = wl[2 * W::WN + r];
+    const double lr = wl[3 * W::WN + r], lg = wl[4 * W::WN + r];
+    double dT = wl[r], dp = wl[5 * W::WN + r];
+    const int gi = sk.x0 - 2 + r % W::WW, gj = sk.y0 - 2 + r / W::WW;
+    const long k = ix(P, gi, gj);
+    if (du != 0.0) unsafeAtomicAdd(lo.u + k, du);
+    if (dv != 0.0) unsafeAtomicAdd(lo.v + k, dv);
+    if ((lr != 0.0 || lg != 0.0) && gi >= 0 && gi < P.nx && gj >= 0 && gj < P.ny) {
+      const double p = o.p[k], T = o.T[k];
+      dp += lr / T;
+      dT += -lr * p / (T * T) + lg / (2.0 * sqrt(T));
+    }
+    if (dp != 0.0) unsafeAtomicAdd(lo.p + k, dp);
+    if (dT != 0.0) unsafeAtomicAdd(lo.T + k, dT);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1545,8 +1566,7 @@ void launch_cell_cache(const Params &P, State o, double *r, double *g, hipStream
 void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, State lo,
                          Consts lC, AdjTmp A, double *gtw0, double *gtw1, int scheme,
                          hipStream_t st) {
-  const dim3 g = agrid(P), b(AB);
-  const dim3 gt = tgrid(P);
+  const dim3 b(AB), gt = tgrid(P);
   hipLaunchKernelGGL(k_adj_front, gt, b, 0, st, P, o, ln, lo, lC, I, A);
   if (scheme & 2) {
     if (P.sj) hipLaunchKernelGGL((k_adj_stage2<true, true>), gt, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
@@ -1555,7 +1575,6 @@ void launch_adjoint_pass(const Params &P, State o, Consts C, Inter I, State ln, 
     if (P.sj) hipLaunchKernelGGL((k_adj_stage2<false, true>), gt, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
     else hipLaunchKernelGGL((k_adj_stage2<false, false>), gt, b, 0, st, P, o, lo, C, lC, I, A, gtw0, gtw1);
   }
-  hipLaunchKernelGGL(k_adj_cell_props, g, b, 0, st, P, o, lo, A.lr, A.lg);
 }
 
 void launch_adjoint_prologue(const Params &P, State m, Consts lC, State lm, AdjTmp A,
