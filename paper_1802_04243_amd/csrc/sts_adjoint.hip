@@ -1054,7 +1054,9 @@ __global__ __launch_bounds__(AB) __attribute__((amdgpu_waves_per_eu(SJ ? 4 : 5))
 }
 
 // ---------------------------------------------------------------------------
-// (0) rho = p / T and Gamma = sqrt(T) per cell
+// (0) rho = p / T and Gamma = sqrt(T) per cell: the rho and Gamma adjoints
+// back to p and T (the reverse of the prologue; the passes do this in the
+// stage-2 flush)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(AB) void k_adj_cell_props(const Params P, const State o,
                                                        const State lo, const double *lr,
