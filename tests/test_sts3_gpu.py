@@ -10,8 +10,9 @@ tests).  Cases: the small duct in every scheme; a periodic box with
 stretched widths, a body force and a random state; walls in y and z of both
 types with moving walls on a ragged grid (extents not multiples of the
 64 x 4 thread blocks); one step of the mid-size duct from a GPU-advanced
-state; the large duct's first step on sampled cells; the uniform stream;
-argument checks.
+state; one configured step of the large duct (the benchmark's workload and
+launch configuration) from a GPU-advanced state, every field; the uniform
+stream; argument checks.
 """
 from __future__ import annotations
 
@@ -127,6 +128,22 @@ def test_duct_160x32x32_step_from_gpu_state(sts3_mod, ora3, name, scheme):
     g.step(run["dt"], run["inner"], scheme)
     o.step(run["dt"], run["inner"], scheme)
     compare(g, o, f"duct_160x32x32/{name}")
+    g.close()
+
+
+@pytest.mark.parametrize("name,scheme", [("explicit_upwind", 0), ("explicit_tvd", 2)])
+def test_duct_512x128x128_step_from_gpu_state(sts3_mod, ora3, name, scheme):
+    # 8.4M cells, 10 passes: the grids of every launch as the benchmark runs
+    # them; the oracle takes about 15 s per step here
+    b, run = W3.workload3("duct_512x128x128")
+    print(f"case duct_512x128x128/{name}: 1 GPU step, then one step on both", flush=True)
+    g, o = sts3_mod.Solver3(b), ora3.Oracle3(b)
+    g.set_fields(*W3.initial_fields3(b, run["seed"]))
+    g.step(run["dt"], run["inner"], scheme)
+    o.set_fields(*g.fields())
+    g.step(run["dt"], run["inner"], scheme)
+    o.step(run["dt"], run["inner"], scheme)
+    compare(g, o, f"duct_512x128x128/{name}")
     g.close()
 
 
