@@ -9,7 +9,8 @@ trajectory that differs by FP32 rounding of the coefficients: checked
 against the gradient through the FP64 forward (itself checked against
 central differences of the FP64 oracle) at a normwise relative difference
 of 1e-5, on the small channel and on the 4096x1024 combined grid (Re 50, two
-squares) for 25 steps.  The sqrt(N) schedule (every=None) must give the
+squares) for 25 steps and for the configured 500 steps (every parameter
+and initial-state gradient).  The sqrt(N) schedule (every=None) must give the
 gradient of the every-step schedule to rounding: the two differ only in the
 order of recomputation, and the reverse kernels' atomic sums make the result
 reproducible to rounding, not bitwise.
@@ -83,4 +84,28 @@ def test_mixed_forward_adjoint_combined_grid(sts_mod):
         print(f"combined gradient {nm}: max|g| {np.abs(b).max():.3e}, rel {d:.2e}", flush=True)
         assert np.abs(b).max() > 0
         assert np.isfinite(a).all()
+        assert d <= TOL_MIXED, (nm, d)
+
+
+def test_mixed_forward_adjoint_combined_configured_run(sts_mod):
+    # the configured combined run: 500 steps x 10 passes, sqrt(N) checkpoints
+    # (23 steps a segment); every parameter and initial-state gradient of the
+    # mixed forward against the FP64 forward's (in 500 steps the drag does
+    # not feel the inlet 1126 cells upstream: that gradient is 0 in both)
+    p, run = W.workload("combined_4096x1024")
+    f0 = W.initial_fields(p, run["seed"])
+    steps, inner, scheme = run["steps"], run["inner"], W.EXPLICIT | W.TVD
+    print(f"case combined 4096x1024 {steps}x{inner} mixed forward vs fp64", flush=True)
+    Lm, gu_m, g0_m, g1_m, fm = adjoint_gradient(p, f0, run["dt"], steps, inner,
+                                                 scheme | W.MIXED, None, fields=True)
+    Lf, gu_f, g0_f, g1_f, ff = adjoint_gradient(p, f0, run["dt"], steps, inner, scheme, None,
+                                                 fields=True)
+    print(f"L mixed {Lm:.15e} fp64 {Lf:.15e}", flush=True)
+    assert abs(Lm - Lf) <= 1e-6 * abs(Lf)
+    assert not gu_f.any() and not gu_m.any(), (np.abs(gu_f).max(), np.abs(gu_m).max())
+    for nm, a, b in zip(["wall_T0", "wall_T1", "u0", "v0", "p0", "T0"],
+                        [g0_m, g1_m, *fm], [g0_f, g1_f, *ff]):
+        d = normdiff(a, b)
+        print(f"combined gradient {nm}: max|g| {np.abs(b).max():.3e}, rel {d:.2e}", flush=True)
+        assert np.abs(b).max() > 0 and np.isfinite(a).all()
         assert d <= TOL_MIXED, (nm, d)
